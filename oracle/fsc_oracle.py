@@ -1,0 +1,359 @@
+"""Plain FP64 CPU oracle for FastSpectralCluster.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
+module: it is used by ``tests/``, by ``__graft_entry__.smoke()`` and by the
+``cpu_baseline`` leg of ``bench.py``.  It shares no code with the HIP path.
+
+Every function follows the paper ("Fast and Simple Spectral Clustering in
+Theory and Practice", Macgregor, NeurIPS 2023) step by step in float64, with
+numpy/scipy primitives (a sparse matrix product, a dense eigendecomposition in
+the checks) as the only library steps.  Readings where the paper is silent are
+marked "Reading:" and are listed in the design notes.
+
+Sections of the paper referenced below:
+  * Sec. 2 (Preliminaries): degree, Laplacian, normalised Laplacian N, the
+    halved signless Laplacian M = I - N/2 with eigenvalues in [0, 1].
+  * Sec. 2.2: the k-means cost; Lloyd's algorithm with k-means++ seeding.
+  * Sec. 2.3, Algorithm 1 (PowerMethod): x_i = M x_{i-1}, no normalisation.
+  * Sec. 3.2, Algorithm 2 (FastSpectralCluster): l Gaussian vectors, each run
+    through PowerMethod for t steps, k-means on D^{-1/2} Y.
+  * Sec. 4.2: ARI as the accuracy score.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+# ----------------------------------------------------------------------------
+# Counter-based random numbers.
+# Philox4x32-10 as published by Salmon, Moraes, Dror and Shaw, "Parallel random
+# numbers: as easy as 1, 2, 3" (SC'11): a 4x32-bit counter, a 2x32-bit key,
+# ten rounds of two 32x32->64 multiplies with a Weyl-sequence key schedule.
+# The paper only fixes the distribution N(0, I) of the start vectors
+# (Sec. 3.1 and Algorithm 2); the generator is this build's reading.
+# ----------------------------------------------------------------------------
+_PHILOX_M0 = np.uint64(0xD2511F53)
+_PHILOX_M1 = np.uint64(0xCD9E8D57)
+_PHILOX_W0 = np.uint64(0x9E3779B9)
+_PHILOX_W1 = np.uint64(0xBB67AE85)
+_MASK32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Philox4x32-10 on arrays of 32-bit words (held in uint64 containers).
+
+    Returns the four output words as uint64 arrays with values < 2**32.
+    """
+    c0, c1, c2, c3 = (np.asarray(c, dtype=np.uint64) & _MASK32 for c in (c0, c1, c2, c3))
+    k0 = np.asarray(k0, dtype=np.uint64) & _MASK32
+    k1 = np.asarray(k1, dtype=np.uint64) & _MASK32
+    for rnd in range(10):
+        if rnd > 0:
+            k0 = (k0 + _PHILOX_W0) & _MASK32
+            k1 = (k1 + _PHILOX_W1) & _MASK32
+        p0 = _PHILOX_M0 * c0          # < 2**64, exact in uint64
+        p1 = _PHILOX_M1 * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _MASK32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _MASK32
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+    return c0, c1, c2, c3
+
+
+def uniform53(hi, lo):
+    """Map a pair of 32-bit words to a double in (0, 1): the top 53 bits of
+    the 64-bit word hi:lo, offset by half a step so that 0 is never hit."""
+    hi = np.asarray(hi, dtype=np.uint64)
+    lo = np.asarray(lo, dtype=np.uint64)
+    w = (hi << np.uint64(32)) | lo
+    return ((w >> np.uint64(11)).astype(np.float64) + 0.5) * (2.0 ** -53)
+
+
+def _key(seed):
+    seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    return seed & 0xFFFFFFFF, seed >> 32
+
+
+def gaussian_block(n, l, seed):
+    """Start block X0 in R^{n x l} with i.i.d. N(0, 1) entries (Algorithm 2,
+    the l Gaussian vectors; Sec. 3.1 for the distribution).
+
+    Entry (i, j) uses Philox counter (i_lo, i_hi, j, 0) under key = seed; the
+    four output words give two uniforms u1, u2 and the Box-Muller (1958)
+    transform z = sqrt(-2 ln u1) cos(2 pi u2) in float64.
+    """
+    k0, k1 = _key(seed)
+    i = np.arange(n, dtype=np.uint64)[:, None]
+    j = np.arange(l, dtype=np.uint64)[None, :]
+    i, j = np.broadcast_arrays(i, j)
+    r0, r1, r2, r3 = philox4x32_10(i & _MASK32, i >> np.uint64(32), j, 0, k0, k1)
+    u1 = uniform53(r0, r1)
+    u2 = uniform53(r2, r3)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def uniform_draw(seed, counter, stream):
+    """One uniform in (0, 1) from Philox counter (counter_lo, counter_hi, 0,
+    stream) under key = seed (used by the k-means++ sampling)."""
+    k0, k1 = _key(seed)
+    c = int(counter)
+    r0, r1, _, _ = philox4x32_10(c & 0xFFFFFFFF, c >> 32, 0, stream, k0, k1)
+    return float(uniform53(r0, r1))
+
+
+# ----------------------------------------------------------------------------
+# Graph quantities (Sec. 2, Preliminaries)
+# ----------------------------------------------------------------------------
+def validate_graph(n, indptr, indices, data=None):
+    """Checks the graph is a weighted undirected graph as Sec. 2 assumes:
+    symmetric A, no self-loops (the degree sums over u != v), weights finite
+    and non-negative.  Raises ValueError otherwise."""
+    indptr = np.asarray(indptr, dtype=np.int64)
+    indices = np.asarray(indices, dtype=np.int64)
+    if indptr.shape != (n + 1,) or indptr[0] != 0 or np.any(np.diff(indptr) < 0):
+        raise ValueError("bad row pointer")
+    if indices.size and (indices.min() < 0 or indices.max() >= n):
+        raise ValueError("column index out of range")
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(indptr))
+    if np.any(rows == indices):
+        raise ValueError("self-loop")
+    w = np.ones(indices.size) if data is None else np.asarray(data, dtype=np.float64)
+    if not np.all(np.isfinite(w)) or np.any(w < 0):
+        raise ValueError("weights must be finite and non-negative")
+    A = sp.csr_matrix((w, indices, indptr), shape=(n, n))
+    if abs(A - A.T).sum() != 0.0:
+        raise ValueError("adjacency is not symmetric")
+
+
+def adjacency(n, indptr, indices, data=None):
+    """A as a float64 sparse matrix (unit weights when data is None)."""
+    w = np.ones(len(indices)) if data is None else np.asarray(data, dtype=np.float64)
+    return sp.csr_matrix((w, np.asarray(indices), np.asarray(indptr)), shape=(n, n))
+
+
+def degrees(n, indptr, indices, data=None):
+    """deg(v) = sum_{u != v} w(u, v) (Sec. 2), summed in float64 over the
+    entries of row v in the order the row stores them."""
+    indptr = np.asarray(indptr, dtype=np.int64)
+    indices = np.asarray(indices, dtype=np.int64)
+    w = np.ones(len(indices)) if data is None else np.asarray(data, dtype=np.float64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(indptr))
+    w = np.where(indices != rows, w, 0.0)
+    d = np.zeros(n)
+    np.add.at(d, rows, w)      # unbuffered, in entry order
+    return d
+
+
+def inv_sqrt_degree(d):
+    """D^{-1/2} as a vector.  Reading: an isolated vertex (d = 0) has no
+    defined D^{-1/2}; it is taken as 0, so its embedding row is 0."""
+    out = np.zeros_like(d)
+    pos = d > 0
+    out[pos] = 1.0 / np.sqrt(d[pos])
+    return out
+
+
+def signless_laplacian(n, indptr, indices, data=None):
+    """M = I - N/2 = (I + D^{-1/2} A D^{-1/2}) / 2 (Sec. 2, with the paper's
+    halving so that the eigenvalues gamma_i = 1 - lambda_i/2 lie in [0, 1]),
+    as a sparse matrix.  An isolated vertex gets the row e_v / 2."""
+    A = adjacency(n, indptr, indices, data)
+    s = inv_sqrt_degree(degrees(n, indptr, indices, data))
+    S = sp.diags(s)
+    return (0.5 * (sp.identity(n, format="csr") + S @ A @ S)).tocsr()
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 (PowerMethod) and the embedding of Algorithm 2
+# ----------------------------------------------------------------------------
+def power_method(M, x0, t):
+    """Algorithm 1: x_i = M x_{i-1} for i = 1..t; returns x_t.  Applied to
+    every column of x0 independently (no normalisation, no
+    orthogonalisation)."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    for _ in range(t):
+        x = M @ x
+    return x
+
+
+def power_method_traced(M, x0, t, rows=None):
+    """Algorithm 1 with the per-step column statistics recorded:
+    sqnorm[i, j] = ||x_i^{(j)}||^2 for i = 0..t and
+    rayleigh[i, j] = x_i^T M x_i / x_i^T x_i = x_i^T x_{i+1} / ||x_i||^2 for
+    i = 0..t-1 (a Rayleigh quotient of M, so it lies in [0, 1] by Sec. 2).
+    `rows` (a boolean mask) restricts the statistics to those rows."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    m = np.ones(x.shape[0], dtype=bool) if rows is None else np.asarray(rows, dtype=bool)
+    sq = [np.einsum("ij,ij->j", x[m], x[m])]
+    ray = []
+    for _ in range(t):
+        xn = M @ x
+        num = np.einsum("ij,ij->j", x[m], xn[m])
+        den = sq[-1]
+        ray.append(np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0))
+        x = xn
+        sq.append(np.einsum("ij,ij->j", x[m], x[m]))
+    return x, np.array(sq), np.array(ray).reshape(t, x.shape[1])
+
+
+def embed(n, indptr, indices, data, l, t, seed=None, x0=None, traced=False):
+    """The embedding that Algorithm 2 hands to k-means: D^{-1/2} Y, where the
+    columns of Y are PowerMethod(M, x_i, t) for l Gaussian x_i.
+
+    x0 (n x l) overrides the seeded start block.  With traced=True it also
+    returns the per-step squared norms and Rayleigh quotients of the y_i.
+    Reading: the statistics are taken over the non-isolated vertices only
+    (an isolated vertex has no D^{-1/2}, see inv_sqrt_degree).
+    """
+    if x0 is None:
+        x0 = gaussian_block(n, l, seed)
+    x0 = np.asarray(x0, dtype=np.float64).reshape(n, l)
+    M = signless_laplacian(n, indptr, indices, data)
+    d = degrees(n, indptr, indices, data)
+    s = inv_sqrt_degree(d)
+    if traced:
+        Y, sq, ray = power_method_traced(M, x0, t, rows=d > 0)
+        return s[:, None] * Y, sq, ray
+    Y = power_method(M, x0, t)
+    return s[:, None] * Y
+
+
+# ----------------------------------------------------------------------------
+# k-means (Sec. 2.2): k-means++ seeding, then Lloyd's algorithm
+# ----------------------------------------------------------------------------
+def kmeans_cost(B, labels, k):
+    """COST_B(A_1..A_k) = sum_i sum_{u in A_i} ||B(u,:) - mu_i||^2 with mu_i the
+    mean of the rows in A_i (Sec. 2.2)."""
+    B = np.asarray(B, dtype=np.float64)
+    total = 0.0
+    for i in range(k):
+        rows = B[labels == i]
+        if len(rows):
+            total += float(((rows - rows.mean(axis=0)) ** 2).sum())
+    return total
+
+
+def kmeanspp(P, k, seed, eligible=None):
+    """k-means++ seeding (Arthur and Vassilvitskii, as cited in Sec. 2.2).
+
+    Reading of the sampling, with the Philox uniforms of this module:
+      * centre 0: with u from stream 1, the row v whose inclusive running
+        count of eligible rows first exceeds u * n_eligible;
+      * centre r >= 1: D2(v) = min over chosen centres of ||P_v - c||^2 on
+        eligible rows (0 on the others); with u from stream 2, counter r, the
+        smallest v whose inclusive float64 running sum of D2 exceeds
+        u * sum(D2);
+      * if sum(D2) == 0: the smallest eligible row not chosen yet, else the
+        smallest row not chosen yet.
+    Returns the chosen row indices.
+    """
+    P = np.asarray(P, dtype=np.float64)
+    n = P.shape[0]
+    elig = np.ones(n, dtype=bool) if eligible is None else np.asarray(eligible, dtype=bool)
+    chosen = []
+
+    def pick(weights, u):
+        run = np.cumsum(weights)        # inclusive running sum, index order
+        total = float(run[-1]) if n else 0.0
+        if total > 0.0:
+            v = int(np.searchsorted(run, u * total, side="right"))
+            if v >= n:  # rounding left the target at the very end
+                v = int(np.nonzero(weights > 0)[0][-1])
+            return v
+        for v in range(n):
+            if elig[v] and v not in chosen:
+                return v
+        for v in range(n):
+            if v not in chosen:
+                return v
+        raise ValueError("k exceeds n")
+
+    chosen.append(pick(elig.astype(np.float64), uniform_draw(seed, 0, 1)))
+    d2 = np.full(n, np.inf)
+    for r in range(1, k):
+        c = P[chosen[-1]]
+        dist = ((P - c) ** 2).sum(axis=1)
+        d2 = np.minimum(d2, dist)
+        w = np.where(elig, d2, 0.0)
+        chosen.append(pick(w, uniform_draw(seed, r, 2)))
+    return chosen
+
+
+def assign(P, centres):
+    """Nearest centre by the direct float64 squared distance; ties go to the
+    lowest centre index."""
+    P = np.asarray(P, dtype=np.float64)
+    C = np.asarray(centres, dtype=np.float64)
+    out = np.empty(P.shape[0], dtype=np.int64)
+    step = 1 << 15
+    for s in range(0, P.shape[0], step):
+        blk = P[s:s + step]
+        dist = ((blk[:, None, :] - C[None, :, :]) ** 2).sum(axis=2)
+        out[s:s + step] = np.argmin(dist, axis=1)  # first minimum wins
+    return out
+
+
+def lloyd(P, centres, iters, eligible=None):
+    """Lloyd's algorithm (Sec. 2.2): `iters` rounds of (assign every row to its
+    nearest centre, move every centre to the mean of its eligible rows).
+    Reading: a centre with no rows keeps its position; a final assignment
+    makes the labels agree with the returned centres."""
+    P = np.asarray(P, dtype=np.float64)
+    C = np.array(centres, dtype=np.float64, copy=True)
+    n = P.shape[0]
+    elig = np.ones(n, dtype=bool) if eligible is None else np.asarray(eligible, dtype=bool)
+    for _ in range(iters):
+        lab = assign(P, C)
+        for j in range(C.shape[0]):
+            rows = P[(lab == j) & elig]
+            if len(rows):
+                C[j] = rows.sum(axis=0) / len(rows)
+    return assign(P, C), C
+
+
+def kmeans(P, k, iters, seed, eligible=None):
+    """k-means++ seeding followed by `iters` Lloyd rounds."""
+    P = np.asarray(P, dtype=np.float64)
+    idx = kmeanspp(P, k, seed, eligible)
+    return lloyd(P, P[idx], iters, eligible)
+
+
+def fast_spectral_cluster(n, indptr, indices, data, k, l, t, seed, kmeans_iters,
+                          x0=None):
+    """Algorithm 2 end to end: embedding D^{-1/2} Y, then k-means on it.
+    Isolated vertices (reading: d = 0) take no part in the k-means fit and are
+    labelled by their nearest final centre.  Returns (labels, centres, E)."""
+    E = embed(n, indptr, indices, data, l, t, seed=seed, x0=x0)
+    d = degrees(n, indptr, indices, data)
+    labels, C = kmeans(E, k, kmeans_iters, seed, eligible=d > 0)
+    return labels, C, E
+
+
+# ----------------------------------------------------------------------------
+# Adjusted Rand index (Hubert and Arabie; the score of Sec. 4.2)
+# ----------------------------------------------------------------------------
+def _comb2(x):
+    x = np.asarray(x, dtype=np.float64)
+    return x * (x - 1.0) / 2.0
+
+
+def ari(a, b):
+    """ARI from the contingency table:
+    (sum_ij C(n_ij, 2) - E) / (mean(sum_i C(a_i,2), sum_j C(b_j,2)) - E), with
+    E = sum_i C(a_i,2) sum_j C(b_j,2) / C(n, 2).  Reading: when the
+    denominator vanishes (both labelings trivial) the score is 1."""
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    n = a.size
+    _, ai = np.unique(a, return_inverse=True)
+    _, bi = np.unique(b, return_inverse=True)
+    table = np.zeros((ai.max() + 1 if n else 1, bi.max() + 1 if n else 1))
+    np.add.at(table, (ai, bi), 1.0)
+    sum_ij = _comb2(table).sum()
+    sa = _comb2(table.sum(axis=1)).sum()
+    sb = _comb2(table.sum(axis=0)).sum()
+    total = _comb2(n)
+    expected = sa * sb / total if total > 0 else 0.0
+    denom = 0.5 * (sa + sb) - expected
+    if denom == 0.0:
+        return 1.0
+    return float((sum_ij - expected) / denom)

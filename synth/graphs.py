@@ -1,0 +1,203 @@
+"""Seeded synthetic graph generators.
+
+These build the inputs that both the oracle and the HIP path consume.  They
+hold none of the clustering method's arithmetic: only random graph models and
+CSR assembly.  Every generator returns a `Graph` whose CSR stores both
+directions of each undirected edge (nnz = 2m), sorted by row then column, with
+no self-loops.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+
+@dataclass
+class Graph:
+    n: int
+    indptr: np.ndarray            # int64 [n+1]
+    indices: np.ndarray           # int32 [nnz]
+    data: Optional[np.ndarray]    # float64 [nnz] or None (unit weights)
+    labels: Optional[np.ndarray] = None   # planted cluster of each vertex
+
+    @property
+    def nnz(self) -> int:
+        return int(self.indptr[-1])
+
+
+def csr_from_edges(n, u, v, w=None) -> Graph:
+    """Symmetric CSR from an undirected edge list (u[i], v[i]) with u != v.
+    Duplicate pairs are merged (first weight kept)."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    if w is not None:
+        w = np.asarray(w, dtype=np.float64)[keep]
+    lo, hi = np.minimum(u, v), np.maximum(u, v)
+    key = lo * n + hi
+    key, first = np.unique(key, return_index=True)
+    lo, hi = key // n, key % n
+    if w is not None:
+        w = w[first]
+    rows = np.concatenate([lo, hi])
+    cols = np.concatenate([hi, lo])
+    order = np.argsort(rows * n + cols, kind="stable")
+    rows, cols = rows[order], cols[order]
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=indptr[1:])
+    data = None if w is None else np.concatenate([w, w])[order]
+    return Graph(n, indptr, cols.astype(np.int32), data)
+
+
+def _pairs_within(rng, lo, size, p, dense_limit=1 << 24):
+    """Bernoulli(p) edges among vertices [lo, lo+size): exact per-pair coin
+    flips when the block is small, otherwise a Binomial edge count followed by
+    uniform pair draws (duplicates merged later)."""
+    npairs = size * (size - 1) // 2
+    if npairs == 0 or p <= 0:
+        return np.empty(0, np.int64), np.empty(0, np.int64)
+    if npairs <= dense_limit:
+        iu, ju = np.triu_indices(size, k=1)
+        m = rng.random(iu.size) < p
+        return iu[m] + lo, ju[m] + lo
+    cnt = rng.binomial(npairs, p)
+    a = rng.integers(0, size, cnt)
+    b = rng.integers(0, size, cnt)
+    return a + lo, b + lo
+
+
+def _pairs_between(rng, lo_a, size_a, lo_b, size_b, p, dense_limit=1 << 24):
+    npairs = size_a * size_b
+    if npairs == 0 or p <= 0:
+        return np.empty(0, np.int64), np.empty(0, np.int64)
+    if npairs <= dense_limit:
+        m = rng.random((size_a, size_b)) < p
+        a, b = np.nonzero(m)
+        return a + lo_a, b + lo_b
+    cnt = rng.binomial(npairs, p)
+    return rng.integers(0, size_a, cnt) + lo_a, rng.integers(0, size_b, cnt) + lo_b
+
+
+def sbm(n, k, p_in, p_out, seed, permute=False) -> Graph:
+    """Stochastic block model as in the paper's synthetic experiments (Sec. 4.1):
+    k clusters of (nearly) equal size, each pair inside a cluster joined with
+    probability p_in and across clusters with p_out, unit weights.  Cluster
+    sizes differ by at most one (the remainder goes to the first clusters).
+    With permute=True the vertex ids are shuffled (seeded)."""
+    rng = np.random.default_rng(seed)
+    sizes = np.full(k, n // k, dtype=np.int64)
+    sizes[: n % k] += 1
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    us, vs = [], []
+    for a in range(k):
+        u, v = _pairs_within(rng, int(starts[a]), int(sizes[a]), p_in)
+        us.append(u); vs.append(v)
+        for b in range(a + 1, k):
+            u, v = _pairs_between(rng, int(starts[a]), int(sizes[a]),
+                                  int(starts[b]), int(sizes[b]), p_out)
+            us.append(u); vs.append(v)
+    u = np.concatenate(us); v = np.concatenate(vs)
+    labels = np.repeat(np.arange(k, dtype=np.int32), sizes)
+    if permute:
+        perm = rng.permutation(n)
+        u, v = perm[u], perm[v]
+        lab = np.empty(n, dtype=np.int32)
+        lab[perm] = labels
+        labels = lab
+    g = csr_from_edges(n, u, v)
+    g.labels = labels
+    return g
+
+
+def sbm_by_degree(n, k, deg_in, deg_out, seed, permute=False) -> Graph:
+    """SBM parameterised by expected in-cluster and out-of-cluster degree."""
+    size = n / k
+    p_in = deg_in / max(size - 1, 1)
+    p_out = deg_out / max(n - size, 1)
+    return sbm(n, k, min(p_in, 1.0), min(p_out, 1.0), seed, permute)
+
+
+def disjoint_cliques(k, s) -> Graph:
+    """k disjoint complete graphs K_s (vertices of clique c are c*s..c*s+s-1)."""
+    us, vs = [], []
+    iu, ju = np.triu_indices(s, k=1)
+    for c in range(k):
+        us.append(iu + c * s); vs.append(ju + c * s)
+    g = csr_from_edges(k * s, np.concatenate(us), np.concatenate(vs))
+    g.labels = np.repeat(np.arange(k, dtype=np.int32), s)
+    return g
+
+
+def cycle(n) -> Graph:
+    """The cycle C_n (n >= 3)."""
+    i = np.arange(n)
+    return csr_from_edges(n, i, (i + 1) % n)
+
+
+def complete_bipartite(a, b) -> Graph:
+    """K_{a,b}: vertices 0..a-1 on one side, a..a+b-1 on the other."""
+    u, v = np.meshgrid(np.arange(a), np.arange(a, a + b), indexing="ij")
+    return csr_from_edges(a + b, u.ravel(), v.ravel())
+
+
+def random_weighted(n, m, seed, hubs=0, hub_degree=0, isolated=0, weighted=True) -> Graph:
+    """A ragged test graph: m uniform random edges, plus `hubs` vertices each
+    joined to `hub_degree` random others, and the last `isolated` vertices left
+    without edges.  Weights are uniform in (0.5, 2) when weighted."""
+    rng = np.random.default_rng(seed)
+    live = n - isolated
+    u = rng.integers(0, live, m)
+    v = rng.integers(0, live, m)
+    if hubs:
+        hu = np.repeat(rng.choice(live, hubs, replace=False), hub_degree)
+        hv = rng.integers(0, live, hu.size)
+        u = np.concatenate([u, hu]); v = np.concatenate([v, hv])
+    w = rng.uniform(0.5, 2.0, u.size) if weighted else None
+    return csr_from_edges(n, u, v, w)
+
+
+def gaussian_mixture(n_per, k, dim, seed, mean_scale=2.0):
+    """Points of a mixture of k isotropic Gaussians: means ~ N(0, mean_scale^2 I),
+    unit covariance, n_per points per component (component c occupies rows
+    c*n_per..).  Returns (X float32 [k*n_per, dim], labels)."""
+    rng = np.random.default_rng(seed)
+    means = rng.standard_normal((k, dim)) * mean_scale
+    X = np.repeat(means, n_per, axis=0) + rng.standard_normal((k * n_per, dim))
+    return X.astype(np.float32), np.repeat(np.arange(k, dtype=np.int32), n_per)
+
+
+def knn_graph(X, knn=10, block=4096) -> Graph:
+    """Symmetrised k-nearest-neighbour graph of the rows of X (the paper's
+    pre-processing of its real-world data, Sec. 4.2, with k = 10).  Exact
+    neighbours by squared Euclidean distance, self excluded, ties to the lower
+    index; union symmetrisation; weight exp(-d^2 / sigma^2) with sigma^2 the
+    median of the directed neighbour distances."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    sq = (X * X).sum(axis=1)
+    nbr = np.empty((n, knn), dtype=np.int64)
+    dist = np.empty((n, knn))
+    for s in range(0, n, block):
+        e = min(n, s + block)
+        D = sq[s:e, None] + sq[None, :] - 2.0 * (X[s:e] @ X.T)
+        D[np.arange(e - s), np.arange(s, e)] = np.inf
+        part = np.argpartition(D, knn, axis=1)[:, : knn + 1]
+        pd = np.take_along_axis(D, part, axis=1)
+        order = np.lexsort((part, pd), axis=1)[:, :knn]
+        nbr[s:e] = np.take_along_axis(part, order, axis=1)
+        dist[s:e] = np.maximum(np.take_along_axis(pd, order, axis=1), 0.0)
+    sigma2 = float(np.median(dist))
+    u = np.repeat(np.arange(n), knn)
+    v = nbr.ravel()
+    w = np.exp(-dist.ravel() / sigma2)
+    return csr_from_edges(n, u, v, w)
+
+
+def knn_mixture(n_per, k, dim, seed, knn=10) -> Graph:
+    X, lab = gaussian_mixture(n_per, k, dim, seed)
+    g = knn_graph(X, knn)
+    g.labels = lab
+    return g

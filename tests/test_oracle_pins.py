@@ -1,0 +1,329 @@
+"""Pins for the FP64 oracle: every check below compares the oracle with
+something other than itself -- published known-answer vectors, closed forms
+from the spectra of special graphs, library routines (scipy's normalised
+Laplacian, numpy's eigensolver and FFT, scikit-learn's Lloyd and ARI),
+brute force, and statistical facts the paper states."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csgraph
+from scipy import stats
+
+import synth
+from oracle import fsc_oracle as o
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+# --------------------------------------------------------------------------
+def test_philox_known_answers():
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        c0, c1, c2, c3, k0, k1 = (int(x, 16) for x in r[:6])
+        want = [int(x, 16) for x in r[6:]]
+        got = [int(x) for x in o.philox4x32_10(c0, c1, c2, c3, k0, k1)]
+        assert got == want
+
+
+def test_uniform53_endpoints():
+    # closed form: the map is ((w >> 11) + 1/2) * 2^-53 on the 64-bit word w
+    assert o.uniform53(0, 0) == 0.5 * 2.0 ** -53
+    assert o.uniform53(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 0.5 * 2.0 ** -53
+    assert o.uniform53(0x80000000, 0) == 0.5 + 0.5 * 2.0 ** -53
+
+
+def test_gaussian_block_distribution():
+    # Sec. 3.1 / Algorithm 2: start vectors are N(0, I).  KS test against the
+    # normal CDF, and the chi-square facts of Lemma A.1 (E||x||^2 = n,
+    # ||x||^2 <= 6n).
+    n, l = 200_000, 4
+    X = o.gaussian_block(n, l, seed=1234)
+    assert X.shape == (n, l)
+    for j in range(l):
+        assert stats.kstest(X[:, j], "norm").pvalue > 1e-4
+        sq = float((X[:, j] ** 2).sum())
+        assert abs(sq - n) < 6 * np.sqrt(2 * n)        # chi^2_n: sd sqrt(2n)
+        assert sq <= 6 * n
+    # columns are independent: correlations at the 1/sqrt(n) scale
+    c = np.corrcoef(X.T)
+    assert np.abs(c - np.eye(l)).max() < 5 / np.sqrt(n)
+    # seeds give different streams, the same seed the same one
+    assert np.array_equal(X[:100], o.gaussian_block(100, l, seed=1234))
+    assert not np.allclose(X[:100], o.gaussian_block(100, l, seed=1235))
+
+
+# --------------------------------------------------------------------------
+# Degrees and the signless Laplacian (Sec. 2)
+# --------------------------------------------------------------------------
+def _hand_graph():
+    # path 0-1-2 with weights 2, 3 and a pendant 3-1 with weight 0.5
+    return synth.csr_from_edges(4, [0, 1, 3], [1, 2, 1], [2.0, 3.0, 0.5])
+
+
+def test_degrees_by_hand():
+    g = _hand_graph()
+    d = o.degrees(g.n, g.indptr, g.indices, g.data)
+    assert d.tolist() == [2.0, 5.5, 3.0, 0.5]
+
+
+def test_degree_sum_is_twice_edge_weight():
+    g = synth.random_weighted(300, 1500, seed=3)
+    d = o.degrees(g.n, g.indptr, g.indices, g.data)
+    # every undirected edge appears twice in the CSR
+    assert np.isclose(d.sum(), g.data.sum(), rtol=1e-14)
+
+
+def _lib_signless(g):
+    """M from scipy's own normalised Laplacian: M = I - N/2 (Sec. 2)."""
+    A = sp.csr_matrix((np.ones(g.nnz) if g.data is None else g.data, g.indices, g.indptr),
+                      shape=(g.n, g.n))
+    N = csgraph.laplacian(A.toarray(), normed=True)
+    return np.eye(g.n) - 0.5 * N
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_signless_laplacian_matches_scipy(seed):
+    g = synth.random_weighted(120, 900, seed=seed)
+    assert np.all(o.degrees(g.n, g.indptr, g.indices, g.data) > 0)
+    M = o.signless_laplacian(g.n, g.indptr, g.indices, g.data).toarray()
+    assert np.abs(M - _lib_signless(g)).max() < 1e-15
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_power_method_equals_eigen_expansion(seed):
+    # x_t = sum_i a_i gamma_i^t f_i (Sec. 3.1), with the spectrum from a
+    # library eigensolver of scipy's normalised Laplacian; gamma in [0, 1].
+    g = synth.random_weighted(150, 1200, seed=seed)
+    l, t = 3, 17
+    Mlib = _lib_signless(g)
+    gam, F = np.linalg.eigh(Mlib)
+    assert gam.min() > -1e-12 and gam.max() < 1 + 1e-12
+    assert abs(gam.max() - 1.0) < 1e-12               # gamma_1 = 1
+    X0 = o.gaussian_block(g.n, l, seed=seed + 10)
+    want = F @ (gam[:, None] ** t * (F.T @ X0))
+    M = o.signless_laplacian(g.n, g.indptr, g.indices, g.data)
+    got = o.power_method(M, X0, t)
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+    # the embedding is D^{-1/2} of that
+    d = np.asarray(sp.csr_matrix((g.data, g.indices, g.indptr)).sum(axis=1)).ravel()
+    E = o.embed(g.n, g.indptr, g.indices, g.data, l, t, x0=X0)
+    assert np.abs(E - want / np.sqrt(d)[:, None]).max() < 1e-12 * np.abs(want).max()
+
+
+def test_cliques_closed_form():
+    # k disjoint K_s: the top eigenspace (gamma = 1, multiplicity k) holds the
+    # per-clique constants; every other eigenvalue is (s-2)/(2(s-1)).  So
+    # Y_t = PX + g^t (X - PX) with PX the per-clique column mean, and the
+    # embedding is constant per clique up to g^t.
+    k, s, l, t = 4, 9, 3, 11
+    g = synth.disjoint_cliques(k, s)
+    X0 = o.gaussian_block(g.n, l, seed=5)
+    PX = np.repeat(X0.reshape(k, s, l).mean(axis=1), s, axis=0)
+    gam = (s - 2) / (2 * (s - 1))
+    want = (PX + gam ** t * (X0 - PX)) / np.sqrt(s - 1)
+    E = o.embed(g.n, g.indptr, g.indices, None, l, t, x0=X0)
+    assert np.abs(E - want).max() < 1e-14
+    E40 = o.embed(g.n, g.indptr, g.indices, None, l, 40, x0=X0)
+    spread = np.abs(E40.reshape(k, s, l) - E40.reshape(k, s, l).mean(axis=1, keepdims=True)).max()
+    assert spread < 1e-12
+
+
+def test_cycle_fourier_closed_form():
+    # C_n: M is a circulant with eigenvalues cos^2(pi j / n) on the Fourier modes
+    n, t = 64, 9
+    g = synth.cycle(n)
+    x = o.gaussian_block(n, 1, seed=2)[:, 0]
+    lam = np.cos(np.pi * np.arange(n) / n) ** 2
+    want = np.real(np.fft.ifft(np.fft.fft(x) * lam ** t))
+    M = o.signless_laplacian(n, g.indptr, g.indices, None)
+    assert np.abs(o.power_method(M, x[:, None], t)[:, 0] - want).max() < 1e-13
+
+
+def test_complete_bipartite_extreme_eigenvectors():
+    # K_{a,b}: D^{1/2} (+1 on one side, -1 on the other) has gamma = 0, and
+    # D^{1/2} 1 has gamma = 1.
+    a, b = 5, 8
+    g = synth.complete_bipartite(a, b)
+    M = o.signless_laplacian(g.n, g.indptr, g.indices, None)
+    sd = np.sqrt(np.r_[np.full(a, b), np.full(b, a)].astype(float))
+    f0 = sd * np.r_[np.ones(a), -np.ones(b)]
+    f1 = sd
+    assert np.abs(M @ f0).max() < 1e-14
+    assert np.abs(M @ f1 - f1).max() < 1e-14
+
+
+def test_large_t_embedding_is_constant_on_connected_graph():
+    # D^{-1/2} f_1 is constant (Sec. 2): after many steps on a connected,
+    # non-bipartite graph every column of E is (nearly) constant.
+    g = synth.sbm(200, 1, 0.2, 0.0, seed=1)
+    assert csgraph.connected_components(sp.csr_matrix((np.ones(g.nnz), g.indices, g.indptr)))[0] == 1
+    E = o.embed(g.n, g.indptr, g.indices, None, 2, 400, seed=9)
+    assert (E.std(axis=0) / np.abs(E.mean(axis=0))).max() < 1e-8
+
+
+def test_trace_rayleigh_quotients():
+    # Rayleigh quotients of M lie in [0, 1] and equal x^T M x / x^T x computed
+    # with the library M; squared norms never grow (||M|| <= 1).
+    g = synth.random_weighted(100, 700, seed=4)
+    X0 = o.gaussian_block(g.n, 2, seed=1)
+    E, sq, ray = o.embed(g.n, g.indptr, g.indices, g.data, 2, 6, x0=X0, traced=True)
+    Mlib = _lib_signless(g)
+    x = X0.copy()
+    for i in range(6):
+        want = np.einsum("ij,ij->j", x, Mlib @ x) / np.einsum("ij,ij->j", x, x)
+        assert np.abs(ray[i] - want).max() < 1e-13
+        assert np.abs(sq[i] - np.einsum("ij,ij->j", x, x)).max() < 1e-10 * sq[i].max()
+        x = Mlib @ x
+    assert np.all((ray >= 0) & (ray <= 1))
+    assert np.all(np.diff(sq, axis=0) <= 1e-12 * sq[:-1])
+
+
+def test_isolated_vertices_embed_to_zero():
+    g = synth.random_weighted(50, 200, seed=1, isolated=5)
+    E = o.embed(g.n, g.indptr, g.indices, g.data, 3, 5, seed=1)
+    assert np.all(E[-5:] == 0.0)
+    assert np.all(np.abs(E[:-5]).sum(axis=1) > 0)
+
+
+def test_validate_graph_rejects_bad_graphs():
+    g = _hand_graph()
+    o.validate_graph(g.n, g.indptr, g.indices, g.data)
+    with pytest.raises(ValueError):
+        o.validate_graph(2, [0, 1, 1], [0], None)                   # self-loop
+    with pytest.raises(ValueError):
+        o.validate_graph(2, [0, 1, 1], [1], None)                   # asymmetric
+    with pytest.raises(ValueError):
+        o.validate_graph(2, [0, 1, 2], [1, 0], [-1.0, -1.0])        # negative
+    with pytest.raises(ValueError):
+        o.validate_graph(2, [0, 1, 2], [1, 2], None)                # out of range
+
+
+# --------------------------------------------------------------------------
+# k-means (Sec. 2.2)
+# --------------------------------------------------------------------------
+def test_kmeans_cost_matrix_identity():
+    # COST_B = ||B - X X^T B||_F^2 with X the scaled partition indicator
+    # (the identity the appendix uses to bound the k-means cost).
+    rng = np.random.default_rng(0)
+    B = rng.standard_normal((40, 3))
+    lab = rng.integers(0, 4, 40)
+    X = np.zeros((40, 4))
+    for i in range(4):
+        m = lab == i
+        X[m, i] = 1 / np.sqrt(m.sum())
+    assert np.isclose(o.kmeans_cost(B, lab, 4), np.linalg.norm(B - X @ X.T @ B) ** 2, rtol=1e-12)
+
+
+def test_kmeans_not_below_brute_force_optimum():
+    rng = np.random.default_rng(1)
+    for trial in range(5):
+        P = rng.standard_normal((8, 2))
+        k = 3
+        best = min(o.kmeans_cost(P, np.array(lab), k)
+                   for lab in itertools.product(range(k), repeat=8) if len(set(lab)) == k)
+        lab, C = o.kmeans(P, k, 20, seed=trial)
+        assert o.kmeans_cost(P, lab, k) >= best - 1e-12
+    # well separated: Lloyd reaches the optimum
+    P = np.r_[rng.normal(0, .05, (3, 2)), rng.normal(5, .05, (3, 2)), rng.normal([0, 5], .05, (2, 2))]
+    best = min(o.kmeans_cost(P, np.array(lab), 3)
+               for lab in itertools.product(range(3), repeat=8) if len(set(lab)) == 3)
+    lab, C = o.kmeans(P, 3, 20, seed=0)
+    assert np.isclose(o.kmeans_cost(P, lab, 3), best, rtol=1e-12)
+
+
+def test_lloyd_matches_sklearn():
+    from sklearn.cluster import KMeans
+    X, _ = synth.gaussian_mixture(300, 5, 4, seed=2, mean_scale=3.0)
+    X = X.astype(np.float64)
+    init = X[[0, 300, 600, 900, 1200]] + 0.3
+    lab, C = o.lloyd(X, init, 50)
+    km = KMeans(5, init=init, n_init=1, max_iter=50, tol=0.0, algorithm="lloyd").fit(X)
+    assert np.array_equal(lab, km.labels_)
+    assert np.abs(C - km.cluster_centers_).max() < 1e-10
+
+
+def test_lloyd_fixed_point_and_empty_cluster():
+    X, _ = synth.gaussian_mixture(100, 3, 2, seed=3, mean_scale=4.0)
+    X = X.astype(np.float64)
+    # a fourth centre far away never gets a row: it must keep its position
+    init = np.r_[X[[0, 100, 200]], [[1e3, 1e3]]]
+    lab, C = o.lloyd(X, init, 30)
+    assert np.array_equal(C[3], [1e3, 1e3])
+    for j in range(3):
+        assert np.allclose(C[j], X[lab == j].mean(axis=0), atol=1e-12)
+    d = ((X[:, None] - C[None]) ** 2).sum(-1)
+    assert np.all(d[np.arange(len(X)), lab] <= d.min(axis=1))
+
+
+def test_kmeanspp_samples_proportional_to_d2():
+    # k-means++: the second centre is drawn with probability D^2 / sum D^2
+    # (the first is uniform).  Empirical frequencies over many seeds.
+    P = np.array([[0.0], [1.0], [3.0], [6.0], [10.0]])
+    trials = 6000
+    first = np.zeros(5)
+    second = np.zeros((5, 5))
+    for s in range(trials):
+        c = o.kmeanspp(P, 2, seed=s)
+        first[c[0]] += 1
+        second[c[0], c[1]] += 1
+    assert stats.chisquare(first).pvalue > 1e-4
+    for a in range(5):
+        d2 = (P[:, 0] - P[a, 0]) ** 2
+        exp = d2 / d2.sum() * second[a].sum()
+        m = exp > 0
+        assert second[a, ~m].sum() == 0                # the centre itself never again
+        assert stats.chisquare(second[a, m], exp[m]).pvalue > 1e-4
+
+
+def test_kmeanspp_respects_eligibility_and_degenerate_case():
+    P = np.zeros((6, 2))                               # all points equal: sum D^2 = 0
+    elig = np.array([0, 1, 0, 1, 1, 0], dtype=bool)
+    c = o.kmeanspp(P, 4, seed=3, eligible=elig)
+    assert sorted(c[:1]) and elig[c[0]]
+    # after the first draw the rule takes the smallest unchosen eligible rows,
+    # then the smallest unchosen rows
+    rest = [v for v in [1, 3, 4] if v != c[0]]
+    assert c[1:3] == rest and c[3] == 0
+    P = np.random.default_rng(0).standard_normal((50, 2))
+    elig = np.arange(50) % 3 == 0
+    for s in range(20):
+        assert all(elig[v] for v in o.kmeanspp(P, 5, seed=s, eligible=elig))
+
+
+# --------------------------------------------------------------------------
+# ARI (Sec. 4.2)
+# --------------------------------------------------------------------------
+def test_ari_matches_sklearn():
+    from sklearn.metrics import adjusted_rand_score
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        n = int(rng.integers(2, 500))
+        a = rng.integers(0, rng.integers(1, 8), n)
+        b = np.where(rng.random(n) < 0.7, a, rng.integers(0, 6, n))
+        assert abs(o.ari(a, b) - adjusted_rand_score(a, b)) < 1e-12
+    a = rng.integers(0, 5, 100)
+    assert o.ari(a, a) == 1.0
+    perm = np.array([3, 1, 4, 0, 2])
+    assert abs(o.ari(a, perm[a]) - 1.0) < 1e-15
+    assert o.ari(np.zeros(10), np.zeros(10)) == 1.0
+
+
+# --------------------------------------------------------------------------
+# Whole pipeline (Algorithm 2)
+# --------------------------------------------------------------------------
+def test_pipeline_recovers_cliques_and_small_sbm():
+    g = synth.disjoint_cliques(5, 12)
+    lab, C, E = o.fast_spectral_cluster(g.n, g.indptr, g.indices, None, 5, 3, 30, 7, 20)
+    assert o.ari(lab, g.labels) == 1.0
+    # the small SBM the paper's synthetic experiments describe: every method
+    # recovers the planted clusters (Sec. 4.1)
+    g = synth.sbm(1000, 5, 0.5, 0.01, seed=0)
+    lab, C, E = o.fast_spectral_cluster(g.n, g.indptr, g.indices, None, 5, 3, 20, 0, 20)
+    assert o.ari(lab, g.labels) > 0.99
