@@ -1,0 +1,162 @@
+/*
+ * fsc.h -- C ABI of libfsc, an MI355X (gfx950) implementation of the hot path
+ * of FastSpectralCluster (Macgregor, "Fast and Simple Spectral Clustering in
+ * Theory and Practice", NeurIPS 2023).
+ *
+ * The method (Sec. 3.2, Algorithm 2): with M = I - N/2 = (I + D^{-1/2} A
+ * D^{-1/2}) / 2 the halved signless Laplacian of a weighted undirected graph
+ * (Sec. 2; eigenvalues in [0, 1]), draw l Gaussian vectors, apply M to each of
+ * them t times (Algorithm 1, PowerMethod, no normalisation), stack them into
+ * Y and run k-means (k-means++ seeding, then Lloyd; Sec. 2.2) on the rows of
+ * D^{-1/2} Y.
+ *
+ * Conventions shared by every entry point:
+ *   - Every array argument is a DEVICE pointer on the context's device, owned
+ *     by the caller, unless stated otherwise.  The library never frees or
+ *     keeps caller memory past the call's stream work.
+ *   - `stream` is a hipStream_t passed as a plain pointer (NULL = the null
+ *     stream).  Every call only enqueues work on that stream and returns; the
+ *     results are ready when the stream reaches that point.  Argument errors
+ *     are reported synchronously by the return value; device-side failures
+ *     surface as FSC_E_HIP on this or a later call.
+ *   - Arrays of n x l values are row-major: vertex i's l values are adjacent.
+ *   - Labels are 0..k-1 and meaningful up to a permutation of the clusters.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by `seed`.
+ *     Start-block entry (i, j) uses counter (i_lo, i_hi, j, 0) and the
+ *     Box-Muller transform of the two 53-bit uniforms it yields; k-means++
+ *     draw r uses counter (r_lo, r_hi, 0, 1) for r = 0 and (r, 0, 0, 2) for
+ *     r >= 1.
+ *   - An isolated vertex (degree 0) has no D^{-1/2} (Sec. 2); it is given
+ *     D^{-1/2} := 0, so its embedding row is 0.  It takes no part in k-means
+ *     seeding or centre updates and is labelled by its nearest final centre.
+ *   - A context is used by one host thread at a time; calls on one context
+ *     share its workspace and must be issued on one stream (or be ordered).
+ */
+#ifndef FSC_H
+#define FSC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes.  Every entry point returns one. */
+typedef enum {
+  FSC_OK = 0,
+  FSC_E_ARG = -1,          /* bad argument: null pointer, size out of range, bad dtype */
+  FSC_E_GRAPH = -2,        /* validation found a self-loop, a negative/NaN weight,
+                              an index out of range or a bad row pointer */
+  FSC_E_HIP = -3,          /* a HIP runtime call or kernel launch failed */
+  FSC_E_NOMEM = -4,        /* device workspace allocation failed */
+  FSC_E_UNSUPPORTED = -5   /* combination of dtypes or sizes not built */
+} fsc_status;
+
+/* Element types. */
+typedef enum {
+  FSC_F64 = 0,   /* IEEE binary64 */
+  FSC_F32 = 1,   /* IEEE binary32 */
+  FSC_BF16 = 2   /* bfloat16 (upper half of a binary32), round-to-nearest-even */
+} fsc_dtype;
+
+/* A weighted undirected graph G = (V, E, w) (Sec. 2) as CSR storing both
+ * directions of every edge, so nnz = 2m.  Device pointers.
+ *   row_ptr: int64[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz.
+ *   col_idx: int32[nnz], each in [0, n); entries of a row in any order.
+ *   val:     nnz weights of type val_dtype (> 0 finite), or NULL for unit
+ *            weights.
+ * Preconditions (checked only when fsc_opts.validate != 0): no self-loops,
+ * symmetric A, non-negative finite weights.  On a graph that breaks them the
+ * result is unspecified, but every access stays in bounds as long as row_ptr
+ * and col_idx are in range. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const void* val;
+  int32_t val_dtype;  /* fsc_dtype; ignored when val == NULL */
+} fsc_csr;
+
+/* Options (all fields may be zero for the defaults). */
+typedef struct {
+  /* Storage and arithmetic type of the iterate block and of the embedding
+   * written by fsc_embed: FSC_F64 (FP64 accumulation), FSC_F32 or FSC_BF16
+   * (FP32 accumulation).  Degrees and column statistics are always FP64. */
+  int32_t vec_dtype;
+  /* Lloyd steps after k-means++ seeding (fsc_cluster); 0 means 30. */
+  int32_t kmeans_iters;
+  /* 0: no checks.  1: check row_ptr, column range, self-loops and weights on
+   * the device; this synchronises the stream once and returns FSC_E_GRAPH on
+   * failure. */
+  int32_t validate;
+  /* Non-zero: after every step rescale each column of the iterate to unit
+   * D-norm (y-space), keeping the FP64 product of the scales, and undo the
+   * product at the last step, so the result equals the un-normalised
+   * PowerMethod output up to rounding.  Algorithm 1 itself has no
+   * normalisation; this only guards the range of low-precision storage. */
+  int32_t renorm;
+  /* Optional FP64 n x l start block X0 (overrides the seeded Gaussian). */
+  const double* x0;
+  /* Optional FP64 outputs, (t+1) x l and t x l: sqnorm[i][j] = ||y_i^(j)||^2
+   * and rayleigh[i][j] = y_i^T M y_i / y_i^T y_i for the j-th PowerMethod
+   * iterate (both over non-isolated vertices). */
+  double* sqnorm_trace;
+  double* rayleigh_trace;
+  /* Tile size of the sparse product in nonzeros (0 = tuned default). */
+  int32_t tile_nnz;
+} fsc_opts;
+
+typedef struct fsc_context fsc_context;
+
+/* Creates a context on HIP device `device` (makes it current on the calling
+ * thread).  *out receives the context.  Returns FSC_E_HIP if the device is not
+ * usable. */
+int fsc_create(int device, fsc_context** out);
+
+/* Waits for the context's outstanding work and frees its workspace. */
+void fsc_destroy(fsc_context* ctx);
+
+/* The embedding D^{-1/2} Y of Algorithm 2: Y's columns are PowerMethod(M,
+ * x_i, t) (Algorithm 1) for the l start vectors.  `emb` receives n x l values
+ * of type opts->vec_dtype.  1 <= l <= 8, t >= 0 (t = 0 gives D^{-1/2} X0). */
+int fsc_embed(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t t, uint64_t seed,
+              const fsc_opts* opts, void* emb, void* stream);
+
+/* FastSpectralCluster (Algorithm 2): the embedding above, then k-means++
+ * seeding and opts->kmeans_iters Lloyd steps on its rows, then a final
+ * assignment.  `labels` receives int32[n].  Optional outputs (NULL to skip):
+ * `emb` (n x l of vec_dtype, as fsc_embed) and `centres` (FP32 k x l).
+ * 1 <= k <= min(n, 64). */
+int fsc_cluster(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t,
+                uint64_t seed, const fsc_opts* opts, int32_t* labels, void* emb,
+                float* centres, void* stream);
+
+/* k-means (Sec. 2.2) alone on n points of dimension l (1 <= l <= 8) stored as
+ * n x l values of `dtype` (FSC_F32 or FSC_F64; computed in FP32): k-means++
+ * seeding then `iters` Lloyd steps and a final assignment.  `eligible` is an
+ * optional uint8[n] mask (0 = the point takes no part in seeding/updates).
+ * Outputs labels int32[n] and, if non-NULL, centres FP32 k x l. */
+int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, int32_t l,
+               int32_t k, int32_t iters, uint64_t seed, const uint8_t* eligible,
+               int32_t* labels, float* centres, void* stream);
+
+/* Adjusted Rand index (Hubert and Arabie; the accuracy score of Sec. 4.2)
+ * between labelings a (values in [0, ka)) and b (values in [0, kb)) of n
+ * items, written as one FP64 value to device memory `out`.  If both labelings
+ * are trivial (the index's denominator is 0) the value is 1.  Labels outside
+ * their range are counted in no cell (and so lower the score). */
+int fsc_ari(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int32_t ka,
+            int32_t kb, double* out, void* stream);
+
+/* Human-readable text of the last error on the calling thread ("" if none). */
+const char* fsc_last_error(void);
+
+/* ABI version: (major << 16) | minor. */
+int fsc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSC_H */

@@ -1,0 +1,255 @@
+// The C ABI of libfsc (include/fsc.h): argument checks, the context and its
+// device workspace, and the order in which the kernels of a call are queued.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "fsc_internal.hpp"
+
+namespace fsc {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return FSC_OK;
+  return fail(FSC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int reserve_arena(Context* ctx, size_t bytes, Arena* out) {
+  if (bytes > ctx->arena_size) {
+    if (ctx->arena) {
+      // the old arena may still be read by queued work: wait for it
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return check_hip(e, "hipDeviceSynchronize");
+      hipFree(ctx->arena);
+      ctx->arena = nullptr;
+      ctx->arena_size = 0;
+    }
+    size_t want = std::max(bytes, ctx->arena_size + ctx->arena_size / 4);
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FSC_E_NOMEM, "cannot allocate " + std::to_string(want) + " bytes of device workspace");
+    }
+    ctx->arena = static_cast<char*>(p);
+    ctx->arena_size = want;
+  }
+  out->base = ctx->arena;
+  out->size = ctx->arena_size;
+  out->used = 0;
+  return FSC_OK;
+}
+
+static int check_csr(const fsc_csr* g) {
+  if (!g) return fail(FSC_E_ARG, "graph is NULL");
+  if (g->n < 1) return fail(FSC_E_ARG, "graph must have n >= 1 vertices");
+  if (g->n > INT32_MAX - 1) return fail(FSC_E_ARG, "n must fit a 32-bit column index");
+  if (g->nnz < 0) return fail(FSC_E_ARG, "nnz must be >= 0");
+  if (!g->row_ptr) return fail(FSC_E_ARG, "row_ptr is NULL");
+  if (g->nnz > 0 && !g->col_idx) return fail(FSC_E_ARG, "col_idx is NULL");
+  if (g->val && (g->val_dtype < FSC_F64 || g->val_dtype > FSC_BF16))
+    return fail(FSC_E_ARG, "val_dtype must be FSC_F64, FSC_F32 or FSC_BF16");
+  return FSC_OK;
+}
+
+static fsc_opts default_opts() {
+  fsc_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.vec_dtype = FSC_F32;
+  return o;
+}
+
+// Embedding setup shared by fsc_embed and fsc_cluster.  `extra` bytes of the
+// arena are left for the caller after the embedding workspace.
+static int prepare_embed(Context* ctx, const fsc_csr* g, int l, int t, uint64_t seed, const fsc_opts& o,
+                         size_t extra, EmbedIO* io, Arena* arena) {
+  int rc;
+  if ((rc = check_csr(g))) return rc;
+  if (l < 1 || l > 8) return fail(FSC_E_ARG, "l must be in [1, 8]");
+  if (t < 0) return fail(FSC_E_ARG, "t must be >= 0");
+  if (o.vec_dtype < FSC_F64 || o.vec_dtype > FSC_BF16) return fail(FSC_E_ARG, "bad vec_dtype");
+  if (o.tile_nnz < 0 || (o.tile_nnz > 0 && o.tile_nnz < 64)) return fail(FSC_E_ARG, "tile_nnz must be 0 or >= 64");
+  if (o.tile_nnz > max_tile_nnz(l, o.vec_dtype))
+    return fail(FSC_E_ARG, "tile_nnz too large for the LDS budget (max " +
+                               std::to_string(max_tile_nnz(l, o.vec_dtype)) + ")");
+  std::memset(io, 0, sizeof(*io));
+  io->g = g;
+  io->l = l;
+  io->t = t;
+  io->LH = padded_width(l);
+  io->seed = seed;
+  io->vec_dtype = o.vec_dtype;
+  io->renorm = o.renorm;
+  io->tile_nnz = o.tile_nnz;
+  io->x0 = o.x0;
+  io->sqnorm_trace = o.sqnorm_trace;
+  io->rayleigh_trace = o.rayleigh_trace;
+  const size_t bytes = embed_workspace_bytes(ctx, g, l, o.vec_dtype, o.tile_nnz) + extra;
+  if ((rc = reserve_arena(ctx, bytes, arena))) return rc;
+  return embed_bind_workspace(ctx, arena, io);
+}
+
+}  // namespace fsc
+
+using namespace fsc;
+
+struct fsc_context {
+  Context c;
+};
+
+extern "C" {
+
+int fsc_version(void) { return (1 << 16) | 0; }
+
+const char* fsc_last_error(void) { return g_last_error.c_str(); }
+
+int fsc_create(int device, fsc_context** out) {
+  if (!out) return fail(FSC_E_ARG, "out is NULL");
+  *out = nullptr;
+  int rc;
+  if ((rc = check_hip(hipSetDevice(device), "hipSetDevice"))) return rc;
+  fsc_context* ctx = new fsc_context();
+  ctx->c.device = device;
+  if ((rc = check_hip(hipGetDeviceProperties(&ctx->c.prop, device), "hipGetDeviceProperties"))) {
+    delete ctx;
+    return rc;
+  }
+  ctx->c.num_cu = ctx->c.prop.multiProcessorCount;
+  if ((rc = check_hip(hipMalloc(&ctx->c.error_flag, 16), "hipMalloc(flag)"))) {
+    delete ctx;
+    return rc;
+  }
+  if ((rc = check_hip(hipHostMalloc(&ctx->c.host_flag, 16, hipHostMallocDefault), "hipHostMalloc(flag)"))) {
+    hipFree(ctx->c.error_flag);
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return FSC_OK;
+}
+
+void fsc_destroy(fsc_context* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->c.device);
+  hipDeviceSynchronize();
+  if (ctx->c.arena) hipFree(ctx->c.arena);
+  if (ctx->c.error_flag) hipFree(ctx->c.error_flag);
+  if (ctx->c.host_flag) hipHostFree(ctx->c.host_flag);
+  delete ctx;
+}
+
+int fsc_embed(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t t, uint64_t seed, const fsc_opts* opts,
+              void* emb, void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (!emb) return fail(FSC_E_ARG, "emb is NULL");
+  const fsc_opts o = opts ? *opts : default_opts();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  EmbedIO io;
+  Arena arena;
+  if ((rc = prepare_embed(&ctx->c, g, l, t, seed, o, 0, &io, &arena))) return rc;
+  if (o.validate && (rc = validate_csr(&ctx->c, g, s))) return rc;
+  if ((rc = embed_run(&ctx->c, &io, s))) return rc;
+  return embed_unpad(&ctx->c, &io, emb, s);
+}
+
+int fsc_cluster(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t, uint64_t seed,
+                const fsc_opts* opts, int32_t* labels, void* emb, float* centres, void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (!labels) return fail(FSC_E_ARG, "labels is NULL");
+  int rc;
+  if ((rc = check_csr(g))) return rc;
+  if (k < 1 || k > 64 || k > g->n) return fail(FSC_E_ARG, "k must be in [1, min(n, 64)]");
+  const fsc_opts o = opts ? *opts : default_opts();
+  const int iters = o.kmeans_iters > 0 ? o.kmeans_iters : 30;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  const int KD = kmeans_width(l);
+  const int LH = padded_width(l);
+  const bool direct = o.vec_dtype == FSC_F32 && LH == KD;
+  const size_t extra = kmeans_workspace_bytes(g->n, KD) + (direct ? 0 : align_up(g->n * KD * 4)) + 1024;
+  EmbedIO io;
+  Arena arena;
+  if ((rc = prepare_embed(&ctx->c, g, l, t, seed, o, extra, &io, &arena))) return rc;
+  KmeansIO km;
+  std::memset(&km, 0, sizeof(km));
+  km.n = g->n;
+  km.l = l;
+  km.KD = KD;
+  km.k = k;
+  km.iters = iters;
+  km.seed = seed;
+  km.labels = labels;
+  km.centres_out = centres;
+  float* pts = direct ? nullptr : arena.take<float>(g->n * KD);
+  if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
+  if (o.validate && (rc = validate_csr(&ctx->c, g, s))) return rc;
+  if ((rc = embed_run(&ctx->c, &io, s))) return rc;
+  if (emb && (rc = embed_unpad(&ctx->c, &io, emb, s))) return rc;
+  if (direct) {
+    km.pts = reinterpret_cast<const float*>(io.zt);
+  } else {
+    if ((rc = embed_to_points(&ctx->c, &io, pts, s))) return rc;
+    km.pts = pts;
+  }
+  km.elig = io.elig;
+  return kmeans_run(&ctx->c, &km, s);
+}
+
+int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, int32_t l, int32_t k, int32_t iters,
+               uint64_t seed, const uint8_t* eligible, int32_t* labels, float* centres, void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (!points || !labels) return fail(FSC_E_ARG, "points and labels must not be NULL");
+  if (n < 1 || n > INT32_MAX) return fail(FSC_E_ARG, "n must be in [1, 2^31)");
+  if (l < 1 || l > 8) return fail(FSC_E_ARG, "l must be in [1, 8]");
+  if (k < 1 || k > 64 || k > n) return fail(FSC_E_ARG, "k must be in [1, min(n, 64)]");
+  if (iters < 0) return fail(FSC_E_ARG, "iters must be >= 0");
+  if (dtype != FSC_F32 && dtype != FSC_F64) return fail(FSC_E_UNSUPPORTED, "points must be FSC_F32 or FSC_F64");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  const int KD = kmeans_width(l);
+  Arena arena;
+  if ((rc = reserve_arena(&ctx->c, kmeans_workspace_bytes(n, KD) + align_up(n * KD * 4) + 1024, &arena))) return rc;
+  float* pts = arena.take<float>(n * KD);
+  KmeansIO km;
+  std::memset(&km, 0, sizeof(km));
+  km.n = n;
+  km.l = l;
+  km.KD = KD;
+  km.k = k;
+  km.iters = iters;
+  km.seed = seed;
+  km.labels = labels;
+  km.centres_out = centres;
+  km.elig = eligible;
+  if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
+  if ((rc = points_from_user(&ctx->c, points, dtype, n, l, KD, pts, s))) return rc;
+  km.pts = pts;
+  return kmeans_run(&ctx->c, &km, s);
+}
+
+int fsc_ari(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int32_t ka, int32_t kb, double* out,
+            void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (!out || (n > 0 && (!a || !b))) return fail(FSC_E_ARG, "null pointer");
+  if (n < 0) return fail(FSC_E_ARG, "n must be >= 0");
+  if (ka < 1 || kb < 1 || (int64_t)ka * kb > (1 << 22)) return fail(FSC_E_ARG, "need ka, kb >= 1 and ka*kb <= 2^22");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  Arena arena;
+  if ((rc = reserve_arena(&ctx->c, align_up((size_t)ka * kb * 8) + 256, &arena))) return rc;
+  unsigned long long* table = arena.take<unsigned long long>((size_t)ka * kb);
+  return ari_run(&ctx->c, a, b, n, ka, kb, out, table, s);
+}
+
+}  // extern "C"

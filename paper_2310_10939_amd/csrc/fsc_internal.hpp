@@ -1,0 +1,145 @@
+// Host-side declarations shared by the libfsc translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fsc.h"
+
+namespace fsc {
+
+// Sets the calling thread's last-error text and returns `code`.
+int fail(int code, const std::string& msg);
+// Checks a HIP result; on failure records `what` and returns FSC_E_HIP.
+int check_hip(hipError_t e, const char* what);
+
+// Padded row width used for an l-column block.
+inline int padded_width(int l) { return l <= 1 ? 1 : l <= 2 ? 2 : l <= 4 ? 4 : 8; }
+// Width of the FP32 k-means point rows (the MFMA contraction depth is 4).
+inline int kmeans_width(int l) { return l <= 4 ? 4 : 8; }
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// A bump allocator over one device arena owned by the context.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = align_up(used);
+    used = off + align_up(count * sizeof(T));
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+// One chunk of a long row: the nonzeros [start, end) of `row`; the row has
+// `count` chunks, this is number `index`, its partial sums go to slot
+// (first + index); `lid` indexes the per-long-row counters.
+struct LongChunk {
+  int64_t start, end;
+  int32_t row, lid, index, count, first, pad;
+};
+
+// Tile plan of one graph for the sparse product (built on the device).
+struct Plan {
+  int32_t nb = 0;          // short tiles: buckets of tile_nnz nonzeros
+  int32_t tile_nnz = 0;
+  int32_t* rb = nullptr;   // int32[nb+1]: first row of each bucket
+  int32_t* nch = nullptr;  // int32[nb]: chunks of the bucket's long last row
+  int32_t* choff = nullptr;  // int32[nb+1]: exclusive scan of nch
+  int32_t* lid = nullptr;    // int32[nb+1]: exclusive scan of (nch > 0)
+  LongChunk* chunks = nullptr;  // up to max_chunks entries
+  int32_t max_chunks = 0;
+  int32_t* meta = nullptr;      // int32[4]: {total chunks, long rows, -, -}
+};
+
+struct Context {
+  int device = 0;
+  int num_cu = 0;
+  hipDeviceProp_t prop{};
+  char* arena = nullptr;
+  size_t arena_size = 0;
+  int32_t* error_flag = nullptr;   // device int32[4]
+  int32_t* host_flag = nullptr;    // pinned host int32[4]
+  int grid_spmm[4][4] = {};        // [vec dtype][log2 LH] persistent grid sizes
+};
+
+// Grows the context arena to at least `bytes` (synchronises the device when
+// it has to reallocate).
+int reserve_arena(Context* ctx, size_t bytes, Arena* out);
+
+// ---- embedding pipeline (fsc_embed.hip) ----
+struct EmbedIO {
+  // inputs
+  const fsc_csr* g;
+  int l, t, LH;
+  uint64_t seed;
+  int vec_dtype;
+  int renorm;
+  int tile_nnz;
+  const double* x0;
+  double* sqnorm_trace;
+  double* rayleigh_trace;
+  // workspace (filled by embed_workspace)
+  double* deg;
+  void* hinv;       // float[n] or double[n]
+  double* isq;
+  uint8_t* elig;
+  void* z[2];       // S[n*LH] ping-pong
+  double* partials; // [grid][2*LH]
+  double* state;    // [4][LH]: prev_sq, cum, scale, spare
+  double* lnorm;    // [max long rows][2*LH]
+  void* lpart;      // A[max chunks][LH]
+  int32_t* lcount;  // [max long rows]
+  Plan plan;
+  int grid;         // persistent grid of the sparse product
+  // result: pointer to Z_t (S[n*LH]) inside the workspace
+  const void* zt;
+};
+
+// Largest tile size whose LDS staging fits a block's budget.
+int max_tile_nnz(int l, int vec_dtype);
+size_t embed_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, int vec_dtype, int tile_nnz);
+int embed_bind_workspace(Context* ctx, Arena* a, EmbedIO* io);
+// Enqueues validation (optional), degrees, start block, t steps and stats.
+int embed_run(Context* ctx, EmbedIO* io, hipStream_t s);
+// Writes Z_t (n x LH, vec dtype) to an unpadded n x l array of the same dtype.
+int embed_unpad(Context* ctx, const EmbedIO* io, void* out, hipStream_t s);
+// Writes Z_t as FP32 n x KD k-means points (KD = kmeans_width(l)).
+int embed_to_points(Context* ctx, const EmbedIO* io, float* pts, hipStream_t s);
+// Device-side validation of a CSR; synchronises `s`.  Returns FSC_OK or
+// FSC_E_GRAPH.
+int validate_csr(Context* ctx, const fsc_csr* g, hipStream_t s);
+
+// ---- k-means (fsc_kmeans.hip) ----
+struct KmeansIO {
+  int64_t n;
+  int l, KD, k, iters;
+  uint64_t seed;
+  const float* pts;        // n x KD FP32
+  const uint8_t* elig;     // optional
+  int32_t* labels;         // n
+  float* centres_out;      // optional k x l
+  // workspace
+  float* d2;               // n
+  double* bsum;            // blocks
+  float* centres;          // 64 x KD (padded)
+  double* cpart;           // blocks x 64 x (KD+1)
+  int32_t* chosen;         // 64
+  int32_t* counter;        // 4
+  int nblk_pp, nblk_ll;
+};
+size_t kmeans_workspace_bytes(int64_t n, int KD);
+int kmeans_bind_workspace(Arena* a, KmeansIO* io);
+int kmeans_run(Context* ctx, KmeansIO* io, hipStream_t s);
+int points_from_user(Context* ctx, const void* pts, int dtype, int64_t n, int l, int KD, float* out,
+                     hipStream_t s);
+
+// ---- ARI (fsc_ari.hip) ----
+int ari_run(Context* ctx, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,
+            unsigned long long* table, hipStream_t s);
+
+}  // namespace fsc

@@ -1,0 +1,192 @@
+"""Thin Python binding of libfsc (include/fsc.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Tensors are torch device tensors on the current HIP device; work is
+queued on torch's current stream.  The library must be built
+(`python -m paper_2310_10939_amd.build`); importing this module without it
+raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfsc.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"libfsc.so is not built ({_LIB_PATH}); run python -m paper_2310_10939_amd.build")
+_lib = ctypes.CDLL(_LIB_PATH)
+
+F64, F32, BF16 = 0, 1, 2
+_DTYPES = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+_TORCH = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
+_NAMES = {"f64": F64, "f32": F32, "bf16": BF16}
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p), ("val_dtype", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("vec_dtype", ctypes.c_int32), ("kmeans_iters", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("renorm", ctypes.c_int32),
+                ("x0", ctypes.c_void_p), ("sqnorm_trace", ctypes.c_void_p),
+                ("rayleigh_trace", ctypes.c_void_p), ("tile_nnz", ctypes.c_int32)]
+
+
+_vp, _i32, _i64, _u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+_lib.fsc_create.argtypes = [ctypes.c_int, ctypes.POINTER(_vp)]
+_lib.fsc_destroy.argtypes = [_vp]
+_lib.fsc_destroy.restype = None
+_lib.fsc_embed.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp]
+_lib.fsc_cluster.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp,
+                             _vp, _vp]
+_lib.fsc_kmeans.argtypes = [_vp, _vp, _i32, _i64, _i32, _i32, _i32, _u64, _vp, _vp, _vp, _vp]
+_lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
+_lib.fsc_last_error.restype = ctypes.c_char_p
+_lib.fsc_version.restype = ctypes.c_int
+
+EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari",
+           "fsc_last_error", "fsc_version")
+
+
+class FscError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libfsc error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise FscError(rc, _lib.fsc_last_error().decode())
+
+
+_ctx_lock = threading.Lock()
+_contexts = {}
+
+
+def context(device=None):
+    """The per-(thread, device) library context."""
+    dev = torch.cuda.current_device() if device is None else int(device)
+    key = (threading.get_ident(), dev)
+    with _ctx_lock:
+        c = _contexts.get(key)
+        if c is None:
+            p = _vp()
+            _check(_lib.fsc_create(dev, ctypes.byref(p)))
+            c = _contexts[key] = p
+    return c
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else _vp(0)
+
+
+def _csr(indptr, indices, data):
+    assert indptr.is_cuda and indptr.dtype == torch.int64 and indptr.is_contiguous()
+    assert indices.is_cuda and indices.dtype == torch.int32 and indices.is_contiguous()
+    g = Csr()
+    g.n = indptr.numel() - 1
+    g.nnz = indices.numel()
+    g.row_ptr = indptr.data_ptr()
+    g.col_idx = indices.data_ptr() if indices.numel() else None
+    if data is not None:
+        assert data.is_cuda and data.is_contiguous() and data.numel() == indices.numel()
+        g.val = data.data_ptr()
+        g.val_dtype = _DTYPES[data.dtype]
+    else:
+        g.val = None
+        g.val_dtype = 0
+    return g
+
+
+def _opts(vec_dtype="f32", kmeans_iters=0, validate=False, renorm=False, x0=None, sqnorm=None,
+          rayleigh=None, tile_nnz=0):
+    o = Opts()
+    o.vec_dtype = _NAMES[vec_dtype] if isinstance(vec_dtype, str) else int(vec_dtype)
+    o.kmeans_iters = int(kmeans_iters)
+    o.validate = int(bool(validate))
+    o.renorm = int(bool(renorm))
+    o.x0 = x0.data_ptr() if x0 is not None else None
+    o.sqnorm_trace = sqnorm.data_ptr() if sqnorm is not None else None
+    o.rayleigh_trace = rayleigh.data_ptr() if rayleigh is not None else None
+    o.tile_nnz = int(tile_nnz)
+    return o
+
+
+def embed(indptr, indices, data, l, t, seed, vec_dtype="f32", x0=None, traces=False, renorm=False,
+          validate=False, tile_nnz=0):
+    """D^{-1/2} Y for l Gaussian start vectors and t PowerMethod steps.
+
+    Returns the n x l embedding (dtype per vec_dtype) and, with traces=True,
+    also the FP64 (t+1) x l squared norms and t x l Rayleigh quotients."""
+    n = indptr.numel() - 1
+    dev = indptr.device
+    vd = _NAMES[vec_dtype]
+    out = torch.empty((n, l), dtype=_TORCH[vd], device=dev)
+    if x0 is not None:
+        assert x0.dtype == torch.float64 and x0.is_contiguous() and x0.shape == (n, l)
+    sq = torch.empty((t + 1, l), dtype=torch.float64, device=dev) if traces else None
+    ray = torch.empty((max(t, 0), l), dtype=torch.float64, device=dev) if traces else None
+    g = _csr(indptr, indices, data)
+    o = _opts(vec_dtype, 0, validate, renorm, x0, sq, ray if (ray is not None and t > 0) else None, tile_nnz)
+    _check(_lib.fsc_embed(context(dev.index), ctypes.byref(g), l, t, seed, ctypes.byref(o), _ptr(out), _stream()))
+    return (out, sq, ray) if traces else out
+
+
+def cluster(indptr, indices, data, k, l, t, seed, kmeans_iters=30, vec_dtype="f32", x0=None, return_embedding=False,
+            return_centres=False, validate=False, renorm=False, traces=False, tile_nnz=0, out=None):
+    """FastSpectralCluster: labels (int32 [n]) of the k-way partition."""
+    n = indptr.numel() - 1
+    dev = indptr.device
+    vd = _NAMES[vec_dtype]
+    labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    emb = torch.empty((n, l), dtype=_TORCH[vd], device=dev) if return_embedding else None
+    cen = torch.empty((k, l), dtype=torch.float32, device=dev) if return_centres else None
+    sq = torch.empty((t + 1, l), dtype=torch.float64, device=dev) if traces else None
+    ray = torch.empty((max(t, 1), l), dtype=torch.float64, device=dev) if traces else None
+    g = _csr(indptr, indices, data)
+    o = _opts(vec_dtype, kmeans_iters, validate, renorm, x0, sq, ray, tile_nnz)
+    _check(_lib.fsc_cluster(context(dev.index), ctypes.byref(g), k, l, t, seed, ctypes.byref(o), _ptr(labels),
+                            _ptr(emb), _ptr(cen), _stream()))
+    res = [labels]
+    if return_embedding:
+        res.append(emb)
+    if return_centres:
+        res.append(cen)
+    if traces:
+        res += [sq, ray[:t]]
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def kmeans(points, k, iters, seed, eligible=None):
+    """k-means++ then `iters` Lloyd steps on the rows of `points` (n x l,
+    float32/float64).  Returns (labels int32 [n], centres float32 [k, l])."""
+    assert points.is_cuda and points.dim() == 2 and points.is_contiguous()
+    n, l = points.shape
+    labels = torch.empty(n, dtype=torch.int32, device=points.device)
+    cen = torch.empty((k, l), dtype=torch.float32, device=points.device)
+    if eligible is not None:
+        assert eligible.dtype == torch.uint8 and eligible.is_contiguous() and eligible.numel() == n
+    _check(_lib.fsc_kmeans(context(points.device.index), _ptr(points), _DTYPES[points.dtype], n, l, k, iters, seed,
+                           _ptr(eligible), _ptr(labels), _ptr(cen), _stream()))
+    return labels, cen
+
+
+def ari(a, b, ka, kb):
+    """Adjusted Rand index of two int32 device labelings (an FP64 0-d tensor)."""
+    out = torch.empty((), dtype=torch.float64, device=a.device)
+    _check(_lib.fsc_ari(context(a.device.index), _ptr(a), _ptr(b), a.numel(), ka, kb, _ptr(out), _stream()))
+    return out
+
+
+def version():
+    v = _lib.fsc_version()
+    return (v >> 16, v & 0xFFFF)
