@@ -1,0 +1,187 @@
+#!/usr/bin/env python
+"""Benchmark of FastSpectralCluster (Algorithm 2) on one MI355X.
+
+Default workload: the large SBM -- n = 1,000,000 vertices, k = 10 equal
+clusters, expected in-degree 36 and out-degree 4 (Bernoulli edges), CSR with
+int32 columns and fp32 unit weights; l = 4 Gaussian vectors, t = 30 power
+steps with per-step FP64 column norms and Rayleigh quotients; k-means++ then
+30 Lloyd steps.  One step = one full fsc_cluster call on inputs already in
+HBM.  value = nnz * l * t / step time (edge x vector x iteration per second).
+
+The JSON line also carries the roofline of the dominant kernel (the sparse
+product of one power step, timed with HIP events inside the library on the
+call's stream) and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edges×vectors×iters/s (SpMM GB/s vs HBM peak) + clustering time at ARI parity"
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "spmm_sbm1m_counters.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2310_10939_amd", "csrc", f)
+                  for f in ("fsc_embed.hip", "fsc_device.hpp")]
+
+WORKLOADS = {
+    # name: (n, k, deg_in, deg_out, l, t, lloyd, vec dtype, weight dtype, permute)
+    "sbm1m": (1_000_000, 10, 36, 4, 4, 30, 30, "f32", "f32", False),
+    "sbm1m-perm": (1_000_000, 10, 36, 4, 4, 30, 30, "f32", "f32", True),
+    "sbm1m-bf16": (1_000_000, 10, 36, 4, 4, 30, 30, "bf16", "bf16", False),
+    "sbm1k": (1000, 5, None, None, 3, 20, 20, "f64", None, False),
+}
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def make_graph(name):
+    import synth
+    n, k, din, dout, *_rest, permute = WORKLOADS[name]
+    if din is None:
+        return synth.sbm(n, k, 0.5, 0.01, seed=0)
+    return synth.sbm_by_degree(n, k, din, dout, seed=0, permute=permute)
+
+
+def spmm_bytes(n, nnz, l, vec, wdt, stats=True):
+    """Algorithmic bytes of one power step: col + val per nonzero, the row
+    pointer, one read and one write of the padded n x l block, 1/(2d), and
+    the FP64 degree read by the statistics epilogue.  Gathers of Z rows are
+    counted once (the block stays cache-resident)."""
+    LH = 1 if l <= 1 else 2 if l <= 2 else 4 if l <= 4 else 8
+    se = {"f64": 8, "f32": 4, "bf16": 2}[vec]
+    sv = {None: 0, "f64": 8, "f32": 4, "bf16": 2}[wdt]
+    ha = 8 if vec == "f64" else 4
+    return nnz * (4 + sv) + (n + 1) * 8 + 2 * n * LH * se + n * ha + (n * 8 if stats else 0)
+
+
+def cpu_baseline(g, l, t_full, lloyd_full, seed):
+    """The oracle on the same graph with a third of the iterations (t/3 power
+    steps, lloyd/3 Lloyd steps), single-threaded, scaled to EVI/s."""
+    from threadpoolctl import threadpool_limits
+    from oracle import fsc_oracle as o
+    t_s = max(1, t_full // 3)
+    ll_s = max(1, lloyd_full // 3)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        E = o.embed(g.n, g.indptr, g.indices, g.data, l, t_s, seed=seed)
+        d = o.degrees(g.n, g.indptr, g.indices, g.data)
+        o.kmeans(E, int(g.labels.max()) + 1, ll_s, seed, eligible=d > 0)
+        dt = time.perf_counter() - t0
+    return {"value": g.nnz * l * t_s / dt, "unit": "EVI/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle on the full graph with t={t_s} power steps and {ll_s} Lloyd steps "
+                      f"(one third of the workload's iterations), {dt:.1f} s single-threaded"}
+
+
+def copy_probe(mb=512, reps=5):
+    """A plain device copy of known size, to calibrate the HBM byte counters."""
+    import torch
+    x = torch.empty(mb * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": x.numel() * 4, "copy_probe_bytes_written": y.numel() * 4,
+                      "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sbm1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        return 2
+    import torch
+    if args.copy_probe:
+        copy_probe()
+        return 0
+    from paper_2310_10939_amd import fsc
+
+    n, k, din, dout, l, t, lloyd, vec, wdt, permute = WORKLOADS[args.workload]
+    t_gen = time.perf_counter()
+    g = make_graph(args.workload)
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ip = torch.from_numpy(g.indptr).to(dev)
+    ix = torch.from_numpy(g.indices).to(dev)
+    if wdt is None:
+        data = None
+    else:
+        tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[wdt]
+        data = torch.ones(g.nnz, dtype=tdt, device=dev)   # unit weights, stored
+    planted = torch.from_numpy(g.labels.astype(np.int32)).to(dev)
+    seed = 0
+
+    def step():
+        return fsc.cluster(ip, ix, data, k, l, t, seed, kmeans_iters=lloyd, vec_dtype=vec, traces=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fsc.timing_enable(True)
+    fsc.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, spmm_ms = fsc.timing_read()
+    fsc.timing_enable(False)
+    labels, sq, ray = out
+    ari = float(fsc.ari(labels, planted, k, k))
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    evi = g.nnz * l * t
+    value = evi / (ms_step / 1e3)
+
+    avg_ms = spmm_ms / max(launches, 1)
+    bytes_launch = spmm_bytes(g.n, g.nnz, l, vec, wdt)
+    achieved = bytes_launch / (avg_ms / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(COUNTERS):
+        c = json.load(open(COUNTERS))
+        if c.get("kernel_hash") == kernel_hash() and c.get("workload") == args.workload:
+            traffic = c.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "tile_kernel<StepOp> (one power step)", "avg_launch_us": round(avg_ms * 1e3, 2),
+                "launches": launches, "algorithmic_bytes_per_launch": bytes_launch}
+    res = {
+        "metric": METRIC, "value": value, "unit": "EVI/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": vec, "data": "synthetic (seeded SBM)",
+        "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "k": k, "l": l, "t": t,
+                   "lloyd_steps": lloyd, "weights": wdt or "unit (implicit)", "vertex_order":
+                   "permuted" if permute else "planted clusters contiguous", "parallelism": "single GPU"},
+        "ari_vs_planted": round(ari, 6),
+        "spmm_ms_per_step": spmm_ms / args.steps,
+        "roofline": roofline,
+        "graph_generation_s": round(t_gen, 1),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(g, l, t, lloyd, seed)
+    print(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

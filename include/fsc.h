@@ -149,6 +149,17 @@ int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, i
 int fsc_ari(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int32_t ka,
             int32_t kb, double* out, void* stream);
 
+/* Kernel timing with HIP events, for profiling (off by default).  While on,
+ * every sparse-product launch (one PowerMethod step, Algorithm 1) queued by
+ * fsc_embed / fsc_cluster on this context is bracketed by two events recorded
+ * on the call's stream.  Turning it off drops unread records. */
+int fsc_timing_enable(fsc_context* ctx, int on);
+
+/* Waits for the recorded events, writes the number of timed sparse-product
+ * launches and their summed duration in milliseconds (host pointers), and
+ * clears the record. */
+int fsc_timing_read(fsc_context* ctx, int64_t* launches, double* total_ms);
+
 /* Human-readable text of the last error on the calling thread ("" if none). */
 const char* fsc_last_error(void);
 

@@ -47,6 +47,27 @@ int reserve_arena(Context* ctx, size_t bytes, Arena* out) {
   return FSC_OK;
 }
 
+std::pair<hipEvent_t, hipEvent_t>* timing_start(Context* ctx, hipStream_t s) {
+  if (!ctx->timing) return nullptr;
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (!ctx->ev_free.empty()) {
+    ev = ctx->ev_free.back();
+    ctx->ev_free.pop_back();
+  } else {
+    if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  ctx->ev_used.push_back(ev);
+  hipEventRecord(ev.first, s);
+  return &ctx->ev_used.back();
+}
+
+void timing_stop(std::pair<hipEvent_t, hipEvent_t>* ev, hipStream_t s) {
+  if (ev) hipEventRecord(ev->second, s);
+}
+
 static int check_csr(const fsc_csr* g) {
   if (!g) return fail(FSC_E_ARG, "graph is NULL");
   if (g->n < 1) return fail(FSC_E_ARG, "graph must have n >= 1 vertices");
@@ -139,6 +160,14 @@ void fsc_destroy(fsc_context* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->c.device);
   hipDeviceSynchronize();
+  for (auto& e : ctx->c.ev_used) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  for (auto& e : ctx->c.ev_free) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
   if (ctx->c.arena) hipFree(ctx->c.arena);
   if (ctx->c.error_flag) hipFree(ctx->c.error_flag);
   if (ctx->c.host_flag) hipHostFree(ctx->c.host_flag);
@@ -250,6 +279,33 @@ int fsc_ari(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int
   if ((rc = reserve_arena(&ctx->c, align_up((size_t)ka * kb * 8) + 256, &arena))) return rc;
   unsigned long long* table = arena.take<unsigned long long>((size_t)ka * kb);
   return ari_run(&ctx->c, a, b, n, ka, kb, out, table, s);
+}
+
+int fsc_timing_enable(fsc_context* ctx, int on) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  ctx->c.timing = on != 0;
+  if (!on) {
+    for (auto& e : ctx->c.ev_used) ctx->c.ev_free.push_back(e);
+    ctx->c.ev_used.clear();
+  }
+  return FSC_OK;
+}
+
+int fsc_timing_read(fsc_context* ctx, int64_t* launches, double* total_ms) {
+  if (!ctx || !launches || !total_ms) return fail(FSC_E_ARG, "null pointer");
+  double sum = 0.0;
+  int rc = FSC_OK;
+  for (auto& e : ctx->c.ev_used) {
+    if (!rc) rc = check_hip(hipEventSynchronize(e.second), "hipEventSynchronize");
+    float ms = 0.f;
+    if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e.first, e.second), "hipEventElapsedTime");
+    sum += ms;
+  }
+  *launches = (int64_t)ctx->c.ev_used.size();
+  *total_ms = sum;
+  for (auto& e : ctx->c.ev_used) ctx->c.ev_free.push_back(e);
+  ctx->c.ev_used.clear();
+  return rc;
 }
 
 }  // extern "C"

@@ -660,7 +660,9 @@ static int run_steps(Context* ctx, EmbedIO* io, TileArgs ta, hipStream_t s, bool
       op.hinv = reinterpret_cast<const A*>(io->hinv);
       op.deg = io->deg;
       op.scale = scale;
+      auto* ev = timing_start(ctx, s);
       rc = launch_tiles(ctx, op, ta, io->grid, s);
+      timing_stop(ev, s);
       if (rc) return rc;
       hipLaunchKernelGGL(finish_stats<LH>, dim3(1), dim3(kBlock), 0, s, io->partials, io->grid, io->lnorm,
                          io->plan.meta, step, io->t, io->l, io->renorm, io->state, io->sqnorm_trace,
@@ -676,7 +678,9 @@ static int run_steps(Context* ctx, EmbedIO* io, TileArgs ta, hipStream_t s, bool
       op.hinv = reinterpret_cast<const A*>(io->hinv);
       op.deg = io->deg;
       op.scale = nullptr;
+      auto* ev = timing_start(ctx, s);
       rc = launch_tiles(ctx, op, ta, io->grid, s);
+      timing_stop(ev, s);
     }
     if (rc) return rc;
   }

@@ -5,6 +5,8 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/fsc.h"
 
@@ -64,8 +66,16 @@ struct Context {
   size_t arena_size = 0;
   int32_t* error_flag = nullptr;   // device int32[4]
   int32_t* host_flag = nullptr;    // pinned host int32[4]
-  int grid_spmm[4][4] = {};        // [vec dtype][log2 LH] persistent grid sizes
+  // event timing of the sparse-product launches
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
 };
+
+// Records a (start) event pair slot; returns the pair to close with
+// timing_stop, or nullptr when timing is off.
+std::pair<hipEvent_t, hipEvent_t>* timing_start(Context* ctx, hipStream_t s);
+void timing_stop(std::pair<hipEvent_t, hipEvent_t>* ev, hipStream_t s);
 
 // Grows the context arena to at least `bytes` (synchronises the device when
 // it has to reallocate).

@@ -46,11 +46,13 @@ _lib.fsc_cluster.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _i32, _u64, c
                              _vp, _vp]
 _lib.fsc_kmeans.argtypes = [_vp, _vp, _i32, _i64, _i32, _i32, _i32, _u64, _vp, _vp, _vp, _vp]
 _lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
+_lib.fsc_timing_enable.argtypes = [_vp, ctypes.c_int]
+_lib.fsc_timing_read.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
 _lib.fsc_last_error.restype = ctypes.c_char_p
 _lib.fsc_version.restype = ctypes.c_int
 
 EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari",
-           "fsc_last_error", "fsc_version")
+           "fsc_timing_enable", "fsc_timing_read", "fsc_last_error", "fsc_version")
 
 
 class FscError(RuntimeError):
@@ -185,6 +187,19 @@ def ari(a, b, ka, kb):
     out = torch.empty((), dtype=torch.float64, device=a.device)
     _check(_lib.fsc_ari(context(a.device.index), _ptr(a), _ptr(b), a.numel(), ka, kb, _ptr(out), _stream()))
     return out
+
+
+def timing_enable(on=True, device=None):
+    """Brackets every sparse-product launch with HIP events (see fsc.h)."""
+    _check(_lib.fsc_timing_enable(context(device), int(bool(on))))
+
+
+def timing_read(device=None):
+    """(launches, total_ms) of the sparse-product launches timed so far."""
+    n = _i64()
+    ms = ctypes.c_double()
+    _check(_lib.fsc_timing_read(context(device), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 def version():
