@@ -109,6 +109,15 @@ typedef struct {
 
 typedef struct fsc_context fsc_context;
 
+/* Launch shape of the sparse product (the tile kernel of one PowerMethod
+ * step), per context.  Zero fields keep the current value. */
+typedef struct {
+  int32_t tile_nnz;       /* nonzeros per short tile (default 1024) */
+  int32_t blocks_per_cu;  /* persistent blocks per compute unit (default 8) */
+  int32_t xcd_order;      /* 1: contiguous short-tile range per XCD, 2: round robin */
+  int32_t unroll;         /* nonzeros in flight per lane: 4 or 8 (default 8) */
+} fsc_tuning;
+
 /* Creates a context on HIP device `device` (makes it current on the calling
  * thread).  *out receives the context.  Returns FSC_E_HIP if the device is not
  * usable. */
@@ -148,6 +157,12 @@ int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, i
  * their range are counted in no cell (and so lower the score). */
 int fsc_ari(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int32_t ka,
             int32_t kb, double* out, void* stream);
+
+/* Sets (fields > 0) and then reports in *t the sparse-product launch shape
+ * used by later calls on this context.  t is a host pointer.  Returns
+ * FSC_E_ARG for out-of-range values (tile_nnz < 64, blocks_per_cu outside
+ * [1, 16], unroll not 4 or 8). */
+int fsc_tuning_set(fsc_context* ctx, fsc_tuning* t);
 
 /* Kernel timing with HIP events, for profiling (off by default).  While on,
  * every sparse-product launch (one PowerMethod step, Algorithm 1) queued by

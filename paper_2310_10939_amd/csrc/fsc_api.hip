@@ -97,9 +97,6 @@ static int prepare_embed(Context* ctx, const fsc_csr* g, int l, int t, uint64_t 
   if (t < 0) return fail(FSC_E_ARG, "t must be >= 0");
   if (o.vec_dtype < FSC_F64 || o.vec_dtype > FSC_BF16) return fail(FSC_E_ARG, "bad vec_dtype");
   if (o.tile_nnz < 0 || (o.tile_nnz > 0 && o.tile_nnz < 64)) return fail(FSC_E_ARG, "tile_nnz must be 0 or >= 64");
-  if (o.tile_nnz > max_tile_nnz(l, o.vec_dtype))
-    return fail(FSC_E_ARG, "tile_nnz too large for the LDS budget (max " +
-                               std::to_string(max_tile_nnz(l, o.vec_dtype)) + ")");
   std::memset(io, 0, sizeof(*io));
   io->g = g;
   io->l = l;
@@ -279,6 +276,30 @@ int fsc_ari(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int
   if ((rc = reserve_arena(&ctx->c, align_up((size_t)ka * kb * 8) + 256, &arena))) return rc;
   unsigned long long* table = arena.take<unsigned long long>((size_t)ka * kb);
   return ari_run(&ctx->c, a, b, n, ka, kb, out, table, s);
+}
+
+int fsc_tuning_set(fsc_context* ctx, fsc_tuning* t) {
+  if (!ctx || !t) return fail(FSC_E_ARG, "null pointer");
+  Tune nt = ctx->c.tune;
+  if (t->tile_nnz > 0) {
+    if (t->tile_nnz < 64) return fail(FSC_E_ARG, "tile_nnz must be >= 64");
+    nt.tile_nnz = t->tile_nnz;
+  }
+  if (t->blocks_per_cu > 0) {
+    if (t->blocks_per_cu > 16) return fail(FSC_E_ARG, "blocks_per_cu must be in [1, 16]");
+    nt.blocks_per_cu = t->blocks_per_cu;
+  }
+  if (t->xcd_order > 0) nt.xcd_order = t->xcd_order == 1 ? 1 : 0;
+  if (t->unroll > 0) {
+    if (t->unroll != 4 && t->unroll != 8) return fail(FSC_E_ARG, "unroll must be 4 or 8");
+    nt.unroll = t->unroll;
+  }
+  ctx->c.tune = nt;
+  t->tile_nnz = nt.tile_nnz;
+  t->blocks_per_cu = nt.blocks_per_cu;
+  t->xcd_order = nt.xcd_order ? 1 : 2;
+  t->unroll = nt.unroll;
+  return FSC_OK;
 }
 
 int fsc_timing_enable(fsc_context* ctx, int on) {

@@ -220,4 +220,36 @@ __device__ __forceinline__ double block_sum(double v, double* lds /* BLOCK/64 */
   return s;
 }
 
+// Inclusive scan across a block of BLOCK threads (wave shuffles, then the
+// wave totals through LDS); fixed order, so deterministic.  Also returns the
+// block total in *total.  `lds` holds BLOCK/64 + 1 values.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_scan_inclusive(T v, T* lds, T* total) {
+  const int lane = threadIdx.x & (FSC_WAVE - 1);
+  const int w = threadIdx.x / FSC_WAVE;
+#pragma unroll
+  for (int off = 1; off < FSC_WAVE; off <<= 1) {
+    const T x = __shfl_up(v, off, FSC_WAVE);
+    if (lane >= off) v += x;
+  }
+  __syncthreads();
+  if (lane == FSC_WAVE - 1) lds[w] = v;
+  __syncthreads();
+  T before = T(0), all = T(0);
+#pragma unroll
+  for (int i = 0; i < BLOCK / FSC_WAVE; ++i) {
+    const T x = lds[i];
+    if (i < w) before += x;
+    all += x;
+  }
+  __syncthreads();
+  *total = all;
+  return before + v;
+}
+
+template <typename T>
+__device__ __forceinline__ T nt_load(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 }  // namespace fsc

@@ -7,17 +7,18 @@
 // so the degree scaling is one multiply per row and Z_t is the embedding
 // itself.  The sparse product is the only pass over the graph per step.
 //
-// Sparse product layout ("tiles"): the nonzeros are cut into buckets of
-// tile_nnz; bucket b owns the rows whose first nonzero lies in
-// [b*tile_nnz, (b+1)*tile_nnz).  A bucket holds at most 2*tile_nnz nonzeros of
-// rows no longer than tile_nnz, plus possibly one longer last row; such long
-// rows are cut into chunks of tile_nnz processed by separate tiles whose
-// partial sums are combined, in chunk order, by the tile that finishes last.
-// A short tile streams its nonzeros with fully coalesced reads of col/val,
-// gathers the l-wide rows of Z, stages the weighted rows in LDS and then sums
-// each matrix row with a lane group sized to the tile's mean row length
-// (wave-shuffle reduction).  The grid is persistent: block g takes tiles g,
-// g + grid, ... so per-block statistics are deterministic.
+// Tiles of the sparse product: the nonzeros are cut into buckets of tile_nnz;
+// bucket b owns the rows whose first nonzero lies in [b*tile_nnz,
+// (b+1)*tile_nnz).  Its rows are no longer than tile_nnz except possibly the
+// last one; such a long row is cut into chunks of tile_nnz, each a tile of its
+// own whose partial sums are combined, in chunk order, by the chunk that
+// finishes last.  A short tile gives each of its rows a group of G lanes
+// (G a power of two chosen per bucket from its row count and mean length);
+// the lanes of a group stream the row's column indices and weights with
+// coalesced non-temporal loads, gather the l-wide rows of Z (which stay in
+// cache), accumulate in registers and combine with wave shuffles.  The grid is
+// persistent with a static tile order, so per-block statistics -- and so the
+// FP64 column norms -- are deterministic.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
 
@@ -40,19 +41,39 @@ __device__ __forceinline__ int64_t lower_bound_i64(const int64_t* a, int64_t len
   return lo;
 }
 
+// Lanes per row for a tile of R rows holding nz nonzeros: every row of the
+// tile in one pass of the block, and no more lanes than the mean row length.
+__device__ __forceinline__ int lanes_per_row(int64_t R, int64_t nz) {
+  if (R <= 0) return 1;
+  int g1 = 1;
+  while (g1 * 2 * R <= kBlock && g1 < FSC_WAVE) g1 *= 2;
+  const int64_t mean = nz / R;
+  int g2 = 1;
+  while (g2 < mean && g2 < FSC_WAVE) g2 *= 2;
+  return g1 < g2 ? g1 : g2;
+}
+
 __global__ void plan_buckets(const int64_t* __restrict__ row_ptr, int32_t n, int32_t nb, int32_t NB,
-                             int32_t* __restrict__ rb, int32_t* __restrict__ nch) {
+                             TileDesc* __restrict__ desc, int32_t* __restrict__ nch) {
   const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   const int64_t r0 = min<int64_t>(lower_bound_i64(row_ptr, (int64_t)n + 1, (int64_t)b * NB), n);
-  const int64_t r1 = min<int64_t>(lower_bound_i64(row_ptr, (int64_t)n + 1, (int64_t)(b + 1) * NB), n);
-  rb[b] = (int32_t)r0;
-  if (b == nb - 1) rb[nb] = n;
+  int64_t r1 = min<int64_t>(lower_bound_i64(row_ptr, (int64_t)n + 1, (int64_t)(b + 1) * NB), n);
+  if (b == nb - 1) r1 = n;
   int32_t c = 0;
   if (r1 > r0) {
     const int64_t len = row_ptr[r1] - row_ptr[r1 - 1];
-    if (len > NB) c = (int32_t)((len + NB - 1) / NB);
+    if (len > NB) {
+      c = (int32_t)((len + NB - 1) / NB);
+      r1 -= 1;  // the long last row goes to chunk tiles
+    }
   }
+  TileDesc d;
+  d.r0 = (int32_t)r0;
+  d.r1 = (int32_t)r1;
+  d.G = lanes_per_row(r1 - r0, row_ptr[r1] - row_ptr[r0]);
+  d.pad = 0;
+  desc[b] = d;
   nch[b] = c;
 }
 
@@ -60,30 +81,21 @@ __global__ void plan_buckets(const int64_t* __restrict__ row_ptr, int32_t n, int
 __global__ __launch_bounds__(1024) void plan_scan(const int32_t* __restrict__ nch, int32_t nb,
                                                   int32_t* __restrict__ choff, int32_t* __restrict__ lid,
                                                   int32_t* __restrict__ meta) {
-  __shared__ int32_t sa[1024], sb[1024];
+  __shared__ int32_t lds_a[1024 / FSC_WAVE + 1], lds_b[1024 / FSC_WAVE + 1];
   int32_t carry_a = 0, carry_b = 0;
   for (int32_t base = 0; base < nb; base += 1024) {
     const int32_t i = base + threadIdx.x;
     const int32_t va = i < nb ? nch[i] : 0;
-    const int32_t vb = i < nb ? (nch[i] > 0) : 0;
-    sa[threadIdx.x] = va;
-    sb[threadIdx.x] = vb;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      int32_t xa = threadIdx.x >= off ? sa[threadIdx.x - off] : 0;
-      int32_t xb = threadIdx.x >= off ? sb[threadIdx.x - off] : 0;
-      __syncthreads();
-      sa[threadIdx.x] += xa;
-      sb[threadIdx.x] += xb;
-      __syncthreads();
-    }
+    const int32_t vb = va > 0 ? 1 : 0;
+    int32_t ta, tb;
+    const int32_t ia = block_scan_inclusive<1024>(va, lds_a, &ta);
+    const int32_t ib = block_scan_inclusive<1024>(vb, lds_b, &tb);
     if (i < nb) {
-      choff[i] = carry_a + sa[threadIdx.x] - va;
-      lid[i] = carry_b + sb[threadIdx.x] - vb;
+      choff[i] = carry_a + ia - va;
+      lid[i] = carry_b + ib - vb;
     }
-    carry_a += sa[1023];
-    carry_b += sb[1023];
-    __syncthreads();
+    carry_a += ta;
+    carry_b += tb;
   }
   if (threadIdx.x == 0) {
     choff[nb] = carry_a;
@@ -94,12 +106,12 @@ __global__ __launch_bounds__(1024) void plan_scan(const int32_t* __restrict__ nc
 }
 
 __global__ void plan_chunks(const int64_t* __restrict__ row_ptr, int32_t nb, int32_t NB,
-                            const int32_t* __restrict__ rb, const int32_t* __restrict__ nch,
+                            const TileDesc* __restrict__ desc, const int32_t* __restrict__ nch,
                             const int32_t* __restrict__ choff, const int32_t* __restrict__ lid,
                             LongChunk* __restrict__ chunks) {
   const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb || nch[b] == 0) return;
-  const int32_t r = rb[b + 1] - 1;
+  const int32_t r = desc[b].r1;  // the long row follows the bucket's short rows
   const int64_t rs = row_ptr[r], re = row_ptr[r + 1];
   const int32_t cnt = nch[b], first = choff[b];
   for (int32_t c = 0; c < cnt; ++c) {
@@ -122,8 +134,109 @@ __global__ void fill_i32(int32_t* p, int64_t count, int32_t v) {
 }
 
 // ---------------------------------------------------------------------------
+// Column statistics, finished by the last block of a step.
+// state: [0..LH) prev_sq, [LH..2LH) cum (product of applied scales),
+//        [2LH..3LH) next scale (FP64), [3LH..4LH) next scale in the step's
+//        accumulation type.
+// ---------------------------------------------------------------------------
+struct StatsArgs {
+  double* partials;     // [grid][2*LH]
+  const double* lnorm;  // [long rows][2*LH]
+  const int32_t* meta;  // meta[1] = long rows
+  double* state;
+  int32_t* counter;
+  double* sqnorm;       // optional (t+1) x l
+  double* rayleigh;     // optional t x l
+  int step, t, l, renorm;
+  int acc_is_double;
+};
+
+template <int LH>
+__device__ void stats_finish(const StatsArgs& sa, int grid) {
+  __shared__ double red[kBlock / FSC_WAVE];
+  __shared__ double tot[2 * LH];
+  const int32_t nlong = sa.step > 0 ? sa.meta[1] : 0;
+  double v[2 * LH];
+#pragma unroll
+  for (int q = 0; q < 2 * LH; ++q) v[q] = 0.0;
+  for (int32_t g = threadIdx.x; g < grid; g += kBlock)
+#pragma unroll
+    for (int q = 0; q < 2 * LH; ++q) v[q] += sa.partials[(int64_t)g * 2 * LH + q];
+  for (int32_t g = threadIdx.x; g < nlong; g += kBlock)
+#pragma unroll
+    for (int q = 0; q < 2 * LH; ++q) v[q] += sa.lnorm[(int64_t)g * 2 * LH + q];
+#pragma unroll
+  for (int q = 0; q < 2 * LH; ++q) {
+    const double s = block_sum<kBlock>(v[q], red);
+    if (threadIdx.x == 0) tot[q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < LH) {
+    const int q = threadIdx.x;
+    double* prev_sq = sa.state;
+    double* cum = sa.state + LH;
+    double* next = sa.state + 2 * LH;
+    const double sq = tot[q];
+    if (sa.step == 0) {
+      cum[q] = 1.0;
+    } else {
+      cum[q] *= next[q];
+      if (sa.rayleigh && q < sa.l) {
+        const double den = prev_sq[q];
+        sa.rayleigh[(int64_t)(sa.step - 1) * sa.l + q] = den > 0.0 ? tot[LH + q] / den : 0.0;
+      }
+    }
+    if (sa.sqnorm && q < sa.l) sa.sqnorm[(int64_t)sa.step * sa.l + q] = sq / (cum[q] * cum[q]);
+    prev_sq[q] = sq;
+    double c = 1.0;
+    if (sa.renorm) {
+      if (sa.step + 1 < sa.t) c = sq > 0.0 ? 1.0 / sqrt(sq) : 1.0;
+      else c = 1.0 / cum[q];  // the last step restores the un-normalised scale
+    }
+    next[q] = c;
+    if (sa.acc_is_double) reinterpret_cast<double*>(sa.state + 3 * LH)[q] = c;
+    else reinterpret_cast<float*>(sa.state + 3 * LH)[q] = (float)c;
+  }
+}
+
+// Writes this block's partial statistics; the last block to arrive finishes
+// them.  Called by every thread of every block.
+template <int LH>
+__device__ __forceinline__ void stats_epilogue(const StatsArgs& sa, const double* st) {
+  __shared__ double red[kBlock / FSC_WAVE];
+  __shared__ int is_last;
+#pragma unroll
+  for (int q = 0; q < 2 * LH; ++q) {
+    const double v = block_sum<kBlock>(st[q], red);
+    if (threadIdx.x == 0) sa.partials[(int64_t)blockIdx.x * 2 * LH + q] = v;
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int prev = atomicAdd(sa.counter, 1);
+    is_last = (prev == (int)gridDim.x - 1);
+  }
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    stats_finish<LH>(sa, gridDim.x);
+    if (threadIdx.x == 0) *sa.counter = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Row-reduction operators run by the tile kernel
 // ---------------------------------------------------------------------------
+template <typename W, typename A>
+__device__ __forceinline__ A load_weight(const W* val, int64_t j) {
+  if constexpr (std::is_void<W>::value) {
+    return A(1);
+  } else if constexpr (std::is_same<W, bf16_t>::value) {
+    return static_cast<A>(bf16_to_f32(nt_load(reinterpret_cast<const uint16_t*>(val) + j)));
+  } else {
+    return static_cast<A>(nt_load(val + j));
+  }
+}
+
 // Degrees: d_v = sum of the weights of row v (Sec. 2; the graph has no
 // self-loops, so this is sum_{u != v} w(u, v)), accumulated in FP64.  The
 // epilogue writes d, 1/(2d), d^{-1/2} and the k-means eligibility mask.
@@ -132,6 +245,7 @@ struct DegreeOp {
   static constexpr int LH = 1;
   static constexpr bool STATS = false;
   using A = double;
+  struct Pre {};
   const W* val;
   double* deg;
   HA* hinv;
@@ -139,12 +253,16 @@ struct DegreeOp {
   uint8_t* elig;
   __device__ __forceinline__ void init() {}
   template <int U>
-  __device__ __forceinline__ void gather_many(const int64_t* j, const int32_t*, const bool* ok,
-                                              double (*out)[1]) const {
+  __device__ __forceinline__ void accumulate(const int32_t*, int64_t j0, int32_t stride, int64_t end,
+                                             double* acc) const {
 #pragma unroll
-    for (int u = 0; u < U; ++u) out[u][0] = ok[u] ? weight<W, double>::get(val, j[u]) : 0.0;
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + (int64_t)u * stride;
+      if (j < end) acc[0] += load_weight<W, double>(val, j);
+    }
   }
-  __device__ __forceinline__ void finish(int32_t r, const double* acc, double*) const {
+  __device__ __forceinline__ void prefetch(int32_t, Pre&) const {}
+  __device__ __forceinline__ void finish(int32_t r, const double* acc, const Pre&, double*) const {
     const double d = acc[0];
     deg[r] = d;
     hinv[r] = d > 0.0 ? static_cast<HA>(0.5 / d) : HA(0);
@@ -153,16 +271,22 @@ struct DegreeOp {
   }
 };
 
-// One PowerMethod step in z-space with an optional per-column scale c:
+// One PowerMethod step in z-space with a per-column scale c (1 unless the
+// iterate is re-normalised):
 //   Z'_r = c (.) (Z_r / 2 + hinv_r (A Z)_r).
-// With STATS the epilogue accumulates, per column, sum_r d_r Z'_r^2 and
-// sum_r d_r Z_r (Z_r/2 + hinv_r (A Z)_r) (y-space norm and the numerator of
-// the Rayleigh quotient of the previous iterate).
+// With STATS the epilogue accumulates, per column, sum_r d_r Z'_r^2 (the
+// y-space squared norm of the stored iterate) and sum_r d_r Z_r (Z_r/2 +
+// hinv_r (A Z)_r) (y_{i-1}^T M y_{i-1}, the Rayleigh numerator).
 template <typename S, typename W, int LH_, bool STATS_>
 struct StepOp {
   static constexpr int LH = LH_;
   static constexpr bool STATS = STATS_;
   using A = typename elem<S>::acc;
+  struct Pre {
+    A z[LH_];
+    A h;
+    double d;
+  };
   const W* val;
   const S* zin;
   S* zout;
@@ -175,39 +299,51 @@ struct StepOp {
     for (int q = 0; q < LH_; ++q) cs[q] = scale ? scale[q] : A(1);
   }
   template <int U>
-  __device__ __forceinline__ void gather_many(const int64_t* j, const int32_t* c, const bool* ok,
-                                              A (*out)[LH_]) const {
+  __device__ __forceinline__ void accumulate(const int32_t* col, int64_t j0, int32_t stride, int64_t end,
+                                             A* acc) const {
+    int32_t c[U];
     A w[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) w[u] = ok[u] ? weight<W, A>::get(val, j[u]) : A(0);
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + (int64_t)u * stride;
+      const bool ok = j < end;
+      c[u] = ok ? nt_load(col + j) : -1;
+      w[u] = ok ? load_weight<W, A>(val, j) : A(0);
+    }
+    A z[U][LH_];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (ok[u]) {
-        rowio<S, LH_>::load(zin + (int64_t)c[u] * LH_, out[u]);
+      if (c[u] >= 0) {
+        rowio<S, LH_>::load(zin + (int64_t)c[u] * LH_, z[u]);
       } else {
 #pragma unroll
-        for (int q = 0; q < LH_; ++q) out[u][q] = A(0);
+        for (int q = 0; q < LH_; ++q) z[u][q] = A(0);
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int q = 0; q < LH_; ++q) out[u][q] *= w[u];
+      for (int q = 0; q < LH_; ++q) {
+        if constexpr (std::is_void<W>::value) acc[q] += z[u][q];
+        else acc[q] += w[u] * z[u][q];
+      }
   }
-  __device__ __forceinline__ void finish(int32_t r, const A* acc, double* st) const {
-    A z[LH_], zn[LH_];
-    rowio<S, LH_>::load(zin + (int64_t)r * LH_, z);
-    const A h = hinv[r];
+  __device__ __forceinline__ void prefetch(int32_t r, Pre& p) const {
+    rowio<S, LH_>::load(zin + (int64_t)r * LH_, p.z);
+    p.h = hinv[r];
+    if constexpr (STATS_) p.d = deg[r];
+  }
+  __device__ __forceinline__ void finish(int32_t r, const A* acc, const Pre& p, double* st) const {
+    A zn[LH_];
 #pragma unroll
     for (int q = 0; q < LH_; ++q) {
-      const A m = A(0.5) * z[q] + h * acc[q];
+      const A m = A(0.5) * p.z[q] + p.h * acc[q];
       zn[q] = cs[q] * m;
       if constexpr (STATS_) {
-        // statistics from the value that is actually stored
+        // statistics of the value that is actually stored
         zn[q] = elem<S>::to_acc(elem<S>::from_acc(zn[q]));
-        const double d = deg[r];
-        st[q] += d * (double)zn[q] * (double)zn[q];
-        st[LH_ + q] += d * (double)z[q] * (double)m;
+        st[q] += p.d * (double)zn[q] * (double)zn[q];
+        st[LH_ + q] += p.d * (double)p.z[q] * (double)m;
       }
     }
     rowio<S, LH_>::store(zout + (int64_t)r * LH_, zn);
@@ -222,14 +358,13 @@ struct TileArgs {
   const int32_t* col;
   int32_t n;
   int32_t nb;
-  int32_t NB;
-  const int32_t* rb;
+  const TileDesc* desc;
   const LongChunk* chunks;
   const int32_t* meta;
-  double* partials;   // [grid][2*LH] (STATS)
   void* lpart;        // A[chunks][LH]
   int32_t* lcount;    // [long rows]
   double* lnorm;      // [long rows][2*LH] (STATS)
+  int xcd_order;      // 1: each XCD takes a contiguous range of short tiles
 };
 
 template <int LH, typename A>
@@ -239,165 +374,107 @@ __device__ __forceinline__ void group_reduce(A* acc, int G) {
     for (int q = 0; q < LH; ++q) acc[q] += shfl_xor(acc[q], m);
 }
 
-template <class Op>
-__global__ __launch_bounds__(kBlock) void tile_kernel(Op op_in, TileArgs ta) {
+template <int kU, class Op>
+__device__ __forceinline__ void short_tile(const Op& op, const TileArgs& ta, const TileDesc d, double* st) {
+  constexpr int LH = Op::LH;
+  using A = typename Op::A;
+  const int G = d.G;
+  const int ngroups = kBlock / G;
+  const int gid = threadIdx.x / G, lane = threadIdx.x % G;
+  for (int32_t rbase = d.r0; rbase < d.r1; rbase += ngroups) {
+    const int32_t r = rbase + gid;
+    const bool active = r < d.r1;
+    A acc[LH];
+#pragma unroll
+    for (int q = 0; q < LH; ++q) acc[q] = A(0);
+    typename Op::Pre pre;
+    if (active) {
+      if (lane == 0) op.prefetch(r, pre);
+      const int64_t a = ta.row_ptr[r], b = ta.row_ptr[r + 1];
+      for (int64_t j0 = a + lane; j0 < b; j0 += (int64_t)G * kU)
+        op.template accumulate<kU>(ta.col, j0, G, b, acc);
+    }
+    group_reduce<LH, A>(acc, G);
+    if (active && lane == 0) op.finish(r, acc, pre, st);
+  }
+}
+
+template <int kU, class Op>
+__device__ __forceinline__ void long_chunk(const Op& op, const TileArgs& ta, int32_t ci) {
+  constexpr int LH = Op::LH;
+  using A = typename Op::A;
+  __shared__ A wred[kBlock / FSC_WAVE][LH];
+  __shared__ int is_last;
+  const LongChunk ch = ta.chunks[ci];
+  A acc[LH];
+#pragma unroll
+  for (int q = 0; q < LH; ++q) acc[q] = A(0);
+  for (int64_t j0 = ch.start + threadIdx.x; j0 < ch.end; j0 += (int64_t)kBlock * kU)
+    op.template accumulate<kU>(ta.col, j0, kBlock, ch.end, acc);
+  group_reduce<LH, A>(acc, FSC_WAVE);
+  const int w = threadIdx.x / FSC_WAVE;
+  if ((threadIdx.x & (FSC_WAVE - 1)) == 0)
+#pragma unroll
+    for (int q = 0; q < LH; ++q) wred[w][q] = acc[q];
+  __syncthreads();
+  A* lpart = reinterpret_cast<A*>(ta.lpart);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < LH; ++q) {
+      A sum = A(0);
+      for (int i = 0; i < kBlock / FSC_WAVE; ++i) sum += wred[i][q];
+      lpart[(int64_t)ci * LH + q] = sum;
+    }
+    __threadfence();
+    const int prev = atomicAdd(&ta.lcount[ch.lid], 1);
+    is_last = (prev == ch.count - 1);
+  }
+  __syncthreads();
+  if (is_last && threadIdx.x == 0) {
+    __threadfence();
+    A tot[LH];
+#pragma unroll
+    for (int q = 0; q < LH; ++q) tot[q] = A(0);
+    for (int c = 0; c < ch.count; ++c)
+#pragma unroll
+      for (int q = 0; q < LH; ++q) tot[q] += lpart[(int64_t)(ch.first + c) * LH + q];
+    double lst[2 * LH];
+#pragma unroll
+    for (int q = 0; q < 2 * LH; ++q) lst[q] = 0.0;
+    typename Op::Pre pre;
+    op.prefetch(ch.row, pre);
+    op.finish(ch.row, tot, pre, lst);
+    if constexpr (Op::STATS) {
+#pragma unroll
+      for (int q = 0; q < 2 * LH; ++q) ta.lnorm[(int64_t)ch.lid * 2 * LH + q] = lst[q];
+    }
+    ta.lcount[ch.lid] = 0;  // ready for the next step
+  }
+  __syncthreads();
+}
+
+template <int kU, class Op>
+__global__ __launch_bounds__(kBlock) void tile_kernel(Op op_in, TileArgs ta, StatsArgs sa) {
   constexpr int LH = Op::LH;
   Op op = op_in;
   op.init();
-  using A = typename Op::A;
-  constexpr int U = 4;  // nonzeros in flight per thread
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  A* prod = reinterpret_cast<A*>(smem_raw);  // [2*NB][LH]
-  __shared__ double red[kBlock / FSC_WAVE];
-  __shared__ A wred[kBlock / FSC_WAVE][LH];
-  __shared__ int is_last;
-
-  const int tid = threadIdx.x;
-  const int32_t NB = ta.NB;
   const int32_t nb = ta.nb;
   const int32_t ntiles = nb + ta.meta[0];
   double st[2 * LH];
 #pragma unroll
   for (int q = 0; q < 2 * LH; ++q) st[q] = 0.0;
 
-  for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    if (tile < nb) {
-      // ------------------------------ short tile ----------------------------
-      const int32_t r0 = ta.rb[tile];
-      int32_t r1 = ta.rb[tile + 1];
-      if (r1 > r0 && ta.row_ptr[r1] - ta.row_ptr[r1 - 1] > NB) --r1;  // long last row
-      const int64_t s = ta.row_ptr[r0];
-      const int32_t ne = (int32_t)(ta.row_ptr[r1] - s);
-      // phase 1: stream nonzeros, gather, weight, stage in LDS
-      for (int32_t base = 0; base < ne; base += kBlock * U) {
-        int64_t jj[U];
-        int32_t cc[U];
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int32_t j = base + u * kBlock + tid;
-          ok[u] = j < ne;
-          jj[u] = s + j;
-          cc[u] = ok[u] ? ta.col[s + j] : 0;
-        }
-        A v[U][LH];
-        op.template gather_many<U>(jj, cc, ok, v);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int32_t j = base + u * kBlock + tid;
-          if (ok[u]) {
-#pragma unroll
-            for (int q = 0; q < LH; ++q) prod[j * LH + q] = v[u][q];
-          }
-        }
-      }
-      __syncthreads();
-      // phase 2: one lane group per row
-      const int32_t R = r1 - r0;
-      if (R > 0) {
-        int G = 1;
-        {
-          const int32_t fit = kBlock / R;          // groups that fit in one pass
-          const int32_t mean = ne / R;
-          int g1 = 1;
-          while (g1 * 2 <= fit && g1 < FSC_WAVE) g1 *= 2;
-          int g2 = 1;
-          while (g2 * 4 < mean && g2 < FSC_WAVE) g2 *= 2;
-          G = g1 < g2 ? g1 : g2;
-        }
-        const int ngroups = kBlock / G;
-        const int gid = tid / G, lane = tid % G;
-        for (int32_t rbase = r0; rbase < r1; rbase += ngroups) {
-          const int32_t r = rbase + gid;
-          const bool active = r < r1;
-          A acc[LH];
-#pragma unroll
-          for (int q = 0; q < LH; ++q) acc[q] = A(0);
-          if (active) {
-            const int32_t a = (int32_t)(ta.row_ptr[r] - s), e = (int32_t)(ta.row_ptr[r + 1] - s);
-            for (int32_t j = a + lane; j < e; j += G)
-#pragma unroll
-              for (int q = 0; q < LH; ++q) acc[q] += prod[j * LH + q];
-          }
-          group_reduce<LH, A>(acc, G);
-          if (active && lane == 0) op.finish(r, acc, st);
-        }
-      }
-      __syncthreads();
-    } else {
-      // ------------------------------ long-row chunk -------------------------
-      const int32_t ci = tile - nb;
-      const LongChunk ch = ta.chunks[ci];
-      A acc[LH];
-#pragma unroll
-      for (int q = 0; q < LH; ++q) acc[q] = A(0);
-      for (int64_t base = ch.start; base < ch.end; base += kBlock * U) {
-        int64_t jj[U];
-        int32_t cc[U];
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t j = base + u * kBlock + tid;
-          ok[u] = j < ch.end;
-          jj[u] = j;
-          cc[u] = ok[u] ? ta.col[j] : 0;
-        }
-        A v[U][LH];
-        op.template gather_many<U>(jj, cc, ok, v);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int q = 0; q < LH; ++q) acc[q] += v[u][q];
-      }
-      // block reduction in a fixed order
-      group_reduce<LH, A>(acc, FSC_WAVE);
-      const int w = tid / FSC_WAVE;
-      if ((tid & (FSC_WAVE - 1)) == 0)
-#pragma unroll
-        for (int q = 0; q < LH; ++q) wred[w][q] = acc[q];
-      __syncthreads();
-      A* lpart = reinterpret_cast<A*>(ta.lpart);
-      if (tid == 0) {
-#pragma unroll
-        for (int q = 0; q < LH; ++q) {
-          A sum = A(0);
-          for (int i = 0; i < kBlock / FSC_WAVE; ++i) sum += wred[i][q];
-          lpart[(int64_t)ci * LH + q] = sum;
-        }
-        __threadfence();
-        const int prev = atomicAdd(&ta.lcount[ch.lid], 1);
-        is_last = (prev == ch.count - 1);
-      }
-      __syncthreads();
-      if (is_last && tid == 0) {
-        __threadfence();
-        A tot[LH];
-#pragma unroll
-        for (int q = 0; q < LH; ++q) tot[q] = A(0);
-        for (int c = 0; c < ch.count; ++c)
-#pragma unroll
-          for (int q = 0; q < LH; ++q)
-            tot[q] += lpart[(int64_t)(ch.first + c) * LH + q];
-        double lst[2 * LH];
-#pragma unroll
-        for (int q = 0; q < 2 * LH; ++q) lst[q] = 0.0;
-        op.finish(ch.row, tot, lst);
-        if constexpr (Op::STATS) {
-#pragma unroll
-          for (int q = 0; q < 2 * LH; ++q) ta.lnorm[(int64_t)ch.lid * 2 * LH + q] = lst[q];
-        }
-        ta.lcount[ch.lid] = 0;  // ready for the next step
-      }
-      __syncthreads();
-    }
+  if (ta.xcd_order) {
+    // blocks are dispatched to the 8 XCDs round-robin: give XCD x the
+    // contiguous range [x*nb/8, (x+1)*nb/8) of short tiles
+    const int x = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
+    const int32_t lo = (int32_t)((int64_t)nb * x / 8), hi = (int32_t)((int64_t)nb * (x + 1) / 8);
+    for (int32_t tile = lo + slot; tile < hi; tile += per) short_tile<kU>(op, ta, ta.desc[tile], st);
+  } else {
+    for (int32_t tile = blockIdx.x; tile < nb; tile += gridDim.x) short_tile<kU>(op, ta, ta.desc[tile], st);
   }
-  if constexpr (Op::STATS) {
-#pragma unroll
-    for (int q = 0; q < 2 * LH; ++q) {
-      const double v = block_sum<kBlock>(st[q], red);
-      if (tid == 0) ta.partials[(int64_t)blockIdx.x * 2 * LH + q] = v;
-    }
-  }
+  for (int32_t tile = nb + blockIdx.x; tile < ntiles; tile += gridDim.x) long_chunk<kU>(op, ta, tile - nb);
+  if constexpr (Op::STATS) stats_epilogue<LH>(sa, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -408,14 +485,14 @@ __global__ __launch_bounds__(kBlock) void start_block(int32_t n, int32_t l, uint
                                                       const double* __restrict__ x0,
                                                       const double* __restrict__ isq,
                                                       const double* __restrict__ deg, S* __restrict__ z,
-                                                      double* __restrict__ partials, int stats) {
+                                                      StatsArgs sa, int stats) {
   using A = typename elem<S>::acc;
-  __shared__ double red[kBlock / FSC_WAVE];
-  double st[LH];
+  double st[2 * LH];
 #pragma unroll
-  for (int q = 0; q < LH; ++q) st[q] = 0.0;
+  for (int q = 0; q < 2 * LH; ++q) st[q] = 0.0;
   for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     const double s = isq[i];
+    const double d = deg[i];
     A row[LH];
 #pragma unroll
     for (int q = 0; q < LH; ++q) {
@@ -430,72 +507,11 @@ __global__ __launch_bounds__(kBlock) void start_block(int32_t n, int32_t l, uint
         }
       }
       row[q] = elem<S>::to_acc(elem<S>::from_acc(static_cast<A>(s * x)));
-      st[q] += deg[i] * (double)row[q] * (double)row[q];
+      st[q] += d * (double)row[q] * (double)row[q];
     }
     rowio<S, LH>::store(z + (int64_t)i * LH, row);
   }
-  if (stats) {
-#pragma unroll
-    for (int q = 0; q < LH; ++q) {
-      const double v = block_sum<kBlock>(st[q], red);
-      if (threadIdx.x == 0) {
-        partials[(int64_t)blockIdx.x * 2 * LH + q] = v;
-        partials[(int64_t)blockIdx.x * 2 * LH + LH + q] = 0.0;
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Column statistics after step `step` (0 = the start block), one block.
-// state: [0] prev_sq, [1] cum (product of applied scales), [2] next scale.
-// ---------------------------------------------------------------------------
-template <int LH>
-__global__ __launch_bounds__(kBlock) void finish_stats(const double* __restrict__ partials, int32_t grid,
-                                                      const double* __restrict__ lnorm,
-                                                      const int32_t* __restrict__ meta, int step, int t, int l,
-                                                      int renorm, double* __restrict__ state,
-                                                      double* __restrict__ sqnorm, double* __restrict__ rayleigh,
-                                                      float* __restrict__ scale_f, double* __restrict__ scale_d) {
-  __shared__ double red[kBlock / FSC_WAVE];
-  __shared__ double tot[2 * LH];
-  const int32_t nlong = step > 0 ? meta[1] : 0;
-  for (int q = 0; q < 2 * LH; ++q) {
-    double v = 0.0;
-    for (int32_t g = threadIdx.x; g < grid; g += kBlock) v += partials[(int64_t)g * 2 * LH + q];
-    for (int32_t g = threadIdx.x; g < nlong; g += kBlock) v += lnorm[(int64_t)g * 2 * LH + q];
-    v = block_sum<kBlock>(v, red);
-    if (threadIdx.x == 0) tot[q] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < LH) {
-    const int q = threadIdx.x;
-    double* prev_sq = state;
-    double* cum = state + LH;
-    double* next = state + 2 * LH;
-    const double sq = tot[q];
-    double c_applied = 1.0;
-    if (step == 0) {
-      cum[q] = 1.0;
-    } else {
-      c_applied = next[q];
-      cum[q] *= c_applied;
-      if (rayleigh && q < l) {
-        const double den = prev_sq[q];
-        rayleigh[(int64_t)(step - 1) * l + q] = den > 0.0 ? tot[LH + q] / den : 0.0;
-      }
-    }
-    if (sqnorm && q < l) sqnorm[(int64_t)step * l + q] = sq / (cum[q] * cum[q]);
-    prev_sq[q] = sq;
-    double c = 1.0;
-    if (renorm) {
-      if (step + 1 < t) c = sq > 0.0 ? 1.0 / sqrt(sq) : 1.0;
-      else c = 1.0 / cum[q];  // the last step restores the un-normalised scale
-    }
-    next[q] = c;
-    if (scale_f) scale_f[q] = (float)c;
-    if (scale_d) scale_d[q] = c;
-  }
+  if (stats) stats_epilogue<LH>(sa, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -553,54 +569,40 @@ __global__ void validate_kernel(const int64_t* __restrict__ row_ptr, const int32
 // ===========================================================================
 // Host side
 // ===========================================================================
-// LDS per block of the tile kernel: 2*NB staged products of LH values, and
-// 2*NB FP64 weights in the degree pass that shares the plan.
-static size_t tile_lds_bytes(int NB, int LH, int vec_dtype) {
-  const size_t row = (size_t)LH * (vec_dtype == FSC_F64 ? 8 : 4);
-  return (size_t)2 * NB * std::max<size_t>(row, 8);
-}
+int effective_tile_nnz(const Context* ctx, int tile_nnz) { return tile_nnz > 0 ? tile_nnz : ctx->tune.tile_nnz; }
 
-static int default_tile_nnz(int LH, int vec_dtype) {
-  int nb = 2048;
-  while (nb > 256 && tile_lds_bytes(nb, LH, vec_dtype) > 32768) nb >>= 1;
-  return nb;
-}
+int max_tile_nnz(int, int) { return 1 << 20; }
 
-int max_tile_nnz(int l, int vec_dtype) {
-  const int LH = padded_width(l);
-  int nb = 1 << 16;
-  while (nb > 64 && tile_lds_bytes(nb, LH, vec_dtype) > 60 * 1024) nb >>= 1;
-  return nb;
-}
+static int64_t num_buckets(int64_t nnz, int NB) { return nnz / NB + 1; }
 
 size_t embed_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, int vec_dtype, int tile_nnz) {
   const int LH = padded_width(l);
-  const int NB = tile_nnz > 0 ? tile_nnz : default_tile_nnz(LH, vec_dtype);
+  const int NB = effective_tile_nnz(ctx, tile_nnz);
   const int64_t n = g->n;
-  const int64_t nb = g->nnz / NB + 1;
+  const int64_t nb = num_buckets(g->nnz, NB);
   const size_t se = vec_dtype == FSC_F64 ? 8 : vec_dtype == FSC_F32 ? 4 : 2;
   const size_t ae = vec_dtype == FSC_F64 ? 8 : 4;
-  const int grid = 4096;
   size_t b = 0;
-  b += align_up(n * 8) * 2 + align_up(n * ae) + align_up(n);       // deg, isq, hinv, elig
-  b += 2 * align_up(n * LH * se);                                  // z ping-pong
-  b += align_up((size_t)grid * 2 * LH * 8);                        // partials
-  b += align_up(4 * LH * 8) + align_up(LH * 8) + align_up(LH * 4); // state, scales
-  b += align_up(nb * 2 * LH * 8);                                  // lnorm
-  b += align_up((2 * nb + 1) * std::max<size_t>(LH * ae, 8));      // lpart (FP64 for degrees)
-  b += align_up(nb * 4);                                           // lcount
-  b += align_up((nb + 1) * 4) * 4 + align_up((2 * nb + 1) * sizeof(LongChunk)) + align_up(16);  // plan
-  b += 16 * 256;                                                   // alignment slack
+  b += align_up(n * 8) * 2 + align_up(n * ae) + align_up(n);        // deg, isq, hinv, elig
+  b += 2 * align_up(n * LH * se);                                   // z ping-pong
+  b += align_up((size_t)kMaxGrid * 2 * LH * 8);                     // partials
+  b += align_up((5 * LH + 8) * 8);                                  // state + counter
+  b += align_up(nb * 2 * LH * 8);                                   // lnorm
+  b += align_up((2 * nb + 1) * std::max<size_t>(LH * ae, 8));       // lpart (FP64 for degrees)
+  b += align_up(nb * 4);                                            // lcount
+  b += align_up(nb * sizeof(TileDesc)) + align_up((nb + 1) * 4) * 3;  // plan
+  b += align_up((2 * nb + 1) * sizeof(LongChunk)) + align_up(16);
+  b += 16 * 256;                                                    // alignment slack
   return b;
 }
 
 int embed_bind_workspace(Context* ctx, Arena* a, EmbedIO* io) {
   const fsc_csr* g = io->g;
   const int LH = io->LH;
-  const int NB = io->tile_nnz > 0 ? io->tile_nnz : default_tile_nnz(LH, io->vec_dtype);
+  const int NB = effective_tile_nnz(ctx, io->tile_nnz);
   io->tile_nnz = NB;
   const int64_t n = g->n;
-  const int64_t nb = g->nnz / NB + 1;
+  const int64_t nb = num_buckets(g->nnz, NB);
   const size_t se = io->vec_dtype == FSC_F64 ? 8 : io->vec_dtype == FSC_F32 ? 4 : 2;
   const size_t ae = io->vec_dtype == FSC_F64 ? 8 : 4;
   io->deg = a->take<double>(n);
@@ -609,14 +611,15 @@ int embed_bind_workspace(Context* ctx, Arena* a, EmbedIO* io) {
   io->elig = a->take<uint8_t>(n);
   io->z[0] = a->take<char>(n * LH * se);
   io->z[1] = a->take<char>(n * LH * se);
-  io->partials = a->take<double>((size_t)4096 * 2 * LH);
-  io->state = a->take<double>(4 * LH);
+  io->partials = a->take<double>((size_t)kMaxGrid * 2 * LH);
+  io->state = a->take<double>(5 * LH + 8);
+  io->counter = reinterpret_cast<int32_t*>(io->state + 5 * LH);
   io->lnorm = a->take<double>(nb * 2 * LH);
   io->lpart = a->take<char>((2 * nb + 1) * std::max<size_t>(LH * ae, 8));
   io->lcount = a->take<int32_t>(nb);
   io->plan.nb = (int32_t)nb;
   io->plan.tile_nnz = NB;
-  io->plan.rb = a->take<int32_t>(nb + 1);
+  io->plan.desc = a->take<TileDesc>(nb);
   io->plan.nch = a->take<int32_t>(nb + 1);
   io->plan.choff = a->take<int32_t>(nb + 1);
   io->plan.lid = a->take<int32_t>(nb + 1);
@@ -628,30 +631,36 @@ int embed_bind_workspace(Context* ctx, Arena* a, EmbedIO* io) {
 }
 
 template <class Op>
-static int launch_tiles(Context* ctx, const Op& op, const TileArgs& ta, int grid, hipStream_t s) {
-  const size_t lds = (size_t)2 * ta.NB * Op::LH * sizeof(typename Op::A);
-  hipLaunchKernelGGL(tile_kernel<Op>, dim3(grid), dim3(kBlock), lds, s, op, ta);
+static int launch_tiles(const Op& op, const TileArgs& ta, const StatsArgs& sa, int grid, int unroll, hipStream_t s) {
+  if (unroll == 4)
+    hipLaunchKernelGGL((tile_kernel<4, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sa);
+  else
+    hipLaunchKernelGGL((tile_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sa);
   return check_hip(hipGetLastError(), "tile_kernel launch");
 }
 
-static int persistent_grid(Context* ctx, int nb) {
-  // enough resident blocks to cover the chip several times over, but never
-  // more tiles-worth of blocks than there are short tiles plus long chunks
-  int g = ctx->num_cu * 8;
-  if (g > 4096) g = 4096;
-  const int cap = 2 * nb + 1;
-  return g < cap ? g : cap;
+// Persistent grid: a few resident blocks per CU, a multiple of 8 so the XCD
+// round-robin is even, never many more blocks than tiles.
+static int persistent_grid(const Context* ctx, int64_t tiles, int blocks_per_cu) {
+  int64_t g = (int64_t)ctx->num_cu * blocks_per_cu;
+  if (g > kMaxGrid) g = kMaxGrid;
+  const int64_t cap = std::max<int64_t>(8, (tiles + 7) / 8 * 8);
+  if (g > cap) g = cap;
+  g = std::max<int64_t>(8, g / 8 * 8);
+  return (int)g;
 }
 
 template <typename S, typename W, int LH>
-static int run_steps(Context* ctx, EmbedIO* io, TileArgs ta, hipStream_t s, bool stats) {
+static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta, StatsArgs sa, hipStream_t s, bool stats) {
   using A = typename elem<S>::acc;
   const fsc_csr* g = io->g;
-  A* scale = reinterpret_cast<A*>(io->state + 3 * LH);  // next step's scale, as A
+  const A* scale = reinterpret_cast<const A*>(io->state + 3 * LH);
   for (int step = 1; step <= io->t; ++step) {
     const S* zin = reinterpret_cast<const S*>(io->z[(step - 1) & 1]);
     S* zout = reinterpret_cast<S*>(io->z[step & 1]);
+    sa.step = step;
     int rc;
+    auto* ev = timing_start(ctx, s);
     if (stats) {
       StepOp<S, W, LH, true> op;
       op.val = reinterpret_cast<const W*>(g->val);
@@ -660,16 +669,7 @@ static int run_steps(Context* ctx, EmbedIO* io, TileArgs ta, hipStream_t s, bool
       op.hinv = reinterpret_cast<const A*>(io->hinv);
       op.deg = io->deg;
       op.scale = scale;
-      auto* ev = timing_start(ctx, s);
-      rc = launch_tiles(ctx, op, ta, io->grid, s);
-      timing_stop(ev, s);
-      if (rc) return rc;
-      hipLaunchKernelGGL(finish_stats<LH>, dim3(1), dim3(kBlock), 0, s, io->partials, io->grid, io->lnorm,
-                         io->plan.meta, step, io->t, io->l, io->renorm, io->state, io->sqnorm_trace,
-                         io->rayleigh_trace,
-                         std::is_same<A, float>::value ? reinterpret_cast<float*>(scale) : nullptr,
-                         std::is_same<A, double>::value ? reinterpret_cast<double*>(scale) : nullptr);
-      rc = check_hip(hipGetLastError(), "finish_stats launch");
+      rc = launch_tiles(op, ta, sa, io->grid, ctx->tune.unroll, s);
     } else {
       StepOp<S, W, LH, false> op;
       op.val = reinterpret_cast<const W*>(g->val);
@@ -678,10 +678,9 @@ static int run_steps(Context* ctx, EmbedIO* io, TileArgs ta, hipStream_t s, bool
       op.hinv = reinterpret_cast<const A*>(io->hinv);
       op.deg = io->deg;
       op.scale = nullptr;
-      auto* ev = timing_start(ctx, s);
-      rc = launch_tiles(ctx, op, ta, io->grid, s);
-      timing_stop(ev, s);
+      rc = launch_tiles(op, ta, sa, io->grid, ctx->tune.unroll, s);
     }
+    timing_stop(ev, s);
     if (rc) return rc;
   }
   io->zt = io->z[io->t & 1];
@@ -699,60 +698,63 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
   // tile plan
   {
     const int blocks = (nb + 255) / 256;
-    hipLaunchKernelGGL(plan_buckets, dim3(blocks), dim3(256), 0, s, g->row_ptr, n, nb, NB, io->plan.rb,
+    hipLaunchKernelGGL(plan_buckets, dim3(blocks), dim3(256), 0, s, g->row_ptr, n, nb, NB, io->plan.desc,
                        io->plan.nch);
     hipLaunchKernelGGL(plan_scan, dim3(1), dim3(1024), 0, s, io->plan.nch, nb, io->plan.choff, io->plan.lid,
                        io->plan.meta);
-    hipLaunchKernelGGL(plan_chunks, dim3(blocks), dim3(256), 0, s, g->row_ptr, nb, NB, io->plan.rb,
+    hipLaunchKernelGGL(plan_chunks, dim3(blocks), dim3(256), 0, s, g->row_ptr, nb, NB, io->plan.desc,
                        io->plan.nch, io->plan.choff, io->plan.lid, io->plan.chunks);
     hipLaunchKernelGGL(fill_i32, dim3((nb + 255) / 256), dim3(256), 0, s, io->lcount, (int64_t)nb, 0);
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, io->counter, (int64_t)1, 0);
     if ((rc = check_hip(hipGetLastError(), "plan kernels"))) return rc;
   }
-  io->grid = persistent_grid(ctx, nb);
+  io->grid = persistent_grid(ctx, nb, ctx->tune.blocks_per_cu);
   TileArgs ta;
   ta.row_ptr = g->row_ptr;
   ta.col = g->col_idx;
   ta.n = n;
   ta.nb = nb;
-  ta.NB = NB;
-  ta.rb = io->plan.rb;
+  ta.desc = io->plan.desc;
   ta.chunks = io->plan.chunks;
   ta.meta = io->plan.meta;
-  ta.partials = io->partials;
   ta.lcount = io->lcount;
   ta.lnorm = io->lnorm;
+  ta.lpart = io->lpart;
+  ta.xcd_order = ctx->tune.xcd_order;
+  const bool stats = io->renorm || io->sqnorm_trace || io->rayleigh_trace;
+  StatsArgs sa;
+  sa.partials = io->partials;
+  sa.lnorm = io->lnorm;
+  sa.meta = io->plan.meta;
+  sa.state = io->state;
+  sa.counter = io->counter;
+  sa.sqnorm = io->sqnorm_trace;
+  sa.rayleigh = io->rayleigh_trace;
+  sa.step = 0;
+  sa.t = io->t;
+  sa.l = io->l;
+  sa.renorm = io->renorm;
+  sa.acc_is_double = std::is_same<A, double>::value ? 1 : 0;
   // degrees (FP64), 1/(2d), d^{-1/2}, eligibility
   {
-    TileArgs td = ta;
-    td.lpart = io->lpart;  // FP64 chunk partials: sized for A = double only when vec is f64
     DegreeOp<W, A> op;
     op.val = reinterpret_cast<const W*>(g->val);
     op.deg = io->deg;
     op.hinv = reinterpret_cast<A*>(io->hinv);
     op.isq = io->isq;
     op.elig = io->elig;
-    if ((rc = launch_tiles(ctx, op, td, io->grid, s))) return rc;
+    if ((rc = launch_tiles(op, ta, sa, io->grid, 8, s))) return rc;
   }
-  ta.lpart = io->lpart;
-  const bool stats = io->renorm || io->sqnorm_trace || io->rayleigh_trace;
-  // start block
+  // start block (and the statistics of X0)
   {
     const uint64_t seed = io->seed;
-    hipLaunchKernelGGL((start_block<S, LH>), dim3(io->grid), dim3(kBlock), 0, s, n, io->l,
+    const int grid = persistent_grid(ctx, ((int64_t)n + 255) / 256, 8);
+    hipLaunchKernelGGL((start_block<S, LH>), dim3(grid), dim3(kBlock), 0, s, n, io->l,
                        (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), io->x0, io->isq, io->deg,
-                       reinterpret_cast<S*>(io->z[0]), io->partials, stats ? 1 : 0);
+                       reinterpret_cast<S*>(io->z[0]), sa, stats ? 1 : 0);
     if ((rc = check_hip(hipGetLastError(), "start_block launch"))) return rc;
-    if (stats) {
-      A* scale = reinterpret_cast<A*>(io->state + 3 * LH);
-      hipLaunchKernelGGL(finish_stats<LH>, dim3(1), dim3(kBlock), 0, s, io->partials, io->grid, io->lnorm,
-                         io->plan.meta, 0, io->t, io->l, io->renorm, io->state, io->sqnorm_trace,
-                         io->rayleigh_trace,
-                         std::is_same<A, float>::value ? reinterpret_cast<float*>(scale) : nullptr,
-                         std::is_same<A, double>::value ? reinterpret_cast<double*>(scale) : nullptr);
-      if ((rc = check_hip(hipGetLastError(), "finish_stats launch"))) return rc;
-    }
   }
-  return run_steps<S, W, LH>(ctx, io, ta, s, stats);
+  return run_steps<S, W, LH>(ctx, io, ta, sa, s, stats);
 }
 
 template <typename S, typename W>

@@ -45,11 +45,26 @@ struct LongChunk {
   int32_t row, lid, index, count, first, pad;
 };
 
+// A short tile: rows [r0, r1), G lanes per row.
+struct TileDesc {
+  int32_t r0, r1, G, pad;
+};
+
+constexpr int kMaxGrid = 4096;
+
+// Tuning knobs of the sparse product (per context).
+struct Tune {
+  int tile_nnz = 1024;     // nonzeros per short tile
+  int blocks_per_cu = 8;   // persistent blocks per CU
+  int xcd_order = 0;       // contiguous short-tile range per XCD
+  int unroll = 8;          // nonzeros in flight per lane
+};
+
 // Tile plan of one graph for the sparse product (built on the device).
 struct Plan {
   int32_t nb = 0;          // short tiles: buckets of tile_nnz nonzeros
   int32_t tile_nnz = 0;
-  int32_t* rb = nullptr;   // int32[nb+1]: first row of each bucket
+  TileDesc* desc = nullptr;  // [nb]
   int32_t* nch = nullptr;  // int32[nb]: chunks of the bucket's long last row
   int32_t* choff = nullptr;  // int32[nb+1]: exclusive scan of nch
   int32_t* lid = nullptr;    // int32[nb+1]: exclusive scan of (nch > 0)
@@ -64,6 +79,7 @@ struct Context {
   hipDeviceProp_t prop{};
   char* arena = nullptr;
   size_t arena_size = 0;
+  Tune tune;
   int32_t* error_flag = nullptr;   // device int32[4]
   int32_t* host_flag = nullptr;    // pinned host int32[4]
   // event timing of the sparse-product launches
@@ -100,7 +116,8 @@ struct EmbedIO {
   uint8_t* elig;
   void* z[2];       // S[n*LH] ping-pong
   double* partials; // [grid][2*LH]
-  double* state;    // [4][LH]: prev_sq, cum, scale, spare
+  double* state;    // [5][LH]: prev_sq, cum, scale, scale as A, spare
+  int32_t* counter; // arrival counter of the statistics epilogue
   double* lnorm;    // [max long rows][2*LH]
   void* lpart;      // A[max chunks][LH]
   int32_t* lcount;  // [max long rows]
@@ -113,6 +130,8 @@ struct EmbedIO {
 // Largest tile size whose LDS staging fits a block's budget.
 int max_tile_nnz(int l, int vec_dtype);
 size_t embed_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, int vec_dtype, int tile_nnz);
+// Tile size used when fsc_opts.tile_nnz is 0.
+int effective_tile_nnz(const Context* ctx, int tile_nnz);
 int embed_bind_workspace(Context* ctx, Arena* a, EmbedIO* io);
 // Enqueues validation (optional), degrees, start block, t steps and stats.
 int embed_run(Context* ctx, EmbedIO* io, hipStream_t s);

@@ -78,23 +78,34 @@ __global__ __launch_bounds__(kKB) void kpp_round(int64_t n, const float* __restr
     }
     const int64_t v0 = (int64_t)blockIdx.x * rpb + (int64_t)threadIdx.x * kRPT;
     double ts = 0.0;
-    for (int i = 0; i < kRPT; ++i) {
-      const int64_t v = v0 + i;
-      if (v >= n) break;
-      float dv = 0.f;
-      if (!first) {
-        float p[KD];
-        rowio<float, KD>::load(pts + v * KD, p);
+    float dv[kRPT];
+    if (!first) {
+      float p[kRPT][KD];
+      float old[kRPT];
+#pragma unroll
+      for (int i = 0; i < kRPT; ++i) {
+        const int64_t v = v0 + i;
+        if (v < n) {
+          rowio<float, KD>::load(pts + v * KD, p[i]);
+          old[i] = r == 1 ? __builtin_inff() : d2[v];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kRPT; ++i) {
         float dist = 0.f;
 #pragma unroll
         for (int q = 0; q < KD; ++q) {
-          const float e = p[q] - c[q];
+          const float e = p[i][q] - c[q];
           dist += e * e;
         }
-        dv = (r == 1) ? dist : fminf(d2[v], dist);
-        d2[v] = dv;
+        dv[i] = fminf(old[i], dist);
+        if (v0 + i < n) d2[v0 + i] = dv[i];
       }
-      ts += seed_weight(first, elig, v, dv);
+    }
+#pragma unroll
+    for (int i = 0; i < kRPT; ++i) {
+      const int64_t v = v0 + i;
+      if (v < n) ts += seed_weight(first, elig, v, first ? 0.f : dv[i]);
     }
     const double inc = block_inclusive_scan(ts, buf);
     if (threadIdx.x == kKB - 1) bsum[blockIdx.x] = inc;
@@ -262,16 +273,26 @@ __global__ __launch_bounds__(kKB) void lloyd_step(int64_t n, const float* __rest
   for (int jt = 0; jt < KT; ++jt) uacc[jt] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   const int64_t tile0 = ((int64_t)blockIdx.x * 4) * tpw;
-  for (int it = 0; it < tpw; ++it) {
-    const int64_t tile = tile0 + (int64_t)it * 4 + wave;
-    const int64_t row0 = tile * 16;
-    if (row0 >= n) break;
-    const int64_t ra = row0 + col;
-    float a0 = 0.f, a1 = 0.f;
-    if (ra < n) {
-      a0 = pts[ra * KD + kk];
-      if (KD == 8) a1 = pts[ra * KD + 4 + kk];
+  constexpr int kB = 4;  // tiles whose loads are in flight together
+  for (int it0 = 0; it0 < tpw; it0 += kB) {
+    float a0s[kB], a1s[kB];
+#pragma unroll
+    for (int bi = 0; bi < kB; ++bi) {
+      const int64_t tile = tile0 + (int64_t)(it0 + bi) * 4 + wave;
+      const int64_t ra = tile * 16 + col;
+      a0s[bi] = 0.f;
+      a1s[bi] = 0.f;
+      if (it0 + bi < tpw && ra < n) {
+        a0s[bi] = pts[ra * KD + kk];
+        if (KD == 8) a1s[bi] = pts[ra * KD + 4 + kk];
+      }
     }
+#pragma unroll
+    for (int bi = 0; bi < kB; ++bi) {
+    const int64_t tile = tile0 + (int64_t)(it0 + bi) * 4 + wave;
+    const int64_t row0 = tile * 16;
+    if (it0 + bi >= tpw || row0 >= n) break;
+    const float a0 = a0s[bi], a1 = a1s[bi];
     float bd[4];
     int bj[4];
 #pragma unroll
@@ -332,6 +353,7 @@ __global__ __launch_bounds__(kKB) void lloyd_step(int64_t n, const float* __rest
         }
       }
     }
+    }
   }
 
   if constexpr (UPDATE) {
@@ -360,12 +382,36 @@ __global__ __launch_bounds__(kKB) void lloyd_step(int64_t n, const float* __rest
     if (!is_last) return;
     __threadfence();
     __shared__ double tot[kMaxK * 9];
-    for (int o = threadIdx.x; o < O; o += kKB) {
-      double s = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) s += cpart[(int64_t)b * O + o];
-      tot[o] = s;
+    __shared__ double part[kKB];
+    // outputs o < O; each summed by S threads over interleaved block subsets,
+    // the S partial sums then combined in subset order
+    const int nblk = (int)gridDim.x;
+    for (int o0 = 0; o0 < O; o0 += kKB) {
+      const int cnt = min(kKB, O - o0);
+      const int S = kKB / cnt;
+      const int o = o0 + threadIdx.x % cnt, sidx = threadIdx.x / cnt;
+      double acc = 0.0;
+      if (sidx < S) {
+        int b = sidx;
+        for (; b + 3 * S < nblk; b += 4 * S) {
+          const double x0 = cpart[(int64_t)b * O + o], x1 = cpart[(int64_t)(b + S) * O + o];
+          const double x2 = cpart[(int64_t)(b + 2 * S) * O + o], x3 = cpart[(int64_t)(b + 3 * S) * O + o];
+          acc += x0;
+          acc += x1;
+          acc += x2;
+          acc += x3;
+        }
+        for (; b < nblk; b += S) acc += cpart[(int64_t)b * O + o];
+      }
+      part[threadIdx.x] = acc;
+      __syncthreads();
+      if (threadIdx.x < cnt) {
+        double s2 = 0.0;
+        for (int i = 0; i < S; ++i) s2 += part[i * cnt + threadIdx.x];
+        tot[o0 + threadIdx.x] = s2;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     for (int o = threadIdx.x; o < k * KD; o += kKB) {
       const int j = o / KD, d = o % KD;
       const double cnt = tot[j * (KD + 1) + KD];

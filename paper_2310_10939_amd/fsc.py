@@ -37,6 +37,11 @@ class Opts(ctypes.Structure):
                 ("rayleigh_trace", ctypes.c_void_p), ("tile_nnz", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_nnz", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("xcd_order", ctypes.c_int32), ("unroll", ctypes.c_int32)]
+
+
 _vp, _i32, _i64, _u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
 _lib.fsc_create.argtypes = [ctypes.c_int, ctypes.POINTER(_vp)]
 _lib.fsc_destroy.argtypes = [_vp]
@@ -46,13 +51,14 @@ _lib.fsc_cluster.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _i32, _u64, c
                              _vp, _vp]
 _lib.fsc_kmeans.argtypes = [_vp, _vp, _i32, _i64, _i32, _i32, _i32, _u64, _vp, _vp, _vp, _vp]
 _lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
+_lib.fsc_tuning_set.argtypes = [_vp, ctypes.POINTER(Tuning)]
 _lib.fsc_timing_enable.argtypes = [_vp, ctypes.c_int]
 _lib.fsc_timing_read.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
 _lib.fsc_last_error.restype = ctypes.c_char_p
 _lib.fsc_version.restype = ctypes.c_int
 
 EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari",
-           "fsc_timing_enable", "fsc_timing_read", "fsc_last_error", "fsc_version")
+           "fsc_tuning_set", "fsc_timing_enable", "fsc_timing_read", "fsc_last_error", "fsc_version")
 
 
 class FscError(RuntimeError):
@@ -187,6 +193,15 @@ def ari(a, b, ka, kb):
     out = torch.empty((), dtype=torch.float64, device=a.device)
     _check(_lib.fsc_ari(context(a.device.index), _ptr(a), _ptr(b), a.numel(), ka, kb, _ptr(out), _stream()))
     return out
+
+
+def tuning(tile_nnz=0, blocks_per_cu=0, xcd_order=0, unroll=0, device=None):
+    """Sets the sparse-product launch shape (0 keeps a field) and returns the
+    current one as a dict (xcd_order: 1 contiguous per XCD, 2 round robin)."""
+    t = Tuning(tile_nnz, blocks_per_cu, xcd_order, unroll)
+    _check(_lib.fsc_tuning_set(context(device), ctypes.byref(t)))
+    return {"tile_nnz": t.tile_nnz, "blocks_per_cu": t.blocks_per_cu, "xcd_order": t.xcd_order,
+            "unroll": t.unroll}
 
 
 def timing_enable(on=True, device=None):
