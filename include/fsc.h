@@ -112,10 +112,10 @@ typedef struct fsc_context fsc_context;
 /* Launch shape of the sparse product (the tile kernel of one PowerMethod
  * step), per context.  Zero fields keep the current value. */
 typedef struct {
-  int32_t tile_nnz;       /* nonzeros per short tile (default 1024) */
-  int32_t blocks_per_cu;  /* persistent blocks per compute unit (default 8) */
-  int32_t xcd_order;      /* 1: contiguous short-tile range per XCD, 2: round robin */
-  int32_t unroll;         /* nonzeros in flight per lane: 4 or 8 (default 8) */
+  int32_t tile_nnz;       /* nonzeros per short tile (default 512) */
+  int32_t blocks_per_cu;  /* persistent blocks per compute unit (default 4) */
+  int32_t xcd_order;      /* 1: contiguous short-tile range per XCD (default), 2: round robin */
+  int32_t unroll;         /* nonzeros in flight per lane: 4 (default) or 8 */
 } fsc_tuning;
 
 /* Creates a context on HIP device `device` (makes it current on the calling

@@ -54,10 +54,12 @@ constexpr int kMaxGrid = 4096;
 
 // Tuning knobs of the sparse product (per context).
 struct Tune {
-  int tile_nnz = 1024;     // nonzeros per short tile
-  int blocks_per_cu = 8;   // persistent blocks per CU
-  int xcd_order = 0;       // contiguous short-tile range per XCD
-  int unroll = 8;          // nonzeros in flight per lane
+  // defaults: the best shape of a sweep on the 1M-vertex SBM (tile 512..4096,
+  // 4 or 8 blocks per CU, both tile orders, 4 or 8 nonzeros in flight)
+  int tile_nnz = 512;      // nonzeros per short tile
+  int blocks_per_cu = 4;   // persistent blocks per CU
+  int xcd_order = 1;       // contiguous short-tile range per XCD
+  int unroll = 4;          // nonzeros in flight per lane
 };
 
 // Tile plan of one graph for the sparse product (built on the device).
