@@ -163,6 +163,26 @@ struct KmeansIO {
   int32_t* counter;        // 4
   int nblk_pp, nblk_ll;
 };
+// One k-means problem as the kernels see it.
+struct KmJob {
+  int64_t n;
+  const float* pts;        // n x KD
+  const uint8_t* elig;     // optional
+  int KD, k;
+  float* d2;
+  double* bsum;
+  int32_t* counter;
+  float* centres;          // 64 x KD
+  int32_t* chosen;
+  int32_t* labels;
+  double* cpart;
+  uint32_t k0, k1;         // Philox key (seed)
+  int nblk_pp, nblk_ll, tpw;
+};
+void kmeans_shape(int64_t n, int num_cu, int* nblk_pp, int* nblk_ll, int* tpw);
+KmJob make_job(Context* ctx, const KmeansIO* io);
+int kmeans_run_batched(Context* ctx, const KmJob* jobs_dev, const int32_t* pp_off_dev, int pp_total,
+                       const int32_t* ll_off_dev, int ll_total, int njobs, int kmax, int iters, hipStream_t s);
 size_t kmeans_workspace_bytes(int64_t n, int KD);
 int kmeans_bind_workspace(Arena* a, KmeansIO* io);
 int kmeans_run(Context* ctx, KmeansIO* io, hipStream_t s);

@@ -1,34 +1,58 @@
 // k-means on the embedding rows (Sec. 2.2): k-means++ seeding, then Lloyd.
 //
 // Points are FP32 rows of KD = 4 or 8 values (the embedding padded with
-// zeros; padding changes no distance).
+// zeros; padding changes no distance).  One k-means problem is a "job"; the
+// single-graph entry points launch one job, the batched form launches many in
+// one grid (blocks map to (job, local block) through a prefix table).
 //
 // Seeding: one launch per centre.  Each block owns a contiguous run of rows,
 // updates D2(v) = min(D2(v), ||p_v - c_{r-1}||^2) and writes the FP64 sum of
-// its weights; the last block to finish scans the block sums, locates the
-// block holding the sample u * sum(D2) and rescans that block's rows (same
-// summation order) to find the sampled row.  No host round trip.
+// its weights; the last block of the job to finish scans the block sums,
+// locates the block holding the sample u * sum(D2) and rescans that block's
+// rows (same summation order) to find the sampled row.  No host round trip.
 //
 // Lloyd: one launch per step.  Distances come from MFMA
-// (v_mfma_f32_16x16x4_f32): a 16-row tile of points times the 16-centre tiles
-// of C^T gives e.c for 16 x 16 pairs, and ||c||^2 - 2 e.c is minimised over
-// the centres with wave shuffles (ties to the lower index).  The centre
+// (v_mfma_f32_16x16x4_f32): a 16-row tile of points times a 16-centre tile of
+// C^T gives e.c for 16 x 16 pairs, and ||c||^2 - 2 e.c is minimised over the
+// centres of a 16-lane row with DPP (ties to the lower index).  The centre
 // update is a second contraction on the same unit: the one-hot matrix of the
 // labels (transposed) times the point tile, with a ones column for the
-// counts, accumulated over the wave's tiles.  Per-block FP64 partial sums are
-// combined by the last block in a fixed order, so results are deterministic.
+// counts, accumulated over the wave's tiles.  The 16 waves of a block are
+// summed in FP64 in wave order, and the per-block sums are combined by the
+// last block of the job in a fixed order, so results are deterministic.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
 
 #include <algorithm>
+#include <vector>
 
 namespace fsc {
 
-constexpr int kKB = 256;   // threads per block
-constexpr int kRPT = 8;    // rows per thread in the seeding kernel
+constexpr int kKB = 256;    // threads per seeding block
+constexpr int kRPT = 8;     // rows per thread in the seeding kernel
+constexpr int kLB = 1024;   // threads per Lloyd block (16 waves)
+constexpr int kLW = kLB / FSC_WAVE;
 constexpr int kMaxK = 64;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Shared state of a block, declared once per kernel (the segmented kernels
+// instantiate several block bodies, which must not each own LDS).
+struct KppShared {
+  double sbuf[kKB / FSC_WAVE + 1];
+  double inc[kKB];
+  double base;
+  int is_last;
+  int32_t found;
+  int32_t block;
+};
+struct LloydShared {
+  float wsum[kLW][kMaxK][9];
+  int lab[kLW][16];
+  double tot[kMaxK * 9];
+  double part[kLB];
+  int is_last;
+};
 
 // ---------------------------------------------------------------------------
 // k-means++ seeding round r (r = 0: uniform over eligible rows).
@@ -39,44 +63,29 @@ __device__ __forceinline__ double seed_weight(int first, const uint8_t* elig, in
   return first ? 1.0 : (double)d2v;
 }
 
-// Inclusive scan of one double per thread over the block (fixed order).
-__device__ __forceinline__ double block_inclusive_scan(double v, double* buf /* kKB */) {
-  buf[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = 1; off < kKB; off <<= 1) {
-    const double x = threadIdx.x >= off ? buf[threadIdx.x - off] : 0.0;
-    __syncthreads();
-    buf[threadIdx.x] += x;
-    __syncthreads();
-  }
-  const double r = buf[threadIdx.x];
-  __syncthreads();
-  return r;
-}
-
 template <int KD>
-__global__ __launch_bounds__(kKB) void kpp_round(int64_t n, const float* __restrict__ pts,
-                                                 const uint8_t* __restrict__ elig, float* __restrict__ d2,
-                                                 double* __restrict__ bsum, int32_t* __restrict__ counter,
-                                                 float* __restrict__ centres, int32_t* __restrict__ chosen,
-                                                 int r, uint32_t k0, uint32_t k1) {
-  __shared__ double buf[kKB];
-  __shared__ int is_last;
-  __shared__ int32_t found;
-  __shared__ double sh_base;
-  __shared__ int32_t sh_block;
+__device__ void kpp_block(const KmJob& J, int blk, int r, KppShared& sh) {
+  double* sbuf = sh.sbuf;
+  int& is_last = sh.is_last;
+  int32_t& found = sh.found;
+  double& sh_base = sh.base;
+  int32_t& sh_block = sh.block;
+  const int64_t n = J.n;
   const int first = (r == 0);
   const int64_t rpb = (int64_t)kKB * kRPT;
-  const int nblk = gridDim.x;
+  const int nblk = J.nblk_pp;
+  const float* pts = J.pts;
+  const uint8_t* elig = J.elig;
+  float* d2 = J.d2;
 
   // phase A: weights of this block's rows
   {
     float c[KD];
     if (!first) {
 #pragma unroll
-      for (int q = 0; q < KD; ++q) c[q] = centres[(r - 1) * KD + q];
+      for (int q = 0; q < KD; ++q) c[q] = J.centres[(r - 1) * KD + q];
     }
-    const int64_t v0 = (int64_t)blockIdx.x * rpb + (int64_t)threadIdx.x * kRPT;
+    const int64_t v0 = (int64_t)blk * rpb + (int64_t)threadIdx.x * kRPT;
     double ts = 0.0;
     float dv[kRPT];
     if (!first) {
@@ -85,9 +94,13 @@ __global__ __launch_bounds__(kKB) void kpp_round(int64_t n, const float* __restr
 #pragma unroll
       for (int i = 0; i < kRPT; ++i) {
         const int64_t v = v0 + i;
+        old[i] = __builtin_inff();
         if (v < n) {
           rowio<float, KD>::load(pts + v * KD, p[i]);
-          old[i] = r == 1 ? __builtin_inff() : d2[v];
+          if (r > 1) old[i] = d2[v];
+        } else {
+#pragma unroll
+          for (int q = 0; q < KD; ++q) p[i][q] = 0.f;
         }
       }
 #pragma unroll
@@ -107,14 +120,14 @@ __global__ __launch_bounds__(kKB) void kpp_round(int64_t n, const float* __restr
       const int64_t v = v0 + i;
       if (v < n) ts += seed_weight(first, elig, v, first ? 0.f : dv[i]);
     }
-    const double inc = block_inclusive_scan(ts, buf);
-    if (threadIdx.x == kKB - 1) bsum[blockIdx.x] = inc;
+    double total;
+    block_scan_inclusive<kKB>(ts, sbuf, &total);
+    if (threadIdx.x == 0) J.bsum[blk] = total;
   }
-  // hand-off to the last block
-  __threadfence();
-  __syncthreads();
+  // hand-off to the last block of the job
   if (threadIdx.x == 0) {
-    const int prev = atomicAdd(counter, 1);
+    __threadfence();
+    const int prev = atomicAdd(J.counter, 1);
     is_last = (prev == nblk - 1);
   }
   __syncthreads();
@@ -124,16 +137,14 @@ __global__ __launch_bounds__(kKB) void kpp_round(int64_t n, const float* __restr
   // phase B (last block): sample u * sum(weights) over the block sums, then
   // inside the block that holds it.  Both passes over the block sums use the
   // same chunked scan, so the prefixes they see are bit-identical.
-  const u32x4 rr = philox4x32_10(u32x4{first ? 0u : (uint32_t)r, 0u, 0u, first ? 1u : 2u}, k0, k1);
+  const u32x4 rr = philox4x32_10(u32x4{first ? 0u : (uint32_t)r, 0u, 0u, first ? 1u : 2u}, J.k0, J.k1);
   const double u = uniform53(rr.x, rr.y);
   double total = 0.0;
   for (int base = 0; base < nblk; base += kKB) {
     const int b = base + threadIdx.x;
-    const double inc = block_inclusive_scan(b < nblk ? bsum[b] : 0.0, buf) + total;
-    buf[threadIdx.x] = inc;
-    __syncthreads();
-    total = buf[kKB - 1];
-    __syncthreads();
+    double ct;
+    block_scan_inclusive<kKB>(b < nblk ? J.bsum[b] : 0.0, sbuf, &ct);
+    total += ct;
   }
   const double target = u * total;
   int64_t pick = -1;
@@ -146,24 +157,29 @@ __global__ __launch_bounds__(kKB) void kpp_round(int64_t n, const float* __restr
     double carry = 0.0;
     for (int base = 0; base < nblk; base += kKB) {
       const int b = base + threadIdx.x;
-      const double inc = block_inclusive_scan(b < nblk ? bsum[b] : 0.0, buf) + carry;
-      buf[threadIdx.x] = inc;
+      double ct;
+      const double inc = block_scan_inclusive<kKB>(b < nblk ? J.bsum[b] : 0.0, sbuf, &ct) + carry;
+      sh.inc[threadIdx.x] = inc;
+      if (threadIdx.x == 0) found = INT32_MAX;
       __syncthreads();
-      const double excl = threadIdx.x == 0 ? carry : buf[threadIdx.x - 1];
-      if (b < nblk && inc > target && excl <= target) {
-        sh_block = b;
-        sh_base = excl;
+      if (b < nblk && inc > target) atomicMin(&found, b);
+      __syncthreads();
+      if (found != INT32_MAX) {
+        // the prefix before the block, exactly as the scan computed it
+        if (threadIdx.x == 0) {
+          sh_block = found;
+          sh_base = found == base ? carry : sh.inc[found - base - 1];
+        }
+        __syncthreads();
+        break;
       }
-      carry = buf[kKB - 1];
-      __syncthreads();
-      if (sh_block >= 0) break;
+      carry += ct;  // equals the chunk's last inclusive value bit for bit
     }
     if (sh_block < 0 && threadIdx.x == 0) {  // rounding at the very end
       for (int b = nblk - 1; b >= 0; --b)
-        if (bsum[b] > 0.0) {
+        if (J.bsum[b] > 0.0) {
           sh_block = b;
-          double e = 0.0;
-          sh_base = e;  // the in-block search below falls back to the last row
+          sh_base = 0.0;  // the in-block search below falls back to the last row
           break;
         }
     }
@@ -180,11 +196,11 @@ __global__ __launch_bounds__(kKB) void kpp_round(int64_t n, const float* __restr
       w[i] = v < n ? seed_weight(first, elig, v, first ? 0.f : d2[v]) : 0.0;
       ts += w[i];
     }
-    const double inc = block_inclusive_scan(ts, buf);
-    buf[threadIdx.x] = inc;
+    double bt;
+    const double inc = block_scan_inclusive<kKB>(ts, sbuf, &bt);
     if (threadIdx.x == 0) found = INT32_MAX;
     __syncthreads();
-    double run = before + (threadIdx.x == 0 ? 0.0 : buf[threadIdx.x - 1]);
+    double run = before + (inc - ts);
 #pragma unroll
     for (int i = 0; i < kRPT; ++i) {
       run += w[i];
@@ -217,7 +233,7 @@ __global__ __launch_bounds__(kKB) void kpp_round(int64_t n, const float* __restr
         if (ok && pass == 0 && elig) ok = elig[v] != 0;
         if (ok)
           for (int j = 0; j < r; ++j)
-            if (chosen[j] == v) {
+            if (J.chosen[j] == v) {
               ok = false;
               break;
             }
@@ -230,22 +246,44 @@ __global__ __launch_bounds__(kKB) void kpp_round(int64_t n, const float* __restr
     pick = found;
   }
   if (threadIdx.x == 0) {
-    chosen[r] = (int32_t)pick;
-    *counter = 0;
+    J.chosen[r] = (int32_t)pick;
+    *J.counter = 0;
   }
-  if (threadIdx.x < KD) centres[r * KD + threadIdx.x] = pts[pick * KD + threadIdx.x];
+  if (threadIdx.x < KD) J.centres[r * KD + threadIdx.x] = pts[pick * KD + threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
 // Lloyd step: assignment (MFMA distances) and, with UPDATE, the centre update.
 // ---------------------------------------------------------------------------
+// DPP row operations used for the 16-lane argmin (a butterfly: quad xor 1,
+// quad xor 2, half-row mirror, row mirror).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ void argmin_step(float& d, int& j) {
+  const float od = dpp_f<CTRL>(d);
+  const int oj = dpp_i<CTRL>(j);
+  if (od < d || (od == d && oj < j)) {
+    d = od;
+    j = oj;
+  }
+}
+
 template <int KD, int KT, bool UPDATE>
-__global__ __launch_bounds__(kKB) void lloyd_step(int64_t n, const float* __restrict__ pts,
-                                                  const uint8_t* __restrict__ elig, float* __restrict__ centres,
-                                                  int k, int32_t* __restrict__ labels, double* __restrict__ cpart,
-                                                  int32_t* __restrict__ counter, int tpw) {
-  __shared__ float wsum[UPDATE ? 4 : 1][UPDATE ? KT * 16 : 1][UPDATE ? 16 : 1];
-  __shared__ int is_last;
+__device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh) {
+  auto& wsum = sh.wsum;
+  auto& lab_s = sh.lab;
+  int& is_last = sh.is_last;
+  const int64_t n = J.n;
+  const int k = J.k;
+  const float* pts = J.pts;
+  const uint8_t* elig = J.elig;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int col = lane & 15;   // output column (centre within a tile)
@@ -260,7 +298,7 @@ __global__ __launch_bounds__(kKB) void lloyd_step(int64_t n, const float* __rest
     float nrm = 0.f;
 #pragma unroll
     for (int q = 0; q < KD; ++q) {
-      c[q] = j < k ? centres[j * KD + q] : 0.f;
+      c[q] = j < k ? J.centres[j * KD + q] : 0.f;
       nrm += c[q] * c[q];
     }
     b0[jt] = c[kk];
@@ -272,123 +310,126 @@ __global__ __launch_bounds__(kKB) void lloyd_step(int64_t n, const float* __rest
 #pragma unroll
   for (int jt = 0; jt < KT; ++jt) uacc[jt] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  const int64_t tile0 = ((int64_t)blockIdx.x * 4) * tpw;
+  const int tpw = J.tpw;
+  const int64_t tile0 = ((int64_t)blk * kLW + wave) * tpw;  // this wave's first tile
   constexpr int kB = 4;  // tiles whose loads are in flight together
   for (int it0 = 0; it0 < tpw; it0 += kB) {
-    float a0s[kB], a1s[kB];
+    float a0s[kB], a1s[kB], bvs[kB][4];
 #pragma unroll
     for (int bi = 0; bi < kB; ++bi) {
-      const int64_t tile = tile0 + (int64_t)(it0 + bi) * 4 + wave;
-      const int64_t ra = tile * 16 + col;
+      const int64_t row0 = (tile0 + it0 + bi) * 16;
+      const int64_t ra = row0 + col;
       a0s[bi] = 0.f;
       a1s[bi] = 0.f;
-      if (it0 + bi < tpw && ra < n) {
+      const bool tile_ok = it0 + bi < tpw;
+      if (tile_ok && ra < n) {
         a0s[bi] = pts[ra * KD + kk];
         if (KD == 8) a1s[bi] = pts[ra * KD + 4 + kk];
       }
+      if constexpr (UPDATE) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t rb = row0 + 4 * q + kk;
+          bvs[bi][q] = (tile_ok && rb < n && col < KD) ? pts[rb * KD + col] : 0.f;
+        }
+      }
     }
 #pragma unroll
     for (int bi = 0; bi < kB; ++bi) {
-    const int64_t tile = tile0 + (int64_t)(it0 + bi) * 4 + wave;
-    const int64_t row0 = tile * 16;
-    if (it0 + bi >= tpw || row0 >= n) break;
-    const float a0 = a0s[bi], a1 = a1s[bi];
-    float bd[4];
-    int bj[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      bd[r] = __builtin_inff();
-      bj[r] = 0;
-    }
-#pragma unroll
-    for (int jt = 0; jt < KT; ++jt) {
-      floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0[jt], floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      if (KD == 8) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1[jt], acc, 0, 0, 0);
+      const int64_t row0 = (tile0 + it0 + bi) * 16;
+      if (it0 + bi >= tpw || row0 >= n) break;
+      float bd[4];
+      int bj[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float d = cn[jt] - 2.f * acc[r];
-        if (d < bd[r]) {
-          bd[r] = d;
-          bj[r] = jt * 16 + col;
+        bd[r] = __builtin_inff();
+        bj[r] = 0;
+      }
+#pragma unroll
+      for (int jt = 0; jt < KT; ++jt) {
+        floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0s[bi], b0[jt], floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        if (KD == 8) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1s[bi], b1[jt], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float d = cn[jt] - 2.f * acc[r];
+          if (d < bd[r]) {
+            bd[r] = d;
+            bj[r] = jt * 16 + col;
+          }
         }
       }
-    }
-    // argmin over the 16 lanes of the group (lexicographic on (d, j))
-#pragma unroll
-    for (int m = 1; m < 16; m <<= 1) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float od = __shfl_xor(bd[r], m, 64);
-        const int oj = __shfl_xor(bj[r], m, 64);
-        if (od < bd[r] || (od == bd[r] && oj < bj[r])) {
-          bd[r] = od;
-          bj[r] = oj;
-        }
+        argmin_step<0xB1>(bd[r], bj[r]);   // quad_perm [1,0,3,2]
+        argmin_step<0x4E>(bd[r], bj[r]);   // quad_perm [2,3,0,1]
+        argmin_step<0x141>(bd[r], bj[r]);  // row_half_mirror
+        argmin_step<0x140>(bd[r], bj[r]);  // row_mirror
       }
-    }
-    // row i = 4*kk + r of the tile is held by the lanes of group kk, reg r
-    if (col < 4) {
-      const int64_t row = row0 + 4 * kk + col;
-      const int lab = col == 0 ? bj[0] : col == 1 ? bj[1] : col == 2 ? bj[2] : bj[3];
-      if (row < n) labels[row] = lab;
-    }
-    if constexpr (UPDATE) {
-      const int sel = lane & 3;
-      const int lab_src = sel == 0 ? bj[0] : sel == 1 ? bj[1] : sel == 2 ? bj[2] : bj[3];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int lab = __shfl(lab_src, 16 * q + kk, 64);     // label of row 4q + kk
-        const int64_t rb = row0 + 4 * q + kk;
-        const bool valid = rb < n && (elig == nullptr || elig[rb] != 0);
-        const int src = (4 * q + kk) + 16 * (col & 3);
-        const float v0 = __shfl(a0, src, 64);
-        const float v1 = __shfl(a1, src, 64);
-        float bval = col < 4 ? v0 : (col < 8 && KD == 8 ? v1 : 0.f);
-        if (col == KD) bval = 1.f;
-        if (!valid) bval = 0.f;
-#pragma unroll
-        for (int jt = 0; jt < KT; ++jt) {
-          const float aval = (valid && lab == jt * 16 + col) ? 1.f : 0.f;
-          uacc[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, uacc[jt], 0, 0, 0);
-        }
+      // row 4*kk + r of the tile is held by the lanes of group kk, reg r
+      if (col < 4) {
+        const int64_t row = row0 + 4 * kk + col;
+        const int lab = col == 0 ? bj[0] : col == 1 ? bj[1] : col == 2 ? bj[2] : bj[3];
+        if (row < n) J.labels[row] = lab;
+        if constexpr (UPDATE) lab_s[wave][4 * kk + col] = lab;
       }
-    }
+      if constexpr (UPDATE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int lab = lab_s[wave][4 * q + kk];   // label of row 4q + kk
+          const int64_t rb = row0 + 4 * q + kk;
+          const bool valid = rb < n && (elig == nullptr || elig[rb] != 0);
+          float bval = bvs[bi][q];
+          if (col == KD) bval = 1.f;
+          if (!valid) bval = 0.f;
+#pragma unroll
+          for (int jt = 0; jt < KT; ++jt) {
+            const float aval = (valid && lab == jt * 16 + col) ? 1.f : 0.f;
+            uacc[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, uacc[jt], 0, 0, 0);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
     }
   }
 
   if constexpr (UPDATE) {
     // uacc[jt][r] = sum over this wave's rows for centre jt*16 + 4*kk + r, dim col
+    if (col <= KD) {
 #pragma unroll
-    for (int jt = 0; jt < KT; ++jt)
+      for (int jt = 0; jt < KT; ++jt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) wsum[wave][jt * 16 + 4 * kk + r][col] = uacc[jt][r];
+        for (int r = 0; r < 4; ++r) wsum[wave][jt * 16 + 4 * kk + r][col] = uacc[jt][r];
+    }
     __syncthreads();
     const int O = k * (KD + 1);
-    for (int o = threadIdx.x; o < O; o += kKB) {
+    double* cpart = J.cpart;
+    for (int o = threadIdx.x; o < O; o += kLB) {
       const int j = o / (KD + 1), d = o % (KD + 1);
-      const int dd = d == KD ? KD : d;  // dim KD holds the count
       double s = 0.0;
 #pragma unroll
-      for (int w = 0; w < 4; ++w) s += (double)wsum[w][j][dd];
-      cpart[(int64_t)blockIdx.x * O + o] = s;
+      for (int w = 0; w < kLW; ++w) s += (double)wsum[w][j][d];
+      cpart[(int64_t)blk * O + o] = s;
     }
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-      const int prev = atomicAdd(counter, 1);
-      is_last = (prev == (int)gridDim.x - 1);
+      __threadfence();
+      const int prev = atomicAdd(J.counter, 1);
+      is_last = (prev == J.nblk_ll - 1);
     }
     __syncthreads();
     if (!is_last) return;
     __threadfence();
-    __shared__ double tot[kMaxK * 9];
-    __shared__ double part[kKB];
+    double* tot = sh.tot;
+    double* part = sh.part;
     // outputs o < O; each summed by S threads over interleaved block subsets,
     // the S partial sums then combined in subset order
-    const int nblk = (int)gridDim.x;
-    for (int o0 = 0; o0 < O; o0 += kKB) {
-      const int cnt = min(kKB, O - o0);
-      const int S = kKB / cnt;
+    const int nblk = J.nblk_ll;
+    for (int o0 = 0; o0 < O; o0 += kLB) {
+      const int cnt = min(kLB, O - o0);
+      const int S = kLB / cnt;
       const int o = o0 + threadIdx.x % cnt, sidx = threadIdx.x / cnt;
       double acc = 0.0;
       if (sidx < S) {
@@ -412,12 +453,66 @@ __global__ __launch_bounds__(kKB) void lloyd_step(int64_t n, const float* __rest
       }
       __syncthreads();
     }
-    for (int o = threadIdx.x; o < k * KD; o += kKB) {
+    for (int o = threadIdx.x; o < k * KD; o += kLB) {
       const int j = o / KD, d = o % KD;
       const double cnt = tot[j * (KD + 1) + KD];
-      if (cnt > 0.0) centres[j * KD + d] = (float)(tot[j * (KD + 1) + d] / cnt);
+      if (cnt > 0.0) J.centres[j * KD + d] = (float)(tot[j * (KD + 1) + d] / cnt);
     }
-    if (threadIdx.x == 0) *counter = 0;
+    if (threadIdx.x == 0) *J.counter = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels: one job, or many jobs in one grid
+// ---------------------------------------------------------------------------
+template <int KD>
+__global__ __launch_bounds__(kKB) void kpp_kernel(KmJob J, int r) {
+  __shared__ KppShared sh;
+  kpp_block<KD>(J, blockIdx.x, r, sh);
+}
+
+template <int KD, int KT, bool UPDATE>
+__global__ __launch_bounds__(kLB) void lloyd_kernel(KmJob J) {
+  __shared__ LloydShared sh;
+  lloyd_block<KD, KT, UPDATE>(J, blockIdx.x, sh);
+}
+
+__device__ __forceinline__ int find_job(const int32_t* off, int njobs, int b) {
+  int lo = 0, hi = njobs;  // off[0] = 0, off[njobs] = total
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kKB) void kpp_kernel_seg(const KmJob* __restrict__ jobs, const int32_t* __restrict__ off,
+                                                      int njobs, int r) {
+  __shared__ KppShared sh;
+  const int g = find_job(off, njobs, blockIdx.x);
+  const KmJob J = jobs[g];
+  if (r >= J.k) return;
+  const int b = blockIdx.x - off[g];
+  if (J.KD == 4) kpp_block<4>(J, b, r, sh);
+  else kpp_block<8>(J, b, r, sh);
+}
+
+template <bool UPDATE>
+__global__ __launch_bounds__(kLB) void lloyd_kernel_seg(const KmJob* __restrict__ jobs,
+                                                        const int32_t* __restrict__ off, int njobs) {
+  __shared__ LloydShared sh;
+  const int g = find_job(off, njobs, blockIdx.x);
+  const KmJob J = jobs[g];
+  const int b = blockIdx.x - off[g];
+  const int KT = (J.k + 15) / 16;
+  if (J.KD == 4) {
+    if (KT == 1) lloyd_block<4, 1, UPDATE>(J, b, sh);
+    else if (KT == 2) lloyd_block<4, 2, UPDATE>(J, b, sh);
+    else lloyd_block<4, 4, UPDATE>(J, b, sh);
+  } else {
+    if (KT == 1) lloyd_block<8, 1, UPDATE>(J, b, sh);
+    else if (KT == 2) lloyd_block<8, 2, UPDATE>(J, b, sh);
+    else lloyd_block<8, 4, UPDATE>(J, b, sh);
   }
 }
 
@@ -444,24 +539,28 @@ __global__ void zero_i32(int32_t* p, int count) {
 // ===========================================================================
 // Host side
 // ===========================================================================
-static int lloyd_tpw(int64_t n, int num_cu) {
+// Lloyd launch shape for n points: tiles of 16 rows, blocks of 16 waves, about
+// one block per CU and at least one tile per wave.
+void kmeans_shape(int64_t n, int num_cu, int* nblk_pp, int* nblk_ll, int* tpw) {
+  *nblk_pp = (int)((n + kKB * kRPT - 1) / (kKB * kRPT));
   const int64_t tiles = (n + 15) / 16;
-  const int64_t target_blocks = 2LL * num_cu;
-  int64_t tpw = (tiles + 4 * target_blocks - 1) / (4 * target_blocks);
-  if (tpw < 1) tpw = 1;
-  if (tpw > 64) tpw = 64;
-  return (int)tpw;
+  int64_t blocks = std::min<int64_t>(num_cu, (tiles + kLW - 1) / kLW);
+  if (blocks < 1) blocks = 1;
+  int64_t t = (tiles + blocks * kLW - 1) / (blocks * kLW);
+  blocks = (tiles + t * kLW - 1) / (t * kLW);
+  *nblk_ll = (int)blocks;
+  *tpw = (int)t;
 }
 
 size_t kmeans_workspace_bytes(int64_t n, int KD) {
   const int64_t nblk_pp = (n + kKB * kRPT - 1) / (kKB * kRPT);
-  const int64_t nblk_ll = (n + 63) / 64 + 1;  // upper bound (tpw >= 1)
+  const int64_t nblk_ll = (n + 15) / 16 / kLW + 1;  // upper bound
   size_t b = 0;
-  b += align_up(n * 4);                              // d2
-  b += align_up(nblk_pp * 8);                        // bsum
-  b += align_up(kMaxK * KD * 4);                     // centres
+  b += align_up(n * 4);                                   // d2
+  b += align_up(nblk_pp * 8);                             // bsum
+  b += align_up(kMaxK * KD * 4);                          // centres
   b += align_up((size_t)nblk_ll * kMaxK * (KD + 1) * 8);  // cpart
-  b += align_up(kMaxK * 4) + align_up(16);           // chosen, counter
+  b += align_up(kMaxK * 4) + align_up(16);                // chosen, counter
   return b + 8 * 256;
 }
 
@@ -471,43 +570,55 @@ int kmeans_bind_workspace(Arena* a, KmeansIO* io) {
   io->d2 = a->take<float>(n);
   io->bsum = a->take<double>(io->nblk_pp);
   io->centres = a->take<float>(kMaxK * io->KD);
-  io->cpart = a->take<double>((size_t)((n + 63) / 64 + 1) * kMaxK * (io->KD + 1));
+  io->cpart = a->take<double>((size_t)((n + 15) / 16 / kLW + 1) * kMaxK * (io->KD + 1));
   io->chosen = a->take<int32_t>(kMaxK);
   io->counter = a->take<int32_t>(4);
   if (a->used > a->size) return fail(FSC_E_NOMEM, "workspace arena too small");
   return FSC_OK;
 }
 
+KmJob make_job(Context* ctx, const KmeansIO* io) {
+  KmJob J;
+  J.n = io->n;
+  J.pts = io->pts;
+  J.elig = io->elig;
+  J.KD = io->KD;
+  J.k = io->k;
+  J.d2 = io->d2;
+  J.bsum = io->bsum;
+  J.counter = io->counter;
+  J.centres = io->centres;
+  J.chosen = io->chosen;
+  J.labels = io->labels;
+  J.cpart = io->cpart;
+  J.k0 = (uint32_t)(io->seed & 0xffffffffu);
+  J.k1 = (uint32_t)(io->seed >> 32);
+  kmeans_shape(io->n, ctx->num_cu, &J.nblk_pp, &J.nblk_ll, &J.tpw);
+  return J;
+}
+
 template <int KD, int KT>
-static int lloyd_all(Context* ctx, KmeansIO* io, hipStream_t s) {
-  const int tpw = lloyd_tpw(io->n, ctx->num_cu);
-  const int64_t tiles = (io->n + 15) / 16;
-  const int nblk = (int)((tiles + 4LL * tpw - 1) / (4LL * tpw));
-  for (int it = 0; it < io->iters; ++it) {
-    hipLaunchKernelGGL((lloyd_step<KD, KT, true>), dim3(nblk), dim3(kKB), 0, s, io->n, io->pts, io->elig,
-                       io->centres, io->k, io->labels, io->cpart, io->counter, tpw);
-  }
-  hipLaunchKernelGGL((lloyd_step<KD, KT, false>), dim3(nblk), dim3(kKB), 0, s, io->n, io->pts, io->elig,
-                     io->centres, io->k, io->labels, io->cpart, io->counter, tpw);
-  return check_hip(hipGetLastError(), "lloyd_step launch");
+static int lloyd_all(const KmJob& J, int iters, hipStream_t s) {
+  for (int it = 0; it < iters; ++it)
+    hipLaunchKernelGGL((lloyd_kernel<KD, KT, true>), dim3(J.nblk_ll), dim3(kLB), 0, s, J);
+  hipLaunchKernelGGL((lloyd_kernel<KD, KT, false>), dim3(J.nblk_ll), dim3(kLB), 0, s, J);
+  return check_hip(hipGetLastError(), "lloyd_kernel launch");
 }
 
 template <int KD>
 static int kmeans_typed(Context* ctx, KmeansIO* io, hipStream_t s) {
   hipLaunchKernelGGL(zero_i32, dim3(1), dim3(64), 0, s, io->counter, 4);
-  const uint32_t k0 = (uint32_t)(io->seed & 0xffffffffu), k1 = (uint32_t)(io->seed >> 32);
-  for (int r = 0; r < io->k; ++r) {
-    hipLaunchKernelGGL(kpp_round<KD>, dim3(io->nblk_pp), dim3(kKB), 0, s, io->n, io->pts, io->elig, io->d2,
-                       io->bsum, io->counter, io->centres, io->chosen, r, k0, k1);
-  }
-  int rc = check_hip(hipGetLastError(), "kpp_round launch");
+  const KmJob J = make_job(ctx, io);
+  for (int r = 0; r < io->k; ++r)
+    hipLaunchKernelGGL(kpp_kernel<KD>, dim3(J.nblk_pp), dim3(kKB), 0, s, J, r);
+  int rc = check_hip(hipGetLastError(), "kpp_kernel launch");
   if (rc) return rc;
   const int KT = (io->k + 15) / 16;
   switch (KT) {
-    case 1: rc = lloyd_all<KD, 1>(ctx, io, s); break;
-    case 2: rc = lloyd_all<KD, 2>(ctx, io, s); break;
-    case 3: rc = lloyd_all<KD, 3>(ctx, io, s); break;
-    default: rc = lloyd_all<KD, 4>(ctx, io, s); break;
+    case 1: rc = lloyd_all<KD, 1>(J, io->iters, s); break;
+    case 2: rc = lloyd_all<KD, 2>(J, io->iters, s); break;
+    case 3: rc = lloyd_all<KD, 3>(J, io->iters, s); break;
+    default: rc = lloyd_all<KD, 4>(J, io->iters, s); break;
   }
   if (rc) return rc;
   if (io->centres_out) {
@@ -522,6 +633,16 @@ int kmeans_run(Context* ctx, KmeansIO* io, hipStream_t s) {
   if (io->KD == 4) return kmeans_typed<4>(ctx, io, s);
   if (io->KD == 8) return kmeans_typed<8>(ctx, io, s);
   return fail(FSC_E_UNSUPPORTED, "k-means point width must be 4 or 8");
+}
+
+int kmeans_run_batched(Context* ctx, const KmJob* jobs_dev, const int32_t* pp_off_dev, int pp_total,
+                       const int32_t* ll_off_dev, int ll_total, int njobs, int kmax, int iters, hipStream_t s) {
+  for (int r = 0; r < kmax; ++r)
+    hipLaunchKernelGGL(kpp_kernel_seg, dim3(pp_total), dim3(kKB), 0, s, jobs_dev, pp_off_dev, njobs, r);
+  for (int it = 0; it < iters; ++it)
+    hipLaunchKernelGGL(lloyd_kernel_seg<true>, dim3(ll_total), dim3(kLB), 0, s, jobs_dev, ll_off_dev, njobs);
+  hipLaunchKernelGGL(lloyd_kernel_seg<false>, dim3(ll_total), dim3(kLB), 0, s, jobs_dev, ll_off_dev, njobs);
+  return check_hip(hipGetLastError(), "batched k-means launch");
 }
 
 int points_from_user(Context*, const void* pts, int dtype, int64_t n, int l, int KD, float* out, hipStream_t s) {
