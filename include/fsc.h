@@ -105,6 +105,10 @@ typedef struct {
   double* rayleigh_trace;
   /* Tile size of the sparse product in nonzeros (0 = tuned default). */
   int32_t tile_nnz;
+  /* fsc_cluster_batched only: 1 = queue the launches directly instead of
+   * capturing them into a hipGraph (which is replayed while the batch stays
+   * the same). */
+  int32_t no_graph;
 } fsc_opts;
 
 typedef struct fsc_context fsc_context;
@@ -149,6 +153,32 @@ int fsc_cluster(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_
 int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, int32_t l,
                int32_t k, int32_t iters, uint64_t seed, const uint8_t* eligible,
                int32_t* labels, float* centres, void* stream);
+
+/* The batched form: FastSpectralCluster on `count` independent graphs of
+ * uneven size in one call.  `graphs`, `k`, `l` and `t` are HOST arrays of
+ * `count` entries (the CSR fields themselves are device pointers); graph g
+ * uses seed + g (so its result equals fsc_cluster on that graph with that
+ * seed, up to summation order).  Every stage runs once over the whole batch
+ * (power iterations level by level over all graphs still iterating), and
+ * the whole launch sequence is captured into a hipGraph that is replayed
+ * while the batch (pointers, sizes, parameters) is unchanged.  Outputs:
+ * `labels`, int32 concatenated per graph (graph g at offset sum_{h<g} n_h);
+ * optional `emb`, FP32 concatenated n_g x l_g blocks.  Supported: FP32
+ * vectors, FP32 or unit weights, 1 <= l <= 8, 1 <= k <= min(n, 64), no
+ * traces or re-normalisation (FSC_E_UNSUPPORTED otherwise).  The tile size of
+ * each graph comes from the autotuned entry of its mean-degree class. */
+int fsc_cluster_batched(fsc_context* ctx, int32_t count, const fsc_csr* graphs, const int32_t* k,
+                        const int32_t* l, const int32_t* t, uint64_t seed, const fsc_opts* opts,
+                        int32_t* labels, float* emb, void* stream);
+
+/* Autotuner of the sparse-product launch shape: times `steps` power steps of
+ * graph g (l columns, FP32) under each candidate shape (tile size 256..4096,
+ * 4 or 8 nonzeros in flight per lane, 4 or 8 blocks per CU, both tile orders)
+ * with HIP events, makes the fastest the context default, records its tile
+ * size for the graph's mean-degree class (used by fsc_cluster_batched) and
+ * writes it to *best (host).  Synchronises the stream. */
+int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, fsc_tuning* best,
+                 void* stream);
 
 /* Adjusted Rand index (Hubert and Arabie; the accuracy score of Sec. 4.2)
  * between labelings a (values in [0, ka)) and b (values in [0, kb)) of n

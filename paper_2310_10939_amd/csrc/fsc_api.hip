@@ -165,6 +165,8 @@ void fsc_destroy(fsc_context* ctx) {
     hipEventDestroy(e.first);
     hipEventDestroy(e.second);
   }
+  if (ctx->c.bexec) hipGraphExecDestroy(ctx->c.bexec);
+  if (ctx->c.barena) hipFree(ctx->c.barena);
   if (ctx->c.arena) hipFree(ctx->c.arena);
   if (ctx->c.error_flag) hipFree(ctx->c.error_flag);
   if (ctx->c.host_flag) hipHostFree(ctx->c.host_flag);
@@ -276,6 +278,93 @@ int fsc_ari(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int
   if ((rc = reserve_arena(&ctx->c, align_up((size_t)ka * kb * 8) + 256, &arena))) return rc;
   unsigned long long* table = arena.take<unsigned long long>((size_t)ka * kb);
   return ari_run(&ctx->c, a, b, n, ka, kb, out, table, s);
+}
+
+int fsc_cluster_batched(fsc_context* ctx, int32_t count, const fsc_csr* graphs, const int32_t* k,
+                        const int32_t* l, const int32_t* t, uint64_t seed, const fsc_opts* opts,
+                        int32_t* labels, float* emb, void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (count < 1) return fail(FSC_E_ARG, "count must be >= 1");
+  if (!graphs || !k || !l || !t || !labels) return fail(FSC_E_ARG, "null pointer");
+  const fsc_opts o = opts ? *opts : default_opts();
+  if (o.vec_dtype != FSC_F32) return fail(FSC_E_UNSUPPORTED, "the batched form computes in FP32 vectors");
+  if (o.renorm || o.sqnorm_trace || o.rayleigh_trace || o.x0 || o.validate)
+    return fail(FSC_E_UNSUPPORTED, "the batched form takes no traces, renorm, x0 or validation");
+  int rc;
+  for (int g = 0; g < count; ++g) {
+    if ((rc = check_csr(&graphs[g]))) return fail(rc, "graph " + std::to_string(g) + ": " + fsc_last_error());
+    if (graphs[g].val && graphs[g].val_dtype != FSC_F32)
+      return fail(FSC_E_UNSUPPORTED, "the batched form takes FP32 or unit weights");
+    if (l[g] < 1 || l[g] > 8) return fail(FSC_E_ARG, "l must be in [1, 8]");
+    if (t[g] < 0) return fail(FSC_E_ARG, "t must be >= 0");
+    if (k[g] < 1 || k[g] > 64 || k[g] > graphs[g].n) return fail(FSC_E_ARG, "k must be in [1, min(n, 64)]");
+  }
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  return batched_run(&ctx->c, count, graphs, k, l, t, seed, o, labels, emb, static_cast<hipStream_t>(stream));
+}
+
+int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, fsc_tuning* best, void* stream) {
+  if (!ctx || !best) return fail(FSC_E_ARG, "null pointer");
+  if (steps < 1) return fail(FSC_E_ARG, "steps must be >= 1");
+  int rc;
+  if ((rc = check_csr(g))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  const Tune saved = ctx->c.tune;
+  const bool saved_timing = ctx->c.timing;
+  fsc_opts o = default_opts();
+  if (g->val && g->val_dtype != FSC_F32) o.vec_dtype = FSC_BF16;
+  Tune bestt = saved;
+  double best_ms = 1e30;
+  const int tiles[] = {256, 512, 1024, 2048, 4096};
+  for (int tile : tiles)
+    for (int un : {4, 8})
+      for (int bpc : {4, 8})
+        for (int xo : {1, 0}) {
+          Tune tu;
+          tu.tile_nnz = tile;
+          tu.unroll = un;
+          tu.blocks_per_cu = bpc;
+          tu.xcd_order = xo;
+          ctx->c.tune = tu;
+          EmbedIO io;
+          Arena arena;
+          if ((rc = prepare_embed(&ctx->c, g, l, steps, 0, o, 0, &io, &arena))) break;
+          // discard earlier records, time this shape
+          for (auto& e : ctx->c.ev_used) ctx->c.ev_free.push_back(e);
+          ctx->c.ev_used.clear();
+          ctx->c.timing = true;
+          rc = embed_run(&ctx->c, &io, s);
+          ctx->c.timing = false;
+          if (rc) break;
+          double sum = 0.0;
+          for (auto& e : ctx->c.ev_used) {
+            if ((rc = check_hip(hipEventSynchronize(e.second), "hipEventSynchronize"))) break;
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e.first, e.second);
+            sum += ms;
+          }
+          const double avg = ctx->c.ev_used.empty() ? 1e30 : sum / ctx->c.ev_used.size();
+          for (auto& e : ctx->c.ev_used) ctx->c.ev_free.push_back(e);
+          ctx->c.ev_used.clear();
+          if (rc) break;
+          if (avg < best_ms) {
+            best_ms = avg;
+            bestt = tu;
+          }
+        }
+  ctx->c.timing = saved_timing;
+  if (rc) {
+    ctx->c.tune = saved;
+    return rc;
+  }
+  ctx->c.tune = bestt;
+  ctx->c.tile_by_class[degree_class(g->n > 0 ? (double)g->nnz / (double)g->n : 0.0)] = bestt.tile_nnz;
+  best->tile_nnz = bestt.tile_nnz;
+  best->blocks_per_cu = bestt.blocks_per_cu;
+  best->xcd_order = bestt.xcd_order ? 1 : 2;
+  best->unroll = bestt.unroll;
+  return FSC_OK;
 }
 
 int fsc_tuning_set(fsc_context* ctx, fsc_tuning* t) {

@@ -21,38 +21,17 @@
 // FP64 column norms -- are deterministic.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
+#include "fsc_tiles.hpp"
 
 #include <algorithm>
 #include <type_traits>
 
 namespace fsc {
 
-constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
 // Tile plan
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t lower_bound_i64(const int64_t* a, int64_t len, int64_t x) {
-  int64_t lo = 0, hi = len;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (a[mid] < x) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-// Lanes per row for a tile of R rows holding nz nonzeros: every row of the
-// tile in one pass of the block, and no more lanes than the mean row length.
-__device__ __forceinline__ int lanes_per_row(int64_t R, int64_t nz) {
-  if (R <= 0) return 1;
-  int g1 = 1;
-  while (g1 * 2 * R <= kBlock && g1 < FSC_WAVE) g1 *= 2;
-  const int64_t mean = nz / R;
-  int g2 = 1;
-  while (g2 < mean && g2 < FSC_WAVE) g2 *= 2;
-  return g1 < g2 ? g1 : g2;
-}
-
 __global__ void plan_buckets(const int64_t* __restrict__ row_ptr, int32_t n, int32_t nb, int32_t NB,
                              TileDesc* __restrict__ desc, int32_t* __restrict__ nch) {
   const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -226,179 +205,9 @@ __device__ __forceinline__ void stats_epilogue(const StatsArgs& sa, const double
 // ---------------------------------------------------------------------------
 // Row-reduction operators run by the tile kernel
 // ---------------------------------------------------------------------------
-template <typename W, typename A>
-__device__ __forceinline__ A load_weight(const W* val, int64_t j) {
-  if constexpr (std::is_void<W>::value) {
-    return A(1);
-  } else if constexpr (std::is_same<W, bf16_t>::value) {
-    return static_cast<A>(bf16_to_f32(nt_load(reinterpret_cast<const uint16_t*>(val) + j)));
-  } else {
-    return static_cast<A>(nt_load(val + j));
-  }
-}
-
-// Degrees: d_v = sum of the weights of row v (Sec. 2; the graph has no
-// self-loops, so this is sum_{u != v} w(u, v)), accumulated in FP64.  The
-// epilogue writes d, 1/(2d), d^{-1/2} and the k-means eligibility mask.
-template <typename W, typename HA>
-struct DegreeOp {
-  static constexpr int LH = 1;
-  static constexpr bool STATS = false;
-  using A = double;
-  struct Pre {};
-  const W* val;
-  double* deg;
-  HA* hinv;
-  double* isq;
-  uint8_t* elig;
-  __device__ __forceinline__ void init() {}
-  template <int U>
-  __device__ __forceinline__ void accumulate(const int32_t*, int64_t j0, int32_t stride, int64_t end,
-                                             double* acc) const {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t j = j0 + (int64_t)u * stride;
-      if (j < end) acc[0] += load_weight<W, double>(val, j);
-    }
-  }
-  __device__ __forceinline__ void prefetch(int32_t, Pre&) const {}
-  __device__ __forceinline__ void finish(int32_t r, const double* acc, const Pre&, double*) const {
-    const double d = acc[0];
-    deg[r] = d;
-    hinv[r] = d > 0.0 ? static_cast<HA>(0.5 / d) : HA(0);
-    isq[r] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
-    elig[r] = d > 0.0 ? 1 : 0;
-  }
-};
-
-// One PowerMethod step in z-space with a per-column scale c (1 unless the
-// iterate is re-normalised):
-//   Z'_r = c (.) (Z_r / 2 + hinv_r (A Z)_r).
-// With STATS the epilogue accumulates, per column, sum_r d_r Z'_r^2 (the
-// y-space squared norm of the stored iterate) and sum_r d_r Z_r (Z_r/2 +
-// hinv_r (A Z)_r) (y_{i-1}^T M y_{i-1}, the Rayleigh numerator).
-template <typename S, typename W, int LH_, bool STATS_>
-struct StepOp {
-  static constexpr int LH = LH_;
-  static constexpr bool STATS = STATS_;
-  using A = typename elem<S>::acc;
-  struct Pre {
-    A z[LH_];
-    A h;
-    double d;
-  };
-  const W* val;
-  const S* zin;
-  S* zout;
-  const A* hinv;
-  const double* deg;
-  const A* scale;  // per-column scale of this step (device), or null for 1
-  A cs[LH_];
-  __device__ __forceinline__ void init() {
-#pragma unroll
-    for (int q = 0; q < LH_; ++q) cs[q] = scale ? scale[q] : A(1);
-  }
-  template <int U>
-  __device__ __forceinline__ void accumulate(const int32_t* col, int64_t j0, int32_t stride, int64_t end,
-                                             A* acc) const {
-    int32_t c[U];
-    A w[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t j = j0 + (int64_t)u * stride;
-      const bool ok = j < end;
-      c[u] = ok ? nt_load(col + j) : -1;
-      w[u] = ok ? load_weight<W, A>(val, j) : A(0);
-    }
-    A z[U][LH_];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (c[u] >= 0) {
-        rowio<S, LH_>::load(zin + (int64_t)c[u] * LH_, z[u]);
-      } else {
-#pragma unroll
-        for (int q = 0; q < LH_; ++q) z[u][q] = A(0);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int q = 0; q < LH_; ++q) {
-        if constexpr (std::is_void<W>::value) acc[q] += z[u][q];
-        else acc[q] += w[u] * z[u][q];
-      }
-  }
-  __device__ __forceinline__ void prefetch(int32_t r, Pre& p) const {
-    rowio<S, LH_>::load(zin + (int64_t)r * LH_, p.z);
-    p.h = hinv[r];
-    if constexpr (STATS_) p.d = deg[r];
-  }
-  __device__ __forceinline__ void finish(int32_t r, const A* acc, const Pre& p, double* st) const {
-    A zn[LH_];
-#pragma unroll
-    for (int q = 0; q < LH_; ++q) {
-      const A m = A(0.5) * p.z[q] + p.h * acc[q];
-      zn[q] = cs[q] * m;
-      if constexpr (STATS_) {
-        // statistics of the value that is actually stored
-        zn[q] = elem<S>::to_acc(elem<S>::from_acc(zn[q]));
-        st[q] += p.d * (double)zn[q] * (double)zn[q];
-        st[LH_ + q] += p.d * (double)p.z[q] * (double)m;
-      }
-    }
-    rowio<S, LH_>::store(zout + (int64_t)r * LH_, zn);
-  }
-};
-
 // ---------------------------------------------------------------------------
 // The tile kernel
 // ---------------------------------------------------------------------------
-struct TileArgs {
-  const int64_t* row_ptr;
-  const int32_t* col;
-  int32_t n;
-  int32_t nb;
-  const TileDesc* desc;
-  const LongChunk* chunks;
-  const int32_t* meta;
-  void* lpart;        // A[chunks][LH]
-  int32_t* lcount;    // [long rows]
-  double* lnorm;      // [long rows][2*LH] (STATS)
-  int xcd_order;      // 1: each XCD takes a contiguous range of short tiles
-};
-
-template <int LH, typename A>
-__device__ __forceinline__ void group_reduce(A* acc, int G) {
-  for (int m = G >> 1; m >= 1; m >>= 1)
-#pragma unroll
-    for (int q = 0; q < LH; ++q) acc[q] += shfl_xor(acc[q], m);
-}
-
-template <int kU, class Op>
-__device__ __forceinline__ void short_tile(const Op& op, const TileArgs& ta, const TileDesc d, double* st) {
-  constexpr int LH = Op::LH;
-  using A = typename Op::A;
-  const int G = d.G;
-  const int ngroups = kBlock / G;
-  const int gid = threadIdx.x / G, lane = threadIdx.x % G;
-  for (int32_t rbase = d.r0; rbase < d.r1; rbase += ngroups) {
-    const int32_t r = rbase + gid;
-    const bool active = r < d.r1;
-    A acc[LH];
-#pragma unroll
-    for (int q = 0; q < LH; ++q) acc[q] = A(0);
-    typename Op::Pre pre;
-    if (active) {
-      if (lane == 0) op.prefetch(r, pre);
-      const int64_t a = ta.row_ptr[r], b = ta.row_ptr[r + 1];
-      for (int64_t j0 = a + lane; j0 < b; j0 += (int64_t)G * kU)
-        op.template accumulate<kU>(ta.col, j0, G, b, acc);
-    }
-    group_reduce<LH, A>(acc, G);
-    if (active && lane == 0) op.finish(r, acc, pre, st);
-  }
-}
-
 template <int kU, class Op>
 __device__ __forceinline__ void long_chunk(const Op& op, const TileArgs& ta, int32_t ci) {
   constexpr int LH = Op::LH;

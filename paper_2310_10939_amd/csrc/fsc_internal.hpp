@@ -84,6 +84,13 @@ struct Context {
   Tune tune;
   int32_t* error_flag = nullptr;   // device int32[4]
   int32_t* host_flag = nullptr;    // pinned host int32[4]
+  // tile size per degree class, filled by the autotuner (0 = use tune)
+  int tile_by_class[4] = {0, 0, 0, 0};
+  // batched form: its own workspace and the captured launch graph
+  char* barena = nullptr;
+  size_t barena_size = 0;
+  hipGraphExec_t bexec = nullptr;
+  uint64_t bkey = 0;
   // event timing of the sparse-product launches
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used;
@@ -188,6 +195,14 @@ int kmeans_bind_workspace(Arena* a, KmeansIO* io);
 int kmeans_run(Context* ctx, KmeansIO* io, hipStream_t s);
 int points_from_user(Context* ctx, const void* pts, int dtype, int64_t n, int l, int KD, float* out,
                      hipStream_t s);
+
+// ---- batched form (fsc_batched.hip) ----
+inline int degree_class(double mean_degree) {
+  return mean_degree < 12.0 ? 0 : mean_degree < 24.0 ? 1 : mean_degree < 48.0 ? 2 : 3;
+}
+int tile_for_degree(const Context* ctx, double mean_degree);
+int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, const int32_t* ls,
+                const int32_t* ts, uint64_t seed, const fsc_opts& o, int32_t* labels, float* emb, hipStream_t s);
 
 // ---- ARI (fsc_ari.hip) ----
 int ari_run(Context* ctx, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,

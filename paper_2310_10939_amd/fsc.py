@@ -34,7 +34,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("vec_dtype", ctypes.c_int32), ("kmeans_iters", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("renorm", ctypes.c_int32),
                 ("x0", ctypes.c_void_p), ("sqnorm_trace", ctypes.c_void_p),
-                ("rayleigh_trace", ctypes.c_void_p), ("tile_nnz", ctypes.c_int32)]
+                ("rayleigh_trace", ctypes.c_void_p), ("tile_nnz", ctypes.c_int32),
+                ("no_graph", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -50,6 +51,9 @@ _lib.fsc_embed.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, ctypes.PO
 _lib.fsc_cluster.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp,
                              _vp, _vp]
 _lib.fsc_kmeans.argtypes = [_vp, _vp, _i32, _i64, _i32, _i32, _i32, _u64, _vp, _vp, _vp, _vp]
+_lib.fsc_cluster_batched.argtypes = [_vp, _i32, ctypes.POINTER(Csr), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                     ctypes.POINTER(_i32), _u64, ctypes.POINTER(Opts), _vp, _vp, _vp]
+_lib.fsc_autotune.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, ctypes.POINTER(Tuning), _vp]
 _lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
 _lib.fsc_tuning_set.argtypes = [_vp, ctypes.POINTER(Tuning)]
 _lib.fsc_timing_enable.argtypes = [_vp, ctypes.c_int]
@@ -58,6 +62,7 @@ _lib.fsc_last_error.restype = ctypes.c_char_p
 _lib.fsc_version.restype = ctypes.c_int
 
 EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari",
+           "fsc_cluster_batched", "fsc_autotune",
            "fsc_tuning_set", "fsc_timing_enable", "fsc_timing_read", "fsc_last_error", "fsc_version")
 
 
@@ -172,6 +177,44 @@ def cluster(indptr, indices, data, k, l, t, seed, kmeans_iters=30, vec_dtype="f3
     if traces:
         res += [sq, ray[:t]]
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def cluster_batched(graphs, ks, ls, ts, seed, kmeans_iters=30, return_embedding=False, use_graph=True):
+    """The batched form: graphs is a list of (indptr, indices, data-or-None)
+    device tensors; graph g uses seed + g.  Returns the concatenated int32
+    labels (and the concatenated FP32 embeddings) plus the per-graph offsets."""
+    G = len(graphs)
+    dev = graphs[0][0].device
+    arr = (Csr * G)()
+    ns = []
+    for g, (ip, ix, d) in enumerate(graphs):
+        arr[g] = _csr(ip, ix, d)
+        ns.append(ip.numel() - 1)
+    off = [0]
+    eoff = [0]
+    for g in range(G):
+        off.append(off[-1] + ns[g])
+        eoff.append(eoff[-1] + ns[g] * int(ls[g]))
+    labels = torch.empty(off[-1], dtype=torch.int32, device=dev)
+    emb = torch.empty(eoff[-1], dtype=torch.float32, device=dev) if return_embedding else None
+    K = (_i32 * G)(*[int(x) for x in ks])
+    L = (_i32 * G)(*[int(x) for x in ls])
+    T = (_i32 * G)(*[int(x) for x in ts])
+    o = _opts("f32", kmeans_iters)
+    o.no_graph = 0 if use_graph else 1
+    _check(_lib.fsc_cluster_batched(context(dev.index), G, arr, K, L, T, seed, ctypes.byref(o), _ptr(labels),
+                                    _ptr(emb), _stream()))
+    return (labels, emb, off, eoff) if return_embedding else (labels, off)
+
+
+def autotune(indptr, indices, data, l, steps=5):
+    """Times the candidate launch shapes of the sparse product on this graph,
+    keeps the fastest as the context default (and for the graph's degree
+    class in the batched form) and returns it."""
+    g = _csr(indptr, indices, data)
+    t = Tuning()
+    _check(_lib.fsc_autotune(context(indptr.device.index), ctypes.byref(g), l, steps, ctypes.byref(t), _stream()))
+    return {"tile_nnz": t.tile_nnz, "blocks_per_cu": t.blocks_per_cu, "xcd_order": t.xcd_order, "unroll": t.unroll}
 
 
 def kmeans(points, k, iters, seed, eligible=None):

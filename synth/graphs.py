@@ -201,3 +201,80 @@ def knn_mixture(n_per, k, dim, seed, knn=10) -> Graph:
     g = knn_graph(X, knn)
     g.labels = lab
     return g
+
+
+# ---------------------------------------------------------------------------
+# Device-side generation for workloads too large for host numpy (torch is used
+# only as a device array library here; the graph model is the SBM above).
+# ---------------------------------------------------------------------------
+def sbm_device(n, k, deg_in, deg_out, seed, device="cuda"):
+    """SBM with k near-equal clusters and expected in/out-cluster degree
+    deg_in/deg_out, built on the device.  Edge counts per block (within) and
+    across blocks are Binomial draws from a host generator; endpoints are
+    uniform draws from a seeded device generator; self-pairs are dropped and
+    duplicate pairs merged.  Returns (indptr int64, indices int32, labels
+    int32) device tensors."""
+    import torch
+    rng = np.random.default_rng(seed)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    sizes = np.full(k, n // k, dtype=np.int64)
+    sizes[: n % k] += 1
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    size = n / k
+    p_in = min(deg_in / max(size - 1, 1), 1.0)
+    p_out = min(deg_out / max(n - size, 1), 1.0)
+    us, vs = [], []
+    for b in range(k):
+        s = int(sizes[b])
+        m = int(rng.binomial(s * (s - 1) // 2, p_in)) if s > 1 else 0
+        if m:
+            us.append(torch.randint(0, s, (m,), generator=gen, device=device) + int(starts[b]))
+            vs.append(torch.randint(0, s, (m,), generator=gen, device=device) + int(starts[b]))
+    cross_pairs = (n * n - int((sizes ** 2).sum())) // 2
+    m = int(rng.binomial(cross_pairs, p_out)) if cross_pairs > 0 else 0
+    lab = torch.repeat_interleave(torch.arange(k, device=device, dtype=torch.int64),
+                                  torch.from_numpy(sizes).to(device))
+    got = 0
+    while got < m:
+        want = int((m - got) * 1.3) + 16
+        u = torch.randint(0, n, (want,), generator=gen, device=device)
+        v = torch.randint(0, n, (want,), generator=gen, device=device)
+        keep = lab[u] != lab[v]
+        u, v = u[keep][: m - got], v[keep][: m - got]
+        us.append(u)
+        vs.append(v)
+        got += u.numel()
+    if us:
+        u = torch.cat(us)
+        v = torch.cat(vs)
+    else:
+        u = v = torch.empty(0, dtype=torch.int64, device=device)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    lo, hi = torch.minimum(u, v), torch.maximum(u, v)
+    key = torch.unique(lo * n + hi)
+    lo, hi = key // n, key % n
+    rows = torch.cat([lo, hi])
+    cols = torch.cat([hi, lo])
+    order = torch.argsort(rows * n + cols)
+    rows, cols = rows[order], cols[order]
+    indptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    indptr[1:] = torch.cumsum(torch.bincount(rows, minlength=n), 0)
+    return indptr, cols.to(torch.int32), lab.to(torch.int32)
+
+
+def batched_sbm_params(count=512, seed=0):
+    """Per-graph parameters of the batched workload: n uniform in
+    [1000, 200000], k uniform in [2, 20], expected degree uniform in [8, 64]
+    split 9:1 into in- and out-cluster degree, l = ceil(log2 k) + 1,
+    t = ceil(3 ln n), graph seed derived from (seed, index)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(1000, 200001))
+        k = int(rng.integers(2, 21))
+        d = float(rng.uniform(8.0, 64.0))
+        out.append(dict(n=n, k=k, deg_in=0.9 * d, deg_out=0.1 * d, l=int(np.ceil(np.log2(k))) + 1,
+                        t=int(np.ceil(3.0 * np.log(n))), seed=int(seed) * 1_000_003 + i))
+    return out

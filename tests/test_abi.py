@@ -21,7 +21,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ["fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari",
-                 "fsc_last_error", "fsc_version"]:
+                 "fsc_cluster_batched", "fsc_autotune", "fsc_tuning_set", "fsc_timing_enable",
+                 "fsc_timing_read", "fsc_last_error", "fsc_version"]:
         assert must in names
 
 
