@@ -166,6 +166,7 @@ void fsc_destroy(fsc_context* ctx) {
     hipEventDestroy(e.second);
   }
   if (ctx->c.bexec) hipGraphExecDestroy(ctx->c.bexec);
+  if (ctx->c.cap_stream) hipStreamDestroy(ctx->c.cap_stream);
   if (ctx->c.barena) hipFree(ctx->c.barena);
   if (ctx->c.arena) hipFree(ctx->c.arena);
   if (ctx->c.error_flag) hipFree(ctx->c.error_flag);

@@ -443,7 +443,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
 
   // ---- the launch sequence
   const int cap = ctx->num_cu * ctx->tune.blocks_per_cu;
-  auto enqueue = [&]() -> int {
+  auto enqueue = [&](hipStream_t s) -> int {
     hipLaunchKernelGGL(bfill_i32, dim3(grid_for((4 * G + 255) / 256, 1024)), dim3(256), 0, s, d_counters,
                        (int64_t)4 * G);
     hipLaunchKernelGGL(bplan_kernel, dim3(grid_for((boff[G] + 255) / 256, 8192)), dim3(256), 0, s, d_graphs, d_boff,
@@ -466,16 +466,22 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     if (r2) return r2;
     return kmeans_run_batched(ctx, d_jobs, d_ppoff, ppoff[G], d_lloff, lloff[G], G, kmax, iters, s);
   };
-  if (o.no_graph) return enqueue();
+  if (o.no_graph) return enqueue(s);
   if (ctx->bexec) {
     hipGraphExecDestroy(ctx->bexec);
     ctx->bexec = nullptr;
   }
-  if ((rc = check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")))
+  // capture on a private stream (the caller's may be the null stream, which
+  // cannot be captured); the instantiated graph is launched on the caller's
+  if (!ctx->cap_stream &&
+      (rc = check_hip(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "hipStreamCreate")))
     return rc;
-  const int erc = enqueue();
+  if ((rc = check_hip(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal),
+                      "hipStreamBeginCapture")))
+    return rc;
+  const int erc = enqueue(ctx->cap_stream);
   hipGraph_t graph = nullptr;
-  rc = check_hip(hipStreamEndCapture(s, &graph), "hipStreamEndCapture");
+  rc = check_hip(hipStreamEndCapture(ctx->cap_stream, &graph), "hipStreamEndCapture");
   if (erc) {
     if (graph) hipGraphDestroy(graph);
     return erc;

@@ -90,6 +90,7 @@ struct Context {
   char* barena = nullptr;
   size_t barena_size = 0;
   hipGraphExec_t bexec = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream used only to capture
   uint64_t bkey = 0;
   // event timing of the sparse-product launches
   bool timing = false;
