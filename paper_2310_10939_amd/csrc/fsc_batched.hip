@@ -191,7 +191,7 @@ __device__ __forceinline__ void step_tile(const BGraph& g, int32_t b, int level,
   run_tile<kU>(op, g, b, wred);
 }
 
-template <int kU>
+template <int kU, int LH>
 __global__ __launch_bounds__(kBlock) void blevel_kernel(const BGraph* __restrict__ gs,
                                                         const int32_t* __restrict__ order,
                                                         const int64_t* __restrict__ toffs, int active,
@@ -205,13 +205,8 @@ __global__ __launch_bounds__(kBlock) void blevel_kernel(const BGraph* __restrict
     while (toffs[p + 1] <= T) ++p;
     const BGraph& g = gs[order[p]];
     const int32_t b = (int32_t)(T - toffs[p]);
-    const bool unit = g.val == nullptr;
-    switch (g.LH) {
-      case 1: unit ? step_tile<kU, 1, void>(g, b, level, wred) : step_tile<kU, 1, float>(g, b, level, wred); break;
-      case 2: unit ? step_tile<kU, 2, void>(g, b, level, wred) : step_tile<kU, 2, float>(g, b, level, wred); break;
-      case 4: unit ? step_tile<kU, 4, void>(g, b, level, wred) : step_tile<kU, 4, float>(g, b, level, wred); break;
-      default: unit ? step_tile<kU, 8, void>(g, b, level, wred) : step_tile<kU, 8, float>(g, b, level, wred); break;
-    }
+    if (g.val == nullptr) step_tile<kU, LH, void>(g, b, level, wred);
+    else step_tile<kU, LH, float>(g, b, level, wred);
   }
 }
 
@@ -304,7 +299,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   auto add = [&](size_t b) { bytes += align_up(b); };
   add(sizeof(BGraph) * G);
   add(sizeof(KmJob) * G);
-  add(8 * (G + 1) * 4);             // boff, noff, toffs, toff
+  add(8 * (G + 4) * 4);             // boff, noff, toffs (per class), toff
   add(4 * G);                       // order
   add(4 * (G + 1) * 2);             // pp_off, ll_off
   add(4 * 4 * G);                   // counters
@@ -348,7 +343,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   KmJob* d_jobs = a.take<KmJob>(G);
   int64_t* d_boff = a.take<int64_t>(G + 1);
   int64_t* d_noff = a.take<int64_t>(G + 1);
-  int64_t* d_toffs = a.take<int64_t>(G + 1);
+  int64_t* d_toffs = a.take<int64_t>(G + 4);
   int64_t* d_toff = a.take<int64_t>(G + 1);
   int32_t* d_order = a.take<int32_t>(G);
   int32_t* d_ppoff = a.take<int32_t>(G + 1);
@@ -357,7 +352,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
 
   std::vector<BGraph> bg(G);
   std::vector<KmJob> jobs(G);
-  std::vector<int64_t> boff(G + 1, 0), noff(G + 1, 0), toff(G + 1, 0), toffs(G + 1, 0);
+  std::vector<int64_t> boff(G + 1, 0), noff(G + 1, 0), toff(G + 1, 0);
   std::vector<int32_t> ppoff(G + 1, 0), lloff(G + 1, 0);
   int64_t label_off = 0, emb_off = 0;
   int tmax = 0, kmax = 0;
@@ -415,16 +410,38 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     kmax = std::max(kmax, x.k);
   }
   if (a.used > a.size) return fail(FSC_E_NOMEM, "batch workspace layout overflow");
-  // graphs sorted by t (descending), so the graphs of level i are a prefix
-  std::vector<int32_t> order(G);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return h[x].t > h[y].t; });
-  for (int p = 0; p < G; ++p) toffs[p + 1] = toffs[p] + h[order[p]].nb;
-  std::vector<int> active(tmax, 0);
-  for (int i = 0; i < tmax; ++i)
-    for (int p = 0; p < G; ++p)
-      if (h[order[p]].t > i) active[i] = p + 1;
-
+  // per width class, graphs sorted by t (descending), so the graphs of a
+  // class still iterating at level i are a prefix of the class
+  const int widths[4] = {1, 2, 4, 8};
+  std::vector<int32_t> order;
+  std::vector<int64_t> toffs_all;
+  int cls_first[4], cls_count[4];
+  std::vector<std::vector<int>> active(4, std::vector<int>(tmax, 0));
+  for (int c = 0; c < 4; ++c) {
+    std::vector<int32_t> og;
+    for (int g = 0; g < G; ++g)
+      if (h[g].LH == widths[c]) og.push_back(g);
+    std::stable_sort(og.begin(), og.end(), [&](int x, int y) { return h[x].t > h[y].t; });
+    cls_first[c] = (int)order.size();
+    cls_count[c] = (int)og.size();
+    toffs_all.push_back(0);
+    for (size_t p = 0; p < og.size(); ++p) {
+      order.push_back(og[p]);
+      toffs_all.push_back(toffs_all.back() + h[og[p]].nb);
+      for (int i = 0; i < tmax; ++i)
+        if (h[og[p]].t > i) active[c][i] = (int)p + 1;
+    }
+  }
+  // toffs_all holds, per class, count+1 prefix entries starting at a 0
+  std::vector<int64_t> toffs(toffs_all);
+  std::vector<int> toffs_first(4);
+  {
+    int pos = 0;
+    for (int c = 0; c < 4; ++c) {
+      toffs_first[c] = pos;
+      pos += cls_count[c] + 1;
+    }
+  }
   // ---- upload the tables (once per batch; the graph replays reuse them)
   if ((rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
   struct Up {
@@ -435,7 +452,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   const size_t G1 = (size_t)G + 1;
   const Up ups[] = {{d_graphs, bg.data(), sizeof(BGraph) * G},  {d_jobs, jobs.data(), sizeof(KmJob) * G},
                     {d_boff, boff.data(), 8 * G1},              {d_noff, noff.data(), 8 * G1},
-                    {d_toffs, toffs.data(), 8 * G1},            {d_toff, toff.data(), 8 * G1},
+                    {d_toffs, toffs.data(), 8 * toffs.size()},  {d_toff, toff.data(), 8 * G1},
                     {d_order, order.data(), 4 * (size_t)G},     {d_ppoff, ppoff.data(), 4 * G1},
                     {d_lloff, lloff.data(), 4 * G1}};
   for (const Up& u : ups)
@@ -452,13 +469,20 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     hipLaunchKernelGGL(bstart_kernel, dim3(grid_for((noff[G] + kBlock - 1) / kBlock, 8192)), dim3(kBlock), 0, s,
                        d_graphs, d_noff, G);
     for (int i = 0; i < tmax; ++i) {
-      const int64_t tiles = toffs[active[i]];
-      if (ctx->tune.unroll == 4)
-        hipLaunchKernelGGL(blevel_kernel<4>, dim3(grid_for(tiles, cap)), dim3(kBlock), 0, s, d_graphs, d_order,
-                           d_toffs, active[i], i);
-      else
-        hipLaunchKernelGGL(blevel_kernel<8>, dim3(grid_for(tiles, cap)), dim3(kBlock), 0, s, d_graphs, d_order,
-                           d_toffs, active[i], i);
+      for (int c = 0; c < 4; ++c) {
+        const int act = active[c][i];
+        if (act == 0) continue;
+        const int64_t* tf = d_toffs + toffs_first[c];
+        const int32_t* od = d_order + cls_first[c];
+        const int64_t tiles = toffs[toffs_first[c] + act];
+        const dim3 grid(grid_for(tiles, cap));
+        switch (widths[c]) {
+          case 1: hipLaunchKernelGGL((blevel_kernel<4, 1>), grid, dim3(kBlock), 0, s, d_graphs, od, tf, act, i); break;
+          case 2: hipLaunchKernelGGL((blevel_kernel<4, 2>), grid, dim3(kBlock), 0, s, d_graphs, od, tf, act, i); break;
+          case 4: hipLaunchKernelGGL((blevel_kernel<4, 4>), grid, dim3(kBlock), 0, s, d_graphs, od, tf, act, i); break;
+          default: hipLaunchKernelGGL((blevel_kernel<4, 8>), grid, dim3(kBlock), 0, s, d_graphs, od, tf, act, i); break;
+        }
+      }
     }
     hipLaunchKernelGGL(bpoints_kernel, dim3(grid_for((noff[G] + kBlock - 1) / kBlock, 8192)), dim3(kBlock), 0, s,
                        d_graphs, d_noff, G);

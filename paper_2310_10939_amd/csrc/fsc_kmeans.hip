@@ -544,7 +544,9 @@ __global__ void zero_i32(int32_t* p, int count) {
 void kmeans_shape(int64_t n, int num_cu, int* nblk_pp, int* nblk_ll, int* tpw) {
   *nblk_pp = (int)((n + kKB * kRPT - 1) / (kKB * kRPT));
   const int64_t tiles = (n + 15) / 16;
-  int64_t blocks = std::min<int64_t>(num_cu, (tiles + kLW - 1) / kLW);
+  // at most one block per CU, and at least 8 tiles per wave so that small
+  // problems do not pay a block's fixed reduction cost many times over
+  int64_t blocks = std::min<int64_t>(num_cu, (tiles + 8 * kLW - 1) / (8 * kLW));
   if (blocks < 1) blocks = 1;
   int64_t t = (tiles + blocks * kLW - 1) / (blocks * kLW);
   blocks = (tiles + t * kLW - 1) / (t * kLW);
