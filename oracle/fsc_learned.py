@@ -1,0 +1,208 @@
+"""FP64 oracle of the learned polynomial-filter form.
+
+TEST INFRASTRUCTURE ONLY (tests, smoke and the CPU baseline use it; the
+product path never does).
+
+The paper computes M^t X0 (Algorithm 1) to project a Gaussian block onto the
+top eigenvectors of M (Sec. 3.1: x_t = sum_i a_i gamma_i^t f_i).  The learned
+form replaces gamma^t by a degree-8 polynomial p(gamma) = sum_j c_j T*_j(gamma)
+in the shifted Chebyshev basis of [0, 1] (T*_j(g) = T_j(2g - 1)), with p(1) = 1
+so the trivial eigenvector (gamma_1 = 1) keeps its weight.  A small MLP maps
+graph statistics to c_1..c_8 (c_0 = 1 - sum_j c_j since T*_j(1) = 1).  It is
+trained to make p(M) X0 match the plain PowerMethod output Y = M^t X0 in the
+relative squared error, which is quadratic in c and so needs only per-graph
+Gram statistics of the basis.  Parity of this part is pinned internally
+(closed forms, finite differences, autograd), not by the paper, which has no
+learned part.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import fsc_oracle as o
+
+DEG = 8            # polynomial degree
+NCOEF = DEG + 1    # c_0..c_8
+NFEAT = 9          # features per graph
+HID = 128          # hidden width
+LAYERS = [(NFEAT, HID), (HID, HID), (HID, HID), (HID, DEG)]
+
+
+# ---------------------------------------------------------------------------
+# Chebyshev basis and the filter
+# ---------------------------------------------------------------------------
+def cheb_basis(M, X0, deg=DEG):
+    """B_j = T*_j(M) X0 for j = 0..deg by the three-term recurrence
+    T*_0 = I, T*_1 = 2M - I, T*_{j+1} = 2 (2M - I) T*_j - T*_{j-1}."""
+    X0 = np.asarray(X0, dtype=np.float64)
+    B = [X0.copy()]
+    if deg >= 1:
+        B.append(2.0 * (M @ X0) - X0)
+    for _ in range(2, deg + 1):
+        Bj = B[-1]
+        B.append(2.0 * (2.0 * (M @ Bj) - Bj) - B[-2])
+    return B
+
+
+def full_coefficients(c_rest):
+    """(c_0, c_1..c_8) with c_0 = 1 - sum(c_1..c_8), so that p(1) = 1."""
+    c_rest = np.asarray(c_rest, dtype=np.float64)
+    return np.concatenate([[1.0 - c_rest.sum()], c_rest])
+
+
+def filter_apply(M, X0, c):
+    """S = p(M) X0 = sum_j c_j T*_j(M) X0 (c has 9 entries)."""
+    B = cheb_basis(M, X0, len(c) - 1)
+    return sum(cj * Bj for cj, Bj in zip(c, B))
+
+
+def filter_embed(n, indptr, indices, data, l, c, seed=None, x0=None):
+    """The filtered embedding D^{-1/2} p(M) X0 (the learned form's analogue of
+    the embedding handed to k-means in Algorithm 2)."""
+    if x0 is None:
+        x0 = o.gaussian_block(n, l, seed)
+    M = o.signless_laplacian(n, indptr, indices, data)
+    s = o.inv_sqrt_degree(o.degrees(n, indptr, indices, data))
+    return s[:, None] * filter_apply(M, np.asarray(x0, dtype=np.float64).reshape(n, l), c)
+
+
+# ---------------------------------------------------------------------------
+# Training statistics of one graph
+# ---------------------------------------------------------------------------
+# fixed centring/scaling of the raw statistics, so the inputs are O(1)
+FEAT_SHIFT = np.array([12.0, 2.0, 3.0, 1.0, 5.0, 0.0, 0.0, 0.0, 0.0])
+FEAT_SCALE = np.array([2.0, 1.0, 1.0, 1.0, 2.0, 1.0, 1.0, 1.0, 1.0])
+
+
+def features(n, k, d, rayleigh4):
+    """log n, log k, log mean degree, degree coefficient of variation,
+    log(max/mean degree) -- over non-isolated vertices -- and the column-mean
+    Rayleigh quotients x^T M x / x^T x of the basis vectors B_0..B_3, then
+    (raw - FEAT_SHIFT) / FEAT_SCALE."""
+    d = np.asarray(d, dtype=np.float64)
+    dd = d[d > 0]
+    mean = dd.mean()
+    cv = dd.std() / mean
+    raw = np.array([np.log(n), np.log(k), np.log(mean), cv, np.log(dd.max() / mean),
+                    *np.asarray(rayleigh4, dtype=np.float64)])
+    return (raw - FEAT_SHIFT) / FEAT_SCALE
+
+
+def graph_stats(n, indptr, indices, data, k, l, t, seed):
+    """Everything the trainer needs from one graph, all in y-space over the
+    non-isolated vertices: features, G_ij = <B_i, B_j>, h_i = <B_i, Y>,
+    yy = <Y, Y> (sums over the l columns), with Y = M^t X0 the plain
+    PowerMethod output."""
+    X0 = o.gaussian_block(n, l, seed)
+    M = o.signless_laplacian(n, indptr, indices, data)
+    d = o.degrees(n, indptr, indices, data)
+    m = d > 0
+    B = cheb_basis(M, X0)
+    Y = o.power_method(M, X0, t)
+    ray = []
+    for j in range(4):
+        Bj = B[j][m]
+        MB = (M @ B[j])[m]
+        ray.append(float(np.mean(np.einsum("ij,ij->j", Bj, MB) / np.einsum("ij,ij->j", Bj, Bj))))
+    G = np.array([[float(np.sum(B[i][m] * B[j][m])) for j in range(NCOEF)] for i in range(NCOEF)])
+    h = np.array([float(np.sum(B[i][m] * Y[m])) for i in range(NCOEF)])
+    yy = float(np.sum(Y[m] * Y[m]))
+    return features(n, k, d, ray), G, h, yy
+
+
+# ---------------------------------------------------------------------------
+# The MLP: 3 hidden layers of 128 with ReLU, 8 outputs
+# ---------------------------------------------------------------------------
+def param_count():
+    return sum(i * o_ + o_ for i, o_ in LAYERS)
+
+
+def unpack(params):
+    """Flat layout: for each layer, W (out x in, row-major) then b (out)."""
+    params = np.asarray(params, dtype=np.float64)
+    out, pos = [], 0
+    for i, o_ in LAYERS:
+        W = params[pos:pos + i * o_].reshape(o_, i)
+        pos += i * o_
+        b = params[pos:pos + o_]
+        pos += o_
+        out.append((W, b))
+    return out
+
+
+def init_params(seed):
+    """He-uniform weights, zero biases (from numpy's generator)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, o_ in LAYERS:
+        lim = np.sqrt(6.0 / i)
+        parts.append(rng.uniform(-lim, lim, size=(o_, i)).ravel())
+        parts.append(np.zeros(o_))
+    p = np.concatenate(parts)
+    # the last layer starts small, so the first filters are near p = T*_0
+    last = LAYERS[-1][0] * LAYERS[-1][1] + LAYERS[-1][1]
+    p[-last:] *= 0.01
+    return p
+
+
+def mlp_forward(params, F):
+    """F: (batch, 9) -> (c_rest (batch, 8), activations)."""
+    x = np.asarray(F, dtype=np.float64)
+    acts = [x]
+    layers = unpack(params)
+    for li, (W, b) in enumerate(layers):
+        z = x @ W.T + b
+        x = np.maximum(z, 0.0) if li < len(layers) - 1 else z
+        acts.append(x)
+    return x, acts
+
+
+def loss_terms(c_rest, G, h, yy):
+    """Per-graph relative error ||S(c) - Y||^2 / ||Y||^2 = (c^T G c - 2 h^T c
+    + yy) / yy with c = (1 - sum c_rest, c_rest), and its gradient in c_rest."""
+    c_rest = np.atleast_2d(c_rest)
+    L, dc = [], []
+    for b in range(c_rest.shape[0]):
+        c = full_coefficients(c_rest[b])
+        Gb, hb, yb = G[b], h[b], yy[b]
+        L.append((c @ Gb @ c - 2.0 * hb @ c + yb) / yb)
+        gfull = 2.0 * (Gb @ c - hb) / yb
+        dc.append(gfull[1:] - gfull[0])      # chain rule through c_0 = 1 - sum
+    return np.array(L), np.array(dc)
+
+
+def loss(params, F, G, h, yy):
+    """Mean relative error over the batch."""
+    c, _ = mlp_forward(params, F)
+    L, _ = loss_terms(c, G, h, yy)
+    return float(L.mean())
+
+
+def loss_and_grad(params, F, G, h, yy):
+    """Mean loss and its gradient in the flat parameters (hand-written
+    backward pass)."""
+    c, acts = mlp_forward(params, F)
+    L, dc = loss_terms(c, G, h, yy)
+    B = c.shape[0]
+    delta = dc / B
+    layers = unpack(params)
+    grads = []
+    for li in range(len(layers) - 1, -1, -1):
+        W, b = layers[li]
+        a_in = acts[li]
+        grads.append((delta.T @ a_in, delta.sum(axis=0)))
+        if li > 0:
+            delta = (delta @ W) * (acts[li] > 0)
+    grads.reverse()
+    flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
+    return float(L.mean()), flat
+
+
+def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba), bias-corrected; returns new
+    (params, m, v)."""
+    m = beta1 * m + (1 - beta1) * grad
+    v = beta2 * v + (1 - beta2) * grad * grad
+    mh = m / (1 - beta1 ** step)
+    vh = v / (1 - beta2 ** step)
+    return params - lr * mh / (np.sqrt(vh) + eps), m, v
