@@ -180,6 +180,83 @@ int fsc_cluster_batched(fsc_context* ctx, int32_t count, const fsc_csr* graphs, 
 int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, fsc_tuning* best,
                  void* stream);
 
+/* ---------------------------------------------------------------------------
+ * The learned polynomial-filter form.
+ *
+ * PowerMethod (Algorithm 1) applies M^t, i.e. gamma^t on each eigenvalue of
+ * M (Sec. 3.1).  This form applies p(M) = sum_{j=0..8} c_j T*_j(M) instead,
+ * with T*_j the Chebyshev polynomials shifted to [0, 1] and c_0 = 1 -
+ * sum_{j>0} c_j so that p(1) = 1 (gamma_1 = 1 keeps its weight): 8 sparse
+ * products instead of t.  A small MLP (9 inputs, 3 hidden layers of 128 with
+ * ReLU, 8 outputs c_1..c_8, FP32) maps graph statistics to the coefficients.
+ * Its inputs, in order: log n, log k, log mean degree, the degree's
+ * coefficient of variation, log(max degree / mean degree) (over non-isolated
+ * vertices), and the column-mean Rayleigh quotients <B_j, M B_j> / <B_j,B_j>
+ * of the basis blocks B_j = T*_j(M) X0, j = 0..3; each input is then centred
+ * and scaled by fixed constants (12, 2, 3, 1, 5, 0, 0, 0, 0) and
+ * (2, 1, 1, 1, 2, 1, 1, 1, 1).  Parameters: one flat FP32 array of
+ * fsc_mlp_param_count() values, for each layer W (out x in, row-major) then
+ * b.  The paper has no learned part; this is built on top of its method.
+ * ------------------------------------------------------------------------- */
+
+/* Number of MLP parameters (35336). */
+int fsc_mlp_param_count(void);
+
+/* Training statistics of one graph (FP32 vectors): features (device float[9]),
+ * and over the non-isolated vertices in y-space, summed over the l columns,
+ * gram[i*9+j] = <B_i, B_j>, h[i] = <B_i, Y>, yy[0] = <Y, Y> (device FP64
+ * [81], [9], [1]) with Y = M^t X0 the plain PowerMethod output.  The MLP's
+ * training loss of the graph is (c^T G c - 2 h^T c + yy) / yy, the relative
+ * squared error of p(M) X0 against Y. */
+int fsc_filter_stats(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t, uint64_t seed,
+                     float* features, double* gram, double* h, double* yy, void* stream);
+
+/* Coefficients c_1..c_8 (device float[count][8]) for `count` feature rows
+ * (device float[count][9]). */
+int fsc_mlp_forward(fsc_context* ctx, const float* params, int32_t count, const float* features,
+                    float* coeffs, void* stream);
+
+/* Mean training loss over `count` graphs (device double[1]) and its gradient
+ * in the parameters (device float[param_count]); inputs as produced by
+ * fsc_filter_stats, stacked. */
+int fsc_mlp_loss_grad(fsc_context* ctx, const float* params, int32_t count, const float* features,
+                      const double* gram, const double* h, const double* yy, float* grad, double* loss,
+                      void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; `step`
+ * counts from 1) on params with moment buffers m, v (device, zeroed before
+ * step 1). */
+int fsc_mlp_adam(fsc_context* ctx, float* params, float* m, float* v, const float* grad, float lr,
+                 int32_t step, void* stream);
+
+/* `steps` full-batch Adam steps of the loss above, all on the device;
+ * loss_trace (device double[steps], optional) receives the loss before each
+ * step.  m and v must be zero for a fresh start; `first_step` is the Adam step
+ * number of the first update (1 for a fresh start). */
+int fsc_mlp_train(fsc_context* ctx, float* params, float* m, float* v, int32_t count, const float* features,
+                  const double* gram, const double* h, const double* yy, int32_t steps, float lr,
+                  int32_t first_step, double* loss_trace, void* stream);
+
+/* The filtered embedding D^{-1/2} p(M) X0 with given coefficients c_1..c_8
+ * (device float[8]); emb: FP32 n x l. */
+int fsc_filter_embed(fsc_context* ctx, const fsc_csr* g, int32_t l, uint64_t seed, const float* coeffs,
+                     float* emb, void* stream);
+
+/* The learned form of FastSpectralCluster: features, then the MLP (params,
+ * device) or the given coefficients (coeffs, device float[8], overrides the
+ * MLP when non-NULL), the filtered embedding, a fallback check, and k-means
+ * (opts->kmeans_iters Lloyd steps).  Fallback: when the column-mean Rayleigh
+ * quotient <S, M S> / <S, S> of the filtered block S is below that of M^8 X0
+ * (what 8 plain PowerMethod steps give; computed from the same basis with
+ * the exact Chebyshev coefficients of gamma^8), or a coefficient is not
+ * finite, and fallback_t > 0, the plain method with t = fallback_t
+ * overwrites the labels; this check synchronises the stream.  Outputs:
+ * labels int32[n]; optional coeffs_out (device float[8]); optional
+ * *used_fallback (host). */
+int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, uint64_t seed,
+                         const float* params, const float* coeffs, int32_t fallback_t, const fsc_opts* opts,
+                         int32_t* labels, float* coeffs_out, int32_t* used_fallback, void* stream);
+
 /* Adjusted Rand index (Hubert and Arabie; the accuracy score of Sec. 4.2)
  * between labelings a (values in [0, ka)) and b (values in [0, kb)) of n
  * items, written as one FP64 value to device memory `out`.  If both labelings

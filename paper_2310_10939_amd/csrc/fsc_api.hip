@@ -114,6 +114,48 @@ static int prepare_embed(Context* ctx, const fsc_csr* g, int l, int t, uint64_t 
   return embed_bind_workspace(ctx, arena, io);
 }
 
+// Workspace of the learned form on top of the embedding's: the 8 further
+// Chebyshev basis blocks, the plain output Y, the filtered block S,
+// statistics, features, coefficients and the small MLP scratch.
+struct FilterWS {
+  float* basis[9];
+  float* Y;
+  float* S;
+  double* ray;       // [16][LH]
+  double* part;      // [2 * num_cu][55]
+  int32_t* counter;  // [4]
+  double* gram;      // [91]
+  float* feat;       // [9]
+  float* coef;       // [8]
+  int32_t* used;     // [1]
+  char* mlp;         // mlp workspace for one row
+};
+
+static size_t filter_extra_bytes(const Context* ctx, const fsc_csr* g, int l) {
+  const int LH = padded_width(l);
+  const size_t blk = align_up((size_t)g->n * LH * 4);
+  return blk * 10 + align_up(16 * 8 * 8) + align_up((size_t)2 * ctx->num_cu * 55 * 8) + 256 * 6 +
+         align_up(91 * 8) + mlp_workspace_bytes(1) + 4096;
+}
+
+static void filter_bind(Context* ctx, Arena* a, EmbedIO* io, FilterWS* w) {
+  const size_t cnt = (size_t)io->g->n * io->LH;
+  w->basis[0] = reinterpret_cast<float*>(io->z[0]);
+  for (int j = 1; j < 9; ++j) w->basis[j] = a->take<float>(cnt);
+  w->Y = a->take<float>(cnt);
+  w->S = a->take<float>(cnt);
+  w->ray = a->take<double>(16 * 8);
+  w->part = a->take<double>((size_t)2 * ctx->num_cu * 55);
+  w->counter = a->take<int32_t>(4);
+  w->gram = a->take<double>(91);
+  w->feat = a->take<float>(9);
+  w->coef = a->take<float>(8);
+  w->used = a->take<int32_t>(4);
+  w->mlp = a->take<char>(mlp_workspace_bytes(1));
+}
+
+static int zero_counter(int32_t* p, hipStream_t s) { return fill_zero_i32(p, 4, s); }
+
 }  // namespace fsc
 
 using namespace fsc;
@@ -365,6 +407,206 @@ int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, f
   best->blocks_per_cu = bestt.blocks_per_cu;
   best->xcd_order = bestt.xcd_order ? 1 : 2;
   best->unroll = bestt.unroll;
+  return FSC_OK;
+}
+
+int fsc_mlp_param_count(void) { return mlp_param_count(); }
+
+int fsc_filter_stats(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t, uint64_t seed,
+                     float* features, double* gram, double* h, double* yy, void* stream) {
+  if (!ctx || !features || !gram || !h || !yy) return fail(FSC_E_ARG, "null pointer");
+  int rc;
+  if ((rc = check_csr(g))) return rc;
+  if (k < 1 || k > g->n) return fail(FSC_E_ARG, "k must be in [1, n]");
+  if (g->val && g->val_dtype != FSC_F32) return fail(FSC_E_UNSUPPORTED, "the learned form takes FP32 or unit weights");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  const fsc_opts o = default_opts();
+  EmbedIO io;
+  Arena arena;
+  if ((rc = prepare_embed(&ctx->c, g, l, t, seed, o, filter_extra_bytes(&ctx->c, g, l), &io, &arena))) return rc;
+  FilterWS w;
+  filter_bind(&ctx->c, &arena, &io, &w);
+  if (arena.used > arena.size) return fail(FSC_E_NOMEM, "workspace layout overflow");
+  const size_t blk = (size_t)g->n * io.LH * 4;
+  // the plain output Y = M^t X0
+  if ((rc = embed_run(&ctx->c, &io, s))) return rc;
+  if ((rc = check_hip(hipMemcpyAsync(w.Y, io.zt, blk, hipMemcpyDeviceToDevice, s), "copy Y"))) return rc;
+  // the start block again (t = 0), then the Chebyshev basis
+  io.t = 0;
+  if ((rc = embed_run(&ctx->c, &io, s))) return rc;
+  if ((rc = zero_counter(w.counter, s))) return rc;
+  if ((rc = cheb_basis_run(&ctx->c, &io, w.basis, w.ray, s))) return rc;
+  if ((rc = gram_run(&ctx->c, &io, w.basis, w.Y, w.part, w.counter, w.gram, s))) return rc;
+  if ((rc = features_run(&ctx->c, &io, k, w.ray, w.part, w.counter + 1, features, s))) return rc;
+  if ((rc = check_hip(hipMemcpyAsync(gram, w.gram, 81 * 8, hipMemcpyDeviceToDevice, s), "copy gram"))) return rc;
+  if ((rc = check_hip(hipMemcpyAsync(h, w.gram + 81, 9 * 8, hipMemcpyDeviceToDevice, s), "copy h"))) return rc;
+  return check_hip(hipMemcpyAsync(yy, w.gram + 90, 8, hipMemcpyDeviceToDevice, s), "copy yy");
+}
+
+int fsc_mlp_forward(fsc_context* ctx, const float* params, int32_t count, const float* features, float* coeffs,
+                    void* stream) {
+  if (!ctx || !params || !features || !coeffs) return fail(FSC_E_ARG, "null pointer");
+  if (count < 1) return fail(FSC_E_ARG, "count must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  Arena arena;
+  if ((rc = reserve_arena(&ctx->c, mlp_workspace_bytes(count), &arena))) return rc;
+  float* acts = arena.take<float>((size_t)count * 3 * 128);
+  return mlp_forward_run(params, count, features, acts, coeffs, s);
+}
+
+int fsc_mlp_loss_grad(fsc_context* ctx, const float* params, int32_t count, const float* features,
+                      const double* gram, const double* h, const double* yy, float* grad, double* loss,
+                      void* stream) {
+  if (!ctx || !params || !features || !gram || !h || !yy || !grad || !loss) return fail(FSC_E_ARG, "null pointer");
+  if (count < 1) return fail(FSC_E_ARG, "count must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  Arena arena;
+  if ((rc = reserve_arena(&ctx->c, mlp_workspace_bytes(count), &arena))) return rc;
+  return mlp_loss_grad_run(params, count, features, gram, h, yy, grad, loss, arena.base, s);
+}
+
+int fsc_mlp_adam(fsc_context* ctx, float* params, float* m, float* v, const float* grad, float lr, int32_t step,
+                 void* stream) {
+  if (!ctx || !params || !m || !v || !grad) return fail(FSC_E_ARG, "null pointer");
+  if (step < 1) return fail(FSC_E_ARG, "step counts from 1");
+  int rc;
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  return mlp_adam_run(params, m, v, grad, lr, step, static_cast<hipStream_t>(stream));
+}
+
+int fsc_mlp_train(fsc_context* ctx, float* params, float* m, float* v, int32_t count, const float* features,
+                  const double* gram, const double* h, const double* yy, int32_t steps, float lr,
+                  int32_t first_step, double* loss_trace, void* stream) {
+  if (!ctx || !params || !m || !v || !features || !gram || !h || !yy) return fail(FSC_E_ARG, "null pointer");
+  if (count < 1 || steps < 0 || first_step < 1) return fail(FSC_E_ARG, "bad count, steps or first_step");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  const size_t np = mlp_param_count();
+  Arena arena;
+  if ((rc = reserve_arena(&ctx->c, mlp_workspace_bytes(count) + align_up(np * 4) + align_up(8) + 512, &arena)))
+    return rc;
+  char* ws = arena.take<char>(mlp_workspace_bytes(count));
+  float* grad = arena.take<float>(np);
+  double* lbuf = arena.take<double>(1);
+  for (int i = 0; i < steps; ++i) {
+    double* lo = loss_trace ? loss_trace + i : lbuf;
+    if ((rc = mlp_loss_grad_run(params, count, features, gram, h, yy, grad, lo, ws, s))) return rc;
+    if ((rc = mlp_adam_run(params, m, v, grad, lr, first_step + i, s))) return rc;
+  }
+  return FSC_OK;
+}
+
+// Shared front half of the filtered paths: degrees, start block, basis,
+// Rayleigh rows 0..7 and the features.
+static int filter_front(Context* ctx, const fsc_csr* g, int k, int l, uint64_t seed, const fsc_opts& o,
+                        size_t extra, EmbedIO* io, Arena* arena, FilterWS* w, hipStream_t s) {
+  int rc;
+  if ((rc = prepare_embed(ctx, g, l, 0, seed, o, filter_extra_bytes(ctx, g, l) + extra, io, arena))) return rc;
+  filter_bind(ctx, arena, io, w);
+  if (arena->used > arena->size) return fail(FSC_E_NOMEM, "workspace layout overflow");
+  if ((rc = embed_run(ctx, io, s))) return rc;
+  if ((rc = zero_counter(w->counter, s))) return rc;
+  if ((rc = cheb_basis_run(ctx, io, w->basis, w->ray, s))) return rc;
+  return features_run(ctx, io, k, w->ray, w->part, w->counter + 1, w->feat, s);
+}
+
+int fsc_filter_embed(fsc_context* ctx, const fsc_csr* g, int32_t l, uint64_t seed, const float* coeffs, float* emb,
+                     void* stream) {
+  if (!ctx || !coeffs || !emb) return fail(FSC_E_ARG, "null pointer");
+  int rc;
+  if ((rc = check_csr(g))) return rc;
+  if (l < 1 || l > 8) return fail(FSC_E_ARG, "l must be in [1, 8]");
+  if (g->val && g->val_dtype != FSC_F32) return fail(FSC_E_UNSUPPORTED, "the learned form takes FP32 or unit weights");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  EmbedIO io;
+  Arena arena;
+  FilterWS w;
+  if ((rc = filter_front(&ctx->c, g, 1, l, seed, default_opts(), 0, &io, &arena, &w, s))) return rc;
+  if ((rc = combine_run(&io, w.basis, coeffs, w.S, s))) return rc;
+  io.zt = w.S;
+  return embed_unpad(&ctx->c, &io, emb, s);
+}
+
+int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, uint64_t seed,
+                         const float* params, const float* coeffs, int32_t fallback_t, const fsc_opts* opts,
+                         int32_t* labels, float* coeffs_out, int32_t* used_fallback, void* stream) {
+  if (!ctx || !labels || (!params && !coeffs)) return fail(FSC_E_ARG, "null pointer");
+  int rc;
+  if ((rc = check_csr(g))) return rc;
+  if (l < 1 || l > 8) return fail(FSC_E_ARG, "l must be in [1, 8]");
+  if (k < 1 || k > 64 || k > g->n) return fail(FSC_E_ARG, "k must be in [1, min(n, 64)]");
+  if (g->val && g->val_dtype != FSC_F32) return fail(FSC_E_UNSUPPORTED, "the learned form takes FP32 or unit weights");
+  fsc_opts o = opts ? *opts : default_opts();
+  o.vec_dtype = FSC_F32;
+  o.sqnorm_trace = nullptr;
+  o.rayleigh_trace = nullptr;
+  o.renorm = 0;
+  o.x0 = nullptr;
+  const int iters = o.kmeans_iters > 0 ? o.kmeans_iters : 30;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  const int KD = kmeans_width(l);
+  const int LH = padded_width(l);
+  const bool direct = LH == KD;
+  const size_t extra = kmeans_workspace_bytes(g->n, KD) + (direct ? 0 : align_up(g->n * KD * 4)) + 1024;
+  EmbedIO io;
+  Arena arena;
+  FilterWS w;
+  if ((rc = filter_front(&ctx->c, g, k, l, seed, o, extra, &io, &arena, &w, s))) return rc;
+  float* pts = direct ? nullptr : arena.take<float>(g->n * KD);
+  KmeansIO km;
+  std::memset(&km, 0, sizeof(km));
+  km.n = g->n;
+  km.l = l;
+  km.KD = KD;
+  km.k = k;
+  km.iters = iters;
+  km.seed = seed;
+  km.labels = labels;
+  if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
+  const float* c_rest = coeffs;
+  if (!c_rest) {
+    float* acts = reinterpret_cast<float*>(w.mlp);
+    if ((rc = mlp_forward_run(params, 1, w.feat, acts, w.coef, s))) return rc;
+    c_rest = w.coef;
+  }
+  if ((rc = combine_run(&io, w.basis, c_rest, w.S, s))) return rc;
+  if ((rc = rayleigh_run(&ctx->c, &io, w.S, w.ray, 8, s))) return rc;
+  // reference: M^8 X0 (the same budget of plain steps), in the free Y buffer
+  if ((rc = combine_run(&io, w.basis, nullptr, w.Y, s))) return rc;
+  if ((rc = rayleigh_run(&ctx->c, &io, w.Y, w.ray, 9, s))) return rc;
+  if ((rc = fallback_run(&io, w.ray, 8, 9, c_rest, w.used, s))) return rc;
+  if (coeffs_out &&
+      (rc = check_hip(hipMemcpyAsync(coeffs_out, c_rest, 32, hipMemcpyDeviceToDevice, s), "copy coefficients")))
+    return rc;
+  io.zt = w.S;
+  if (direct) {
+    km.pts = w.S;
+  } else {
+    if ((rc = embed_to_points(&ctx->c, &io, pts, s))) return rc;
+    km.pts = pts;
+  }
+  km.elig = io.elig;
+  if ((rc = kmeans_run(&ctx->c, &km, s))) return rc;
+  int32_t used = 0;
+  if (fallback_t > 0 || used_fallback) {
+    if ((rc = check_hip(hipMemcpyAsync(ctx->c.host_flag, w.used, 4, hipMemcpyDeviceToHost, s), "copy flag")))
+      return rc;
+    if ((rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
+    used = ctx->c.host_flag[0];
+  }
+  if (used_fallback) *used_fallback = used;
+  if (used && fallback_t > 0) {
+    fsc_opts po = o;
+    return fsc_cluster(ctx, g, k, l, fallback_t, seed, &po, labels, nullptr, nullptr, stream);
+  }
   return FSC_OK;
 }
 

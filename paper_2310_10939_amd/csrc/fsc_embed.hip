@@ -113,180 +113,6 @@ __global__ void fill_i32(int32_t* p, int64_t count, int32_t v) {
 }
 
 // ---------------------------------------------------------------------------
-// Column statistics, finished by the last block of a step.
-// state: [0..LH) prev_sq, [LH..2LH) cum (product of applied scales),
-//        [2LH..3LH) next scale (FP64), [3LH..4LH) next scale in the step's
-//        accumulation type.
-// ---------------------------------------------------------------------------
-struct StatsArgs {
-  double* partials;     // [grid][2*LH]
-  const double* lnorm;  // [long rows][2*LH]
-  const int32_t* meta;  // meta[1] = long rows
-  double* state;
-  int32_t* counter;
-  double* sqnorm;       // optional (t+1) x l
-  double* rayleigh;     // optional t x l
-  int step, t, l, renorm;
-  int acc_is_double;
-};
-
-template <int LH>
-__device__ void stats_finish(const StatsArgs& sa, int grid) {
-  __shared__ double red[kBlock / FSC_WAVE];
-  __shared__ double tot[2 * LH];
-  const int32_t nlong = sa.step > 0 ? sa.meta[1] : 0;
-  double v[2 * LH];
-#pragma unroll
-  for (int q = 0; q < 2 * LH; ++q) v[q] = 0.0;
-  for (int32_t g = threadIdx.x; g < grid; g += kBlock)
-#pragma unroll
-    for (int q = 0; q < 2 * LH; ++q) v[q] += sa.partials[(int64_t)g * 2 * LH + q];
-  for (int32_t g = threadIdx.x; g < nlong; g += kBlock)
-#pragma unroll
-    for (int q = 0; q < 2 * LH; ++q) v[q] += sa.lnorm[(int64_t)g * 2 * LH + q];
-#pragma unroll
-  for (int q = 0; q < 2 * LH; ++q) {
-    const double s = block_sum<kBlock>(v[q], red);
-    if (threadIdx.x == 0) tot[q] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < LH) {
-    const int q = threadIdx.x;
-    double* prev_sq = sa.state;
-    double* cum = sa.state + LH;
-    double* next = sa.state + 2 * LH;
-    const double sq = tot[q];
-    if (sa.step == 0) {
-      cum[q] = 1.0;
-    } else {
-      cum[q] *= next[q];
-      if (sa.rayleigh && q < sa.l) {
-        const double den = prev_sq[q];
-        sa.rayleigh[(int64_t)(sa.step - 1) * sa.l + q] = den > 0.0 ? tot[LH + q] / den : 0.0;
-      }
-    }
-    if (sa.sqnorm && q < sa.l) sa.sqnorm[(int64_t)sa.step * sa.l + q] = sq / (cum[q] * cum[q]);
-    prev_sq[q] = sq;
-    double c = 1.0;
-    if (sa.renorm) {
-      if (sa.step + 1 < sa.t) c = sq > 0.0 ? 1.0 / sqrt(sq) : 1.0;
-      else c = 1.0 / cum[q];  // the last step restores the un-normalised scale
-    }
-    next[q] = c;
-    if (sa.acc_is_double) reinterpret_cast<double*>(sa.state + 3 * LH)[q] = c;
-    else reinterpret_cast<float*>(sa.state + 3 * LH)[q] = (float)c;
-  }
-}
-
-// Writes this block's partial statistics; the last block to arrive finishes
-// them.  Called by every thread of every block.
-template <int LH>
-__device__ __forceinline__ void stats_epilogue(const StatsArgs& sa, const double* st) {
-  __shared__ double red[kBlock / FSC_WAVE];
-  __shared__ int is_last;
-#pragma unroll
-  for (int q = 0; q < 2 * LH; ++q) {
-    const double v = block_sum<kBlock>(st[q], red);
-    if (threadIdx.x == 0) sa.partials[(int64_t)blockIdx.x * 2 * LH + q] = v;
-  }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(sa.counter, 1);
-    is_last = (prev == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (is_last) {
-    __threadfence();
-    stats_finish<LH>(sa, gridDim.x);
-    if (threadIdx.x == 0) *sa.counter = 0;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Row-reduction operators run by the tile kernel
-// ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
-// The tile kernel
-// ---------------------------------------------------------------------------
-template <int kU, class Op>
-__device__ __forceinline__ void long_chunk(const Op& op, const TileArgs& ta, int32_t ci) {
-  constexpr int LH = Op::LH;
-  using A = typename Op::A;
-  __shared__ A wred[kBlock / FSC_WAVE][LH];
-  __shared__ int is_last;
-  const LongChunk ch = ta.chunks[ci];
-  A acc[LH];
-#pragma unroll
-  for (int q = 0; q < LH; ++q) acc[q] = A(0);
-  for (int64_t j0 = ch.start + threadIdx.x; j0 < ch.end; j0 += (int64_t)kBlock * kU)
-    op.template accumulate<kU>(ta.col, j0, kBlock, ch.end, acc);
-  group_reduce<LH, A>(acc, FSC_WAVE);
-  const int w = threadIdx.x / FSC_WAVE;
-  if ((threadIdx.x & (FSC_WAVE - 1)) == 0)
-#pragma unroll
-    for (int q = 0; q < LH; ++q) wred[w][q] = acc[q];
-  __syncthreads();
-  A* lpart = reinterpret_cast<A*>(ta.lpart);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < LH; ++q) {
-      A sum = A(0);
-      for (int i = 0; i < kBlock / FSC_WAVE; ++i) sum += wred[i][q];
-      lpart[(int64_t)ci * LH + q] = sum;
-    }
-    __threadfence();
-    const int prev = atomicAdd(&ta.lcount[ch.lid], 1);
-    is_last = (prev == ch.count - 1);
-  }
-  __syncthreads();
-  if (is_last && threadIdx.x == 0) {
-    __threadfence();
-    A tot[LH];
-#pragma unroll
-    for (int q = 0; q < LH; ++q) tot[q] = A(0);
-    for (int c = 0; c < ch.count; ++c)
-#pragma unroll
-      for (int q = 0; q < LH; ++q) tot[q] += lpart[(int64_t)(ch.first + c) * LH + q];
-    double lst[2 * LH];
-#pragma unroll
-    for (int q = 0; q < 2 * LH; ++q) lst[q] = 0.0;
-    typename Op::Pre pre;
-    op.prefetch(ch.row, pre);
-    op.finish(ch.row, tot, pre, lst);
-    if constexpr (Op::STATS) {
-#pragma unroll
-      for (int q = 0; q < 2 * LH; ++q) ta.lnorm[(int64_t)ch.lid * 2 * LH + q] = lst[q];
-    }
-    ta.lcount[ch.lid] = 0;  // ready for the next step
-  }
-  __syncthreads();
-}
-
-template <int kU, class Op>
-__global__ __launch_bounds__(kBlock) void tile_kernel(Op op_in, TileArgs ta, StatsArgs sa) {
-  constexpr int LH = Op::LH;
-  Op op = op_in;
-  op.init();
-  const int32_t nb = ta.nb;
-  const int32_t ntiles = nb + ta.meta[0];
-  double st[2 * LH];
-#pragma unroll
-  for (int q = 0; q < 2 * LH; ++q) st[q] = 0.0;
-
-  if (ta.xcd_order) {
-    // blocks are dispatched to the 8 XCDs round-robin: give XCD x the
-    // contiguous range [x*nb/8, (x+1)*nb/8) of short tiles
-    const int x = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
-    const int32_t lo = (int32_t)((int64_t)nb * x / 8), hi = (int32_t)((int64_t)nb * (x + 1) / 8);
-    for (int32_t tile = lo + slot; tile < hi; tile += per) short_tile<kU>(op, ta, ta.desc[tile], st);
-  } else {
-    for (int32_t tile = blockIdx.x; tile < nb; tile += gridDim.x) short_tile<kU>(op, ta, ta.desc[tile], st);
-  }
-  for (int32_t tile = nb + blockIdx.x; tile < ntiles; tile += gridDim.x) long_chunk<kU>(op, ta, tile - nb);
-  if constexpr (Op::STATS) stats_epilogue<LH>(sa, st);
-}
-
-// ---------------------------------------------------------------------------
 // Start block: Z0 = D^{-1/2} X0, X0 Gaussian (Algorithm 2) or given.
 // ---------------------------------------------------------------------------
 template <typename S, int LH>
@@ -378,6 +204,11 @@ __global__ void validate_kernel(const int64_t* __restrict__ row_ptr, const int32
 // ===========================================================================
 // Host side
 // ===========================================================================
+int fill_zero_i32(int32_t* p, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(fill_i32, dim3((int)std::min<int64_t>((count + 255) / 256, 1024)), dim3(256), 0, s, p, count, 0);
+  return check_hip(hipGetLastError(), "fill launch");
+}
+
 int effective_tile_nnz(const Context* ctx, int tile_nnz) { return tile_nnz > 0 ? tile_nnz : ctx->tune.tile_nnz; }
 
 int max_tile_nnz(int, int) { return 1 << 20; }

@@ -140,6 +140,8 @@ struct EmbedIO {
 // Largest tile size whose LDS staging fits a block's budget.
 int max_tile_nnz(int l, int vec_dtype);
 size_t embed_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, int vec_dtype, int tile_nnz);
+// Zeroes count int32 values with a kernel (capturable, unlike a memset node).
+int fill_zero_i32(int32_t* p, int64_t count, hipStream_t s);
 // Tile size used when fsc_opts.tile_nnz is 0.
 int effective_tile_nnz(const Context* ctx, int tile_nnz);
 int embed_bind_workspace(Context* ctx, Arena* a, EmbedIO* io);
@@ -204,6 +206,23 @@ inline int degree_class(double mean_degree) {
 int tile_for_degree(const Context* ctx, double mean_degree);
 int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, const int32_t* ls,
                 const int32_t* ts, uint64_t seed, const fsc_opts& o, int32_t* labels, float* emb, hipStream_t s);
+
+// ---- learned form (fsc_filter.hip, fsc_mlp.hip) ----
+int cheb_basis_run(Context* ctx, EmbedIO* io, float* const* basis, double* ray, hipStream_t s);
+int rayleigh_run(Context* ctx, EmbedIO* io, const float* x, double* ray, int row, hipStream_t s);
+int gram_run(Context* ctx, const EmbedIO* io, float* const* basis, const float* Y, double* partials,
+             int32_t* counter, double* out, hipStream_t s);
+int features_run(Context* ctx, const EmbedIO* io, int k, const double* ray, double* partials, int32_t* counter,
+                 float* feat, hipStream_t s);
+int combine_run(const EmbedIO* io, float* const* basis, const float* c_rest, float* S, hipStream_t s);
+int fallback_run(const EmbedIO* io, const double* ray, int row_f, int row_ref, const float* c_rest, int32_t* used,
+                 hipStream_t s);
+int mlp_param_count();
+size_t mlp_workspace_bytes(int B);
+int mlp_forward_run(const float* params, int B, const float* feats, float* acts, float* c_out, hipStream_t s);
+int mlp_loss_grad_run(const float* params, int B, const float* feats, const double* G, const double* h,
+                      const double* yy, float* grad, double* loss_out, char* ws, hipStream_t s);
+int mlp_adam_run(float* p, float* m, float* v, const float* g, float lr, int step, hipStream_t s);
 
 // ---- ARI (fsc_ari.hip) ----
 int ari_run(Context* ctx, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,

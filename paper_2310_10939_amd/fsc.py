@@ -54,6 +54,16 @@ _lib.fsc_kmeans.argtypes = [_vp, _vp, _i32, _i64, _i32, _i32, _i32, _u64, _vp, _
 _lib.fsc_cluster_batched.argtypes = [_vp, _i32, ctypes.POINTER(Csr), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                      ctypes.POINTER(_i32), _u64, ctypes.POINTER(Opts), _vp, _vp, _vp]
 _lib.fsc_autotune.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, ctypes.POINTER(Tuning), _vp]
+_f = ctypes.c_float
+_lib.fsc_mlp_param_count.restype = ctypes.c_int
+_lib.fsc_filter_stats.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _i32, _u64, _vp, _vp, _vp, _vp, _vp]
+_lib.fsc_mlp_forward.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
+_lib.fsc_mlp_loss_grad.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.fsc_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, _f, _i32, _vp]
+_lib.fsc_mlp_train.argtypes = [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i32, _f, _i32, _vp, _vp]
+_lib.fsc_filter_embed.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _u64, _vp, _vp, _vp]
+_lib.fsc_cluster_filtered.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, _vp, _vp, _i32,
+                                      ctypes.POINTER(Opts), _vp, _vp, ctypes.POINTER(_i32), _vp]
 _lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
 _lib.fsc_tuning_set.argtypes = [_vp, ctypes.POINTER(Tuning)]
 _lib.fsc_timing_enable.argtypes = [_vp, ctypes.c_int]
@@ -62,7 +72,9 @@ _lib.fsc_last_error.restype = ctypes.c_char_p
 _lib.fsc_version.restype = ctypes.c_int
 
 EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari",
-           "fsc_cluster_batched", "fsc_autotune",
+           "fsc_cluster_batched", "fsc_autotune", "fsc_mlp_param_count", "fsc_filter_stats",
+           "fsc_mlp_forward", "fsc_mlp_loss_grad", "fsc_mlp_adam", "fsc_mlp_train", "fsc_filter_embed",
+           "fsc_cluster_filtered",
            "fsc_tuning_set", "fsc_timing_enable", "fsc_timing_read", "fsc_last_error", "fsc_version")
 
 
@@ -215,6 +227,81 @@ def autotune(indptr, indices, data, l, steps=5):
     t = Tuning()
     _check(_lib.fsc_autotune(context(indptr.device.index), ctypes.byref(g), l, steps, ctypes.byref(t), _stream()))
     return {"tile_nnz": t.tile_nnz, "blocks_per_cu": t.blocks_per_cu, "xcd_order": t.xcd_order, "unroll": t.unroll}
+
+
+# ---------------------------------------------------------------------------
+# The learned polynomial-filter form
+# ---------------------------------------------------------------------------
+def mlp_param_count():
+    return _lib.fsc_mlp_param_count()
+
+
+def filter_stats(indptr, indices, data, k, l, t, seed):
+    """Training statistics of one graph: (features float32[9], G float64[9,9],
+    h float64[9], yy float64[1]) device tensors."""
+    dev = indptr.device
+    feat = torch.empty(9, dtype=torch.float32, device=dev)
+    G = torch.empty((9, 9), dtype=torch.float64, device=dev)
+    h = torch.empty(9, dtype=torch.float64, device=dev)
+    yy = torch.empty(1, dtype=torch.float64, device=dev)
+    g = _csr(indptr, indices, data)
+    _check(_lib.fsc_filter_stats(context(dev.index), ctypes.byref(g), k, l, t, seed, _ptr(feat), _ptr(G), _ptr(h),
+                                 _ptr(yy), _stream()))
+    return feat, G, h, yy
+
+
+def mlp_forward(params, feats):
+    feats = feats.contiguous()
+    out = torch.empty((feats.shape[0], 8), dtype=torch.float32, device=feats.device)
+    _check(_lib.fsc_mlp_forward(context(feats.device.index), _ptr(params), feats.shape[0], _ptr(feats), _ptr(out),
+                                _stream()))
+    return out
+
+
+def mlp_loss_grad(params, feats, G, h, yy):
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float64, device=params.device)
+    _check(_lib.fsc_mlp_loss_grad(context(params.device.index), _ptr(params), feats.shape[0], _ptr(feats), _ptr(G),
+                                  _ptr(h), _ptr(yy), _ptr(grad), _ptr(loss), _stream()))
+    return loss, grad
+
+
+def mlp_adam(params, m, v, grad, lr, step):
+    _check(_lib.fsc_mlp_adam(context(params.device.index), _ptr(params), _ptr(m), _ptr(v), _ptr(grad), lr, step,
+                             _stream()))
+
+
+def mlp_train(params, m, v, feats, G, h, yy, steps, lr, first_step=1):
+    """`steps` full-batch Adam steps on the device; returns the loss trace."""
+    trace = torch.empty(steps, dtype=torch.float64, device=params.device)
+    _check(_lib.fsc_mlp_train(context(params.device.index), _ptr(params), _ptr(m), _ptr(v), feats.shape[0],
+                              _ptr(feats), _ptr(G), _ptr(h), _ptr(yy), steps, lr, first_step, _ptr(trace), _stream()))
+    return trace
+
+
+def filter_embed(indptr, indices, data, l, seed, coeffs):
+    """D^{-1/2} p(M) X0 with coefficients c_1..c_8 (float32[8] device)."""
+    n = indptr.numel() - 1
+    out = torch.empty((n, l), dtype=torch.float32, device=indptr.device)
+    g = _csr(indptr, indices, data)
+    _check(_lib.fsc_filter_embed(context(indptr.device.index), ctypes.byref(g), l, seed, _ptr(coeffs), _ptr(out),
+                                 _stream()))
+    return out
+
+
+def cluster_filtered(indptr, indices, data, k, l, seed, params=None, coeffs=None, fallback_t=0, kmeans_iters=30):
+    """The learned form: returns (labels, coefficients used, used_fallback)."""
+    n = indptr.numel() - 1
+    dev = indptr.device
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    cout = torch.empty(8, dtype=torch.float32, device=dev)
+    used = _i32(0)
+    g = _csr(indptr, indices, data)
+    o = _opts("f32", kmeans_iters)
+    _check(_lib.fsc_cluster_filtered(context(dev.index), ctypes.byref(g), k, l, seed, _ptr(params), _ptr(coeffs),
+                                     fallback_t, ctypes.byref(o), _ptr(labels), _ptr(cout), ctypes.byref(used),
+                                     _stream()))
+    return labels, cout, bool(used.value)
 
 
 def kmeans(points, k, iters, seed, eligible=None):

@@ -278,3 +278,89 @@ def batched_sbm_params(count=512, seed=0):
         out.append(dict(n=n, k=k, deg_in=0.9 * d, deg_out=0.1 * d, l=int(np.ceil(np.log2(k))) + 1,
                         t=int(np.ceil(3.0 * np.log(n))), seed=int(seed) * 1_000_003 + i))
     return out
+
+
+def _csr_device(n, u, v):
+    """Symmetric CSR (dropping self-pairs, merging duplicates) from device
+    endpoint arrays."""
+    import torch
+    keep = u != v
+    u, v = u[keep], v[keep]
+    lo, hi = torch.minimum(u, v), torch.maximum(u, v)
+    key = torch.unique(lo * n + hi)
+    lo, hi = key // n, key % n
+    rows = torch.cat([lo, hi])
+    cols = torch.cat([hi, lo])
+    order = torch.argsort(rows * n + cols)
+    rows, cols = rows[order], cols[order]
+    indptr = torch.zeros(n + 1, dtype=torch.int64, device=u.device)
+    indptr[1:] = torch.cumsum(torch.bincount(rows, minlength=n), 0)
+    return indptr, cols.to(torch.int32)
+
+
+def dcsbm_device(n, k, mean_deg, seed, alpha=2.5, in_frac=0.9, device="cuda"):
+    """Degree-corrected SBM (Karrer and Newman style): k near-equal contiguous
+    clusters; degree propensities theta ~ Pareto with density exponent alpha
+    and mean mean_deg (x_min = mean_deg (alpha-2)/(alpha-1)); a fraction
+    in_frac of each vertex's expected degree inside its cluster.  Edges are
+    Chung-Lu draws: endpoints chosen with probability proportional to theta
+    (inside a cluster for the in-cluster edges, across clusters for the
+    rest); self-pairs dropped, duplicates merged.  Returns (indptr, indices,
+    labels) device tensors."""
+    import torch
+    rng = np.random.default_rng(seed)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    xmin = mean_deg * (alpha - 2.0) / (alpha - 1.0)
+    u01 = torch.rand(n, generator=gen, device=device, dtype=torch.float64)
+    theta = xmin * (1.0 - u01) ** (-1.0 / (alpha - 1.0))
+    sizes = np.full(k, n // k, dtype=np.int64)
+    sizes[: n % k] += 1
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    lab = torch.repeat_interleave(torch.arange(k, device=device, dtype=torch.int64),
+                                  torch.from_numpy(sizes).to(device))
+    cum = torch.cumsum(theta, 0)
+    cum0 = torch.cat([torch.zeros(1, dtype=torch.float64, device=device), cum])
+    Theta = (cum0[torch.from_numpy(starts[1:]).to(device)] - cum0[torch.from_numpy(starts[:-1]).to(device)]).cpu().numpy()
+    total = float(cum0[-1])
+    # in-cluster edges: per cluster a Poisson count, endpoints theta-weighted
+    m_in = rng.poisson(in_frac * Theta / 2.0)
+    blk = torch.repeat_interleave(torch.arange(k, device=device), torch.from_numpy(m_in).to(device))
+    lo_c = cum0[torch.from_numpy(starts[:-1]).to(device)][blk]
+    span = (cum0[torch.from_numpy(starts[1:]).to(device)] - cum0[torch.from_numpy(starts[:-1]).to(device)])[blk]
+    def draw_in():
+        r = lo_c + torch.rand(blk.numel(), generator=gen, device=device, dtype=torch.float64) * span
+        return torch.clamp(torch.searchsorted(cum, r, right=True), max=n - 1)
+    u_in, v_in = draw_in(), draw_in()
+    # cross-cluster edges: theta-weighted endpoints, same-cluster pairs redrawn
+    m_out = int(rng.poisson((1.0 - in_frac) * total / 2.0))
+    us, vs, got = [], [], 0
+    while got < m_out:
+        want = int((m_out - got) * 1.3) + 16
+        a = torch.clamp(torch.searchsorted(cum, torch.rand(want, generator=gen, device=device,
+                                                             dtype=torch.float64) * total, right=True), max=n - 1)
+        b = torch.clamp(torch.searchsorted(cum, torch.rand(want, generator=gen, device=device,
+                                                             dtype=torch.float64) * total, right=True), max=n - 1)
+        keep = lab[a] != lab[b]
+        a, b = a[keep][: m_out - got], b[keep][: m_out - got]
+        us.append(a)
+        vs.append(b)
+        got += a.numel()
+    u = torch.cat([u_in] + us)
+    v = torch.cat([v_in] + vs)
+    indptr, indices = _csr_device(n, u, v)
+    return indptr, indices, lab.to(torch.int32)
+
+
+def learned_params(count, seed0):
+    """Per-graph parameters of the learned-form workload: n uniform in
+    [100000, 2000000], k uniform in [2, 50], mean degree 20, l = ceil(log2 k)
+    + 1, t = ceil(3 ln n), graph seed seed0 + index."""
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(100_000, 2_000_001))
+        k = int(rng.integers(2, 51))
+        out.append(dict(n=n, k=k, l=int(np.ceil(np.log2(k))) + 1, t=int(np.ceil(3.0 * np.log(n))),
+                        seed=seed0 + i))
+    return out

@@ -1,0 +1,135 @@
+"""The learned polynomial-filter form on the GPU against its FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+from numpy.polynomial import chebyshev as C
+
+import synth
+from oracle import fsc_learned as fl
+from oracle import fsc_oracle as o
+from tests.gpu_util import col_rel_err, host_weights, say, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _gamma8():
+    return C.poly2cheb(np.polynomial.polynomial.polypow([0.5, 0.5], 8))
+
+
+@pytest.mark.parametrize("l", [2, 4, 7])
+def test_filter_embed_matches_oracle(gpu_lib, l):
+    g = synth.random_weighted(2500, 10000, seed=l, hubs=2, hub_degree=900, isolated=4)
+    ip, ix, d = to_device(g, "f32")
+    c_rest = np.random.default_rng(l).standard_normal(8) * 0.3
+    cg = torch.tensor(c_rest, dtype=torch.float32, device="cuda")
+    E = gpu_lib.filter_embed(ip, ix, d, l, 5, cg).cpu().numpy()
+    want = fl.filter_embed(g.n, g.indptr, g.indices, host_weights(d), l,
+                           fl.full_coefficients(cg.cpu().double().numpy()), seed=5)
+    err = col_rel_err(E, want)
+    say("filter l", l, "rel err", err)
+    assert err <= 1e-5
+
+
+def test_gamma8_coefficients_equal_eight_power_steps(gpu_lib):
+    g = synth.sbm(3000, 6, 0.02, 0.001, seed=2)
+    ip, ix, _ = to_device(g)
+    c = _gamma8()
+    E8 = gpu_lib.filter_embed(ip, ix, None, 4, 3, torch.tensor(c[1:], dtype=torch.float32, device="cuda")).cpu().numpy()
+    P8 = gpu_lib.embed(ip, ix, None, 4, 8, 3).cpu().numpy()
+    assert col_rel_err(E8, P8) <= 1e-5
+
+
+def test_filter_stats_match_oracle(gpu_lib):
+    g = synth.sbm(2000, 4, 0.03, 0.002, seed=3)
+    ip, ix, _ = to_device(g)
+    feat, G, h, yy = gpu_lib.filter_stats(ip, ix, None, 4, 3, 17, 9)
+    F_o, G_o, h_o, yy_o = fl.graph_stats(g.n, g.indptr, g.indices, None, 4, 3, 17, 9)
+    feat, G, h, yy = feat.cpu().numpy(), G.cpu().numpy(), h.cpu().numpy(), float(yy.cpu()[0])
+    say("features gpu", np.round(feat, 5), "oracle", np.round(F_o, 5))
+    assert np.abs(feat - F_o).max() <= 1e-4
+    assert np.abs(G - G_o).max() <= 1e-5 * np.abs(G_o).max()
+    assert np.abs(h - h_o).max() <= 1e-5 * max(np.abs(h_o).max(), 1e-30)
+    assert abs(yy - yy_o) <= 1e-5 * yy_o
+
+
+def _batch(B=6, seed=0):
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((B, 9)).astype(np.float32)
+    G, h, yy = [], [], []
+    for _ in range(B):
+        A = rng.standard_normal((9, 12))
+        G.append(A @ A.T)
+        h.append(rng.standard_normal(9))
+        yy.append(float(rng.uniform(1, 3)))
+    return F, np.array(G), np.array(h), np.array(yy)
+
+
+def _dev(*xs):
+    return [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in xs]
+
+
+def test_mlp_forward_grad_adam_match_oracle(gpu_lib):
+    assert gpu_lib.mlp_param_count() == fl.param_count()
+    p = fl.init_params(1)
+    p[-1000:] *= 50.0
+    F, G, h, yy = _batch()
+    pg, Fg, Gg, hg, yg = _dev(p.astype(np.float32), F, G, h, yy)
+    c = gpu_lib.mlp_forward(pg, Fg).cpu().numpy()
+    c_o, _ = fl.mlp_forward(p.astype(np.float32).astype(np.float64), F.astype(np.float64))
+    assert np.abs(c - c_o).max() <= 1e-5 * max(1.0, np.abs(c_o).max())
+    loss, grad = gpu_lib.mlp_loss_grad(pg, Fg, Gg, hg, yg)
+    L_o, g_o = fl.loss_and_grad(p.astype(np.float32).astype(np.float64), F.astype(np.float64), G, h, yy)
+    grad = grad.cpu().numpy()
+    say("loss gpu", float(loss.cpu()[0]), "oracle", L_o)
+    assert abs(float(loss.cpu()[0]) - L_o) <= 1e-5 * abs(L_o)
+    assert np.linalg.norm(grad - g_o) <= 1e-4 * np.linalg.norm(g_o)
+    m = torch.zeros_like(pg)
+    v = torch.zeros_like(pg)
+    gpu_lib.mlp_adam(pg, m, v, torch.from_numpy(g_o.astype(np.float32)).cuda(), 1e-3, 1)
+    p1, _, _ = fl.adam_step(p.astype(np.float32).astype(np.float64), g_o.astype(np.float32).astype(np.float64),
+                            np.zeros_like(p), np.zeros_like(p), 1, 1e-3)
+    assert np.abs(pg.cpu().numpy() - p1).max() <= 1e-6
+
+
+def test_mlp_training_descends(gpu_lib):
+    F, G, h, yy = _batch(16, seed=4)
+    p = fl.init_params(2).astype(np.float32)
+    pg, Fg, Gg, hg, yg = _dev(p, F, G, h, yy)
+    m = torch.zeros_like(pg)
+    v = torch.zeros_like(pg)
+    trace = gpu_lib.mlp_train(pg, m, v, Fg, Gg, hg, yg, 200, 1e-3).cpu().numpy()
+    say("train loss", trace[0], "->", trace[-1])
+    assert trace[-1] < 0.5 * trace[0]
+    # the same steps in FP64 on the CPU stay close for the first steps
+    po = p.astype(np.float64)
+    mo = np.zeros_like(po)
+    vo = np.zeros_like(po)
+    for step in range(1, 6):
+        L, gr = fl.loss_and_grad(po, F.astype(np.float64), G, h, yy)
+        assert abs(L - trace[step - 1]) <= 1e-4 * abs(L)
+        po, mo, vo = fl.adam_step(po, gr, mo, vo, step, 1e-3)
+
+
+def test_cluster_filtered_and_fallback(gpu_lib):
+    g = synth.sbm(4000, 5, 0.02, 0.0005, seed=6)
+    ip, ix, _ = to_device(g)
+    c8 = torch.tensor(_gamma8()[1:], dtype=torch.float32, device="cuda")
+    lab, cout, used = gpu_lib.cluster_filtered(ip, ix, None, 5, 4, 7, coeffs=c8, kmeans_iters=20)
+    plain8 = gpu_lib.cluster(ip, ix, None, 5, 4, 8, 7, kmeans_iters=20)
+    assert torch.equal(cout, c8)
+    assert o.ari(lab.cpu().numpy(), plain8.cpu().numpy()) >= 0.99
+    # identity filter (p = T*_0): no amplification, the check falls back to
+    # the plain method with t = 30
+    zero = torch.zeros(8, dtype=torch.float32, device="cuda")
+    lab, _, used = gpu_lib.cluster_filtered(ip, ix, None, 5, 4, 7, coeffs=zero, fallback_t=30, kmeans_iters=20)
+    assert used
+    plain = gpu_lib.cluster(ip, ix, None, 5, 4, 30, 7, kmeans_iters=20)
+    assert torch.equal(lab, plain)
+    # through the MLP (untrained parameters still give valid labels)
+    params = torch.from_numpy(fl.init_params(0).astype(np.float32)).cuda()
+    lab, cout, used = gpu_lib.cluster_filtered(ip, ix, None, 5, 4, 7, params=params, kmeans_iters=20)
+    lab = lab.cpu().numpy()
+    assert lab.min() >= 0 and lab.max() < 5
+    c_o, _ = fl.mlp_forward(fl.init_params(0).astype(np.float32).astype(np.float64),
+                            gpu_lib.filter_stats(ip, ix, None, 5, 4, 1, 7)[0].cpu().numpy()[None].astype(np.float64))
+    assert np.abs(cout.cpu().numpy() - c_o[0]).max() <= 1e-4
