@@ -94,15 +94,29 @@ def train(F, G, H, YY, steps, lr, seed, log=print):
     return p, torch.cat(traces)
 
 
+def ls_optimum(G, h, yy):
+    """Per-graph least-squares coefficients c_1..c_8 of the training loss
+    (the best any degree-8 filter with p(1) = 1 can do on that graph) and the
+    loss there.  Host FP64 solve of the 8 x 8 normal equations."""
+    A = np.eye(9)[:, 1:] - np.outer(np.eye(9)[0], np.ones(8))   # c = e0 + A c_rest
+    e0 = np.eye(9)[0]
+    Gr = A.T @ G @ A
+    rhs = A.T @ (h - G @ e0)
+    c = np.linalg.solve(Gr, rhs)
+    full = e0 + A @ c
+    return c, float((full @ G @ full - 2 * h @ full + yy) / yy)
+
+
 def heldout_loss(p, F, G, H, YY):
     from . import fsc
     loss, _ = fsc.mlp_loss_grad(p, F, G, H, YY)
     return float(loss[0])
 
 
-def evaluate(p, specs, device, log=print):
+def evaluate(p, specs, device, stats=None, log=print):
     """ARI against the plain method (and the planted clusters) of the learned
-    filter and of the fixed gamma^8 filter, with wall times."""
+    filter, of the fixed gamma^8 filter and of the per-graph least-squares
+    optimum, with wall times."""
     import torch
     import synth
     from . import fsc
@@ -123,7 +137,14 @@ def evaluate(p, specs, device, log=print):
         fixed, _, _ = fsc.cluster_filtered(ip, ix, None, k, l, seed, coeffs=g8)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        rows.append(dict(n=s["n"], k=k, l=l, t=t,
+        extra = {}
+        if stats is not None:
+            Gi, hi, yi = (x[i].double().cpu().numpy() for x in stats)
+            c_ls, loss_ls = ls_optimum(Gi, hi, float(yi))
+            best, _, _ = fsc.cluster_filtered(ip, ix, None, k, l, seed,
+                                              coeffs=torch.tensor(c_ls, dtype=torch.float32, device=device))
+            extra = dict(loss_ls_optimum=loss_ls, ari_lsopt_vs_plain=float(fsc.ari(best, plain, k, k)))
+        rows.append(dict(n=s["n"], k=k, l=l, t=t, **extra,
                          ari_learned_vs_plain=float(fsc.ari(learned, plain, k, k)),
                          ari_fixed8_vs_plain=float(fsc.ari(fixed, plain, k, k)),
                          ari_plain_vs_planted=float(fsc.ari(plain, lab, k, k)),
@@ -137,7 +158,7 @@ def evaluate(p, specs, device, log=print):
 
 
 def summarize(rows):
-    keys = [k for k in rows[0] if k.startswith("ari") or k.startswith("ms")]
+    keys = [k for k in rows[0] if k.startswith("ari") or k.startswith("ms") or k.startswith("loss")]
     out = {k: float(np.mean([r[k] for r in rows])) for k in keys}
     out["fallback_rate"] = float(np.mean([r["fallback"] for r in rows]))
     out["graphs"] = len(rows)
@@ -148,7 +169,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--graphs", type=int, default=2000)
     ap.add_argument("--heldout", type=int, default=100)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=PARAMS_FILE)
@@ -168,7 +189,7 @@ def main(argv=None):
     Ft, Gt, Ht, YYt = collect(test_specs, dev, log)
     p, trace = train(F, G, H, YY, args.steps, args.lr, args.seed, log)
     np.save(args.out, p.cpu().numpy())
-    rows = evaluate(p, test_specs, dev, log)
+    rows = evaluate(p, test_specs, dev, (Gt, Ht, YYt), log)
     report = {"train_graphs": args.graphs, "heldout_graphs": args.heldout, "steps": args.steps,
               "train_loss_first": float(trace[0]), "train_loss_last": float(trace[-1]),
               "heldout_loss": heldout_loss(p, Ft, Gt, Ht, YYt),
