@@ -245,17 +245,21 @@ int fsc_filter_embed(fsc_context* ctx, const fsc_csr* g, int32_t l, uint64_t see
 /* The learned form of FastSpectralCluster: features, then the MLP (params,
  * device) or the given coefficients (coeffs, device float[8], overrides the
  * MLP when non-NULL), the filtered embedding, a fallback check, and k-means
- * (opts->kmeans_iters Lloyd steps).  Fallback: when the column-mean Rayleigh
- * quotient <S, M S> / <S, S> of the filtered block S is below that of M^8 X0
- * (what 8 plain PowerMethod steps give; computed from the same basis with
- * the exact Chebyshev coefficients of gamma^8), or a coefficient is not
- * finite, and fallback_t > 0, the plain method with t = fallback_t
- * overwrites the labels; this check synchronises the stream.  Outputs:
- * labels int32[n]; optional coeffs_out (device float[8]); optional
- * *used_fallback (host). */
+ * (opts->kmeans_iters Lloyd steps).  Fallback check: (a) the column-mean
+ * Rayleigh quotient <S, M S> / <S, S> of the filtered block S is below that
+ * of M^8 X0 (what 8 plain PowerMethod steps give; computed from the same
+ * basis with the exact Chebyshev coefficients of gamma^8), or (b) the
+ * normalised k-means cost of the filtered embedding (within-cluster over
+ * total variance) exceeds 0.5, or (c) a coefficient is not finite.  When it
+ * fires and fallback_t > 0, the plain method with t = fallback_t overwrites
+ * the labels; reading the check synchronises the stream.  Outputs: labels
+ * int32[n]; optional coeffs_out (device float[8]); optional diagnostics
+ * (device double[4]: the two Rayleigh quotients, the normalised cost, the
+ * flag); optional *used_fallback (host). */
 int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, uint64_t seed,
                          const float* params, const float* coeffs, int32_t fallback_t, const fsc_opts* opts,
-                         int32_t* labels, float* coeffs_out, int32_t* used_fallback, void* stream);
+                         int32_t* labels, float* coeffs_out, double* diagnostics, int32_t* used_fallback,
+                         void* stream);
 
 /* Adjusted Rand index (Hubert and Arabie; the accuracy score of Sec. 4.2)
  * between labelings a (values in [0, ka)) and b (values in [0, kb)) of n

@@ -156,6 +156,10 @@ static void filter_bind(Context* ctx, Arena* a, EmbedIO* io, FilterWS* w) {
 
 static int zero_counter(int32_t* p, hipStream_t s) { return fill_zero_i32(p, 4, s); }
 
+// Largest normalised k-means cost (within-cluster over total variance of the
+// embedding rows) accepted from the filtered embedding before falling back.
+constexpr double kFilterMaxCost = 0.5;
+
 }  // namespace fsc
 
 using namespace fsc;
@@ -536,7 +540,8 @@ int fsc_filter_embed(fsc_context* ctx, const fsc_csr* g, int32_t l, uint64_t see
 
 int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, uint64_t seed,
                          const float* params, const float* coeffs, int32_t fallback_t, const fsc_opts* opts,
-                         int32_t* labels, float* coeffs_out, int32_t* used_fallback, void* stream) {
+                         int32_t* labels, float* coeffs_out, double* diagnostics, int32_t* used_fallback,
+                         void* stream) {
   if (!ctx || !labels || (!params && !coeffs)) return fail(FSC_E_ARG, "null pointer");
   int rc;
   if ((rc = check_csr(g))) return rc;
@@ -582,7 +587,6 @@ int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t 
   // reference: M^8 X0 (the same budget of plain steps), in the free Y buffer
   if ((rc = combine_run(&io, w.basis, nullptr, w.Y, s))) return rc;
   if ((rc = rayleigh_run(&ctx->c, &io, w.Y, w.ray, 9, s))) return rc;
-  if ((rc = fallback_run(&io, w.ray, 8, 9, c_rest, w.used, s))) return rc;
   if (coeffs_out &&
       (rc = check_hip(hipMemcpyAsync(coeffs_out, c_rest, 32, hipMemcpyDeviceToDevice, s), "copy coefficients")))
     return rc;
@@ -595,6 +599,8 @@ int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t 
   }
   km.elig = io.elig;
   if ((rc = kmeans_run(&ctx->c, &km, s))) return rc;
+  if ((rc = kmeans_cost_run(&ctx->c, &km, w.part, w.counter + 2, w.gram, s))) return rc;
+  if ((rc = fallback_run(&io, w.ray, 8, 9, w.gram, kFilterMaxCost, c_rest, w.used, diagnostics, s))) return rc;
   int32_t used = 0;
   if (fallback_t > 0 || used_fallback) {
     if ((rc = check_hip(hipMemcpyAsync(ctx->c.host_flag, w.used, 4, hipMemcpyDeviceToHost, s), "copy flag")))

@@ -310,21 +310,33 @@ __global__ void combine_kernel(Blocks B, const float* __restrict__ c_rest, int64
   }
 }
 
-// used = 1 when the filtered block's column-mean Rayleigh quotient (row
+// used = 1 when (a) the filtered block's column-mean Rayleigh quotient (row
 // row_f) is below that of M^8 X0 (row row_ref): the filter concentrated the
 // block on the top of the spectrum less than the same budget of plain
-// PowerMethod steps does; or when a coefficient is not finite.
+// PowerMethod steps does; or (b) the normalised k-means cost of the filtered
+// embedding exceeds kmax (its clusters are not tight); or (c) a coefficient
+// is not finite.  diag (optional): rho_f, rho_8, normalised cost, used.
 __global__ void fallback_kernel(const double* __restrict__ ray, int l, int LH, int row_f, int row_ref,
-                                const float* __restrict__ c_rest, int32_t* __restrict__ used) {
+                                const double* __restrict__ kcost, double kmax, const float* __restrict__ c_rest,
+                                int32_t* __restrict__ used, double* __restrict__ diag) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double rf = 0.0, rr = 0.0;
   for (int q = 0; q < l; ++q) {
     rf += ray[row_f * LH + q];
     rr += ray[row_ref * LH + q];
   }
-  bool bad = !(rf >= rr);
+  rf /= l;
+  rr /= l;
+  const double kc = *kcost;
+  bool bad = !(rf >= rr) || !(kc <= kmax);
   for (int j = 0; j < 8; ++j) bad = bad || !isfinite(c_rest[j]);
   *used = bad ? 1 : 0;
+  if (diag) {
+    diag[0] = rf;
+    diag[1] = rr;
+    diag[2] = kc;
+    diag[3] = bad ? 1.0 : 0.0;
+  }
 }
 
 // ===========================================================================
@@ -469,9 +481,10 @@ int combine_run(const EmbedIO* io, float* const* basis, const float* c_rest, flo
   return check_hip(hipGetLastError(), "combine launch");
 }
 
-int fallback_run(const EmbedIO* io, const double* ray, int row_f, int row_ref, const float* c_rest, int32_t* used,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(fallback_kernel, dim3(1), dim3(64), 0, s, ray, io->l, io->LH, row_f, row_ref, c_rest, used);
+int fallback_run(const EmbedIO* io, const double* ray, int row_f, int row_ref, const double* kcost, double kmax,
+                 const float* c_rest, int32_t* used, double* diag, hipStream_t s) {
+  hipLaunchKernelGGL(fallback_kernel, dim3(1), dim3(64), 0, s, ray, io->l, io->LH, row_f, row_ref, kcost, kmax, c_rest,
+                     used, diag);
   return check_hip(hipGetLastError(), "fallback launch");
 }
 

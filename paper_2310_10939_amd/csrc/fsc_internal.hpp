@@ -196,6 +196,8 @@ int kmeans_run_batched(Context* ctx, const KmJob* jobs_dev, const int32_t* pp_of
 size_t kmeans_workspace_bytes(int64_t n, int KD);
 int kmeans_bind_workspace(Arena* a, KmeansIO* io);
 int kmeans_run(Context* ctx, KmeansIO* io, hipStream_t s);
+int kmeans_cost_run(Context* ctx, const KmeansIO* io, double* partials, int32_t* counter, double* out,
+                    hipStream_t s);
 int points_from_user(Context* ctx, const void* pts, int dtype, int64_t n, int l, int KD, float* out,
                      hipStream_t s);
 
@@ -215,8 +217,8 @@ int gram_run(Context* ctx, const EmbedIO* io, float* const* basis, const float* 
 int features_run(Context* ctx, const EmbedIO* io, int k, const double* ray, double* partials, int32_t* counter,
                  float* feat, hipStream_t s);
 int combine_run(const EmbedIO* io, float* const* basis, const float* c_rest, float* S, hipStream_t s);
-int fallback_run(const EmbedIO* io, const double* ray, int row_f, int row_ref, const float* c_rest, int32_t* used,
-                 hipStream_t s);
+int fallback_run(const EmbedIO* io, const double* ray, int row_f, int row_ref, const double* kcost, double kmax,
+                 const float* c_rest, int32_t* used, double* diag, hipStream_t s);
 int mlp_param_count();
 size_t mlp_workspace_bytes(int B);
 int mlp_forward_run(const float* params, int B, const float* feats, float* acts, float* c_out, hipStream_t s);

@@ -516,6 +516,56 @@ __global__ __launch_bounds__(kLB) void lloyd_kernel_seg(const KmJob* __restrict_
   }
 }
 
+// Normalised k-means cost of the final assignment over the eligible rows:
+// out[0] = sum ||p - mu_label||^2 / sum ||p - mean||^2 (FP64 partials, the
+// last block combines them in block order).
+__global__ __launch_bounds__(kKB) void kmeans_cost_kernel(KmJob J, double* __restrict__ partials,
+                                                          int32_t* __restrict__ counter, double* __restrict__ out) {
+  __shared__ double red[kKB / FSC_WAVE];
+  __shared__ int is_last;
+  double cost = 0.0, sq = 0.0, cnt = 0.0, s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t v = (int64_t)blockIdx.x * kKB + threadIdx.x; v < J.n; v += (int64_t)gridDim.x * kKB) {
+    if (J.elig && !J.elig[v]) continue;
+    const int lab = J.labels[v];
+    for (int q = 0; q < J.KD; ++q) {
+      const double x = J.pts[v * J.KD + q];
+      const double e = x - (double)J.centres[lab * J.KD + q];
+      cost += e * e;
+      sq += x * x;
+      s[q] += x;
+    }
+    cnt += 1.0;
+  }
+  double vals[11] = {cost, sq, cnt, s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7]};
+  for (int i = 0; i < 11; ++i) {
+    const double t = block_sum<kKB>(vals[i], red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * 11 + i] = t;
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    is_last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!is_last || threadIdx.x != 0) return;
+  __threadfence();
+  double tot[11] = {0};
+  for (int g = 0; g < (int)gridDim.x; ++g)
+    for (int i = 0; i < 11; ++i) tot[i] += partials[(int64_t)g * 11 + i];
+  double var = tot[1];
+  if (tot[2] > 0.0)
+    for (int q = 0; q < 8; ++q) var -= tot[3 + q] * tot[3 + q] / tot[2];
+  out[0] = var > 0.0 ? tot[0] / var : 1.0;
+  *counter = 0;
+}
+
+int kmeans_cost_run(Context* ctx, const KmeansIO* io, double* partials, int32_t* counter, double* out,
+                    hipStream_t s) {
+  const KmJob J = make_job(ctx, io);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((io->n + kKB - 1) / kKB, 2 * ctx->num_cu));
+  hipLaunchKernelGGL(kmeans_cost_kernel, dim3(grid), dim3(kKB), 0, s, J, partials, counter, out);
+  return check_hip(hipGetLastError(), "kmeans cost launch");
+}
+
 __global__ void centres_out_kernel(const float* __restrict__ c, int k, int KD, int l, float* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k * l) out[i] = c[(i / l) * KD + (i % l)];

@@ -63,7 +63,7 @@ _lib.fsc_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, _f, _i32, _vp]
 _lib.fsc_mlp_train.argtypes = [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i32, _f, _i32, _vp, _vp]
 _lib.fsc_filter_embed.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _u64, _vp, _vp, _vp]
 _lib.fsc_cluster_filtered.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, _vp, _vp, _i32,
-                                      ctypes.POINTER(Opts), _vp, _vp, ctypes.POINTER(_i32), _vp]
+                                      ctypes.POINTER(Opts), _vp, _vp, _vp, ctypes.POINTER(_i32), _vp]
 _lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
 _lib.fsc_tuning_set.argtypes = [_vp, ctypes.POINTER(Tuning)]
 _lib.fsc_timing_enable.argtypes = [_vp, ctypes.c_int]
@@ -289,18 +289,24 @@ def filter_embed(indptr, indices, data, l, seed, coeffs):
     return out
 
 
-def cluster_filtered(indptr, indices, data, k, l, seed, params=None, coeffs=None, fallback_t=0, kmeans_iters=30):
-    """The learned form: returns (labels, coefficients used, used_fallback)."""
+def cluster_filtered(indptr, indices, data, k, l, seed, params=None, coeffs=None, fallback_t=0, kmeans_iters=30,
+                     diagnostics=False):
+    """The learned form: returns (labels, coefficients used, used_fallback)
+    and, with diagnostics=True, the device double[4] (rho_f, rho_8,
+    normalised k-means cost, flag)."""
     n = indptr.numel() - 1
     dev = indptr.device
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     cout = torch.empty(8, dtype=torch.float32, device=dev)
+    diag = torch.empty(4, dtype=torch.float64, device=dev)
     used = _i32(0)
     g = _csr(indptr, indices, data)
     o = _opts("f32", kmeans_iters)
     _check(_lib.fsc_cluster_filtered(context(dev.index), ctypes.byref(g), k, l, seed, _ptr(params), _ptr(coeffs),
-                                     fallback_t, ctypes.byref(o), _ptr(labels), _ptr(cout), ctypes.byref(used),
-                                     _stream()))
+                                     fallback_t, ctypes.byref(o), _ptr(labels), _ptr(cout), _ptr(diag),
+                                     ctypes.byref(used), _stream()))
+    if diagnostics:
+        return labels, cout, bool(used.value), diag
     return labels, cout, bool(used.value)
 
 

@@ -131,12 +131,23 @@ def evaluate(p, specs, device, stats=None, log=print):
         plain = fsc.cluster(ip, ix, None, k, l, t, seed)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        learned, coef, used = fsc.cluster_filtered(ip, ix, None, k, l, seed, params=p)
+        learned, coef, used, diag = fsc.cluster_filtered(ip, ix, None, k, l, seed, params=p, diagnostics=True)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        fixed, _, _ = fsc.cluster_filtered(ip, ix, None, k, l, seed, coeffs=g8)
+        fixed, _, _, diag8 = fsc.cluster_filtered(ip, ix, None, k, l, seed, coeffs=g8, diagnostics=True)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        guarded, _, used_g = fsc.cluster_filtered(ip, ix, None, k, l, seed, params=p, fallback_t=t)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        # normalised k-means cost of the plain embedding, for calibration
+        _, E, Cn = fsc.cluster(ip, ix, None, k, l, t, seed, return_embedding=True, return_centres=True)
+        Eh = E.double().cpu().numpy()
+        lab_p = plain.cpu().numpy()
+        keep = np.diff(ip.cpu().numpy()) > 0
+        Ek, lk = Eh[keep], lab_p[keep]
+        cost_plain = float(((Ek - Cn.double().cpu().numpy()[lk]) ** 2).sum() / ((Ek - Ek.mean(0)) ** 2).sum())
+        dg, d8 = diag.cpu().numpy(), diag8.cpu().numpy()
         extra = {}
         if stats is not None:
             Gi, hi, yi = (x[i].double().cpu().numpy() for x in stats)
@@ -150,15 +161,18 @@ def evaluate(p, specs, device, stats=None, log=print):
                          ari_plain_vs_planted=float(fsc.ari(plain, lab, k, k)),
                          ari_learned_vs_planted=float(fsc.ari(learned, lab, k, k)),
                          ari_fixed8_vs_planted=float(fsc.ari(fixed, lab, k, k)),
+                         ari_guarded_vs_plain=float(fsc.ari(guarded, plain, k, k)),
                          fallback=used, ms_plain=(t1 - t0) * 1e3, ms_learned=(t2 - t1) * 1e3,
-                         ms_fixed8=(t3 - t2) * 1e3))
+                         ms_fixed8=(t3 - t2) * 1e3, ms_guarded=(t4 - t3) * 1e3,
+                         rho_learned=float(dg[0]), rho_8=float(dg[1]), cost_learned=float(dg[2]),
+                         cost_fixed8=float(d8[2]), cost_plain=cost_plain))
         if (i + 1) % 10 == 0 or i + 1 == len(specs):
             log(f"eval {i + 1}/{len(specs)}")
     return rows
 
 
 def summarize(rows):
-    keys = [k for k in rows[0] if k.startswith("ari") or k.startswith("ms") or k.startswith("loss")]
+    keys = [k for k in rows[0] if k.split("_")[0] in ("ari", "ms", "loss", "rho", "cost")]
     out = {k: float(np.mean([r[k] for r in rows])) for k in keys}
     out["fallback_rate"] = float(np.mean([r["fallback"] for r in rows]))
     out["graphs"] = len(rows)
@@ -174,6 +188,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=PARAMS_FILE)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--eval-only", action="store_true", help="evaluate the saved parameters (--out)")
     args = ap.parse_args(argv)
     import torch
     import synth
@@ -183,8 +198,19 @@ def main(argv=None):
     def log(msg):
         print(msg, flush=True)
 
-    train_specs = synth.learned_params(args.graphs, 0)
     test_specs = synth.learned_params(args.heldout, 100000)
+    if args.eval_only:
+        Ft, Gt, Ht, YYt = collect(test_specs, dev, log)
+        p = load_params(args.out, dev)
+        rows = evaluate(p, test_specs, dev, (Gt, Ht, YYt), log)
+        report = {"heldout_graphs": args.heldout, "heldout_loss": heldout_loss(p, Ft, Gt, Ht, YYt),
+                  "summary": summarize(rows), "rows": rows}
+        if args.report:
+            with open(args.report, "w") as fh:
+                json.dump(report, fh, indent=1)
+        log(json.dumps({k: v for k, v in report.items() if k != "rows"}))
+        return 0
+    train_specs = synth.learned_params(args.graphs, 0)
     F, G, H, YY = collect(train_specs, dev, log)
     Ft, Gt, Ht, YYt = collect(test_specs, dev, log)
     p, trace = train(F, G, H, YY, args.steps, args.lr, args.seed, log)
