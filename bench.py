@@ -28,7 +28,7 @@ METRIC = "edges×vectors×iters/s (SpMM GB/s vs HBM peak) + clustering time at A
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "spmm_sbm1m_counters.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2310_10939_amd", "csrc", f)
-                  for f in ("fsc_embed.hip", "fsc_device.hpp")]
+                  for f in ("fsc_embed.hip", "fsc_tiles.hpp", "fsc_device.hpp")]
 
 WORKLOADS = {
     # name: (n, k, deg_in, deg_out, l, t, lloyd, vec dtype, weight dtype, permute)

@@ -250,7 +250,7 @@ int fsc_filter_embed(fsc_context* ctx, const fsc_csr* g, int32_t l, uint64_t see
  * of M^8 X0 (what 8 plain PowerMethod steps give; computed from the same
  * basis with the exact Chebyshev coefficients of gamma^8), or (b) the
  * normalised k-means cost of the filtered embedding (within-cluster over
- * total variance) exceeds 0.5, or (c) a coefficient is not finite.  When it
+ * total variance) exceeds 0.1, or (c) a coefficient is not finite.  When it
  * fires and fallback_t > 0, the plain method with t = fallback_t overwrites
  * the labels; reading the check synchronises the stream.  Outputs: labels
  * int32[n]; optional coeffs_out (device float[8]); optional diagnostics

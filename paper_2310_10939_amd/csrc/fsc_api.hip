@@ -158,7 +158,7 @@ static int zero_counter(int32_t* p, hipStream_t s) { return fill_zero_i32(p, 4, 
 
 // Largest normalised k-means cost (within-cluster over total variance of the
 // embedding rows) accepted from the filtered embedding before falling back.
-constexpr double kFilterMaxCost = 0.5;
+constexpr double kFilterMaxCost = 0.1;
 
 }  // namespace fsc
 
