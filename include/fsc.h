@@ -120,6 +120,13 @@ typedef struct {
   int32_t blocks_per_cu;  /* persistent blocks per compute unit (default 4) */
   int32_t xcd_order;      /* 1: contiguous short-tile range per XCD (default), 2: round robin */
   int32_t unroll;         /* nonzeros in flight per lane: 4 (default) or 8 */
+  /* Column-slab size in KiB of the n x l block (default 1024; < 0 turns the
+   * slab form off).  When an FP32 or BF16 block is larger than one slab, the
+   * columns are cut into slabs of this size (at most 16; larger slabs if
+   * needed) and each step gathers from one slab at a time, so that the rows
+   * an XCD gathers stay in its L2.  Results do not depend on it beyond
+   * summation order. */
+  int32_t slab_kb;
 } fsc_tuning;
 
 /* Creates a context on HIP device `device` (makes it current on the calling
@@ -269,10 +276,11 @@ int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t 
 int fsc_ari(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int32_t ka,
             int32_t kb, double* out, void* stream);
 
-/* Sets (fields > 0) and then reports in *t the sparse-product launch shape
- * used by later calls on this context.  t is a host pointer.  Returns
- * FSC_E_ARG for out-of-range values (tile_nnz < 64, blocks_per_cu outside
- * [1, 16], unroll not 4 or 8). */
+/* Sets (fields > 0; slab_kb < 0 turns the slab form off) and then reports in
+ * *t the sparse-product launch shape used by later calls on this context
+ * (slab_kb reported as -1 when off).  t is a host pointer.  Returns FSC_E_ARG
+ * for out-of-range values (tile_nnz < 64, blocks_per_cu outside [1, 16],
+ * unroll not 4 or 8, slab_kb above 65536). */
 int fsc_tuning_set(fsc_context* ctx, fsc_tuning* t);
 
 /* Kernel timing with HIP events, for profiling (off by default).  While on,

@@ -369,6 +369,7 @@ int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, f
       for (int bpc : {4, 8})
         for (int xo : {1, 0}) {
           Tune tu;
+          tu.slab_kb = saved.slab_kb;
           tu.tile_nnz = tile;
           tu.unroll = un;
           tu.blocks_per_cu = bpc;
@@ -411,6 +412,7 @@ int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, f
   best->blocks_per_cu = bestt.blocks_per_cu;
   best->xcd_order = bestt.xcd_order ? 1 : 2;
   best->unroll = bestt.unroll;
+  best->slab_kb = bestt.slab_kb > 0 ? bestt.slab_kb : -1;
   return FSC_OK;
 }
 
@@ -632,11 +634,14 @@ int fsc_tuning_set(fsc_context* ctx, fsc_tuning* t) {
     if (t->unroll != 4 && t->unroll != 8) return fail(FSC_E_ARG, "unroll must be 4 or 8");
     nt.unroll = t->unroll;
   }
+  if (t->slab_kb > 65536) return fail(FSC_E_ARG, "slab_kb must be <= 65536");
+  if (t->slab_kb != 0) nt.slab_kb = t->slab_kb > 0 ? t->slab_kb : -1;
   ctx->c.tune = nt;
   t->tile_nnz = nt.tile_nnz;
   t->blocks_per_cu = nt.blocks_per_cu;
   t->xcd_order = nt.xcd_order ? 1 : 2;
   t->unroll = nt.unroll;
+  t->slab_kb = nt.slab_kb > 0 ? nt.slab_kb : -1;
   return FSC_OK;
 }
 

@@ -21,6 +21,7 @@
 // FP64 column norms -- are deterministic.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
+#include "fsc_slab.hpp"
 #include "fsc_tiles.hpp"
 
 #include <algorithm>
@@ -233,6 +234,7 @@ size_t embed_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, int ve
   b += align_up(nb * sizeof(TileDesc)) + align_up((nb + 1) * 4) * 3;  // plan
   b += align_up((2 * nb + 1) * sizeof(LongChunk)) + align_up(16);
   b += 16 * 256;                                                    // alignment slack
+  b += slab_workspace_bytes(ctx, g, LH, vec_dtype);
   return b;
 }
 
@@ -267,7 +269,7 @@ int embed_bind_workspace(Context* ctx, Arena* a, EmbedIO* io) {
   io->plan.chunks = a->take<LongChunk>(2 * nb + 1);
   io->plan.meta = a->take<int32_t>(4);
   if (a->used > a->size) return fail(FSC_E_NOMEM, "workspace arena too small");
-  return FSC_OK;
+  return slab_bind(ctx, a, io);
 }
 
 template <class Op>
@@ -277,6 +279,23 @@ static int launch_tiles(const Op& op, const TileArgs& ta, const StatsArgs& sa, i
   else
     hipLaunchKernelGGL((tile_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sa);
   return check_hip(hipGetLastError(), "tile_kernel launch");
+}
+
+template <class Op>
+static int launch_slab(const Op& op, const TileArgs& ta, const SlabArgs& sb, const StatsArgs& sa, int grid,
+                       hipStream_t s) {
+  hipLaunchKernelGGL((slab_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb, sa);
+  return check_hip(hipGetLastError(), "slab_kernel launch");
+}
+
+// One step's launch: the column-slab kernel when the plan has slabs.
+template <class Op>
+static int launch_step(const Op& op, const TileArgs& ta, const SlabArgs* sb, const StatsArgs& sa, int grid,
+                       int unroll, hipStream_t s) {
+  if constexpr (!std::is_same<typename Op::A, double>::value) {
+    if (sb) return launch_slab(op, ta, *sb, sa, grid, s);
+  }
+  return launch_tiles(op, ta, sa, grid, unroll, s);
 }
 
 // Persistent grid: a few resident blocks per CU, a multiple of 8 so the XCD
@@ -291,9 +310,12 @@ static int persistent_grid(const Context* ctx, int64_t tiles, int blocks_per_cu)
 }
 
 template <typename S, typename W, int LH>
-static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta, StatsArgs sa, hipStream_t s, bool stats) {
+static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta, const SlabArgs* sb_in, StatsArgs sa,
+                     hipStream_t s, bool stats) {
+  const SlabArgs* sb = sb_in;
   using A = typename elem<S>::acc;
   const fsc_csr* g = io->g;
+  const W* sval = reinterpret_cast<const W*>(io->slab.sval);
   const A* scale = reinterpret_cast<const A*>(io->state + 3 * LH);
   for (int step = 1; step <= io->t; ++step) {
     const S* zin = reinterpret_cast<const S*>(io->z[(step - 1) & 1]);
@@ -304,21 +326,23 @@ static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta, StatsArgs sa
     if (stats) {
       StepOp<S, W, LH, true> op;
       op.val = reinterpret_cast<const W*>(g->val);
+      op.sval = sval;
       op.zin = zin;
       op.zout = zout;
       op.hinv = reinterpret_cast<const A*>(io->hinv);
       op.deg = io->deg;
       op.scale = scale;
-      rc = launch_tiles(op, ta, sa, io->grid, ctx->tune.unroll, s);
+      rc = launch_step(op, ta, sb, sa, io->grid, ctx->tune.unroll, s);
     } else {
       StepOp<S, W, LH, false> op;
       op.val = reinterpret_cast<const W*>(g->val);
+      op.sval = sval;
       op.zin = zin;
       op.zout = zout;
       op.hinv = reinterpret_cast<const A*>(io->hinv);
       op.deg = io->deg;
       op.scale = nullptr;
-      rc = launch_tiles(op, ta, sa, io->grid, ctx->tune.unroll, s);
+      rc = launch_step(op, ta, sb, sa, io->grid, ctx->tune.unroll, s);
     }
     timing_stop(ev, s);
     if (rc) return rc;
@@ -394,7 +418,33 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
                        reinterpret_cast<S*>(io->z[0]), sa, stats ? 1 : 0);
     if ((rc = check_hip(hipGetLastError(), "start_block launch"))) return rc;
   }
-  return run_steps<S, W, LH>(ctx, io, ta, sa, s, stats);
+  if (!io->slab.enabled || std::is_same<A, double>::value)
+    return run_steps<S, W, LH>(ctx, io, ta, nullptr, sa, s, stats);
+  // column-slab plan: its own tiles and long-row chunks for the steps
+  if ((rc = slab_build(ctx, io, s))) return rc;
+  const SlabPlan& sp = io->slab;
+  TileArgs ts = ta;
+  ts.nb = 0;
+  ts.chunks = sp.chunks;
+  ts.meta = sp.meta;
+  ts.lcount = sp.lcount;
+  ts.lnorm = sp.lnorm;
+  ts.lpart = sp.lpart;
+  StatsArgs ss = sa;
+  ss.lnorm = sp.lnorm;
+  ss.meta = sp.meta;
+  SlabArgs sb;
+  sb.ntiles = sp.ntiles;
+  sb.rows = sp.rows;
+  sb.nslab = sp.nslab;
+  sb.logS = sp.logS;
+  sb.scol = sp.scol;
+  sb.sperm = sp.sperm;
+  sb.sbase = sp.sbase;
+  sb.smax = sp.smax;
+  sb.sreg = sp.sreg;
+  io->grid = persistent_grid(ctx, sp.ntiles, ctx->tune.slab_bpc);
+  return run_steps<S, W, LH>(ctx, io, ts, &sb, ss, s, stats);
 }
 
 template <typename S, typename W>
@@ -414,11 +464,11 @@ static int run_embed_val(Context* ctx, EmbedIO* io, hipStream_t s) {
   if (!g->val) return run_embed_lh<S, void>(ctx, io, s);
   switch (g->val_dtype) {
     case FSC_F64:
-      if (std::is_same<S, double>::value) return run_embed_lh<S, double>(ctx, io, s);
+      if constexpr (std::is_same<S, double>::value) return run_embed_lh<S, double>(ctx, io, s);
       break;
     case FSC_F32: return run_embed_lh<S, float>(ctx, io, s);
     case FSC_BF16:
-      if (!std::is_same<S, double>::value) return run_embed_lh<S, bf16_t>(ctx, io, s);
+      if constexpr (!std::is_same<S, double>::value) return run_embed_lh<S, bf16_t>(ctx, io, s);
       break;
   }
   return fail(FSC_E_UNSUPPORTED, "unsupported combination of weight and vector dtypes "

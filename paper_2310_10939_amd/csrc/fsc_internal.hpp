@@ -52,6 +52,12 @@ struct TileDesc {
 
 constexpr int kMaxGrid = 4096;
 
+// Column-slab form of the sparse product (fsc_slab.hpp, fsc_slab.hip).
+constexpr int kSlabRows = 1024;   // rows per slab tile
+constexpr int kSlabLong = 256;    // longer rows are summed by long-row chunks
+constexpr int kSlabMax = 16;      // most slabs per graph
+constexpr int kSlabChunk = 2048;  // nonzeros per long-row chunk
+
 // Tuning knobs of the sparse product (per context).
 struct Tune {
   // defaults: the best shape of a sweep on the 1M-vertex SBM (tile 512..4096,
@@ -60,6 +66,8 @@ struct Tune {
   int blocks_per_cu = 4;   // persistent blocks per CU
   int xcd_order = 1;       // contiguous short-tile range per XCD
   int unroll = 4;          // nonzeros in flight per lane
+  int slab_kb = 1024;      // column-slab size (KiB of the start block); <= 0: off
+  int slab_bpc = 6;        // resident blocks per CU of the column-slab kernel
 };
 
 // Tile plan of one graph for the sparse product (built on the device).
@@ -73,6 +81,30 @@ struct Plan {
   LongChunk* chunks = nullptr;  // up to max_chunks entries
   int32_t max_chunks = 0;
   int32_t* meta = nullptr;      // int32[4]: {total chunks, long rows, -, -}
+};
+
+// Column-slab plan of one graph (built on the device by slab_build).
+struct SlabPlan {
+  int enabled = 0;
+  int32_t logS = 0, nslab = 0, ntiles = 0, rows = 0;
+  int64_t max_long = 0, max_chunks = 0;
+  int32_t* scol = nullptr;     // [nnz] column indices in slab order
+  void* sval = nullptr;        // [nnz] weights in slab order (null: unit weights)
+  uint16_t* sperm = nullptr;   // [n * nslab]
+  int32_t* sbase = nullptr;    // [ntiles * nslab][kSlabLong + 1]
+  int32_t* smax = nullptr;     // [ntiles * nslab]
+  int64_t* sreg = nullptr;     // [ntiles * nslab]
+  int64_t* tshort = nullptr;   // [ntiles] short-row nonzeros per tile
+  int64_t* toff = nullptr;     // [ntiles + 1] exclusive scan of tshort
+  int32_t* tlong = nullptr;    // [ntiles] long rows per tile
+  int32_t* tchunks = nullptr;  // [ntiles] long-row chunks per tile
+  int32_t* loff = nullptr;     // [ntiles + 1]
+  int32_t* coff = nullptr;     // [ntiles + 1]
+  LongChunk* chunks = nullptr; // [max_chunks]
+  int32_t* meta = nullptr;     // {chunks, long rows, -, -}
+  double* lnorm = nullptr;     // [max_long][2 * LH]
+  void* lpart = nullptr;       // float[max_chunks][LH]
+  int32_t* lcount = nullptr;   // [max_long]
 };
 
 struct Context {
@@ -132,6 +164,7 @@ struct EmbedIO {
   void* lpart;      // A[max chunks][LH]
   int32_t* lcount;  // [max long rows]
   Plan plan;
+  SlabPlan slab;    // column-slab plan (slab.enabled = 0: plain tiles)
   int grid;         // persistent grid of the sparse product
   // result: pointer to Z_t (S[n*LH]) inside the workspace
   const void* zt;
@@ -154,6 +187,16 @@ int embed_to_points(Context* ctx, const EmbedIO* io, float* pts, hipStream_t s);
 // Device-side validation of a CSR; synchronises `s`.  Returns FSC_OK or
 // FSC_E_GRAPH.
 int validate_csr(Context* ctx, const fsc_csr* g, hipStream_t s);
+
+// ---- column-slab plan (fsc_slab.hip) ----
+// Slab shape for an n-row block of LH columns: true (and logS, nslab) when
+// the block is larger than one slab of ctx->tune.slab_kb KiB.
+bool slab_shape(const Context* ctx, int64_t n, int LH, int vec_dtype, int32_t* logS, int32_t* nslab);
+size_t slab_workspace_bytes(const Context* ctx, const fsc_csr* g, int LH, int vec_dtype);
+// Takes the slab arrays from the arena (sets io->slab.enabled when used).
+int slab_bind(Context* ctx, Arena* a, EmbedIO* io);
+// Enqueues the kernels that build io->slab from the CSR.
+int slab_build(Context* ctx, EmbedIO* io, hipStream_t s);
 
 // ---- k-means (fsc_kmeans.hip) ----
 struct KmeansIO {

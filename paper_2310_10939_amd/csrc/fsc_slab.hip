@@ -1,0 +1,368 @@
+// Builds the column-slab layout of a graph for the sparse product (the
+// layout is described in fsc_slab.hpp).  Three kernels, all on the caller's
+// stream and free of host synchronisation:
+//   slab_count_kernel  per tile: nonzeros of its short rows, its long rows and
+//                      their chunks;
+//   slab_scan_kernel   exclusive scans of those over the tiles;
+//   slab_build_kernel  per tile: segment lengths per (row, slab), rows sorted
+//                      by length per slab (counting sort in LDS), diagonal
+//                      starts, the scatter of the nonzeros into slab order,
+//                      and the long-row chunks.
+// Rows of equal length may take their sorted positions in any order, but a
+// row's nonzeros keep their CSR order within its segment and a row's segments
+// are summed in slab order, so every row's sum -- and so every result of a
+// step -- is the same whatever positions the rows get.
+#include "fsc_device.hpp"
+#include "fsc_internal.hpp"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace fsc {
+
+static_assert(kSlabLong == 256, "the diagonal scan uses one 256-thread block pass");
+static_assert(kSlabRows == 1024, "one build thread per row of a tile");
+
+__device__ __forceinline__ int slab_of(int32_t c, int logS, int last) {
+  const int p = c >> logS;
+  return p < 0 ? 0 : (p > last ? last : p);
+}
+
+__global__ __launch_bounds__(256) void slab_count_kernel(const int64_t* __restrict__ row_ptr, int32_t n,
+                                                         int32_t rows, int64_t* __restrict__ tshort,
+                                                         int32_t* __restrict__ tlong, int32_t* __restrict__ tchunks) {
+  __shared__ int64_t l64[256 / FSC_WAVE];
+  __shared__ int32_t l32[256 / FSC_WAVE];
+  const int32_t T = blockIdx.x;
+  const int32_t r0 = T * rows;
+  const int32_t R = min(rows, n - r0);
+  int64_t sh = 0;
+  int32_t nl = 0, nc = 0;
+  for (int32_t rl = threadIdx.x; rl < R; rl += 256) {
+    const int64_t len = row_ptr[r0 + rl + 1] - row_ptr[r0 + rl];
+    if (len > kSlabLong) {
+      ++nl;
+      nc += (int32_t)((len + kSlabChunk - 1) / kSlabChunk);
+    } else {
+      sh += len;
+    }
+  }
+  int64_t t64;
+  int32_t t32;
+  block_scan_inclusive<256, int64_t>(sh, l64, &t64);
+  if (threadIdx.x == 0) tshort[T] = t64;
+  block_scan_inclusive<256, int32_t>(nl, l32, &t32);
+  if (threadIdx.x == 0) tlong[T] = t32;
+  block_scan_inclusive<256, int32_t>(nc, l32, &t32);
+  if (threadIdx.x == 0) tchunks[T] = t32;
+}
+
+__global__ __launch_bounds__(1024) void slab_scan_kernel(const int64_t* __restrict__ tshort,
+                                                         const int32_t* __restrict__ tlong,
+                                                         const int32_t* __restrict__ tchunks, int32_t ntiles,
+                                                         int64_t* __restrict__ toff, int32_t* __restrict__ loff,
+                                                         int32_t* __restrict__ coff, int32_t* __restrict__ meta) {
+  __shared__ int64_t l64[1024 / FSC_WAVE];
+  __shared__ int32_t la[1024 / FSC_WAVE], lb[1024 / FSC_WAVE];
+  int64_t c64 = 0;
+  int32_t ca = 0, cb = 0;
+  for (int32_t base = 0; base < ntiles; base += 1024) {
+    const int32_t i = base + threadIdx.x;
+    const int64_t v = i < ntiles ? tshort[i] : 0;
+    const int32_t va = i < ntiles ? tlong[i] : 0;
+    const int32_t vb = i < ntiles ? tchunks[i] : 0;
+    int64_t t64;
+    int32_t ta, tb;
+    const int64_t iv = block_scan_inclusive<1024, int64_t>(v, l64, &t64);
+    const int32_t ia = block_scan_inclusive<1024, int32_t>(va, la, &ta);
+    const int32_t ib = block_scan_inclusive<1024, int32_t>(vb, lb, &tb);
+    if (i < ntiles) {
+      toff[i] = c64 + iv - v;
+      loff[i] = ca + ia - va;
+      coff[i] = cb + ib - vb;
+    }
+    c64 += t64;
+    ca += ta;
+    cb += tb;
+  }
+  if (threadIdx.x == 0) {
+    toff[ntiles] = c64;
+    loff[ntiles] = ca;
+    coff[ntiles] = cb;
+    meta[0] = cb;
+    meta[1] = ca;
+  }
+}
+
+constexpr int kBuild = 1024;  // threads of the build kernel: one per row of a tile
+constexpr int kBuildU = 8;    // nonzeros of a row loaded at once
+
+template <typename W>
+__global__ __launch_bounds__(kBuild) void slab_build_kernel(
+    const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const W* __restrict__ val, int32_t n,
+    int32_t rows, int32_t logS, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
+    const int32_t* __restrict__ coff, int32_t* __restrict__ scol, W* __restrict__ sval, uint16_t* __restrict__ sperm,
+    int32_t* __restrict__ sbase, int32_t* __restrict__ smax, int64_t* __restrict__ sreg,
+    LongChunk* __restrict__ chunks) {
+  __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
+  __shared__ uint16_t spos[kSlabMax * kSlabRows];  // sorted position of each row per slab
+  __shared__ int32_t hist[kSlabLong + 1];          // rows per segment length
+  __shared__ int32_t cursor[kSlabLong + 1];        // next sorted position per length
+  __shared__ int32_t cntk[kSlabLong];              // rows longer than k
+  __shared__ int32_t baseL[kSlabMax * (kSlabLong + 1)];
+  __shared__ int64_t regL[kSlabMax];
+  __shared__ int32_t scan32[kBuild / FSC_WAVE];
+  const int32_t T = blockIdx.x;
+  const int32_t r0 = T * rows;
+  const int32_t R = min(rows, n - r0);
+  const int last = nslab - 1;
+  const int rl = threadIdx.x;  // this thread's row (rows <= kSlabRows == kBuild)
+  int64_t a = 0, b = 0;
+  if (rl < R) {
+    a = row_ptr[r0 + rl];
+    b = row_ptr[r0 + rl + 1];
+  }
+  const bool shortrow = rl < R && b - a <= kSlabLong;
+  for (int i = threadIdx.x; i < nslab * R; i += kBuild) cnt[i] = 0;
+  __syncthreads();
+  // segment length of every short row in every slab
+  if (shortrow) {
+    for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
+      int32_t c[kBuildU];
+#pragma unroll
+      for (int u = 0; u < kBuildU; ++u) c[u] = j0 + u < b ? col[j0 + u] : 0;
+#pragma unroll
+      for (int u = 0; u < kBuildU; ++u)
+        if (j0 + u < b) cnt[slab_of(c[u], logS, last) * R + rl] += 1;
+    }
+  }
+  __syncthreads();
+  int64_t region = toff[T];
+  for (int p = 0; p < nslab; ++p) {
+    // counting sort of the rows by decreasing segment length: rows longer
+    // than k come first, so the count of rows longer than k is both the start
+    // of length k in the sorted order and the height of diagonal k
+    if (threadIdx.x <= kSlabLong) hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int len = rl < R ? (int)cnt[p * R + rl] : 0;
+    if (rl < R) atomicAdd(&hist[len], 1);
+    __syncthreads();
+    {
+      const int t = threadIdx.x;  // suffix sums over lengths 256, 255, ...
+      const int32_t v = t <= kSlabLong ? hist[kSlabLong - t] : 0;
+      int32_t tot;
+      const int32_t incl = block_scan_inclusive<kBuild, int32_t>(v, scan32, &tot);
+      // incl(t) = rows with length >= 256 - t; rows longer than k: t = 255 - k
+      if (t < kSlabLong) cntk[kSlabLong - 1 - t] = incl;
+    }
+    __syncthreads();
+    int32_t maxlen = 0;
+    {
+      // longest segment: the number of k with a nonempty diagonal
+      int32_t lo = 0, hi = kSlabLong;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (cntk[mid] > 0) lo = mid + 1; else hi = mid;
+      }
+      maxlen = lo;
+    }
+    if (threadIdx.x <= kSlabLong) cursor[threadIdx.x] = threadIdx.x < kSlabLong ? cntk[threadIdx.x] : 0;
+    __syncthreads();
+    if (rl < R) {
+      const int i = atomicAdd(&cursor[len], 1);
+      sperm[(int64_t)r0 * nslab + (int64_t)p * R + i] = (uint16_t)rl;
+      spos[p * R + rl] = (uint16_t)i;
+    }
+    // diagonal starts: exclusive scan of cntk[0..maxlen)
+    const int k = threadIdx.x;
+    const int32_t v = k < maxlen ? cntk[k] : 0;
+    int32_t total;
+    const int32_t incl = block_scan_inclusive<kBuild, int32_t>(v, scan32, &total);
+    int32_t* bl = baseL + p * (kSlabLong + 1);
+    if (k < kSlabLong) bl[k + 1] = incl;
+    const int64_t tp = (int64_t)T * nslab + p;
+    int32_t* gb = sbase + tp * (kSlabLong + 1);
+    if (k + 1 <= maxlen) gb[k + 1] = incl;
+    if (k == 0) {
+      bl[0] = 0;
+      gb[0] = 0;
+      smax[tp] = maxlen;
+      sreg[tp] = region;
+      regL[p] = region;
+    }
+    region += total;
+    __syncthreads();
+  }
+  // scatter the short rows' nonzeros into slab order (CSR order within a
+  // row's segment)
+  for (int i = threadIdx.x; i < nslab * R; i += kBuild) cnt[i] = 0;
+  __syncthreads();
+  if (shortrow) {
+    for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
+      using WS = typename std::conditional<std::is_void<W>::value, char, W>::type;
+      int32_t c[kBuildU];
+      WS w[kBuildU];
+#pragma unroll
+      for (int u = 0; u < kBuildU; ++u) {
+        c[u] = j0 + u < b ? col[j0 + u] : 0;
+        if constexpr (!std::is_void<W>::value) {
+          if (j0 + u < b) w[u] = val[j0 + u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBuildU; ++u) {
+        if (j0 + u < b) {
+          const int p = slab_of(c[u], logS, last);
+          const int kk = cnt[p * R + rl]++;
+          const int64_t pos = regL[p] + baseL[p * (kSlabLong + 1) + kk] + spos[p * R + rl];
+          scol[pos] = c[u];
+          if constexpr (!std::is_void<W>::value) sval[pos] = w[u];
+        }
+      }
+    }
+  }
+  // long rows: chunks of kSlabChunk nonzeros of the original CSR
+  {
+    const int32_t isl = rl < R && !shortrow ? 1 : 0;
+    const int32_t nc = isl ? (int32_t)((b - a + kSlabChunk - 1) / kSlabChunk) : 0;
+    int32_t tl, tc;
+    const int32_t il = block_scan_inclusive<kBuild, int32_t>(isl, scan32, &tl);
+    const int32_t ic = block_scan_inclusive<kBuild, int32_t>(nc, scan32, &tc);
+    if (isl) {
+      const int32_t lid = loff[T] + il - 1;
+      const int32_t first = coff[T] + ic - nc;
+      for (int32_t c = 0; c < nc; ++c) {
+        LongChunk ch;
+        ch.start = a + (int64_t)c * kSlabChunk;
+        ch.end = min<int64_t>(ch.start + kSlabChunk, b);
+        ch.row = r0 + rl;
+        ch.lid = lid;
+        ch.index = c;
+        ch.count = nc;
+        ch.first = first;
+        ch.pad = 0;
+        chunks[first + c] = ch;
+      }
+    }
+  }
+}
+
+__global__ void slab_fill_i32(int32_t* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+bool slab_shape(const Context* ctx, int64_t n, int LH, int vec_dtype, int32_t* logS, int32_t* nslab) {
+  if (ctx->tune.slab_kb <= 0 || vec_dtype == FSC_F64 || n <= 0) return false;
+  const int64_t row = (int64_t)LH * (vec_dtype == FSC_F32 ? 4 : 2);
+  int64_t S = 1;
+  while (S * 2 * row <= (int64_t)ctx->tune.slab_kb * 1024) S *= 2;
+  if (n <= S) return false;  // the block is one slab: the plain tiles do
+  while ((n + S - 1) / S > kSlabMax) S *= 2;
+  int ls = 0;
+  while ((int64_t(1) << ls) < S) ++ls;
+  *logS = ls;
+  *nslab = (int32_t)((n + S - 1) / S);
+  return true;
+}
+
+static size_t weight_bytes(const fsc_csr* g) {
+  if (!g->val) return 0;
+  return g->val_dtype == FSC_F64 ? 8 : g->val_dtype == FSC_F32 ? 4 : 2;
+}
+
+// Rows per tile: about one tile per resident block, a multiple of 64 in
+// [256, kSlabRows].
+int32_t slab_rows(const Context* ctx, int64_t n) {
+  const int64_t blocks = (int64_t)ctx->num_cu * ctx->tune.slab_bpc;
+  int64_t r = (n + blocks - 1) / std::max<int64_t>(blocks, 1);
+  r = (r + 63) / 64 * 64;
+  return (int32_t)std::min<int64_t>(kSlabRows, std::max<int64_t>(256, r));
+}
+
+size_t slab_workspace_bytes(const Context* ctx, const fsc_csr* g, int LH, int vec_dtype) {
+  int32_t logS, nslab;
+  if (!slab_shape(ctx, g->n, LH, vec_dtype, &logS, &nslab)) return 0;
+  const int64_t n = g->n, nnz = g->nnz;
+  const int32_t rows = slab_rows(ctx, n);
+  const int64_t nt = (n + rows - 1) / rows;
+  const int64_t ml = nnz / (kSlabLong + 1) + 1;
+  const int64_t mc = nnz / kSlabChunk + ml + 1;
+  size_t b = 0;
+  b += align_up(nnz * 4) + align_up(nnz * weight_bytes(g));
+  b += align_up(n * nslab * 2);
+  b += align_up(nt * nslab * (kSlabLong + 1) * 4) + align_up(nt * nslab * 4) + align_up(nt * nslab * 8);
+  b += align_up(nt * 8) + align_up((nt + 1) * 8) + 4 * align_up((nt + 1) * 4);
+  b += align_up(mc * sizeof(LongChunk)) + align_up(16);
+  b += align_up(ml * 2 * LH * 8) + align_up(mc * LH * 4) + align_up(ml * 4);
+  b += 24 * 256;  // alignment slack
+  return b;
+}
+
+int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
+  SlabPlan& sp = io->slab;
+  sp = SlabPlan();
+  const fsc_csr* g = io->g;
+  if (!slab_shape(ctx, g->n, io->LH, io->vec_dtype, &sp.logS, &sp.nslab)) return FSC_OK;
+  const int64_t n = g->n, nnz = g->nnz;
+  sp.rows = slab_rows(ctx, n);
+  const int64_t nt = (n + sp.rows - 1) / sp.rows;
+  sp.enabled = 1;
+  sp.ntiles = (int32_t)nt;
+  sp.max_long = nnz / (kSlabLong + 1) + 1;
+  sp.max_chunks = nnz / kSlabChunk + sp.max_long + 1;
+  sp.scol = a->take<int32_t>(nnz);
+  sp.sval = g->val ? (void*)a->take<char>(nnz * weight_bytes(g)) : nullptr;
+  sp.sperm = a->take<uint16_t>(n * sp.nslab);
+  sp.sbase = a->take<int32_t>(nt * sp.nslab * (kSlabLong + 1));
+  sp.smax = a->take<int32_t>(nt * sp.nslab);
+  sp.sreg = a->take<int64_t>(nt * sp.nslab);
+  sp.tshort = a->take<int64_t>(nt);
+  sp.toff = a->take<int64_t>(nt + 1);
+  sp.tlong = a->take<int32_t>(nt + 1);
+  sp.tchunks = a->take<int32_t>(nt + 1);
+  sp.loff = a->take<int32_t>(nt + 1);
+  sp.coff = a->take<int32_t>(nt + 1);
+  sp.chunks = a->take<LongChunk>(sp.max_chunks);
+  sp.meta = a->take<int32_t>(4);
+  sp.lnorm = a->take<double>(sp.max_long * 2 * io->LH);
+  sp.lpart = a->take<float>(sp.max_chunks * io->LH);
+  sp.lcount = a->take<int32_t>(sp.max_long);
+  if (a->used > a->size) return fail(FSC_E_NOMEM, "workspace arena too small for the slab plan");
+  return FSC_OK;
+}
+
+template <typename W>
+static void launch_build(const fsc_csr* g, SlabPlan& sp, hipStream_t s) {
+  hipLaunchKernelGGL((slab_build_kernel<W>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
+                     reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.logS, sp.nslab, sp.toff, sp.loff,
+                     sp.coff, sp.scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax, sp.sreg,
+                     sp.chunks);
+}
+
+int slab_build(Context*, EmbedIO* io, hipStream_t s) {
+  SlabPlan& sp = io->slab;
+  const fsc_csr* g = io->g;
+  const int32_t n = (int32_t)g->n;
+  hipLaunchKernelGGL(slab_count_kernel, dim3(sp.ntiles), dim3(256), 0, s, g->row_ptr, n, sp.rows, sp.tshort,
+                     sp.tlong, sp.tchunks);
+  hipLaunchKernelGGL(slab_scan_kernel, dim3(1), dim3(1024), 0, s, sp.tshort, sp.tlong, sp.tchunks, sp.ntiles,
+                     sp.toff, sp.loff, sp.coff, sp.meta);
+  if (!g->val) {
+    launch_build<void>(g, sp, s);
+  } else if (g->val_dtype == FSC_F32) {
+    launch_build<float>(g, sp, s);
+  } else if (g->val_dtype == FSC_BF16) {
+    launch_build<bf16_t>(g, sp, s);
+  } else {
+    return fail(FSC_E_UNSUPPORTED, "the slab form takes f32 or bf16 weights");
+  }
+  hipLaunchKernelGGL(slab_fill_i32, dim3((int)std::min<int64_t>((sp.max_long + 255) / 256, 1024)), dim3(256), 0,
+                     s, sp.lcount, sp.max_long);
+  return check_hip(hipGetLastError(), "slab plan kernels");
+}
+
+}  // namespace fsc

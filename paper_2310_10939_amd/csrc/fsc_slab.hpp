@@ -1,0 +1,136 @@
+// Column-slab form of the sparse product of one PowerMethod step, for blocks
+// Z too large for one XCD's L2.
+//
+// The gathers of Z rows dominate a step on a large sparse graph: one random
+// 8..32-byte row per nonzero.  They run at the L2's request rate only while
+// the rows an XCD touches fit its 4 MB L2; spread over a 16 MB block they
+// miss to the Infinity Cache and run almost 3x slower.  So the columns are
+// cut into nslab slabs of about 2 MB of Z each, and a step makes nslab phases:
+// in phase p every block gathers only from slab p, so each XCD's L2 holds one
+// slab at a time.
+//
+// Layout (built once per graph, fsc_slab.hip): the rows are cut into tiles of
+// at most kSlabRows consecutive rows (about one tile per resident block).  In each (tile, phase) the rows' nonzeros in
+// the phase's slab are stored in jagged-diagonal order: rows sorted by their
+// segment length (longest first), and diagonal k holds the k-th nonzero of
+// every row longer than k, in sorted order.  A wave takes 64 sorted rows, one
+// per lane, so the loads of diagonal k by a wave are contiguous, and no
+// padding is stored.  Per-row sums of a phase are added to an LDS accumulator
+// in a fixed order (phase by phase, diagonal by diagonal), so results are
+// deterministic.  Rows longer than kSlabLong are left out of the tiles and
+// summed by the long-row chunks of the plain tile kernel (original CSR).
+#pragma once
+
+#include "fsc_tiles.hpp"
+
+namespace fsc {
+
+struct SlabArgs {
+  int32_t ntiles, rows, nslab, logS;  // tiles of `rows` consecutive rows (<= kSlabRows)
+  const int32_t* scol;    // column indices in slab order
+  const uint16_t* sperm;  // tile T, phase p, sorted position i -> local row, at r0*nslab + p*R + i
+  const int32_t* sbase;   // [ntiles*nslab][kSlabLong+1]: start of diagonal k within the region
+  const int32_t* smax;    // [ntiles*nslab]: longest segment of the (tile, phase)
+  const int64_t* sreg;    // [ntiles*nslab]: start of the (tile, phase) region
+};
+
+
+// Start of diagonal kk of the current (tile, phase): from the lane-resident
+// copy of the first 64 starts, else from memory.
+__device__ __forceinline__ int32_t diag_start(const int32_t* base, int32_t lane_copy, int32_t kk) {
+  return kk < FSC_WAVE ? __builtin_amdgcn_readlane(lane_copy, kk) : base[kk];
+}
+
+template <int kU, class Op>
+__global__ __launch_bounds__(kBlock) void slab_kernel(Op op_in, TileArgs ta, SlabArgs sb, StatsArgs sa) {
+  constexpr int LH = Op::LH;
+  using A = typename Op::A;
+  __shared__ A acc[kSlabRows * LH];
+  __shared__ double red[kBlock / FSC_WAVE];
+  __shared__ double blk[2 * LH];  // this block's statistics so far (thread 0 adds)
+  Op op = op_in;
+  op.init();
+  if (threadIdx.x < 2 * LH) blk[threadIdx.x] = 0.0;
+  const int wave = threadIdx.x / FSC_WAVE, lane = threadIdx.x % FSC_WAVE;
+  const int32_t n = ta.n;
+  for (int32_t T = blockIdx.x; T < sb.ntiles; T += gridDim.x) {
+    const int32_t r0 = T * sb.rows;
+    const int32_t R = min(sb.rows, n - r0);
+    for (int i = threadIdx.x; i < R * LH; i += kBlock) acc[i] = A(0);
+    __syncthreads();
+    for (int p = 0; p < sb.nslab; ++p) {
+      const int64_t tp = (int64_t)T * sb.nslab + p;
+      const int32_t maxlen = sb.smax[tp];
+      if (maxlen > 0) {
+        const int64_t reg = sb.sreg[tp];
+        const int32_t* base = sb.sbase + tp * (kSlabLong + 1);
+        const uint16_t* perm = sb.sperm + (int64_t)r0 * sb.nslab + (int64_t)p * R;
+        // diagonal starts 0..63 live in the lanes of every wave
+        const int32_t bl = lane <= maxlen ? base[lane] : 0;
+        const int32_t active = diag_start(base, bl, 1);  // rows with a nonempty segment
+        for (int32_t s0 = wave * FSC_WAVE; s0 < active; s0 += kBlock) {
+          const int32_t i = s0 + lane;
+          const int rl = i < active ? (int)perm[i] : 0;
+          A a[LH];
+#pragma unroll
+          for (int q = 0; q < LH; ++q) a[q] = A(0);
+          int32_t b0 = 0;
+          for (int32_t k = 0; k < maxlen; k += kU) {
+            int32_t off[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+              const int32_t kk = k + u;
+              off[u] = -1;
+              if (kk < maxlen) {
+                const int32_t b1 = diag_start(base, bl, kk + 1);
+                if (i < b1 - b0) off[u] = b0 + i;
+                b0 = b1;
+              }
+            }
+            op.template accumulate_at<kU>(sb.scol, reg, off, a);
+            // rows are sorted by length: once diagonal k+kU is no longer than
+            // s0 rows, the whole slice is done
+            const int32_t kn = k + kU;
+            if (kn < maxlen && s0 >= diag_start(base, bl, kn + 1) - b0) break;
+          }
+          if (i < active) {
+#pragma unroll
+            for (int q = 0; q < LH; ++q) acc[rl * LH + q] += a[q];
+          }
+        }
+      }
+      __syncthreads();  // the next phase may give a row to another wave
+    }
+    // statistics stay out of registers during the phases: each tile's are
+    // reduced over the block and added to blk in tile order
+    double st[2 * LH];
+#pragma unroll
+    for (int q = 0; q < 2 * LH; ++q) st[q] = 0.0;
+    for (int32_t rl = threadIdx.x; rl < R; rl += kBlock) {
+      const int32_t r = r0 + rl;
+      if (ta.row_ptr[r + 1] - ta.row_ptr[r] > kSlabLong) continue;  // finished by its chunks
+      typename Op::Pre pre;
+      op.prefetch(r, pre);
+      op.finish(r, &acc[rl * LH], pre, st);
+    }
+    if constexpr (Op::STATS) {
+#pragma unroll
+      for (int q = 0; q < 2 * LH; ++q) {
+        const double v = block_sum<kBlock>(st[q], red);
+        if (threadIdx.x == 0) blk[q] += v;
+      }
+    }
+    __syncthreads();
+  }
+  const int32_t nch = ta.meta[0];
+  for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) long_chunk<kU>(op, ta, c);
+  if constexpr (Op::STATS) {
+    __syncthreads();
+    double st[2 * LH];
+#pragma unroll
+    for (int q = 0; q < 2 * LH; ++q) st[q] = threadIdx.x == 0 ? blk[q] : 0.0;
+    op.epilogue(sa, st);
+  }
+}
+
+}  // namespace fsc

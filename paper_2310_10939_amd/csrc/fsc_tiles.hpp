@@ -40,6 +40,29 @@ __device__ __forceinline__ int lanes_per_row(int64_t R, int64_t nz) {
 // ---------------------------------------------------------------------------
 // Row-reduction operators
 // ---------------------------------------------------------------------------
+// acc += sum_u w[u] * Z[c[u]] over U gathered rows (c[u] < 0: skipped); all
+// U loads are issued before the first use.
+template <typename S, typename W, int LH, int U, typename A>
+__device__ __forceinline__ void gather_rows(const S* __restrict__ z, const int32_t* c, const A* w, A* acc) {
+  A zr[U][LH];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (c[u] >= 0) {
+      rowio<S, LH>::load(z + (int64_t)c[u] * LH, zr[u]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < LH; ++q) zr[u][q] = A(0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int q = 0; q < LH; ++q) {
+      if constexpr (std::is_void<W>::value) acc[q] += zr[u][q];
+      else acc[q] += w[u] * zr[u][q];
+    }
+}
+
 template <typename W, typename A>
 __device__ __forceinline__ A load_weight(const W* val, int64_t j) {
   if constexpr (std::is_void<W>::value) {
@@ -104,6 +127,7 @@ struct StepOp {
     double d;
   };
   const W* val;
+  const W* sval;   // weights in slab order (column-slab product only)
   const S* zin;
   S* zout;
   const A* hinv;
@@ -126,23 +150,27 @@ struct StepOp {
       c[u] = ok ? nt_load(col + j) : -1;
       w[u] = ok ? load_weight<W, A>(val, j) : A(0);
     }
-    A z[U][LH_];
+    gather_rows<S, W, LH_, U>(zin, c, w, acc);
+  }
+  // The same over positions reg + off[u] of the slab-ordered copy (off < 0:
+  // none); reg is uniform, so the loads take a scalar base and 32-bit offsets.
+  template <int U>
+  __device__ __forceinline__ void accumulate_at(const int32_t* scol, int64_t reg, const int32_t* off,
+                                                A* acc) const {
+    const int32_t* cp = scol + reg;
+    int32_t c[U];
+    A w[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (c[u] >= 0) {
-        rowio<S, LH_>::load(zin + (int64_t)c[u] * LH_, z[u]);
+      const bool ok = off[u] >= 0;
+      c[u] = ok ? nt_load(cp + off[u]) : -1;
+      if constexpr (std::is_void<W>::value) {
+        w[u] = A(1);
       } else {
-#pragma unroll
-        for (int q = 0; q < LH_; ++q) z[u][q] = A(0);
+        w[u] = ok ? load_weight<W, A>(sval + reg, off[u]) : A(0);
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int q = 0; q < LH_; ++q) {
-        if constexpr (std::is_void<W>::value) acc[q] += z[u][q];
-        else acc[q] += w[u] * z[u][q];
-      }
+    gather_rows<S, W, LH_, U>(zin, c, w, acc);
   }
   __device__ __forceinline__ void prefetch(int32_t r, Pre& p) const {
     rowio<S, LH_>::load(zin + (int64_t)r * LH_, p.z);
