@@ -139,3 +139,36 @@ def test_adam_reduces_loss():
         Lmin, _ = fl.loss_terms(cr[None], G[b][None], h[b][None], yy[b:b + 1])
         Lb, _ = fl.loss_terms(fl.mlp_forward(p, F[b:b + 1])[0], G[b][None], h[b][None], yy[b:b + 1])
         assert Lb[0] >= Lmin[0] - 1e-9
+
+
+def test_adam_matches_torch_optimizer():
+    """adam_step against torch.optim.Adam (CPU, float64) on the same gradient
+    sequence: Kingma and Ba's bias-corrected update."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(11)
+    p = rng.standard_normal(50)
+    m = np.zeros_like(p); v = np.zeros_like(p)
+    P = torch.tensor(p.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([P], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    for step in range(1, 31):
+        g = rng.standard_normal(50) * (1 + step % 3)
+        p, m, v = fl.adam_step(p, g, m, v, step, 3e-3)
+        opt.zero_grad()
+        P.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+    assert np.abs(P.detach().numpy() - p).max() < 1e-12
+
+
+def test_features_closed_form_on_a_cycle():
+    """On a cycle every degree is 2: mean 2, coefficient of variation 0,
+    max/mean 1; the shifted and scaled raw statistics follow."""
+    n, k = 40, 3
+    d = np.full(n, 2.0)
+    ray = [0.5, 0.6, 0.7, 0.8]
+    f = fl.features(n, k, d, ray)
+    raw = np.array([np.log(n), np.log(k), np.log(2.0), 0.0, 0.0, *ray])
+    want = (raw - fl.FEAT_SHIFT) / fl.FEAT_SCALE
+    assert np.allclose(f, want, rtol=0, atol=1e-15)
+    # isolated vertices do not enter the degree statistics
+    d2 = np.concatenate([d, np.zeros(5)])
+    assert np.allclose(fl.features(n + 5, k, d2, ray)[2:], want[2:], rtol=0, atol=1e-15)
