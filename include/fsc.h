@@ -127,6 +127,11 @@ typedef struct {
    * an XCD gathers stay in its L2.  Results do not depend on it beyond
    * summation order. */
   int32_t slab_kb;
+  /* Which slab form (0 keeps the current one): 1 phases -- every block walks
+   * all slabs, one at a time; 2 per-XCD -- 8 slabs, one per XCD, whose
+   * per-row partial sums a second kernel adds in slab order; 3 automatic
+   * (default: per-XCD while a slab is at most 3 MiB, else phases). */
+  int32_t slab_mode;
 } fsc_tuning;
 
 /* Creates a context on HIP device `device` (makes it current on the calling

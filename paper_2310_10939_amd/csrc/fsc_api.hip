@@ -370,6 +370,7 @@ int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, f
         for (int xo : {1, 0}) {
           Tune tu;
           tu.slab_kb = saved.slab_kb;
+          tu.slab_mode = saved.slab_mode;
           tu.tile_nnz = tile;
           tu.unroll = un;
           tu.blocks_per_cu = bpc;
@@ -413,6 +414,7 @@ int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, f
   best->xcd_order = bestt.xcd_order ? 1 : 2;
   best->unroll = bestt.unroll;
   best->slab_kb = bestt.slab_kb > 0 ? bestt.slab_kb : -1;
+  best->slab_mode = bestt.slab_mode == 0 ? 3 : bestt.slab_mode;
   return FSC_OK;
 }
 
@@ -636,12 +638,15 @@ int fsc_tuning_set(fsc_context* ctx, fsc_tuning* t) {
   }
   if (t->slab_kb > 65536) return fail(FSC_E_ARG, "slab_kb must be <= 65536");
   if (t->slab_kb != 0) nt.slab_kb = t->slab_kb > 0 ? t->slab_kb : -1;
+  if (t->slab_mode < 0 || t->slab_mode > 3) return fail(FSC_E_ARG, "slab_mode must be in [0, 3]");
+  if (t->slab_mode != 0) nt.slab_mode = t->slab_mode == 3 ? 0 : t->slab_mode;
   ctx->c.tune = nt;
   t->tile_nnz = nt.tile_nnz;
   t->blocks_per_cu = nt.blocks_per_cu;
   t->xcd_order = nt.xcd_order ? 1 : 2;
   t->unroll = nt.unroll;
   t->slab_kb = nt.slab_kb > 0 ? nt.slab_kb : -1;
+  t->slab_mode = nt.slab_mode == 0 ? 3 : nt.slab_mode;
   return FSC_OK;
 }
 

@@ -283,8 +283,13 @@ static int launch_tiles(const Op& op, const TileArgs& ta, const StatsArgs& sa, i
 
 template <class Op>
 static int launch_slab(const Op& op, const TileArgs& ta, const SlabArgs& sb, const StatsArgs& sa, int grid,
-                       hipStream_t s) {
-  hipLaunchKernelGGL((slab_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb, sa);
+                       int rgrid, hipStream_t s) {
+  if (sb.xcd) {
+    hipLaunchKernelGGL((slab_xcd_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb);
+    hipLaunchKernelGGL((slab_reduce_kernel<Op>), dim3(rgrid), dim3(kBlock), 0, s, op, ta, sb, sa);
+  } else {
+    hipLaunchKernelGGL((slab_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb, sa);
+  }
   return check_hip(hipGetLastError(), "slab_kernel launch");
 }
 
@@ -293,7 +298,7 @@ template <class Op>
 static int launch_step(const Op& op, const TileArgs& ta, const SlabArgs* sb, const StatsArgs& sa, int grid,
                        int unroll, hipStream_t s) {
   if constexpr (!std::is_same<typename Op::A, double>::value) {
-    if (sb) return launch_slab(op, ta, *sb, sa, grid, s);
+    if (sb) return launch_slab(op, ta, *sb, sa, grid, sb->rgrid, s);
   }
   return launch_tiles(op, ta, sa, grid, unroll, s);
 }
@@ -437,7 +442,9 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
   sb.ntiles = sp.ntiles;
   sb.rows = sp.rows;
   sb.nslab = sp.nslab;
-  sb.logS = sp.logS;
+  sb.xcd = sp.xcd;
+  sb.part = sp.part;
+  sb.rgrid = persistent_grid(ctx, ((int64_t)n + kBlock - 1) / kBlock, 8);
   sb.scol = sp.scol;
   sb.sperm = sp.sperm;
   sb.sbase = sp.sbase;

@@ -68,6 +68,7 @@ struct Tune {
   int unroll = 4;          // nonzeros in flight per lane
   int slab_kb = 1024;      // column-slab size (KiB of the start block); <= 0: off
   int slab_bpc = 6;        // resident blocks per CU of the column-slab kernel
+  int slab_mode = 0;       // 0 automatic, 1 phases, 2 per-XCD slabs
 };
 
 // Tile plan of one graph for the sparse product (built on the device).
@@ -86,7 +87,9 @@ struct Plan {
 // Column-slab plan of one graph (built on the device by slab_build).
 struct SlabPlan {
   int enabled = 0;
-  int32_t logS = 0, nslab = 0, ntiles = 0, rows = 0;
+  int32_t S = 0, nslab = 0, ntiles = 0, rows = 0;  // slabs of S columns
+  int xcd = 0;                 // 1: per-XCD slabs with partial sums
+  float* part = nullptr;       // per-XCD form: [nslab][n][LH] partial sums
   int64_t max_long = 0, max_chunks = 0;
   int32_t* scol = nullptr;     // [nnz] column indices in slab order
   void* sval = nullptr;        // [nnz] weights in slab order (null: unit weights)
@@ -189,9 +192,10 @@ int embed_to_points(Context* ctx, const EmbedIO* io, float* pts, hipStream_t s);
 int validate_csr(Context* ctx, const fsc_csr* g, hipStream_t s);
 
 // ---- column-slab plan (fsc_slab.hip) ----
-// Slab shape for an n-row block of LH columns: true (and logS, nslab) when
-// the block is larger than one slab of ctx->tune.slab_kb KiB.
-bool slab_shape(const Context* ctx, int64_t n, int LH, int vec_dtype, int32_t* logS, int32_t* nslab);
+// Slab shape for an n-row block of LH columns: true (and the slab width S,
+// nslab, and the form) when the block is larger than one slab of
+// ctx->tune.slab_kb KiB.
+bool slab_shape(const Context* ctx, int64_t n, int LH, int vec_dtype, int32_t* S, int32_t* nslab, int* xcd);
 size_t slab_workspace_bytes(const Context* ctx, const fsc_csr* g, int LH, int vec_dtype);
 // Takes the slab arrays from the arena (sets io->slab.enabled when used).
 int slab_bind(Context* ctx, Arena* a, EmbedIO* io);

@@ -23,9 +23,10 @@ namespace fsc {
 static_assert(kSlabLong == 256, "the diagonal scan uses one 256-thread block pass");
 static_assert(kSlabRows == 1024, "one build thread per row of a tile");
 
-__device__ __forceinline__ int slab_of(int32_t c, int logS, int last) {
-  const int p = c >> logS;
-  return p < 0 ? 0 : (p > last ? last : p);
+// Slab of column c: slabs are S consecutive columns.
+__device__ __forceinline__ int slab_of(int32_t c, int32_t S, int last) {
+  const int p = c < 0 ? 0 : c / S;
+  return p > last ? last : p;
 }
 
 __global__ __launch_bounds__(256) void slab_count_kernel(const int64_t* __restrict__ row_ptr, int32_t n,
@@ -100,7 +101,7 @@ constexpr int kBuildU = 8;    // nonzeros of a row loaded at once
 template <typename W>
 __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const W* __restrict__ val, int32_t n,
-    int32_t rows, int32_t logS, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
+    int32_t rows, int32_t S, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
     const int32_t* __restrict__ coff, int32_t* __restrict__ scol, W* __restrict__ sval, uint16_t* __restrict__ sperm,
     int32_t* __restrict__ sbase, int32_t* __restrict__ smax, int64_t* __restrict__ sreg,
     LongChunk* __restrict__ chunks) {
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
       for (int u = 0; u < kBuildU; ++u) c[u] = j0 + u < b ? col[j0 + u] : 0;
 #pragma unroll
       for (int u = 0; u < kBuildU; ++u)
-        if (j0 + u < b) cnt[slab_of(c[u], logS, last) * R + rl] += 1;
+        if (j0 + u < b) cnt[slab_of(c[u], S, last) * R + rl] += 1;
     }
   }
   __syncthreads();
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
 #pragma unroll
       for (int u = 0; u < kBuildU; ++u) {
         if (j0 + u < b) {
-          const int p = slab_of(c[u], logS, last);
+          const int p = slab_of(c[u], S, last);
           const int kk = cnt[p * R + rl]++;
           const int64_t pos = regL[p] + baseL[p * (kSlabLong + 1) + kk] + spos[p * R + rl];
           scol[pos] = c[u];
@@ -255,17 +256,34 @@ __global__ void slab_fill_i32(int32_t* p, int64_t count) {
 // ===========================================================================
 // Host side
 // ===========================================================================
-bool slab_shape(const Context* ctx, int64_t n, int LH, int vec_dtype, int32_t* logS, int32_t* nslab) {
+// Which slab form a block of n rows x LH columns takes (slab_kb of the
+// context's tuning, slab_mode 0 automatic, 1 phases, 2 per-XCD):
+//   - none when the block fits one slab (FP64 blocks never take one);
+//   - per-XCD: 8 slabs of ceil(n/8) rows, one per XCD, when a slab is at most
+//     kXcdSlabMax bytes (the partial sums cost 2 x 8 reads and writes of the
+//     block per step);
+//   - phases: slabs of a power of two rows of at most slab_kb KiB, no more
+//     than kSlabMax of them (larger slabs if needed).
+constexpr int64_t kXcdSlabMax = 3 << 20;
+
+bool slab_shape(const Context* ctx, int64_t n, int LH, int vec_dtype, int32_t* S_out, int32_t* nslab, int* xcd) {
   if (ctx->tune.slab_kb <= 0 || vec_dtype == FSC_F64 || n <= 0) return false;
   const int64_t row = (int64_t)LH * (vec_dtype == FSC_F32 ? 4 : 2);
   int64_t S = 1;
   while (S * 2 * row <= (int64_t)ctx->tune.slab_kb * 1024) S *= 2;
   if (n <= S) return false;  // the block is one slab: the plain tiles do
+  const int64_t sx = (n + 7) / 8;
+  const bool per_xcd = ctx->tune.slab_mode == 2 || (ctx->tune.slab_mode == 0 && sx * row <= kXcdSlabMax);
+  if (per_xcd) {
+    *S_out = (int32_t)sx;
+    *nslab = (int32_t)((n + sx - 1) / sx);
+    *xcd = 1;
+    return true;
+  }
   while ((n + S - 1) / S > kSlabMax) S *= 2;
-  int ls = 0;
-  while ((int64_t(1) << ls) < S) ++ls;
-  *logS = ls;
+  *S_out = (int32_t)S;
   *nslab = (int32_t)((n + S - 1) / S);
+  *xcd = 0;
   return true;
 }
 
@@ -274,9 +292,11 @@ static size_t weight_bytes(const fsc_csr* g) {
   return g->val_dtype == FSC_F64 ? 8 : g->val_dtype == FSC_F32 ? 4 : 2;
 }
 
-// Rows per tile: about one tile per resident block, a multiple of 64 in
-// [256, kSlabRows].
-int32_t slab_rows(const Context* ctx, int64_t n) {
+// Rows per tile.  Phase form: about one tile per resident block, a multiple
+// of 64 in [256, kSlabRows], so blocks move through the slabs together.
+// Per-XCD form: kSlabRows (each (tile, slab) region is a work item).
+int32_t slab_rows(const Context* ctx, int64_t n, int xcd) {
+  if (xcd) return kSlabRows;
   const int64_t blocks = (int64_t)ctx->num_cu * ctx->tune.slab_bpc;
   int64_t r = (n + blocks - 1) / std::max<int64_t>(blocks, 1);
   r = (r + 63) / 64 * 64;
@@ -284,10 +304,11 @@ int32_t slab_rows(const Context* ctx, int64_t n) {
 }
 
 size_t slab_workspace_bytes(const Context* ctx, const fsc_csr* g, int LH, int vec_dtype) {
-  int32_t logS, nslab;
-  if (!slab_shape(ctx, g->n, LH, vec_dtype, &logS, &nslab)) return 0;
+  int32_t S, nslab;
+  int xcd;
+  if (!slab_shape(ctx, g->n, LH, vec_dtype, &S, &nslab, &xcd)) return 0;
   const int64_t n = g->n, nnz = g->nnz;
-  const int32_t rows = slab_rows(ctx, n);
+  const int32_t rows = slab_rows(ctx, n, xcd);
   const int64_t nt = (n + rows - 1) / rows;
   const int64_t ml = nnz / (kSlabLong + 1) + 1;
   const int64_t mc = nnz / kSlabChunk + ml + 1;
@@ -298,6 +319,7 @@ size_t slab_workspace_bytes(const Context* ctx, const fsc_csr* g, int LH, int ve
   b += align_up(nt * 8) + align_up((nt + 1) * 8) + 4 * align_up((nt + 1) * 4);
   b += align_up(mc * sizeof(LongChunk)) + align_up(16);
   b += align_up(ml * 2 * LH * 8) + align_up(mc * LH * 4) + align_up(ml * 4);
+  if (xcd) b += align_up((size_t)nslab * n * LH * 4);  // partial sums (float)
   b += 24 * 256;  // alignment slack
   return b;
 }
@@ -306,9 +328,9 @@ int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
   SlabPlan& sp = io->slab;
   sp = SlabPlan();
   const fsc_csr* g = io->g;
-  if (!slab_shape(ctx, g->n, io->LH, io->vec_dtype, &sp.logS, &sp.nslab)) return FSC_OK;
+  if (!slab_shape(ctx, g->n, io->LH, io->vec_dtype, &sp.S, &sp.nslab, &sp.xcd)) return FSC_OK;
   const int64_t n = g->n, nnz = g->nnz;
-  sp.rows = slab_rows(ctx, n);
+  sp.rows = slab_rows(ctx, n, sp.xcd);
   const int64_t nt = (n + sp.rows - 1) / sp.rows;
   sp.enabled = 1;
   sp.ntiles = (int32_t)nt;
@@ -331,6 +353,7 @@ int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
   sp.lnorm = a->take<double>(sp.max_long * 2 * io->LH);
   sp.lpart = a->take<float>(sp.max_chunks * io->LH);
   sp.lcount = a->take<int32_t>(sp.max_long);
+  sp.part = sp.xcd ? a->take<float>((size_t)sp.nslab * n * io->LH) : nullptr;
   if (a->used > a->size) return fail(FSC_E_NOMEM, "workspace arena too small for the slab plan");
   return FSC_OK;
 }
@@ -338,7 +361,7 @@ int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
 template <typename W>
 static void launch_build(const fsc_csr* g, SlabPlan& sp, hipStream_t s) {
   hipLaunchKernelGGL((slab_build_kernel<W>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
-                     reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.logS, sp.nslab, sp.toff, sp.loff,
+                     reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
                      sp.coff, sp.scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax, sp.sreg,
                      sp.chunks);
 }

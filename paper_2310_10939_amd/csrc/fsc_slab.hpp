@@ -26,7 +26,10 @@
 namespace fsc {
 
 struct SlabArgs {
-  int32_t ntiles, rows, nslab, logS;  // tiles of `rows` consecutive rows (<= kSlabRows)
+  int32_t ntiles, rows, nslab;        // tiles of `rows` consecutive rows (<= kSlabRows)
+  int32_t xcd;                        // 1: per-XCD slabs with partial sums (slab_xcd_kernel)
+  int32_t rgrid;                      // per-XCD form: grid of slab_reduce_kernel
+  void* part;                         // per-XCD form: A[nslab][n][LH] partial sums
   const int32_t* scol;    // column indices in slab order
   const uint16_t* sperm;  // tile T, phase p, sorted position i -> local row, at r0*nslab + p*R + i
   const int32_t* sbase;   // [ntiles*nslab][kSlabLong+1]: start of diagonal k within the region
@@ -41,6 +44,57 @@ __device__ __forceinline__ int32_t diag_start(const int32_t* base, int32_t lane_
   return kk < FSC_WAVE ? __builtin_amdgcn_readlane(lane_copy, kk) : base[kk];
 }
 
+// Adds the (tile T, slab p) region's per-row sums to acc (LDS, R x LH): one
+// lane per sorted row, kU nonzeros in flight per lane.
+template <int kU, class Op>
+__device__ __forceinline__ void slab_region(const Op& op, const SlabArgs& sb, int32_t T, int p, int32_t r0,
+                                            int32_t R, typename Op::A* acc) {
+  constexpr int LH = Op::LH;
+  using A = typename Op::A;
+  const int wave = threadIdx.x / FSC_WAVE, lane = threadIdx.x % FSC_WAVE;
+  const int64_t tp = (int64_t)T * sb.nslab + p;
+  const int32_t maxlen = sb.smax[tp];
+  if (maxlen <= 0) return;
+  const int64_t reg = sb.sreg[tp];
+  const int32_t* base = sb.sbase + tp * (kSlabLong + 1);
+  const uint16_t* perm = sb.sperm + (int64_t)r0 * sb.nslab + (int64_t)p * R;
+  // diagonal starts 0..63 live in the lanes of every wave
+  const int32_t bl = lane <= maxlen ? base[lane] : 0;
+  const int32_t active = diag_start(base, bl, 1);  // rows with a nonempty segment
+  for (int32_t s0 = wave * FSC_WAVE; s0 < active; s0 += kBlock) {
+    const int32_t i = s0 + lane;
+    const int rl = i < active ? (int)perm[i] : 0;
+    A a[LH];
+#pragma unroll
+    for (int q = 0; q < LH; ++q) a[q] = A(0);
+    int32_t b0 = 0;
+    for (int32_t k = 0; k < maxlen; k += kU) {
+      int32_t off[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int32_t kk = k + u;
+        off[u] = -1;
+        if (kk < maxlen) {
+          const int32_t b1 = diag_start(base, bl, kk + 1);
+          if (i < b1 - b0) off[u] = b0 + i;
+          b0 = b1;
+        }
+      }
+      op.template accumulate_at<kU>(sb.scol, reg, off, a);
+      // rows are sorted by length: once diagonal k+kU is no longer than s0
+      // rows, the whole slice is done
+      const int32_t kn = k + kU;
+      if (kn < maxlen && s0 >= diag_start(base, bl, kn + 1) - b0) break;
+    }
+    if (i < active) {
+#pragma unroll
+      for (int q = 0; q < LH; ++q) acc[rl * LH + q] += a[q];
+    }
+  }
+}
+
+// Phase form: each block takes whole tiles and walks the slabs in order, so
+// at any time the blocks gather from about one slab.
 template <int kU, class Op>
 __global__ __launch_bounds__(kBlock) void slab_kernel(Op op_in, TileArgs ta, SlabArgs sb, StatsArgs sa) {
   constexpr int LH = Op::LH;
@@ -51,7 +105,6 @@ __global__ __launch_bounds__(kBlock) void slab_kernel(Op op_in, TileArgs ta, Sla
   Op op = op_in;
   op.init();
   if (threadIdx.x < 2 * LH) blk[threadIdx.x] = 0.0;
-  const int wave = threadIdx.x / FSC_WAVE, lane = threadIdx.x % FSC_WAVE;
   const int32_t n = ta.n;
   for (int32_t T = blockIdx.x; T < sb.ntiles; T += gridDim.x) {
     const int32_t r0 = T * sb.rows;
@@ -59,46 +112,7 @@ __global__ __launch_bounds__(kBlock) void slab_kernel(Op op_in, TileArgs ta, Sla
     for (int i = threadIdx.x; i < R * LH; i += kBlock) acc[i] = A(0);
     __syncthreads();
     for (int p = 0; p < sb.nslab; ++p) {
-      const int64_t tp = (int64_t)T * sb.nslab + p;
-      const int32_t maxlen = sb.smax[tp];
-      if (maxlen > 0) {
-        const int64_t reg = sb.sreg[tp];
-        const int32_t* base = sb.sbase + tp * (kSlabLong + 1);
-        const uint16_t* perm = sb.sperm + (int64_t)r0 * sb.nslab + (int64_t)p * R;
-        // diagonal starts 0..63 live in the lanes of every wave
-        const int32_t bl = lane <= maxlen ? base[lane] : 0;
-        const int32_t active = diag_start(base, bl, 1);  // rows with a nonempty segment
-        for (int32_t s0 = wave * FSC_WAVE; s0 < active; s0 += kBlock) {
-          const int32_t i = s0 + lane;
-          const int rl = i < active ? (int)perm[i] : 0;
-          A a[LH];
-#pragma unroll
-          for (int q = 0; q < LH; ++q) a[q] = A(0);
-          int32_t b0 = 0;
-          for (int32_t k = 0; k < maxlen; k += kU) {
-            int32_t off[kU];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-              const int32_t kk = k + u;
-              off[u] = -1;
-              if (kk < maxlen) {
-                const int32_t b1 = diag_start(base, bl, kk + 1);
-                if (i < b1 - b0) off[u] = b0 + i;
-                b0 = b1;
-              }
-            }
-            op.template accumulate_at<kU>(sb.scol, reg, off, a);
-            // rows are sorted by length: once diagonal k+kU is no longer than
-            // s0 rows, the whole slice is done
-            const int32_t kn = k + kU;
-            if (kn < maxlen && s0 >= diag_start(base, bl, kn + 1) - b0) break;
-          }
-          if (i < active) {
-#pragma unroll
-            for (int q = 0; q < LH; ++q) acc[rl * LH + q] += a[q];
-          }
-        }
-      }
+      slab_region<kU>(op, sb, T, p, r0, R, acc);
       __syncthreads();  // the next phase may give a row to another wave
     }
     // statistics stay out of registers during the phases: each tile's are
@@ -131,6 +145,67 @@ __global__ __launch_bounds__(kBlock) void slab_kernel(Op op_in, TileArgs ta, Sla
     for (int q = 0; q < 2 * LH; ++q) st[q] = threadIdx.x == 0 ? blk[q] : 0.0;
     op.epilogue(sa, st);
   }
+}
+
+// Per-XCD form: blocks reach the 8 XCDs round-robin by index, and block b
+// takes only the regions of slabs b % 8, b % 8 + 8, ...: each XCD gathers
+// from its own slab the whole time, whatever the pace of other blocks.  The
+// rows' sums of each slab go to part[slab]; slab_reduce_kernel adds them in
+// slab order and applies the row operator.  Long rows are summed and finished
+// by their chunks here.
+template <int kU, class Op>
+__global__ __launch_bounds__(kBlock) void slab_xcd_kernel(Op op_in, TileArgs ta, SlabArgs sb) {
+  constexpr int LH = Op::LH;
+  using A = typename Op::A;
+  __shared__ A acc[kSlabRows * LH];
+  Op op = op_in;
+  op.init();
+  const int32_t n = ta.n;
+  const int x = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
+  A* part = reinterpret_cast<A*>(sb.part);
+  for (int p = x; p < sb.nslab; p += 8)
+    for (int32_t T = slot; T < sb.ntiles; T += per) {
+      const int32_t r0 = T * sb.rows;
+      const int32_t R = min(sb.rows, n - r0);
+      for (int i = threadIdx.x; i < R * LH; i += kBlock) acc[i] = A(0);
+      __syncthreads();
+      slab_region<kU>(op, sb, T, p, r0, R, acc);
+      __syncthreads();
+      A* dst = part + ((int64_t)p * n + r0) * LH;
+      for (int i = threadIdx.x; i < R * LH; i += kBlock) dst[i] = acc[i];
+      __syncthreads();
+    }
+  const int32_t nch = ta.meta[0];
+  for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) long_chunk<kU>(op, ta, c);
+}
+
+template <class Op>
+__global__ __launch_bounds__(kBlock) void slab_reduce_kernel(Op op_in, TileArgs ta, SlabArgs sb, StatsArgs sa) {
+  constexpr int LH = Op::LH;
+  using A = typename Op::A;
+  Op op = op_in;
+  op.init();
+  const int32_t n = ta.n;
+  const A* part = reinterpret_cast<const A*>(sb.part);
+  double st[2 * LH];
+#pragma unroll
+  for (int q = 0; q < 2 * LH; ++q) st[q] = 0.0;
+  for (int32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+    if (ta.row_ptr[r + 1] - ta.row_ptr[r] > kSlabLong) continue;  // finished by its chunks
+    A sum[LH];
+#pragma unroll
+    for (int q = 0; q < LH; ++q) sum[q] = A(0);
+    for (int p = 0; p < sb.nslab; ++p) {
+      A v[LH];
+      rowio<A, LH>::load(part + ((int64_t)p * n + r) * LH, v);
+#pragma unroll
+      for (int q = 0; q < LH; ++q) sum[q] += v[q];
+    }
+    typename Op::Pre pre;
+    op.prefetch(r, pre);
+    op.finish(r, sum, pre, st);
+  }
+  if constexpr (Op::STATS) op.epilogue(sa, st);
 }
 
 }  // namespace fsc

@@ -40,7 +40,8 @@ class Opts(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_nnz", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("xcd_order", ctypes.c_int32), ("unroll", ctypes.c_int32), ("slab_kb", ctypes.c_int32)]
+                ("xcd_order", ctypes.c_int32), ("unroll", ctypes.c_int32), ("slab_kb", ctypes.c_int32),
+                ("slab_mode", ctypes.c_int32)]
 
 
 _vp, _i32, _i64, _u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
@@ -227,7 +228,7 @@ def autotune(indptr, indices, data, l, steps=5):
     t = Tuning()
     _check(_lib.fsc_autotune(context(indptr.device.index), ctypes.byref(g), l, steps, ctypes.byref(t), _stream()))
     return {"tile_nnz": t.tile_nnz, "blocks_per_cu": t.blocks_per_cu, "xcd_order": t.xcd_order, "unroll": t.unroll,
-            "slab_kb": t.slab_kb}
+            "slab_kb": t.slab_kb, "slab_mode": t.slab_mode}
 
 
 # ---------------------------------------------------------------------------
@@ -332,14 +333,15 @@ def ari(a, b, ka, kb):
     return out
 
 
-def tuning(tile_nnz=0, blocks_per_cu=0, xcd_order=0, unroll=0, slab_kb=0, device=None):
+def tuning(tile_nnz=0, blocks_per_cu=0, xcd_order=0, unroll=0, slab_kb=0, slab_mode=0, device=None):
     """Sets the sparse-product launch shape (0 keeps a field; slab_kb < 0
-    turns the column-slab form off) and returns the current one as a dict
-    (xcd_order: 1 contiguous per XCD, 2 round robin)."""
-    t = Tuning(tile_nnz, blocks_per_cu, xcd_order, unroll, slab_kb)
+    turns the column-slab form off; slab_mode 1 phases, 2 per-XCD, 3
+    automatic) and returns the current one as a dict (xcd_order: 1 contiguous
+    per XCD, 2 round robin)."""
+    t = Tuning(tile_nnz, blocks_per_cu, xcd_order, unroll, slab_kb, slab_mode)
     _check(_lib.fsc_tuning_set(context(device), ctypes.byref(t)))
     return {"tile_nnz": t.tile_nnz, "blocks_per_cu": t.blocks_per_cu, "xcd_order": t.xcd_order,
-            "unroll": t.unroll, "slab_kb": t.slab_kb}
+            "unroll": t.unroll, "slab_kb": t.slab_kb, "slab_mode": t.slab_mode}
 
 
 def timing_enable(on=True, device=None):

@@ -49,4 +49,4 @@ def test_struct_layouts_match_header():
     # int64 n, nnz, 3 pointers, int32 dtype (+pad) ; opts: 4 int32, 3 pointers, int32 (+pad)
     assert ctypes.sizeof(fsc.Csr) == 8 * 5 + 8
     assert ctypes.sizeof(fsc.Opts) == 4 * 4 + 8 * 3 + 8
-    assert ctypes.sizeof(fsc.Tuning) == 5 * 4
+    assert ctypes.sizeof(fsc.Tuning) == 6 * 4

@@ -1,8 +1,9 @@
 """Column-slab form of the sparse product: parity with the FP64 oracle and
 with the plain tile kernel.
 
-Small graphs are cut into many slabs by a small slab size (4 KiB of the
-block), with long rows (hubs, summed by chunks of the original CSR),
+Both forms are checked: phases (every block walks the slabs) and per-XCD
+(8 slabs, partial sums added by a second kernel).  Small graphs are cut into
+many slabs by a small slab size (4 KiB of the block), with long rows (hubs, summed by chunks of the original CSR),
 isolated vertices and a ragged last tile of rows.  The full-size test runs
 the 1M-vertex SBM (vertex ids permuted, as the benchmark's default workload)
 in the launch configuration the benchmark times (default tuning: 1 MiB
@@ -24,30 +25,36 @@ TOL = {"f32": 1e-5, "bf16": 2e-2}
 
 @pytest.fixture
 def slab(gpu_lib):
-    def set_kb(kb):
-        return gpu_lib.tuning(slab_kb=kb)
+    def set_kb(kb, mode=0):
+        return gpu_lib.tuning(slab_kb=kb, slab_mode=mode)
     yield set_kb
-    gpu_lib.tuning(slab_kb=1024)
+    gpu_lib.tuning(slab_kb=1024, slab_mode=3)
 
 
 def test_slab_size_is_reported(gpu_lib, slab):
     assert slab(4)["slab_kb"] == 4
     assert slab(-1)["slab_kb"] == -1
     assert slab(1024)["slab_kb"] == 1024
+    assert slab(0, 1)["slab_mode"] == 1
+    assert slab(0, 2)["slab_mode"] == 2
+    assert slab(0, 3)["slab_mode"] == 3
+    with pytest.raises(RuntimeError):
+        slab(0, 4)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("l", [1, 2, 3, 4, 6, 8])
 @pytest.mark.parametrize("vec,wt", [("f32", "f32"), ("f32", "none"), ("bf16", "bf16")])
-def test_slab_matches_oracle_and_tiles(gpu_lib, slab, l, vec, wt):
+def test_slab_matches_oracle_and_tiles(gpu_lib, slab, l, vec, wt, mode):
     # 5000 rows: 20 tiles of 256 rows, the last one ragged; hubs of 1200
     # nonzeros are long rows; 17 isolated vertices at the end
     g = synth.random_weighted(5000, 30000, seed=20 + l, hubs=5, hub_degree=1200, isolated=17)
     ip, ix, d = to_device(g, wt)
     want = o.embed(g.n, g.indptr, g.indices, host_weights(d), l, 7, seed=3)
-    say(f"slab n=5000 nnz={g.nnz} l={l} vec={vec} weights={wt}")
+    say(f"slab n=5000 nnz={g.nnz} l={l} vec={vec} weights={wt} mode={mode}")
     slab(-1)
     plain = gpu_lib.embed(ip, ix, d, l, 7, seed=3, vec_dtype=vec).float().cpu().numpy()
-    slab(4)
+    slab(4, mode)
     E = gpu_lib.embed(ip, ix, d, l, 7, seed=3, vec_dtype=vec).float().cpu().numpy()
     err, err_plain = col_rel_err(E, want), col_rel_err(plain, want)
     say("  rel err slab", err, "tiles", err_plain)
@@ -57,11 +64,12 @@ def test_slab_matches_oracle_and_tiles(gpu_lib, slab, l, vec, wt):
         assert col_rel_err(E, plain) <= 1e-5
 
 
-def test_slab_traces_and_renorm(gpu_lib, slab):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_slab_traces_and_renorm(gpu_lib, slab, mode):
     g = synth.random_weighted(4000, 20000, seed=11, hubs=3, hub_degree=900, isolated=5)
     ip, ix, d = to_device(g, "f32")
     _, sq_o, ray_o = o.embed(g.n, g.indptr, g.indices, host_weights(d), 3, 12, seed=4, traced=True)
-    slab(4)
+    slab(4, mode)
     E, sq, ray = gpu_lib.embed(ip, ix, d, 3, 12, seed=4, traces=True)
     sq, ray = sq.cpu().numpy(), ray.cpu().numpy()
     assert np.abs(sq - sq_o).max() <= 1e-4 * np.abs(sq_o).max()
@@ -71,20 +79,22 @@ def test_slab_traces_and_renorm(gpu_lib, slab):
     assert np.abs(sqn.cpu().numpy() - sq_o).max() <= 1e-4 * np.abs(sq_o).max()
 
 
-def test_slab_deterministic(gpu_lib, slab):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_slab_deterministic(gpu_lib, slab, mode):
     g = synth.random_weighted(6000, 50000, seed=2, hubs=3, hub_degree=3000)
     ip, ix, d = to_device(g, "f32")
-    slab(8)
+    slab(8, mode)
     a = gpu_lib.embed(ip, ix, d, 4, 10, seed=9, traces=True)
     b = gpu_lib.embed(ip, ix, d, 4, 10, seed=9, traces=True)
     for x, y in zip(a, b):
         assert torch.equal(x, y)
 
 
-def test_slab_cluster_small(gpu_lib, slab):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_slab_cluster_small(gpu_lib, slab, mode):
     g = synth.sbm_by_degree(20000, 6, 24, 3, seed=5, permute=True)
     ip, ix, _ = to_device(g)
-    slab(16)
+    slab(16, mode)
     lab = gpu_lib.cluster(ip, ix, None, 6, 4, 25, 1, kmeans_iters=20)
     lab_o, _, _ = o.fast_spectral_cluster(g.n, g.indptr, g.indices, None, 6, 4, 25, 1, 20)
     ari = float(gpu_lib.ari(lab, torch.from_numpy(np.asarray(lab_o, dtype=np.int32)).cuda(), 6, 6))
