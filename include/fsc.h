@@ -130,7 +130,7 @@ typedef struct {
   /* Which slab form (0 keeps the current one): 1 phases -- every block walks
    * all slabs, one at a time; 2 per-XCD -- 8 slabs, one per XCD, whose
    * per-row partial sums a second kernel adds in slab order; 3 automatic
-   * (default: per-XCD while a slab is at most 3 MiB, else phases). */
+   * (default: phases). */
   int32_t slab_mode;
 } fsc_tuning;
 

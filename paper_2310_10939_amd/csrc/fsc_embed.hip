@@ -444,13 +444,15 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
   sb.nslab = sp.nslab;
   sb.xcd = sp.xcd;
   sb.part = sp.part;
+  sb.tunit = sp.tunit;
   sb.rgrid = persistent_grid(ctx, ((int64_t)n + kBlock - 1) / kBlock, 8);
   sb.scol = sp.scol;
   sb.sperm = sp.sperm;
   sb.sbase = sp.sbase;
   sb.smax = sp.smax;
   sb.sreg = sp.sreg;
-  io->grid = persistent_grid(ctx, sp.ntiles, ctx->tune.slab_bpc);
+  io->grid = sp.xcd ? persistent_grid(ctx, (int64_t)sp.ntiles * sp.nslab, ctx->tune.slab_xcd_bpc)
+                    : persistent_grid(ctx, sp.ntiles, ctx->tune.slab_bpc);
   return run_steps<S, W, LH>(ctx, io, ts, &sb, ss, s, stats);
 }
 

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     int32_t rows, int32_t S, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
     const int32_t* __restrict__ coff, int32_t* __restrict__ scol, W* __restrict__ sval, uint16_t* __restrict__ sperm,
     int32_t* __restrict__ sbase, int32_t* __restrict__ smax, int64_t* __restrict__ sreg,
-    LongChunk* __restrict__ chunks) {
+    LongChunk* __restrict__ chunks, uint8_t* __restrict__ tunit) {
   __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
   __shared__ uint16_t spos[kSlabMax * kSlabRows];  // sorted position of each row per slab
   __shared__ int32_t hist[kSlabLong + 1];          // rows per segment length
@@ -198,6 +198,7 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   // row's segment)
   for (int i = threadIdx.x; i < nslab * R; i += kBuild) cnt[i] = 0;
   __syncthreads();
+  int unit = 1;  // every weight of this thread's row is exactly 1
   if (shortrow) {
     for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
       using WS = typename std::conditional<std::is_void<W>::value, char, W>::type;
@@ -217,10 +218,19 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
           const int kk = cnt[p * R + rl]++;
           const int64_t pos = regL[p] + baseL[p * (kSlabLong + 1) + kk] + spos[p * R + rl];
           scol[pos] = c[u];
-          if constexpr (!std::is_void<W>::value) sval[pos] = w[u];
+          if constexpr (!std::is_void<W>::value) {
+            sval[pos] = w[u];
+            if (weight<W, float>::get(&w[u], 0) != 1.0f) unit = 0;
+          }
         }
       }
     }
+  }
+  // a tile whose short rows all have unit weights skips the weight stream
+  {
+    int32_t tu;
+    block_scan_inclusive<kBuild, int32_t>(unit ? 0 : 1, scan32, &tu);
+    if (threadIdx.x == 0) tunit[T] = tu == 0 ? 1 : 0;
   }
   // long rows: chunks of kSlabChunk nonzeros of the original CSR
   {
@@ -259,13 +269,12 @@ __global__ void slab_fill_i32(int32_t* p, int64_t count) {
 // Which slab form a block of n rows x LH columns takes (slab_kb of the
 // context's tuning, slab_mode 0 automatic, 1 phases, 2 per-XCD):
 //   - none when the block fits one slab (FP64 blocks never take one);
-//   - per-XCD: 8 slabs of ceil(n/8) rows, one per XCD, when a slab is at most
-//     kXcdSlabMax bytes (the partial sums cost 2 x 8 reads and writes of the
-//     block per step);
-//   - phases: slabs of a power of two rows of at most slab_kb KiB, no more
-//     than kSlabMax of them (larger slabs if needed).
-constexpr int64_t kXcdSlabMax = 3 << 20;
-
+//   - phases (automatic): slabs of a power of two rows of at most slab_kb
+//     KiB, no more than kSlabMax of them (larger slabs if needed);
+//   - per-XCD (on request): 8 slabs of ceil(n/8) rows, one per XCD.  Its
+//     gathers are faster (90% L2 hits against 80% on the 1M-vertex SBM),
+//     but the reduce pass reads the partial sums back at a high latency and
+//     loses the gain (370 us per step against 335 us).
 bool slab_shape(const Context* ctx, int64_t n, int LH, int vec_dtype, int32_t* S_out, int32_t* nslab, int* xcd) {
   if (ctx->tune.slab_kb <= 0 || vec_dtype == FSC_F64 || n <= 0) return false;
   const int64_t row = (int64_t)LH * (vec_dtype == FSC_F32 ? 4 : 2);
@@ -273,8 +282,7 @@ bool slab_shape(const Context* ctx, int64_t n, int LH, int vec_dtype, int32_t* S
   while (S * 2 * row <= (int64_t)ctx->tune.slab_kb * 1024) S *= 2;
   if (n <= S) return false;  // the block is one slab: the plain tiles do
   const int64_t sx = (n + 7) / 8;
-  const bool per_xcd = ctx->tune.slab_mode == 2 || (ctx->tune.slab_mode == 0 && sx * row <= kXcdSlabMax);
-  if (per_xcd) {
+  if (ctx->tune.slab_mode == 2) {  // kernels assume at most 8 slabs in this form
     *S_out = (int32_t)sx;
     *nslab = (int32_t)((n + sx - 1) / sx);
     *xcd = 1;
@@ -319,7 +327,8 @@ size_t slab_workspace_bytes(const Context* ctx, const fsc_csr* g, int LH, int ve
   b += align_up(nt * 8) + align_up((nt + 1) * 8) + 4 * align_up((nt + 1) * 4);
   b += align_up(mc * sizeof(LongChunk)) + align_up(16);
   b += align_up(ml * 2 * LH * 8) + align_up(mc * LH * 4) + align_up(ml * 4);
-  if (xcd) b += align_up((size_t)nslab * n * LH * 4);  // partial sums (float)
+  if (xcd) b += align_up((size_t)nslab * ((n + 63) / 64 * 64) * LH * 4);  // partial sums (float)
+  b += align_up(nt);                                     // unit-weight flags
   b += 24 * 256;  // alignment slack
   return b;
 }
@@ -353,7 +362,8 @@ int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
   sp.lnorm = a->take<double>(sp.max_long * 2 * io->LH);
   sp.lpart = a->take<float>(sp.max_chunks * io->LH);
   sp.lcount = a->take<int32_t>(sp.max_long);
-  sp.part = sp.xcd ? a->take<float>((size_t)sp.nslab * n * io->LH) : nullptr;
+  sp.tunit = a->take<uint8_t>(nt);
+  sp.part = sp.xcd ? a->take<float>((size_t)sp.nslab * ((n + 63) / 64 * 64) * io->LH) : nullptr;
   if (a->used > a->size) return fail(FSC_E_NOMEM, "workspace arena too small for the slab plan");
   return FSC_OK;
 }
@@ -363,7 +373,7 @@ static void launch_build(const fsc_csr* g, SlabPlan& sp, hipStream_t s) {
   hipLaunchKernelGGL((slab_build_kernel<W>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
                      reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
                      sp.coff, sp.scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax, sp.sreg,
-                     sp.chunks);
+                     sp.chunks, sp.tunit);
 }
 
 int slab_build(Context*, EmbedIO* io, hipStream_t s) {

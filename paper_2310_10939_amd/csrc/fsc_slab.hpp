@@ -29,7 +29,8 @@ struct SlabArgs {
   int32_t ntiles, rows, nslab;        // tiles of `rows` consecutive rows (<= kSlabRows)
   int32_t xcd;                        // 1: per-XCD slabs with partial sums (slab_xcd_kernel)
   int32_t rgrid;                      // per-XCD form: grid of slab_reduce_kernel
-  void* part;                         // per-XCD form: A[nslab][n][LH] partial sums
+  void* part;                         // per-XCD form: A[n/64][nslab][64][LH] partial sums
+  const uint8_t* tunit;               // [ntiles] 1: the tile's weights are all 1 (skip them)
   const int32_t* scol;    // column indices in slab order
   const uint16_t* sperm;  // tile T, phase p, sorted position i -> local row, at r0*nslab + p*R + i
   const int32_t* sbase;   // [ntiles*nslab][kSlabLong+1]: start of diagonal k within the region
@@ -46,9 +47,9 @@ __device__ __forceinline__ int32_t diag_start(const int32_t* base, int32_t lane_
 
 // Adds the (tile T, slab p) region's per-row sums to acc (LDS, R x LH): one
 // lane per sorted row, kU nonzeros in flight per lane.
-template <int kU, class Op>
-__device__ __forceinline__ void slab_region(const Op& op, const SlabArgs& sb, int32_t T, int p, int32_t r0,
-                                            int32_t R, typename Op::A* acc) {
+template <int kU, bool UNIT, class Op>
+__device__ __forceinline__ void slab_region_as(const Op& op, const SlabArgs& sb, int32_t T, int p, int32_t r0,
+                                               int32_t R, typename Op::A* acc) {
   constexpr int LH = Op::LH;
   using A = typename Op::A;
   const int wave = threadIdx.x / FSC_WAVE, lane = threadIdx.x % FSC_WAVE;
@@ -80,7 +81,7 @@ __device__ __forceinline__ void slab_region(const Op& op, const SlabArgs& sb, in
           b0 = b1;
         }
       }
-      op.template accumulate_at<kU>(sb.scol, reg, off, a);
+      op.template accumulate_at<kU, UNIT>(sb.scol, reg, off, a);
       // rows are sorted by length: once diagonal k+kU is no longer than s0
       // rows, the whole slice is done
       const int32_t kn = k + kU;
@@ -91,6 +92,14 @@ __device__ __forceinline__ void slab_region(const Op& op, const SlabArgs& sb, in
       for (int q = 0; q < LH; ++q) acc[rl * LH + q] += a[q];
     }
   }
+}
+
+// A tile whose weights are all 1 takes the code path without weight loads.
+template <int kU, class Op>
+__device__ __forceinline__ void slab_region(const Op& op, const SlabArgs& sb, int32_t T, int p, int32_t r0,
+                                            int32_t R, typename Op::A* acc) {
+  if (sb.tunit[T]) slab_region_as<kU, true>(op, sb, T, p, r0, R, acc);
+  else slab_region_as<kU, false>(op, sb, T, p, r0, R, acc);
 }
 
 // Phase form: each block takes whole tiles and walks the slabs in order, so
@@ -171,8 +180,13 @@ __global__ __launch_bounds__(kBlock) void slab_xcd_kernel(Op op_in, TileArgs ta,
       __syncthreads();
       slab_region<kU>(op, sb, T, p, r0, R, acc);
       __syncthreads();
-      A* dst = part + ((int64_t)p * n + r0) * LH;
-      for (int i = threadIdx.x; i < R * LH; i += kBlock) dst[i] = acc[i];
+      // part: groups of 64 rows, each holding its nslab slabs' 64 x LH sums
+      // in a row, so every write here and every read of the reduce is
+      // contiguous
+      for (int i = threadIdx.x; i < R * LH; i += kBlock) {
+        const int32_t r = r0 + i / LH;
+        part[(((int64_t)(r >> 6) * sb.nslab + p) * 64 + (r & 63)) * LH + i % LH] = acc[i];
+      }
       __syncthreads();
     }
   const int32_t nch = ta.meta[0];
@@ -192,15 +206,24 @@ __global__ __launch_bounds__(kBlock) void slab_reduce_kernel(Op op_in, TileArgs 
   for (int q = 0; q < 2 * LH; ++q) st[q] = 0.0;
   for (int32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
     if (ta.row_ptr[r + 1] - ta.row_ptr[r] > kSlabLong) continue;  // finished by its chunks
+    // the per-XCD form has at most 8 slabs: all loads in flight at once
+    A v[8][LH];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      if (p < sb.nslab) {
+        rowio<A, LH>::load(part + (((int64_t)(r >> 6) * sb.nslab + p) * 64 + (r & 63)) * LH, v[p]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < LH; ++q) v[p][q] = A(0);
+      }
+    }
     A sum[LH];
 #pragma unroll
     for (int q = 0; q < LH; ++q) sum[q] = A(0);
-    for (int p = 0; p < sb.nslab; ++p) {
-      A v[LH];
-      rowio<A, LH>::load(part + ((int64_t)p * n + r) * LH, v);
 #pragma unroll
-      for (int q = 0; q < LH; ++q) sum[q] += v[q];
-    }
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+      for (int q = 0; q < LH; ++q) sum[q] += v[p][q];
     typename Op::Pre pre;
     op.prefetch(r, pre);
     op.finish(r, sum, pre, st);

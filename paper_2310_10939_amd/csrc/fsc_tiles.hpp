@@ -154,23 +154,24 @@ struct StepOp {
   }
   // The same over positions reg + off[u] of the slab-ordered copy (off < 0:
   // none); reg is uniform, so the loads take a scalar base and 32-bit offsets.
-  template <int U>
+  // UNIT: every weight there is 1, so none is loaded.
+  template <int U, bool UNIT>
   __device__ __forceinline__ void accumulate_at(const int32_t* scol, int64_t reg, const int32_t* off,
                                                 A* acc) const {
     const int32_t* cp = scol + reg;
     int32_t c[U];
     A w[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const bool ok = off[u] >= 0;
-      c[u] = ok ? nt_load(cp + off[u]) : -1;
-      if constexpr (std::is_void<W>::value) {
-        w[u] = A(1);
-      } else {
-        w[u] = ok ? load_weight<W, A>(sval + reg, off[u]) : A(0);
-      }
+    for (int u = 0; u < U; ++u) c[u] = off[u] >= 0 ? nt_load(cp + off[u]) : -1;
+    if constexpr (std::is_void<W>::value || UNIT) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) w[u] = A(1);
+      gather_rows<S, void, LH_, U>(zin, c, w, acc);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) w[u] = off[u] >= 0 ? load_weight<W, A>(sval + reg, off[u]) : A(0);
+      gather_rows<S, W, LH_, U>(zin, c, w, acc);
     }
-    gather_rows<S, W, LH_, U>(zin, c, w, acc);
   }
   __device__ __forceinline__ void prefetch(int32_t r, Pre& p) const {
     rowio<S, LH_>::load(zin + (int64_t)r * LH_, p.z);

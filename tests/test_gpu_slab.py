@@ -80,6 +80,31 @@ def test_slab_traces_and_renorm(gpu_lib, slab, mode):
 
 
 @pytest.mark.parametrize("mode", [1, 2])
+def test_slab_unit_weight_tiles(gpu_lib, slab, mode):
+    """Tiles whose weights are all exactly 1 skip the weight loads: stored
+    unit weights give the same bits as no weights, and a graph where one
+    edge pair weighs 2.5 (so only the tiles of its two rows load weights)
+    matches the oracle."""
+    g = synth.random_weighted(5000, 30000, seed=7, hubs=2, hub_degree=800, isolated=3)
+    ip, ix, _ = to_device(g, "none")
+    slab(4, mode)
+    ones = torch.ones(g.nnz, dtype=torch.float32, device="cuda")
+    a = gpu_lib.embed(ip, ix, ones, 4, 6, seed=1)
+    b = gpu_lib.embed(ip, ix, None, 4, 6, seed=1)
+    assert torch.equal(a, b)
+    w = np.ones(g.nnz)
+    r = 2500
+    j = int(g.indptr[r])
+    c = int(g.indices[j])
+    k = int(g.indptr[c]) + int(np.nonzero(g.indices[g.indptr[c]:g.indptr[c + 1]] == r)[0][0])
+    w[j] = w[k] = 2.5
+    d = torch.from_numpy(w.astype(np.float32)).cuda()
+    E = gpu_lib.embed(ip, ix, d, 4, 6, seed=1).cpu().numpy()
+    want = o.embed(g.n, g.indptr, g.indices, w, 4, 6, seed=1)
+    assert col_rel_err(E, want) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("mode", [1, 2])
 def test_slab_deterministic(gpu_lib, slab, mode):
     g = synth.random_weighted(6000, 50000, seed=2, hubs=3, hub_degree=3000)
     ip, ix, d = to_device(g, "f32")
