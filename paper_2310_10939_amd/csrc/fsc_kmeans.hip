@@ -12,9 +12,10 @@
 // rows (same summation order) to find the sampled row.  No host round trip.
 //
 // Lloyd: one launch per step.  Distances come from MFMA
-// (v_mfma_f32_16x16x4_f32): a 16-row tile of points times a 16-centre tile of
-// C^T gives e.c for 16 x 16 pairs, and ||c||^2 - 2 e.c is minimised over the
-// centres of a 16-lane row with DPP (ties to the lower index).  The centre
+// (v_mfma_f32_16x16x4_f32): a 16-centre tile of C times a 16-point tile of
+// P^T gives c.e for 16 x 16 pairs, so each lane holds 4 centres of one point;
+// ||c||^2 - 2 c.e is minimised over them in the lane and then across the 4
+// lane groups of the point (ties to the lower index).  The centre
 // update is a second contraction on the same unit: the one-hot matrix of the
 // labels (transposed) times the point tile, with a ones column for the
 // counts, accumulated over the wave's tiles.  The 16 waves of a block are
@@ -47,6 +48,7 @@ struct KppShared {
   int32_t block;
 };
 struct LloydShared {
+  float cn[kMaxK];  // ||c_j||^2, +inf past k
   float wsum[kLW][kMaxK][9];
   int lab[kLW][16];
   double tot[kMaxK * 9];
@@ -255,20 +257,10 @@ __device__ void kpp_block(const KmJob& J, int blk, int r, KppShared& sh) {
 // ---------------------------------------------------------------------------
 // Lloyd step: assignment (MFMA distances) and, with UPDATE, the centre update.
 // ---------------------------------------------------------------------------
-// DPP row operations used for the 16-lane argmin (a butterfly: quad xor 1,
-// quad xor 2, half-row mirror, row mirror).
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ void argmin_step(float& d, int& j) {
-  const float od = dpp_f<CTRL>(d);
-  const int oj = dpp_i<CTRL>(j);
+// Lexicographic (distance, index) minimum with the lane `mask` away.
+__device__ __forceinline__ void argmin_xor(float& d, int& j, int mask) {
+  const float od = shfl_xor(d, mask);
+  const int oj = shfl_xor(j, mask);
   if (od < d || (od == d && oj < j)) {
     d = od;
     j = oj;
@@ -286,25 +278,36 @@ __device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh) {
   const uint8_t* elig = J.elig;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int col = lane & 15;   // output column (centre within a tile)
+  const int col = lane & 15;   // output column: the point within a tile
   const int kk = lane >> 4;    // contraction index / output row group
 
-  // centre operands and squared norms for this lane's output column
-  float b0[KT], b1[KT], cn[KT];
+  // The distance MFMA computes D = C P^T for 16 centres x 16 points: lane
+  // (col, kk) supplies centre col's dimension kk (A) and point col's
+  // dimension kk (B), and receives D[4 kk + r][col], the products of centres
+  // 4 kk + r with point col.  So each lane scans 4 centres of one point and
+  // the 4 lane groups of a point combine in two cross-lane steps.
+  float b0[KT], b1[KT];
 #pragma unroll
   for (int jt = 0; jt < KT; ++jt) {
     const int j = jt * 16 + col;
     float c[KD];
+#pragma unroll
+    for (int q = 0; q < KD; ++q) c[q] = j < k ? J.centres[j * KD + q] : 0.f;
+    b0[jt] = c[kk];
+    b1[jt] = KD == 8 ? c[4 + kk] : 0.f;
+  }
+  float* cn = sh.cn;
+  if (threadIdx.x < 16 * KT) {
+    const int j = threadIdx.x;
     float nrm = 0.f;
 #pragma unroll
     for (int q = 0; q < KD; ++q) {
-      c[q] = j < k ? J.centres[j * KD + q] : 0.f;
-      nrm += c[q] * c[q];
+      const float v = j < k ? J.centres[j * KD + q] : 0.f;
+      nrm += v * v;
     }
-    b0[jt] = c[kk];
-    b1[jt] = KD == 8 ? c[4 + kk] : 0.f;
-    cn[jt] = j < k ? nrm : __builtin_inff();
+    cn[j] = j < k ? nrm : __builtin_inff();
   }
+  __syncthreads();
 
   floatx4 uacc[KT];
 #pragma unroll
@@ -313,64 +316,63 @@ __device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh) {
   const int tpw = J.tpw;
   const int64_t tile0 = ((int64_t)blk * kLW + wave) * tpw;  // this wave's first tile
   constexpr int kB = 4;  // tiles whose loads are in flight together
-  for (int it0 = 0; it0 < tpw; it0 += kB) {
-    float a0s[kB], a1s[kB], bvs[kB][4];
+  // Lane (col, kk) loads dimension kk (and 4 + kk) of row col of a tile: the
+  // A operand of the distance MFMA.  The update MFMA needs the transpose --
+  // lane (col, kk) holding dimension col of row 4q + kk -- which comes from
+  // the same registers by a cross-lane permute, not a second load.
+  // Batches of kB tiles are software-pipelined: the next batch's loads are in
+  // flight while this one computes.
+  float a0n[kB], a1n[kB];
+  auto load_batch = [&](int it0, float* a0, float* a1) {
 #pragma unroll
     for (int bi = 0; bi < kB; ++bi) {
-      const int64_t row0 = (tile0 + it0 + bi) * 16;
-      const int64_t ra = row0 + col;
-      a0s[bi] = 0.f;
-      a1s[bi] = 0.f;
-      const bool tile_ok = it0 + bi < tpw;
-      if (tile_ok && ra < n) {
-        a0s[bi] = pts[ra * KD + kk];
-        if (KD == 8) a1s[bi] = pts[ra * KD + 4 + kk];
-      }
-      if constexpr (UPDATE) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t rb = row0 + 4 * q + kk;
-          bvs[bi][q] = (tile_ok && rb < n && col < KD) ? pts[rb * KD + col] : 0.f;
-        }
+      const int64_t ra = (tile0 + it0 + bi) * 16 + col;
+      a0[bi] = 0.f;
+      a1[bi] = 0.f;
+      if (it0 + bi < tpw && ra < n) {
+        a0[bi] = pts[ra * KD + kk];
+        if (KD == 8) a1[bi] = pts[ra * KD + 4 + kk];
       }
     }
+  };
+  load_batch(0, a0n, a1n);
+  for (int it0 = 0; it0 < tpw; it0 += kB) {
+    float a0s[kB], a1s[kB];
+#pragma unroll
+    for (int bi = 0; bi < kB; ++bi) {
+      a0s[bi] = a0n[bi];
+      a1s[bi] = a1n[bi];
+    }
+    if (it0 + kB < tpw) load_batch(it0 + kB, a0n, a1n);
 #pragma unroll
     for (int bi = 0; bi < kB; ++bi) {
       const int64_t row0 = (tile0 + it0 + bi) * 16;
       if (it0 + bi >= tpw || row0 >= n) break;
-      float bd[4];
-      int bj[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        bd[r] = __builtin_inff();
-        bj[r] = 0;
-      }
+      // nearest centre of point col: ||c||^2 - 2 c.p, ties to the lowest
+      // centre index (centres are scanned in increasing order in a lane, and
+      // the cross-lane steps compare (distance, index) pairs)
+      float bd = __builtin_inff();
+      int bj = 0;
 #pragma unroll
       for (int jt = 0; jt < KT; ++jt) {
-        floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0s[bi], b0[jt], floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        if (KD == 8) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1s[bi], b1[jt], acc, 0, 0, 0);
+        floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(b0[jt], a0s[bi], floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        if (KD == 8) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(b1[jt], a1s[bi], acc, 0, 0, 0);
+        const floatx4 c4 = *reinterpret_cast<const floatx4*>(cn + jt * 16 + 4 * kk);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float d = cn[jt] - 2.f * acc[r];
-          if (d < bd[r]) {
-            bd[r] = d;
-            bj[r] = jt * 16 + col;
+          const float d = c4[r] - 2.f * acc[r];
+          if (d < bd) {
+            bd = d;
+            bj = jt * 16 + 4 * kk + r;
           }
         }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        argmin_step<0xB1>(bd[r], bj[r]);   // quad_perm [1,0,3,2]
-        argmin_step<0x4E>(bd[r], bj[r]);   // quad_perm [2,3,0,1]
-        argmin_step<0x141>(bd[r], bj[r]);  // row_half_mirror
-        argmin_step<0x140>(bd[r], bj[r]);  // row_mirror
-      }
-      // row 4*kk + r of the tile is held by the lanes of group kk, reg r
-      if (col < 4) {
-        const int64_t row = row0 + 4 * kk + col;
-        const int lab = col == 0 ? bj[0] : col == 1 ? bj[1] : col == 2 ? bj[2] : bj[3];
-        if (row < n) J.labels[row] = lab;
-        if constexpr (UPDATE) lab_s[wave][4 * kk + col] = lab;
+      argmin_xor(bd, bj, 16);
+      argmin_xor(bd, bj, 32);
+      if (kk == 0) {
+        const int64_t row = row0 + col;
+        if (row < n) J.labels[row] = bj;
+        if constexpr (UPDATE) lab_s[wave][col] = bj;
       }
       if constexpr (UPDATE) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -378,10 +380,19 @@ __device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+          // dimension col of row 4q + kk sits in lane (4q + kk, col & 3),
+          // register a0 (col < 4) or a1 (4 <= col < 8)
+          const int src = ((col & 3) * 16 + 4 * q + kk) * 4;
+          const float t0 = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(a0s[bi])));
+          float bval = t0;
+          if (KD == 8) {
+            const float t1 = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(a1s[bi])));
+            bval = col < 4 ? t0 : t1;
+          }
           const int lab = lab_s[wave][4 * q + kk];   // label of row 4q + kk
           const int64_t rb = row0 + 4 * q + kk;
           const bool valid = rb < n && (elig == nullptr || elig[rb] != 0);
-          float bval = bvs[bi][q];
+          if (col >= KD) bval = 0.f;
           if (col == KD) bval = 1.f;
           if (!valid) bval = 0.f;
 #pragma unroll
