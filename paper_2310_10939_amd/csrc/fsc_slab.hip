@@ -6,12 +6,11 @@
 //   slab_scan_kernel   exclusive scans of those over the tiles;
 //   slab_build_kernel  per tile: segment lengths per (row, slab), rows sorted
 //                      by length per slab (counting sort in LDS), diagonal
-//                      starts, the scatter of the nonzeros into slab order,
-//                      and the long-row chunks.
-// Rows of equal length may take their sorted positions in any order, but a
-// row's nonzeros keep their CSR order within its segment and a row's segments
-// are summed in slab order, so every row's sum -- and so every result of a
-// step -- is the same whatever positions the rows get.
+//                      starts, the scatter of the nonzeros into slab order
+//                      (assembled in LDS, written out coalesced), and the
+//                      long-row chunks.
+// The layout is a function of the CSR alone: rows are sorted stably, and a
+// row's nonzeros keep their CSR order within its segment.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
 
@@ -97,6 +96,7 @@ __global__ __launch_bounds__(1024) void slab_scan_kernel(const int64_t* __restri
 
 constexpr int kBuild = 1024;  // threads of the build kernel: one per row of a tile
 constexpr int kBuildU = 8;    // nonzeros of a row loaded at once
+constexpr int kStage = 6144;  // entries of the LDS staging buffer
 
 template <typename W>
 __global__ __launch_bounds__(kBuild) void slab_build_kernel(
@@ -107,12 +107,15 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     LongChunk* __restrict__ chunks, uint8_t* __restrict__ tunit) {
   __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
   __shared__ uint16_t spos[kSlabMax * kSlabRows];  // sorted position of each row per slab
-  __shared__ int32_t hist[kSlabLong + 1];          // rows per segment length
-  __shared__ int32_t cursor[kSlabLong + 1];        // next sorted position per length
+  __shared__ int32_t wcnt[kBuild / FSC_WAVE * (kSlabLong + 1)];  // per wave and length
+  __shared__ int32_t wmx[kBuild / FSC_WAVE];
   __shared__ int32_t cntk[kSlabLong];              // rows longer than k
   __shared__ int32_t baseL[kSlabMax * (kSlabLong + 1)];
-  __shared__ int64_t regL[kSlabMax];
+  __shared__ int64_t regL[kSlabMax + 1];
   __shared__ int32_t scan32[kBuild / FSC_WAVE];
+  using WS = typename std::conditional<std::is_void<W>::value, char, W>::type;
+  __shared__ int32_t stcol[kStage];                // staging of a group of regions
+  __shared__ WS stval[std::is_void<W>::value ? 1 : kStage];
   const int32_t T = blockIdx.x;
   const int32_t r0 = T * rows;
   const int32_t R = min(rows, n - r0);
@@ -140,37 +143,52 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   __syncthreads();
   int64_t region = toff[T];
   for (int p = 0; p < nslab; ++p) {
-    // counting sort of the rows by decreasing segment length: rows longer
-    // than k come first, so the count of rows longer than k is both the start
-    // of length k in the sorted order and the height of diagonal k
-    if (threadIdx.x <= kSlabLong) hist[threadIdx.x] = 0;
-    __syncthreads();
+    // Rows by decreasing segment length, in row order within a length (a
+    // stable counting sort): each wave counts its lanes of every length with
+    // ballots, so no two threads update one counter.  The count of rows
+    // longer than k is both the start of length k in the sorted order and
+    // the height of diagonal k.
     const int len = rl < R ? (int)cnt[p * R + rl] : 0;
-    if (rl < R) atomicAdd(&hist[len], 1);
-    __syncthreads();
+    const int wave = threadIdx.x / FSC_WAVE, lane = threadIdx.x % FSC_WAVE;
     {
-      const int t = threadIdx.x;  // suffix sums over lengths 256, 255, ...
-      const int32_t v = t <= kSlabLong ? hist[kSlabLong - t] : 0;
-      int32_t tot;
-      const int32_t incl = block_scan_inclusive<kBuild, int32_t>(v, scan32, &tot);
-      // incl(t) = rows with length >= 256 - t; rows longer than k: t = 255 - k
-      if (t < kSlabLong) cntk[kSlabLong - 1 - t] = incl;
+      int m = len;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o, FSC_WAVE));
+      if (lane == 0) wmx[wave] = m;
     }
     __syncthreads();
     int32_t maxlen = 0;
-    {
-      // longest segment: the number of k with a nonempty diagonal
-      int32_t lo = 0, hi = kSlabLong;
-      while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (cntk[mid] > 0) lo = mid + 1; else hi = mid;
-      }
-      maxlen = lo;
+#pragma unroll
+    for (int w = 0; w < kBuild / FSC_WAVE; ++w) maxlen = max(maxlen, wmx[w]);
+    int rank = 0;
+    for (int L = 0; L <= maxlen; ++L) {
+      const uint64_t m = __ballot(rl < R && len == L);
+      if (len == L) rank = __popcll(m & (((uint64_t)1 << lane) - 1));
+      if (lane == 0) wcnt[wave * (kSlabLong + 1) + L] = __popcll(m);
     }
-    if (threadIdx.x <= kSlabLong) cursor[threadIdx.x] = threadIdx.x < kSlabLong ? cntk[threadIdx.x] : 0;
+    __syncthreads();
+    {
+      const int t = threadIdx.x;  // one thread per length, longest first
+      const int L = kSlabLong - t;
+      int32_t tot = 0;
+      if (t <= kSlabLong && L <= maxlen)
+        for (int w = 0; w < kBuild / FSC_WAVE; ++w) tot += wcnt[w * (kSlabLong + 1) + L];
+      int32_t all;
+      const int32_t incl = block_scan_inclusive<kBuild, int32_t>(tot, scan32, &all);
+      if (t <= kSlabLong) {
+        int32_t run = incl - tot;  // rows longer than L
+        if (L < kSlabLong) cntk[L] = run;
+        if (L <= maxlen)
+          for (int w = 0; w < kBuild / FSC_WAVE; ++w) {
+            const int32_t c = wcnt[w * (kSlabLong + 1) + L];
+            wcnt[w * (kSlabLong + 1) + L] = run;  // start of (length L, wave w)
+            run += c;
+          }
+      }
+    }
     __syncthreads();
     if (rl < R) {
-      const int i = atomicAdd(&cursor[len], 1);
+      const int i = wcnt[wave * (kSlabLong + 1) + len] + rank;
       sperm[(int64_t)r0 * nslab + (int64_t)p * R + i] = (uint16_t)rl;
       spos[p * R + rl] = (uint16_t)i;
     }
@@ -194,37 +212,54 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     region += total;
     __syncthreads();
   }
-  // scatter the short rows' nonzeros into slab order (CSR order within a
-  // row's segment)
-  for (int i = threadIdx.x; i < nslab * R; i += kBuild) cnt[i] = 0;
+  if (threadIdx.x == 0) regL[nslab] = region;  // end of the tile's last region
   __syncthreads();
+  // Scatter the short rows' nonzeros into slab order (CSR order within a
+  // row's segment), a group of consecutive slabs at a time: the group's
+  // regions are contiguous, so they are assembled in LDS and written out in
+  // one coalesced pass.  A region too large for the buffer is written
+  // directly.
   int unit = 1;  // every weight of this thread's row is exactly 1
-  if (shortrow) {
-    for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
-      using WS = typename std::conditional<std::is_void<W>::value, char, W>::type;
-      int32_t c[kBuildU];
-      WS w[kBuildU];
+  for (int p0 = 0; p0 < nslab;) {
+    int p1 = p0 + 1;
+    while (p1 < nslab && regL[p1 + 1] - regL[p0] <= kStage) ++p1;
+    const int64_t g0 = regL[p0];
+    const int32_t gsz = (int32_t)(regL[p1] - g0);
+    const bool staged = gsz <= kStage;
+    for (int i = p0 * R + threadIdx.x; i < p1 * R; i += kBuild) cnt[i] = 0;
+    __syncthreads();
+    if (shortrow) {
+      for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
+        int32_t c[kBuildU];
 #pragma unroll
-      for (int u = 0; u < kBuildU; ++u) {
-        c[u] = j0 + u < b ? col[j0 + u] : 0;
-        if constexpr (!std::is_void<W>::value) {
-          if (j0 + u < b) w[u] = val[j0 + u];
-        }
-      }
+        for (int u = 0; u < kBuildU; ++u) c[u] = j0 + u < b ? col[j0 + u] : 0;
 #pragma unroll
-      for (int u = 0; u < kBuildU; ++u) {
-        if (j0 + u < b) {
+        for (int u = 0; u < kBuildU; ++u) {
+          if (j0 + u >= b) continue;
           const int p = slab_of(c[u], S, last);
+          if (p < p0 || p >= p1) continue;
           const int kk = cnt[p * R + rl]++;
-          const int64_t pos = regL[p] + baseL[p * (kSlabLong + 1) + kk] + spos[p * R + rl];
-          scol[pos] = c[u];
+          const int32_t off = (int32_t)(regL[p] - g0) + baseL[p * (kSlabLong + 1) + kk] + spos[p * R + rl];
+          if (staged) stcol[off] = c[u];
+          else scol[g0 + off] = c[u];
           if constexpr (!std::is_void<W>::value) {
-            sval[pos] = w[u];
-            if (weight<W, float>::get(&w[u], 0) != 1.0f) unit = 0;
+            const W w = val[j0 + u];
+            if (staged) stval[off] = w;
+            else sval[g0 + off] = w;
+            if (weight<W, float>::get(&w, 0) != 1.0f) unit = 0;
           }
         }
       }
     }
+    __syncthreads();
+    if (staged) {
+      for (int32_t e = threadIdx.x; e < gsz; e += kBuild) {
+        scol[g0 + e] = stcol[e];
+        if constexpr (!std::is_void<W>::value) sval[g0 + e] = stval[e];
+      }
+    }
+    __syncthreads();
+    p0 = p1;
   }
   // a tile whose short rows all have unit weights skips the weight stream
   {
