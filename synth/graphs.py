@@ -205,8 +205,54 @@ def knn_mixture(n_per, k, dim, seed, knn=10) -> Graph:
 
 # ---------------------------------------------------------------------------
 # Device-side generation for workloads too large for host numpy (torch is used
-# only as a device array library here; the graph model is the SBM above).
+# only as a device array library here; the graph models are the ones above).
 # ---------------------------------------------------------------------------
+def knn_mixture_device(n_per, k, dim, seed, knn=10, device="cuda", block=2048):
+    """The symmetrised k-NN graph of `knn_graph` over the points of
+    `gaussian_mixture`, built on the device: the same points, exact
+    neighbours by FP32 squared distance (self excluded, a stable sort so ties
+    go to the lower index), sigma^2 the median of the directed neighbour
+    distances (mean of the two middle values), weight exp(-d^2 / sigma^2),
+    union symmetrisation keeping the first weight of a pair.  Returns device
+    (indptr int64, indices int32, weights float32) and the host labels."""
+    import torch
+    X_h, lab = gaussian_mixture(n_per, k, dim, seed)
+    X = torch.from_numpy(X_h).to(device)
+    n = X.shape[0]
+    sq = (X * X).sum(1)
+    nbr = torch.empty((n, knn), dtype=torch.int64, device=device)
+    dist = torch.empty((n, knn), dtype=torch.float32, device=device)
+    XT = X.t().contiguous()
+    for s in range(0, n, block):
+        e = min(n, s + block)
+        D = sq[s:e, None] + sq[None, :] - 2.0 * (X[s:e] @ XT)
+        D[torch.arange(e - s, device=device), torch.arange(s, e, device=device)] = float("inf")
+        val, idx = torch.sort(D, dim=1, stable=True)
+        nbr[s:e] = idx[:, :knn]
+        dist[s:e] = val[:, :knn].clamp_min(0.0)
+        del D, val, idx
+    flat = torch.sort(dist.flatten()).values
+    m = flat.numel() // 2
+    sigma2 = float(flat[m]) if flat.numel() % 2 else 0.5 * (float(flat[m - 1]) + float(flat[m]))
+    u = torch.arange(n, device=device).repeat_interleave(knn)
+    v = nbr.flatten()
+    w = torch.exp(-dist.flatten().double() / sigma2)
+    lo, hi = torch.minimum(u, v), torch.maximum(u, v)
+    key = lo * n + hi
+    key_s, order = torch.sort(key, stable=True)
+    first = torch.ones_like(key_s, dtype=torch.bool)
+    first[1:] = key_s[1:] != key_s[:-1]
+    key_u, w_u = key_s[first], w[order][first]
+    lo, hi = key_u // n, key_u % n
+    rows = torch.cat([lo, hi])
+    cols = torch.cat([hi, lo])
+    ww = torch.cat([w_u, w_u])
+    order = torch.argsort(rows * n + cols)
+    rows, cols, ww = rows[order], cols[order], ww[order]
+    indptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    indptr[1:] = torch.cumsum(torch.bincount(rows, minlength=n), 0)
+    return indptr, cols.to(torch.int32), ww.to(torch.float32), lab
+
 def sbm_device(n, k, deg_in, deg_out, seed, device="cuda"):
     """SBM with k near-equal clusters and expected in/out-cluster degree
     deg_in/deg_out, built on the device.  Edge counts per block (within) and

@@ -1,0 +1,75 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (default tuning).
+
+* Precision form on the k-NN graph: 70,000 points of 10 Gaussians in 784
+  dimensions, symmetrised 10-NN graph, BF16 weights and vectors, l = 4,
+  t = 40.  The whole embedding against the FP64 oracle run on the same
+  BF16-rounded weights (2e-2 relative per column), and the labels against
+  the oracle's k-means (ARI >= 0.99).
+* Batched form: the 512-graph batch, every graph's labels against the plain
+  single-graph path (itself checked against the oracle elsewhere), ARI >=
+  0.99, and the first graphs against the oracle directly.
+
+(The 1M-vertex SBM is in test_gpu_slab.py.)
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import fsc_oracle as o
+from tests.gpu_util import col_rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_knn70k_bf16_matches_oracle(gpu_lib):
+    ip, ix, w, lab = synth.knn_mixture_device(7000, 10, 784, seed=0)
+    d = w.to(torch.bfloat16)
+    n = ip.numel() - 1
+    say(f"kNN graph n={n} nnz={ix.numel()}")
+    ip_h, ix_h = ip.cpu().numpy(), ix.cpu().numpy()
+    w_h = d.double().cpu().numpy()
+    E = gpu_lib.embed(ip, ix, d, 4, 40, seed=0, vec_dtype="bf16").float().cpu().numpy()
+    want = o.embed(n, ip_h, ix_h, w_h, 4, 40, seed=0)
+    err = col_rel_err(E, want)
+    # the same with the FP64 weights the generator drew, for the record
+    err_w = col_rel_err(E, o.embed(n, ip_h, ix_h, w.double().cpu().numpy(), 4, 40, seed=0))
+    say("  bf16 rel err vs oracle on bf16 weights", err, "vs fp32 weights", err_w)
+    assert err <= 2e-2
+    labels = gpu_lib.cluster(ip, ix, d, 10, 4, 40, 0, kmeans_iters=30, vec_dtype="bf16")
+    deg = o.degrees(n, ip_h, ix_h, w_h)
+    lab_o, _ = o.kmeans(want, 10, 30, 0, eligible=deg > 0)
+    ari = float(gpu_lib.ari(labels, torch.from_numpy(np.asarray(lab_o, dtype=np.int32)).cuda(), 10, 10))
+    ari_planted = float(gpu_lib.ari(labels, torch.from_numpy(lab.astype(np.int32)).cuda(), 10, 10))
+    say("  ARI vs oracle", ari, "vs mixture labels", ari_planted)
+    assert ari >= 0.99
+
+
+def test_batched512_matches_plain_path(gpu_lib):
+    params = synth.batched_sbm_params(512, seed=0)
+    graphs = []
+    for p in params:
+        ip, ix, _ = synth.sbm_device(p["n"], p["k"], p["deg_in"], p["deg_out"], p["seed"])
+        graphs.append((ip, ix, torch.ones(ix.numel(), dtype=torch.float32, device="cuda")))
+    ks = [p["k"] for p in params]
+    ls = [p["l"] for p in params]
+    ts = [p["t"] for p in params]
+    say(f"batched: {len(graphs)} graphs, sum nnz {sum(g[1].numel() for g in graphs)}")
+    labels, off = gpu_lib.cluster_batched(graphs, ks, ls, ts, 0, kmeans_iters=30)
+    worst = 1.0
+    for i, g in enumerate(graphs):
+        plain = gpu_lib.cluster(*g, ks[i], ls[i], ts[i], i, kmeans_iters=30)
+        a = float(gpu_lib.ari(labels[off[i]:off[i + 1]], plain, ks[i], ks[i]))
+        worst = min(worst, a)
+    say("  min ARI vs plain path", worst)
+    assert worst >= 0.99
+    # the two smallest graphs against the oracle directly
+    for i in sorted(range(len(params)), key=lambda j: params[j]["n"])[:2]:
+        ip, ix, d = graphs[i]
+        n = ip.numel() - 1
+        lab_o, _, _ = o.fast_spectral_cluster(n, ip.cpu().numpy(), ix.cpu().numpy(), None, ks[i], ls[i], ts[i], i, 30)
+        a = float(gpu_lib.ari(labels[off[i]:off[i + 1]], torch.from_numpy(np.asarray(lab_o, dtype=np.int32)).cuda(),
+                              ks[i], ks[i]))
+        say(f"  graph {i} (n={n}) ARI vs oracle", a)
+        assert a >= 0.99
