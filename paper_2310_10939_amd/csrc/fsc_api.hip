@@ -90,7 +90,7 @@ static fsc_opts default_opts() {
 // Embedding setup shared by fsc_embed and fsc_cluster.  `extra` bytes of the
 // arena are left for the caller after the embedding workspace.
 static int prepare_embed(Context* ctx, const fsc_csr* g, int l, int t, uint64_t seed, const fsc_opts& o,
-                         size_t extra, EmbedIO* io, Arena* arena) {
+                         size_t extra, EmbedIO* io, Arena* arena, const Arena* given = nullptr) {
   int rc;
   if ((rc = check_csr(g))) return rc;
   if (l < 1 || l > 8) return fail(FSC_E_ARG, "l must be in [1, 8]");
@@ -110,7 +110,13 @@ static int prepare_embed(Context* ctx, const fsc_csr* g, int l, int t, uint64_t 
   io->sqnorm_trace = o.sqnorm_trace;
   io->rayleigh_trace = o.rayleigh_trace;
   const size_t bytes = embed_workspace_bytes(ctx, g, l, o.vec_dtype, o.tile_nnz) + extra;
-  if ((rc = reserve_arena(ctx, bytes, arena))) return rc;
+  if (given) {
+    if (given->size < bytes) return fail(FSC_E_NOMEM, "given workspace too small");
+    *arena = *given;
+    arena->used = 0;
+  } else if ((rc = reserve_arena(ctx, bytes, arena))) {
+    return rc;
+  }
   return embed_bind_workspace(ctx, arena, io);
 }
 
@@ -159,6 +165,50 @@ static int zero_counter(int32_t* p, hipStream_t s) { return fill_zero_i32(p, 4, 
 // Largest normalised k-means cost (within-cluster over total variance of the
 // embedding rows) accepted from the filtered embedding before falling back.
 constexpr double kFilterMaxCost = 0.1;
+
+size_t cluster_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, const fsc_opts& o) {
+  const int KD = kmeans_width(l);
+  const int LH = padded_width(l);
+  const bool direct = o.vec_dtype == FSC_F32 && LH == KD;
+  const size_t extra = kmeans_workspace_bytes(g->n, KD) + (direct ? 0 : align_up(g->n * KD * 4)) + 1024;
+  return embed_workspace_bytes(ctx, g, l, o.vec_dtype, o.tile_nnz) + extra;
+}
+
+int cluster_run(Context* c, const fsc_csr* g, int k, int l, int t, uint64_t seed, const fsc_opts& o,
+                int32_t* labels, void* emb, float* centres, hipStream_t s, const Arena* ws) {
+  int rc;
+  const int iters = o.kmeans_iters > 0 ? o.kmeans_iters : 30;
+  const int KD = kmeans_width(l);
+  const int LH = padded_width(l);
+  const bool direct = o.vec_dtype == FSC_F32 && LH == KD;
+  const size_t extra = kmeans_workspace_bytes(g->n, KD) + (direct ? 0 : align_up(g->n * KD * 4)) + 1024;
+  EmbedIO io;
+  Arena arena;
+  if ((rc = prepare_embed(c, g, l, t, seed, o, extra, &io, &arena, ws))) return rc;
+  KmeansIO km;
+  std::memset(&km, 0, sizeof(km));
+  km.n = g->n;
+  km.l = l;
+  km.KD = KD;
+  km.k = k;
+  km.iters = iters;
+  km.seed = seed;
+  km.labels = labels;
+  km.centres_out = centres;
+  float* pts = direct ? nullptr : arena.take<float>(g->n * KD);
+  if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
+  if (o.validate && (rc = validate_csr(c, g, s))) return rc;
+  if ((rc = embed_run(c, &io, s))) return rc;
+  if (emb && (rc = embed_unpad(c, &io, emb, s))) return rc;
+  if (direct) {
+    km.pts = reinterpret_cast<const float*>(io.zt);
+  } else {
+    if ((rc = embed_to_points(c, &io, pts, s))) return rc;
+    km.pts = pts;
+  }
+  km.elig = io.elig;
+  return kmeans_run(c, &km, s);
+}
 
 }  // namespace fsc
 
@@ -213,7 +263,10 @@ void fsc_destroy(fsc_context* ctx) {
   }
   if (ctx->c.bexec) hipGraphExecDestroy(ctx->c.bexec);
   if (ctx->c.cap_stream) hipStreamDestroy(ctx->c.cap_stream);
+  for (auto st : ctx->c.side_streams) hipStreamDestroy(st);
+  for (auto ev : ctx->c.side_events) hipEventDestroy(ev);
   if (ctx->c.barena) hipFree(ctx->c.barena);
+  if (ctx->c.sarena) hipFree(ctx->c.sarena);
   if (ctx->c.arena) hipFree(ctx->c.arena);
   if (ctx->c.error_flag) hipFree(ctx->c.error_flag);
   if (ctx->c.host_flag) hipHostFree(ctx->c.host_flag);
@@ -244,39 +297,8 @@ int fsc_cluster(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_
   if ((rc = check_csr(g))) return rc;
   if (k < 1 || k > 64 || k > g->n) return fail(FSC_E_ARG, "k must be in [1, min(n, 64)]");
   const fsc_opts o = opts ? *opts : default_opts();
-  const int iters = o.kmeans_iters > 0 ? o.kmeans_iters : 30;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
-  const int KD = kmeans_width(l);
-  const int LH = padded_width(l);
-  const bool direct = o.vec_dtype == FSC_F32 && LH == KD;
-  const size_t extra = kmeans_workspace_bytes(g->n, KD) + (direct ? 0 : align_up(g->n * KD * 4)) + 1024;
-  EmbedIO io;
-  Arena arena;
-  if ((rc = prepare_embed(&ctx->c, g, l, t, seed, o, extra, &io, &arena))) return rc;
-  KmeansIO km;
-  std::memset(&km, 0, sizeof(km));
-  km.n = g->n;
-  km.l = l;
-  km.KD = KD;
-  km.k = k;
-  km.iters = iters;
-  km.seed = seed;
-  km.labels = labels;
-  km.centres_out = centres;
-  float* pts = direct ? nullptr : arena.take<float>(g->n * KD);
-  if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
-  if (o.validate && (rc = validate_csr(&ctx->c, g, s))) return rc;
-  if ((rc = embed_run(&ctx->c, &io, s))) return rc;
-  if (emb && (rc = embed_unpad(&ctx->c, &io, emb, s))) return rc;
-  if (direct) {
-    km.pts = reinterpret_cast<const float*>(io.zt);
-  } else {
-    if ((rc = embed_to_points(&ctx->c, &io, pts, s))) return rc;
-    km.pts = pts;
-  }
-  km.elig = io.elig;
-  return kmeans_run(&ctx->c, &km, s);
+  return cluster_run(&ctx->c, g, k, l, t, seed, o, labels, emb, centres, static_cast<hipStream_t>(stream), nullptr);
 }
 
 int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, int32_t l, int32_t k, int32_t iters,

@@ -128,6 +128,12 @@ struct Context {
   size_t barena_size = 0;
   hipGraphExec_t bexec = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture
+  // batched form: side streams (and fork/join events) on which the graphs
+  // of the single-graph path run concurrently, each with its own workspace
+  std::vector<hipStream_t> side_streams;
+  std::vector<hipEvent_t> side_events;
+  char* sarena = nullptr;
+  size_t sarena_size = 0;
   uint64_t bkey = 0;
   // event timing of the sparse-product launches
   bool timing = false;
@@ -249,6 +255,15 @@ int kmeans_cost_run(Context* ctx, const KmeansIO* io, double* partials, int32_t*
                     hipStream_t s);
 int points_from_user(Context* ctx, const void* pts, int dtype, int64_t n, int l, int KD, float* out,
                      hipStream_t s);
+
+// ---- the plain single-graph path (fsc_api.hip) ----
+// Workspace of cluster_run on the context arena, and the run itself (labels,
+// optional unpadded embedding and centres); it reserves the arena, which
+// allocates only when the arena is too small.
+size_t cluster_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, const fsc_opts& o);
+// With ws, the run uses that workspace instead of the context arena.
+int cluster_run(Context* c, const fsc_csr* g, int k, int l, int t, uint64_t seed, const fsc_opts& o,
+                int32_t* labels, void* emb, float* centres, hipStream_t s, const Arena* ws);
 
 // ---- batched form (fsc_batched.hip) ----
 inline int degree_class(double mean_degree) {

@@ -25,7 +25,17 @@ def _batch():
     return specs
 
 
-def test_batched_matches_single_graph_path(gpu_lib):
+@pytest.fixture(params=[1024, 16], ids=["shared-launches", "hybrid"])
+def slab_kb(request, gpu_lib):
+    """1024: every graph of the batch is small enough for the shared
+    per-level launches; 16 (KiB): the larger graphs take the single-graph
+    path inside the batched call."""
+    gpu_lib.tuning(slab_kb=request.param)
+    yield request.param
+    gpu_lib.tuning(slab_kb=1024)
+
+
+def test_batched_matches_single_graph_path(gpu_lib, slab_kb):
     specs = _batch()
     dev = []
     for g, k, l, t in specs:
@@ -59,6 +69,9 @@ def test_batched_matches_single_graph_path(gpu_lib):
         assert err_single <= 1e-5
         assert a >= 0.99
         assert L.min() >= 0 and L.max() < k
+        if slab_kb == 16 and g.n * (4 if l <= 4 else 8) * 4 > 16 * 1024:
+            # a graph on the single-graph path inside the batch: same bits
+            assert np.array_equal(L, Ls) and np.array_equal(E, Es)
 
 
 def test_batched_errors(gpu_lib):
