@@ -8,12 +8,19 @@ top eigenvectors of M (Sec. 3.1: x_t = sum_i a_i gamma_i^t f_i).  The learned
 form replaces gamma^t by a degree-8 polynomial p(gamma) = sum_j c_j T*_j(gamma)
 in the shifted Chebyshev basis of [0, 1] (T*_j(g) = T_j(2g - 1)), with p(1) = 1
 so the trivial eigenvector (gamma_1 = 1) keeps its weight.  A small MLP maps
-graph statistics to c_1..c_8 (c_0 = 1 - sum_j c_j since T*_j(1) = 1).  It is
-trained to make p(M) X0 match the plain PowerMethod output Y = M^t X0 in the
-relative squared error, which is quadratic in c and so needs only per-graph
-Gram statistics of the basis.  Parity of this part is pinned internally
-(closed forms, finite differences, autograd), not by the paper, which has no
-learned part.
+graph statistics to c_1..c_8 (c_0 = 1 - sum_j c_j since T*_j(1) = 1).
+
+Reading (the paper has no learned part): the filter is trained on the plain
+method's clustering.  For a graph, the plain method (t power steps, then
+k-means, Algorithm 2) labels the vertices; the loss of coefficients c is the
+normalised k-means cost (Sec. 2.2) of the filtered embedding
+E(c) = D^{-1/2} p(M) X0 under those labels: within-cluster scatter over total
+scatter.  Both are quadratic forms in c (c^T W c / c^T T c), so training needs
+only per-graph 9 x 9 scatter statistics of the basis blocks; the loss is
+scale-free, so a filter need not reproduce gamma^t, only separate the
+clusters as the plain embedding does.  Parity of this part is pinned
+internally (the k-means cost, finite differences, autograd, the generalised
+eigenvalue bound), not by the paper.
 """
 from __future__ import annotations
 
@@ -88,26 +95,44 @@ def features(n, k, d, rayleigh4):
     return (raw - FEAT_SHIFT) / FEAT_SCALE
 
 
-def graph_stats(n, indptr, indices, data, k, l, t, seed):
-    """Everything the trainer needs from one graph, all in y-space over the
-    non-isolated vertices: features, G_ij = <B_i, B_j>, h_i = <B_i, Y>,
-    yy = <Y, Y> (sums over the l columns), with Y = M^t X0 the plain
-    PowerMethod output."""
+def scatter_stats(Bz, labels, mask):
+    """W, T (9 x 9) with c^T W c the within-cluster scatter and c^T T c the
+    total scatter of the rows v in `mask` of E(c) = sum_j c_j Bz[j] (the sum
+    of squared distances to the cluster's mean, respectively to the mean of
+    all those rows), by centring the blocks and taking inner products."""
+    mask = np.asarray(mask, dtype=bool)
+    X = np.stack([np.asarray(b, dtype=np.float64)[mask] for b in Bz])   # nb x m x l
+    L = np.asarray(labels)[mask]
+    Xt = X - X.mean(axis=1, keepdims=True)
+    Xw = X.copy()
+    for c in np.unique(L):
+        sel = L == c
+        Xw[:, sel] -= X[:, sel].mean(axis=1, keepdims=True)
+    W = np.einsum("imq,jmq->ij", Xw, Xw)
+    T = np.einsum("imq,jmq->ij", Xt, Xt)
+    return W, T
+
+
+def graph_stats(n, indptr, indices, data, k, l, t, seed, kmeans_iters=30):
+    """Everything the trainer needs from one graph: features, the scatter
+    statistics W, T of the z-space basis blocks D^{-1/2} T*_j(M) X0 over the
+    non-isolated vertices, under the labels of the plain method (t steps,
+    k-means with kmeans_iters Lloyd rounds, Algorithm 2), and those labels."""
     X0 = o.gaussian_block(n, l, seed)
     M = o.signless_laplacian(n, indptr, indices, data)
     d = o.degrees(n, indptr, indices, data)
     m = d > 0
+    s = o.inv_sqrt_degree(d)
     B = cheb_basis(M, X0)
-    Y = o.power_method(M, X0, t)
+    E = s[:, None] * o.power_method(M, X0, t)
+    labels, _ = o.kmeans(E, k, kmeans_iters, seed, eligible=m)
+    W, T = scatter_stats([s[:, None] * b for b in B], labels, m)
     ray = []
     for j in range(4):
         Bj = B[j][m]
         MB = (M @ B[j])[m]
         ray.append(float(np.mean(np.einsum("ij,ij->j", Bj, MB) / np.einsum("ij,ij->j", Bj, Bj))))
-    G = np.array([[float(np.sum(B[i][m] * B[j][m])) for j in range(NCOEF)] for i in range(NCOEF)])
-    h = np.array([float(np.sum(B[i][m] * Y[m])) for i in range(NCOEF)])
-    yy = float(np.sum(Y[m] * Y[m]))
-    return features(n, k, d, ray), G, h, yy
+    return features(n, k, d, ray), W, T, labels
 
 
 # ---------------------------------------------------------------------------
@@ -157,42 +182,50 @@ def mlp_forward(params, F):
     return x, acts
 
 
-def loss_terms(c_rest, G, h, yy):
-    """Per-graph relative error ||S(c) - Y||^2 / ||Y||^2 = (c^T G c - 2 h^T c
-    + yy) / yy with c = (1 - sum c_rest, c_rest), and its gradient in c_rest."""
+def ratio(c, W, T):
+    """c^T W c / c^T T c for full coefficients c (9)."""
+    c = np.asarray(c, dtype=np.float64)
+    return float(c @ W @ c) / float(c @ T @ c)
+
+
+def loss_terms(c_rest, W, T):
+    """Per-graph normalised k-means cost c^T W c / c^T T c with
+    c = (1 - sum c_rest, c_rest), and its gradient in c_rest."""
     c_rest = np.atleast_2d(c_rest)
     L, dc = [], []
     for b in range(c_rest.shape[0]):
         c = full_coefficients(c_rest[b])
-        Gb, hb, yb = G[b], h[b], yy[b]
-        L.append((c @ Gb @ c - 2.0 * hb @ c + yb) / yb)
-        gfull = 2.0 * (Gb @ c - hb) / yb
+        num = c @ W[b] @ c
+        den = c @ T[b] @ c
+        Lb = num / den
+        L.append(Lb)
+        gfull = 2.0 * (W[b] @ c - Lb * (T[b] @ c)) / den
         dc.append(gfull[1:] - gfull[0])      # chain rule through c_0 = 1 - sum
     return np.array(L), np.array(dc)
 
 
-def loss(params, F, G, h, yy):
-    """Mean relative error over the batch."""
+def loss(params, F, W, T):
+    """Mean normalised cost over the batch."""
     c, _ = mlp_forward(params, F)
-    L, _ = loss_terms(c, G, h, yy)
+    L, _ = loss_terms(c, W, T)
     return float(L.mean())
 
 
-def loss_and_grad(params, F, G, h, yy):
+def loss_and_grad(params, F, W, T):
     """Mean loss and its gradient in the flat parameters (hand-written
     backward pass)."""
     c, acts = mlp_forward(params, F)
-    L, dc = loss_terms(c, G, h, yy)
+    L, dc = loss_terms(c, W, T)
     B = c.shape[0]
     delta = dc / B
     layers = unpack(params)
     grads = []
     for li in range(len(layers) - 1, -1, -1):
-        W, b = layers[li]
+        W_, b = layers[li]
         a_in = acts[li]
         grads.append((delta.T @ a_in, delta.sum(axis=0)))
         if li > 0:
-            delta = (delta @ W) * (acts[li] > 0)
+            delta = (delta @ W_) * (acts[li] > 0)
     grads.reverse()
     flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
     return float(L.mean()), flat

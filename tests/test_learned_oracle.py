@@ -1,6 +1,8 @@
 """Pins for the learned-form oracle: dense eigen closed forms of the filter,
-the exact Chebyshev expansion of gamma^8, the loss identity, and gradients
-against central finite differences and torch's autograd."""
+the exact Chebyshev expansion of gamma^8, the scatter statistics against the
+k-means cost of Sec. 2.2 and against pairwise distances, the loss's lower
+bound (smallest generalised eigenvalue), and gradients against central
+finite differences and torch's autograd."""
 import numpy as np
 import pytest
 import scipy.sparse.csgraph as csgraph
@@ -55,90 +57,160 @@ def test_filter_keeps_trivial_eigenvector():
     assert np.abs(fl.filter_apply(M, f1, c) - f1).max() < 1e-11
 
 
-def test_loss_identity_against_explicit_blocks():
+def _stats_graph():
+    # 3 planted clusters plus 4 isolated vertices (excluded from the scatter)
     g = synth.sbm(300, 3, 0.1, 0.01, seed=2)
-    F, G, h, yy = fl.graph_stats(g.n, g.indptr, g.indices, None, 3, 2, 15, seed=4)
-    assert G.shape == (9, 9) and np.allclose(G, G.T)
-    assert np.all(np.linalg.eigvalsh(G) > -1e-9 * np.abs(G).max())
-    c_rest = np.random.default_rng(1).standard_normal(8) * 0.1
-    L, _ = fl.loss_terms(c_rest[None], G[None], h[None], np.array([yy]))
-    X0 = o.gaussian_block(g.n, 2, 4)
-    M = o.signless_laplacian(g.n, g.indptr, g.indices, None)
-    S = fl.filter_apply(M, X0, fl.full_coefficients(c_rest))
-    Y = o.power_method(M, X0, 15)
-    assert abs(L[0] - ((S - Y) ** 2).sum() / (Y ** 2).sum()) < 1e-10
+    n = g.n + 4
+    indptr = np.concatenate([g.indptr, np.full(4, g.indptr[-1])])
+    return n, indptr, g.indices
+
+
+def test_scatter_stats_are_the_kmeans_cost():
+    n, ip, ix = _stats_graph()
+    F, W, T, labels = fl.graph_stats(n, ip, ix, None, 3, 2, 15, seed=4)
+    assert W.shape == T.shape == (9, 9) and np.allclose(W, W.T) and np.allclose(T, T.T)
+    X0 = o.gaussian_block(n, 2, 4)
+    M = o.signless_laplacian(n, ip, ix, None)
+    d = o.degrees(n, ip, ix, None)
+    m = d > 0
+    s = o.inv_sqrt_degree(d)
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        c = fl.full_coefficients(rng.standard_normal(8) * 0.3)
+        E = (s[:, None] * fl.filter_apply(M, X0, c))[m]
+        assert abs(c @ W @ c - o.kmeans_cost(E, labels[m], 3)) <= 1e-10 * (c @ T @ c)
+        # total scatter: the cost of one cluster holding every row
+        assert abs(c @ T @ c - o.kmeans_cost(E, np.zeros(m.sum(), dtype=int), 1)) <= 1e-10 * (c @ T @ c)
+    # the labels are the plain method's (Algorithm 2)
+    lab_p, _, _ = o.fast_spectral_cluster(n, ip, ix, None, 3, 2, 15, 4, 30)
+    assert np.array_equal(labels[m], np.asarray(lab_p)[m])
     assert F.shape == (9,)
     # Rayleigh features are quotients of M: inside [0, 1]
     assert np.all((F[5:] >= 0) & (F[5:] <= 1))
 
 
+def test_scatter_by_pairwise_distances():
+    """Within scatter of a cluster C = sum over pairs u < v in C of
+    ||e_u - e_v||^2 / |C| (no means involved), on a tiny brute-force case;
+    T - W (the between-cluster scatter) is positive semidefinite."""
+    rng = np.random.default_rng(3)
+    n, l = 23, 3
+    Bz = [rng.standard_normal((n, l)) for _ in range(9)]
+    labels = rng.integers(0, 4, n)
+    mask = np.ones(n, dtype=bool)
+    mask[[2, 9]] = False
+    W, T = fl.scatter_stats(Bz, labels, mask)
+    c = rng.standard_normal(9)
+    E = sum(cj * b for cj, b in zip(c, Bz))
+    idx = np.nonzero(mask)[0]
+    want_w = want_t = 0.0
+    for a_ in range(len(idx)):
+        for b_ in range(a_ + 1, len(idx)):
+            u, v = idx[a_], idx[b_]
+            dist = ((E[u] - E[v]) ** 2).sum()
+            want_t += dist / len(idx)
+            if labels[u] == labels[v]:
+                want_w += dist / np.sum(labels[idx] == labels[u])
+    assert abs(c @ W @ c - want_w) < 1e-10 * want_t
+    assert abs(c @ T @ c - want_t) < 1e-10 * want_t
+    assert np.linalg.eigvalsh(W).min() > -1e-10 * np.abs(T).max()
+    assert np.linalg.eigvalsh(T - W).min() > -1e-10 * np.abs(T).max()
+
+
+def test_loss_at_gamma_t_is_the_plain_embeddings_cost():
+    """With t = 8 the coefficients of gamma^8 give E(c) = the plain embedding
+    (Algorithm 1 output in z-space), so the loss is that embedding's k-means
+    cost under its own labels over its total scatter."""
+    n, ip, ix = _stats_graph()
+    F, W, T, labels = fl.graph_stats(n, ip, ix, None, 3, 2, 8, seed=6)
+    c8 = C.poly2cheb(np.polynomial.polynomial.polypow([0.5, 0.5], 8))
+    L, _ = fl.loss_terms(c8[1:][None], W[None], T[None])
+    m = o.degrees(n, ip, ix, None) > 0
+    E = o.embed(n, ip, ix, None, 2, 8, seed=6)[m]
+    want = o.kmeans_cost(E, labels[m], 3) / o.kmeans_cost(E, np.zeros(m.sum(), dtype=int), 1)
+    assert abs(L[0] - want) < 1e-10
+    assert abs(fl.ratio(c8, W, T) - want) < 1e-10
+
+
 def _batch(B=5, seed=0):
     rng = np.random.default_rng(seed)
     F = rng.standard_normal((B, fl.NFEAT))
-    G, h, yy = [], [], []
+    W, T = [], []
     for _ in range(B):
-        A = rng.standard_normal((9, 12))
-        G.append(A @ A.T)
-        h.append(rng.standard_normal(9))
-        yy.append(float(rng.uniform(1, 3)))
-    return F, np.array(G), np.array(h), np.array(yy)
+        A = rng.standard_normal((9, 14))
+        Bm = rng.standard_normal((9, 5))
+        W.append(A @ A.T)
+        T.append(A @ A.T + Bm @ Bm.T)      # T = W + a positive semidefinite between part
+    return F, np.array(W), np.array(T)
+
+
+def _lambda_min(W, T):
+    """Smallest generalised eigenvalue of (W, T): the least possible ratio."""
+    Lc = np.linalg.cholesky(T)
+    Li = np.linalg.inv(Lc)
+    return float(np.linalg.eigvalsh(Li @ W @ Li.T).min())
 
 
 def test_gradient_matches_finite_differences():
     p = fl.init_params(1)
     p[-1000:] *= 100.0       # a last layer large enough to give the loss curvature
-    F, G, h, yy = _batch()
-    L, g = fl.loss_and_grad(p, F, G, h, yy)
+    F, W, T = _batch()
+    L, g = fl.loss_and_grad(p, F, W, T)
     rng = np.random.default_rng(2)
     idx = rng.choice(p.size, 60, replace=False)
     eps = 1e-6
     for i in idx:
         e = np.zeros_like(p); e[i] = eps
-        fd = (fl.loss(p + e, F, G, h, yy) - fl.loss(p - e, F, G, h, yy)) / (2 * eps)
+        fd = (fl.loss(p + e, F, W, T) - fl.loss(p - e, F, W, T)) / (2 * eps)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd))
 
 
 def test_gradient_matches_torch_autograd():
     torch = pytest.importorskip("torch")
     p = fl.init_params(3)
-    F, G, h, yy = _batch(4, seed=5)
-    L, g = fl.loss_and_grad(p, F, G, h, yy)
+    p[-1000:] *= 30.0
+    F, W, T = _batch(4, seed=5)
+    L, g = fl.loss_and_grad(p, F, W, T)
     P = torch.tensor(p, dtype=torch.float64, requires_grad=True)
     pos, x = 0, torch.tensor(F)
     for li, (i, o_) in enumerate(fl.LAYERS):
-        W = P[pos:pos + i * o_].view(o_, i); pos += i * o_
+        Wl = P[pos:pos + i * o_].view(o_, i); pos += i * o_
         b = P[pos:pos + o_]; pos += o_
-        x = x @ W.T + b
+        x = x @ Wl.T + b
         if li < len(fl.LAYERS) - 1:
             x = torch.relu(x)
     c = torch.cat([1 - x.sum(1, keepdim=True), x], 1)
-    Gt, ht, yt = torch.tensor(G), torch.tensor(h), torch.tensor(yy)
-    Lt = ((torch.einsum("bi,bij,bj->b", c, Gt, c) - 2 * (ht * c).sum(1) + yt) / yt).mean()
+    Wt, Tt = torch.tensor(W), torch.tensor(T)
+    num = torch.bmm(torch.bmm(c[:, None, :], Wt), c[:, :, None]).flatten()
+    den = torch.bmm(torch.bmm(c[:, None, :], Tt), c[:, :, None]).flatten()
+    Lt = (num / den).mean()
     Lt.backward()
     assert abs(Lt.item() - L) < 1e-12
     assert np.abs(P.grad.numpy() - g).max() < 1e-10
 
 
-def test_adam_reduces_loss():
-    F, G, h, yy = _batch(8, seed=7)
+def test_adam_reduces_loss_to_no_less_than_the_bound():
+    F, W, T = _batch(8, seed=7)
     p = fl.init_params(4)
     m = np.zeros_like(p); v = np.zeros_like(p)
-    L0 = fl.loss(p, F, G, h, yy)
+    L0 = fl.loss(p, F, W, T)
     for step in range(1, 201):
-        _, g = fl.loss_and_grad(p, F, G, h, yy)
+        _, g = fl.loss_and_grad(p, F, W, T)
         p, m, v = fl.adam_step(p, g, m, v, step, 1e-3)
-    assert fl.loss(p, F, G, h, yy) < 0.5 * L0
-    # the optimum per graph is the least-squares solution: the loss never
-    # goes below it
+    L1 = fl.loss(p, F, W, T)
+    bound = np.mean([_lambda_min(W[b], T[b]) for b in range(8)])
+    assert L1 < L0 - 0.3 * (L0 - bound)
+    # the ratio never goes below the smallest generalised eigenvalue, and the
+    # eigenvector (scaled so p(1) = 1) attains it
     for b in range(8):
-        A = np.eye(9)[:, 1:] - np.outer(np.eye(9)[0], np.ones(8))   # c = e0 + A c_rest
-        e0 = np.eye(9)[0]
-        Gr = A.T @ G[b] @ A
-        rhs = A.T @ (h[b] - G[b] @ e0)
-        cr = np.linalg.solve(Gr, rhs)
-        Lmin, _ = fl.loss_terms(cr[None], G[b][None], h[b][None], yy[b:b + 1])
-        Lb, _ = fl.loss_terms(fl.mlp_forward(p, F[b:b + 1])[0], G[b][None], h[b][None], yy[b:b + 1])
-        assert Lb[0] >= Lmin[0] - 1e-9
+        lam = _lambda_min(W[b], T[b])
+        Lb, _ = fl.loss_terms(fl.mlp_forward(p, F[b:b + 1])[0], W[b][None], T[b][None])
+        assert Lb[0] >= lam - 1e-12
+        ev, V = np.linalg.eig(np.linalg.solve(T[b], W[b]))
+        x = np.real(V[:, np.argmin(np.real(ev))])
+        x = x / x.sum()
+        La, _ = fl.loss_terms(x[1:][None], W[b][None], T[b][None])
+        assert abs(La[0] - lam) < 1e-9
 
 
 def test_adam_matches_torch_optimizer():
