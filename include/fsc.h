@@ -214,14 +214,21 @@ int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, f
 /* Number of MLP parameters (35336). */
 int fsc_mlp_param_count(void);
 
-/* Training statistics of one graph (FP32 vectors): features (device float[9]),
- * and over the non-isolated vertices in y-space, summed over the l columns,
- * gram[i*9+j] = <B_i, B_j>, h[i] = <B_i, Y>, yy[0] = <Y, Y> (device FP64
- * [81], [9], [1]) with Y = M^t X0 the plain PowerMethod output.  The MLP's
- * training loss of the graph is (c^T G c - 2 h^T c + yy) / yy, the relative
- * squared error of p(M) X0 against Y. */
+/* Training statistics of one graph (FP32 vectors).  The plain method
+ * (Algorithm 2: t PowerMethod steps from the start block of `seed`, then
+ * k-means with opts->kmeans_iters Lloyd steps; opts may be NULL, its vector
+ * type, traces, renorm and x0 are ignored) labels the vertices: labels
+ * (device int32[n]).  Over the non-isolated vertices, the filtered embedding
+ * E(c) = D^{-1/2} p(M) X0 = sum_j c_j B_j (B_j = D^{-1/2} T*_j(M) X0, the
+ * same X0) has within-cluster scatter c^T W c under those labels (the k-means
+ * cost of Sec. 2.2) and total scatter c^T T c (its value for one cluster):
+ * within and total (device FP64 9 x 9, row-major, symmetric).  features:
+ * device float[9].  The MLP's training loss of the graph is the ratio
+ * c^T W c / c^T T c, the normalised k-means cost, scale-free and in [0, 1].
+ * k in [1, min(n, 64)], l in [1, 8], t >= 0. */
 int fsc_filter_stats(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t, uint64_t seed,
-                     float* features, double* gram, double* h, double* yy, void* stream);
+                     const fsc_opts* opts, float* features, double* within, double* total, int32_t* labels,
+                     void* stream);
 
 /* Coefficients c_1..c_8 (device float[count][8]) for `count` feature rows
  * (device float[count][9]). */
@@ -229,11 +236,12 @@ int fsc_mlp_forward(fsc_context* ctx, const float* params, int32_t count, const 
                     float* coeffs, void* stream);
 
 /* Mean training loss over `count` graphs (device double[1]) and its gradient
- * in the parameters (device float[param_count]); inputs as produced by
- * fsc_filter_stats, stacked. */
+ * in the parameters (device float[param_count]); features (float[count][9]),
+ * within and total (double[count][81]) as produced by fsc_filter_stats,
+ * stacked.  A graph whose total scatter c^T T c is 0 contributes 0 with a
+ * zero gradient. */
 int fsc_mlp_loss_grad(fsc_context* ctx, const float* params, int32_t count, const float* features,
-                      const double* gram, const double* h, const double* yy, float* grad, double* loss,
-                      void* stream);
+                      const double* within, const double* total, float* grad, double* loss, void* stream);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; `step`
  * counts from 1) on params with moment buffers m, v (device, zeroed before
@@ -246,8 +254,8 @@ int fsc_mlp_adam(fsc_context* ctx, float* params, float* m, float* v, const floa
  * step.  m and v must be zero for a fresh start; `first_step` is the Adam step
  * number of the first update (1 for a fresh start). */
 int fsc_mlp_train(fsc_context* ctx, float* params, float* m, float* v, int32_t count, const float* features,
-                  const double* gram, const double* h, const double* yy, int32_t steps, float lr,
-                  int32_t first_step, double* loss_trace, void* stream);
+                  const double* within, const double* total, int32_t steps, float lr, int32_t first_step,
+                  double* loss_trace, void* stream);
 
 /* The filtered embedding D^{-1/2} p(M) X0 with given coefficients c_1..c_8
  * (device float[8]); emb: FP32 n x l. */

@@ -190,13 +190,19 @@ def ratio(c, W, T):
 
 def loss_terms(c_rest, W, T):
     """Per-graph normalised k-means cost c^T W c / c^T T c with
-    c = (1 - sum c_rest, c_rest), and its gradient in c_rest."""
+    c = (1 - sum c_rest, c_rest), and its gradient in c_rest.  With zero
+    total scatter (every row equal) the ratio is undefined; such a graph
+    counts 0 with a zero gradient."""
     c_rest = np.atleast_2d(c_rest)
     L, dc = [], []
     for b in range(c_rest.shape[0]):
         c = full_coefficients(c_rest[b])
         num = c @ W[b] @ c
         den = c @ T[b] @ c
+        if not den > 0:
+            L.append(0.0)
+            dc.append(np.zeros(DEG))
+            continue
         Lb = num / den
         L.append(Lb)
         gfull = 2.0 * (W[b] @ c - Lb * (T[b] @ c)) / den

@@ -121,8 +121,9 @@ static int prepare_embed(Context* ctx, const fsc_csr* g, int l, int t, uint64_t 
 }
 
 // Workspace of the learned form on top of the embedding's: the 8 further
-// Chebyshev basis blocks, the plain output Y, the filtered block S,
-// statistics, features, coefficients and the small MLP scratch.
+// Chebyshev basis blocks, a spare block Y (M^8 X0 for the fallback check),
+// the filtered block S, statistics, features, coefficients and the small MLP
+// scratch.
 struct FilterWS {
   float* basis[9];
   float* Y;
@@ -130,7 +131,7 @@ struct FilterWS {
   double* ray;       // [16][LH]
   double* part;      // [2 * num_cu][55]
   int32_t* counter;  // [4]
-  double* gram;      // [91]
+  double* gram;      // [91]: the basis Gram matrix, or the k-means cost
   float* feat;       // [9]
   float* coef;       // [8]
   int32_t* used;     // [1]
@@ -442,36 +443,40 @@ int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, f
 
 int fsc_mlp_param_count(void) { return mlp_param_count(); }
 
+static int filter_front(Context* ctx, const fsc_csr* g, int k, int l, uint64_t seed, const fsc_opts& o,
+                        size_t extra, EmbedIO* io, Arena* arena, FilterWS* w, hipStream_t s);
+
 int fsc_filter_stats(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t, uint64_t seed,
-                     float* features, double* gram, double* h, double* yy, void* stream) {
-  if (!ctx || !features || !gram || !h || !yy) return fail(FSC_E_ARG, "null pointer");
+                     const fsc_opts* opts, float* features, double* within, double* total, int32_t* labels,
+                     void* stream) {
+  if (!ctx || !features || !within || !total || !labels) return fail(FSC_E_ARG, "null pointer");
   int rc;
   if ((rc = check_csr(g))) return rc;
-  if (k < 1 || k > g->n) return fail(FSC_E_ARG, "k must be in [1, n]");
+  if (l < 1 || l > 8) return fail(FSC_E_ARG, "l must be in [1, 8]");
+  if (k < 1 || k > 64 || k > g->n) return fail(FSC_E_ARG, "k must be in [1, min(n, 64)]");
+  if (t < 0) return fail(FSC_E_ARG, "t must be >= 0");
   if (g->val && g->val_dtype != FSC_F32) return fail(FSC_E_UNSUPPORTED, "the learned form takes FP32 or unit weights");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
-  const fsc_opts o = default_opts();
+  fsc_opts o = opts ? *opts : default_opts();
+  o.vec_dtype = FSC_F32;
+  o.sqnorm_trace = nullptr;
+  o.rayleigh_trace = nullptr;
+  o.renorm = 0;
+  o.x0 = nullptr;
+  // the plain method's labels (Algorithm 2)
+  if ((rc = cluster_run(&ctx->c, g, k, l, t, seed, o, labels, nullptr, nullptr, s, nullptr))) return rc;
+  // the basis blocks, features, and the scatter statistics under those labels
   EmbedIO io;
   Arena arena;
-  if ((rc = prepare_embed(&ctx->c, g, l, t, seed, o, filter_extra_bytes(&ctx->c, g, l), &io, &arena))) return rc;
   FilterWS w;
-  filter_bind(&ctx->c, &arena, &io, &w);
+  const size_t sums_bytes = scatter_workspace_bytes(g->n, l, k);
+  if ((rc = filter_front(&ctx->c, g, k, l, seed, o, sums_bytes + 256, &io, &arena, &w, s))) return rc;
+  double* sums = arena.take<double>(sums_bytes / 8);
   if (arena.used > arena.size) return fail(FSC_E_NOMEM, "workspace layout overflow");
-  const size_t blk = (size_t)g->n * io.LH * 4;
-  // the plain output Y = M^t X0
-  if ((rc = embed_run(&ctx->c, &io, s))) return rc;
-  if ((rc = check_hip(hipMemcpyAsync(w.Y, io.zt, blk, hipMemcpyDeviceToDevice, s), "copy Y"))) return rc;
-  // the start block again (t = 0), then the Chebyshev basis
-  io.t = 0;
-  if ((rc = embed_run(&ctx->c, &io, s))) return rc;
-  if ((rc = zero_counter(w.counter, s))) return rc;
-  if ((rc = cheb_basis_run(&ctx->c, &io, w.basis, w.ray, s))) return rc;
-  if ((rc = gram_run(&ctx->c, &io, w.basis, w.Y, w.part, w.counter, w.gram, s))) return rc;
-  if ((rc = features_run(&ctx->c, &io, k, w.ray, w.part, w.counter + 1, features, s))) return rc;
-  if ((rc = check_hip(hipMemcpyAsync(gram, w.gram, 81 * 8, hipMemcpyDeviceToDevice, s), "copy gram"))) return rc;
-  if ((rc = check_hip(hipMemcpyAsync(h, w.gram + 81, 9 * 8, hipMemcpyDeviceToDevice, s), "copy h"))) return rc;
-  return check_hip(hipMemcpyAsync(yy, w.gram + 90, 8, hipMemcpyDeviceToDevice, s), "copy yy");
+  if ((rc = gram_run(&ctx->c, &io, w.basis, w.part, w.counter, w.gram, s))) return rc;
+  if ((rc = scatter_run(&io, w.basis, labels, k, w.gram, sums, within, total, s))) return rc;
+  return check_hip(hipMemcpyAsync(features, w.feat, 9 * 4, hipMemcpyDeviceToDevice, s), "copy features");
 }
 
 int fsc_mlp_forward(fsc_context* ctx, const float* params, int32_t count, const float* features, float* coeffs,
@@ -488,16 +493,15 @@ int fsc_mlp_forward(fsc_context* ctx, const float* params, int32_t count, const 
 }
 
 int fsc_mlp_loss_grad(fsc_context* ctx, const float* params, int32_t count, const float* features,
-                      const double* gram, const double* h, const double* yy, float* grad, double* loss,
-                      void* stream) {
-  if (!ctx || !params || !features || !gram || !h || !yy || !grad || !loss) return fail(FSC_E_ARG, "null pointer");
+                      const double* within, const double* total, float* grad, double* loss, void* stream) {
+  if (!ctx || !params || !features || !within || !total || !grad || !loss) return fail(FSC_E_ARG, "null pointer");
   if (count < 1) return fail(FSC_E_ARG, "count must be >= 1");
   hipStream_t s = static_cast<hipStream_t>(stream);
   int rc;
   if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
   Arena arena;
   if ((rc = reserve_arena(&ctx->c, mlp_workspace_bytes(count), &arena))) return rc;
-  return mlp_loss_grad_run(params, count, features, gram, h, yy, grad, loss, arena.base, s);
+  return mlp_loss_grad_run(params, count, features, within, total, grad, loss, arena.base, s);
 }
 
 int fsc_mlp_adam(fsc_context* ctx, float* params, float* m, float* v, const float* grad, float lr, int32_t step,
@@ -510,9 +514,9 @@ int fsc_mlp_adam(fsc_context* ctx, float* params, float* m, float* v, const floa
 }
 
 int fsc_mlp_train(fsc_context* ctx, float* params, float* m, float* v, int32_t count, const float* features,
-                  const double* gram, const double* h, const double* yy, int32_t steps, float lr,
-                  int32_t first_step, double* loss_trace, void* stream) {
-  if (!ctx || !params || !m || !v || !features || !gram || !h || !yy) return fail(FSC_E_ARG, "null pointer");
+                  const double* within, const double* total, int32_t steps, float lr, int32_t first_step,
+                  double* loss_trace, void* stream) {
+  if (!ctx || !params || !m || !v || !features || !within || !total) return fail(FSC_E_ARG, "null pointer");
   if (count < 1 || steps < 0 || first_step < 1) return fail(FSC_E_ARG, "bad count, steps or first_step");
   hipStream_t s = static_cast<hipStream_t>(stream);
   int rc;
@@ -526,7 +530,7 @@ int fsc_mlp_train(fsc_context* ctx, float* params, float* m, float* v, int32_t c
   double* lbuf = arena.take<double>(1);
   for (int i = 0; i < steps; ++i) {
     double* lo = loss_trace ? loss_trace + i : lbuf;
-    if ((rc = mlp_loss_grad_run(params, count, features, gram, h, yy, grad, lo, ws, s))) return rc;
+    if ((rc = mlp_loss_grad_run(params, count, features, within, total, grad, lo, ws, s))) return rc;
     if ((rc = mlp_adam_run(params, m, v, grad, lr, first_step + i, s))) return rc;
   }
   return FSC_OK;

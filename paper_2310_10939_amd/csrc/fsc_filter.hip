@@ -9,9 +9,16 @@
 // PowerMethod step, so each basis block costs one sparse product (the tile
 // kernel with a Chebyshev epilogue).  The epilogue also accumulates the
 // column Rayleigh quotients <B_j, M B_j> / <B_j, B_j> (y-space) used as
-// features.  The Gram statistics <B_i, B_j>, <B_i, Y>, <Y, Y> (FP64, over the
-// l columns) are what the trainer needs; the filtered embedding is
-// S = sum_j c_j B_j with c_0 = 1 - sum_{j>0} c_j (so p(1) = 1).
+// features.  The filtered embedding is E(c) = sum_j c_j B_j with
+// c_0 = 1 - sum_{j>0} c_j (so p(1) = 1).
+//
+// Training statistics: for labels of the non-isolated vertices, the
+// within-cluster and total scatter of E(c) (the k-means cost of Sec. 2.2 and
+// its one-cluster value) are quadratic forms c^T W c and c^T T c.  With
+// G_ij = sum_v <B_i[v], B_j[v]>, S_ic = sum_{v in C_c} B_i[v] and m_c = |C_c|:
+//   W_ij = G_ij - sum_c <S_ic, S_jc> / m_c,
+//   T_ij = G_ij - <S_i, S_j> / m   (S_i = sum_c S_ic, m = sum_c m_c),
+// all in FP64 from the FP32 blocks, each sum in a fixed order.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
 #include "fsc_tiles.hpp"
@@ -144,39 +151,35 @@ struct ChebOp {
 };
 
 // ---------------------------------------------------------------------------
-// Gram statistics: G_ij = sum_v d_v <B_i[v], B_j[v]>, h_i = <B_i, Y>, yy.
-// out: [0..81) G (both triangles), [81..90) h, [90] yy.
+// Gram matrix of the basis blocks over the non-isolated vertices:
+// G_ij = sum_{v: d_v > 0} <B_i[v], B_j[v]>, written to out[81] (both
+// triangles).
 // ---------------------------------------------------------------------------
 struct Blocks {
   const float* b[9];
 };
 
-constexpr int kGram = 45 + 9 + 1;
+constexpr int kGram = 45;
 
-__global__ __launch_bounds__(kBlock) void gram_kernel(Blocks B, const float* __restrict__ Y,
-                                                      const double* __restrict__ deg, int32_t n, int l, int LH,
-                                                      double* __restrict__ partials, int32_t* __restrict__ counter,
-                                                      double* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void gram_kernel(Blocks B, const double* __restrict__ deg, int32_t n, int l,
+                                                      int LH, double* __restrict__ partials,
+                                                      int32_t* __restrict__ counter, double* __restrict__ out) {
   __shared__ double red[kBlock / FSC_WAVE];
   __shared__ int is_last;
   double acc[kGram];
 #pragma unroll
   for (int i = 0; i < kGram; ++i) acc[i] = 0.0;
   for (int32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
-    const double d = deg[r];
+    if (!(deg[r] > 0.0)) continue;
     for (int q = 0; q < l; ++q) {
       double b[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) b[i] = (double)B.b[i][(int64_t)r * LH + q];
-      const double y = Y ? (double)Y[(int64_t)r * LH + q] : 0.0;
       int idx = 0;
 #pragma unroll
       for (int i = 0; i < 9; ++i)
 #pragma unroll
-        for (int j = i; j < 9; ++j) acc[idx++] += d * b[i] * b[j];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) acc[45 + i] += d * b[i] * y;
-      acc[54] += d * y * y;
+        for (int j = i; j < 9; ++j) acc[idx++] += b[i] * b[j];
     }
   }
 #pragma unroll
@@ -195,20 +198,118 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(Blocks B, const float* __r
     double s = 0.0;
     for (int g = 0; g < (int)gridDim.x; ++g) s += partials[(int64_t)g * kGram + threadIdx.x];
     const int k = threadIdx.x;
-    if (k < 45) {
-      int i = 0, base = 0;
-      while (k >= base + (9 - i)) {
-        base += 9 - i;
-        ++i;
-      }
-      const int j = i + (k - base);
-      out[i * 9 + j] = s;
-      out[j * 9 + i] = s;
-    } else {
-      out[81 + (k - 45)] = s;
+    int i = 0, base = 0;
+    while (k >= base + (9 - i)) {
+      base += 9 - i;
+      ++i;
     }
+    const int j = i + (k - base);
+    out[i * 9 + j] = s;
+    out[j * 9 + i] = s;
   }
   if (threadIdx.x == 0) *counter = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Per-cluster sums of the basis blocks.  Block g takes rows
+// [g * chunk, (g + 1) * chunk); thread e < 9l owns component e = i * l + q
+// (block B_i, column q) and thread 9l counts the rows: each walks the chunk's
+// rows in order and adds to its own LDS column acc[c][e], so no two threads
+// touch one word and the sums are deterministic.  part[g][c][e].
+// ---------------------------------------------------------------------------
+constexpr int kSumsRowsLds = 1024;  // labels and degree flags of this many rows staged at a time
+
+__global__ __launch_bounds__(kBlock) void cluster_sums_kernel(Blocks B, const int32_t* __restrict__ labels,
+                                                              const double* __restrict__ deg, int32_t n, int l,
+                                                              int LH, int k, int32_t chunk,
+                                                              double* __restrict__ part) {
+  extern __shared__ double acc[];  // k * E
+  __shared__ int32_t lab[kSumsRowsLds];
+  __shared__ const float* bp[9];
+  const int E = 9 * l + 1;
+  if (threadIdx.x < 9) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      if ((int)threadIdx.x == i) bp[i] = B.b[i];
+  }
+  for (int i = threadIdx.x; i < k * E; i += kBlock) acc[i] = 0.0;
+  const int32_t r0 = blockIdx.x * chunk;
+  const int32_t r1 = min(n, r0 + chunk);
+  const int e = threadIdx.x;
+  for (int32_t s0 = r0; s0 < r1; s0 += kSumsRowsLds) {
+    const int32_t cnt = min(kSumsRowsLds, r1 - s0);
+    __syncthreads();
+    // -1 marks a row in no cluster: an isolated vertex (or a label outside
+    // [0, k), which the k-means labels never are)
+    for (int i = threadIdx.x; i < cnt; i += kBlock) {
+      const int32_t c = labels[s0 + i];
+      lab[i] = deg[s0 + i] > 0.0 && c >= 0 && c < k ? c : -1;
+    }
+    __syncthreads();
+    if (e < E) {
+      const bool is_count = e == E - 1;
+      const float* src = is_count ? nullptr : bp[e / l] + (e % l);
+      int32_t i = 0;
+      for (; i + 8 <= cnt; i += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = is_count ? 1.0 : (double)src[(int64_t)(s0 + i + u) * LH];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int c = lab[i + u];
+          if (c >= 0) acc[c * E + e] += v[u];
+        }
+      }
+      for (; i < cnt; ++i) {
+        const int c = lab[i];
+        if (c >= 0) acc[c * E + e] += is_count ? 1.0 : (double)src[(int64_t)(s0 + i) * LH];
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k * E; i += kBlock) part[(int64_t)blockIdx.x * k * E + i] = acc[i];
+}
+
+// W and T from G (gram[81]) and the per-block cluster sums (one block).
+__global__ __launch_bounds__(kBlock) void scatter_finish_kernel(const double* __restrict__ part, int nblk, int l,
+                                                                int k, const double* __restrict__ gram,
+                                                                double* __restrict__ within,
+                                                                double* __restrict__ total) {
+  extern __shared__ double S[];  // k * E cluster sums, then E totals
+  const int E = 9 * l + 1;
+  for (int i = threadIdx.x; i < k * E; i += kBlock) {
+    double s = 0.0;
+    for (int g = 0; g < nblk; ++g) s += part[(int64_t)g * k * E + i];
+    S[i] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < E; e += kBlock) {
+    double s = 0.0;
+    for (int c = 0; c < k; ++c) s += S[c * E + e];
+    S[k * E + e] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 81) {
+    const int i = threadIdx.x / 9, j = threadIdx.x % 9;
+    double wb = 0.0;
+    for (int c = 0; c < k; ++c) {
+      const double* Sc = S + c * E;
+      const double m = Sc[E - 1];
+      if (!(m > 0.0)) continue;
+      double dot = 0.0;
+      for (int q = 0; q < l; ++q) dot += Sc[i * l + q] * Sc[j * l + q];
+      wb += dot / m;
+    }
+    const double* St = S + k * E;
+    const double m = St[E - 1];
+    double tb = 0.0;
+    if (m > 0.0) {
+      for (int q = 0; q < l; ++q) tb += St[i * l + q] * St[j * l + q];
+      tb /= m;
+    }
+    within[threadIdx.x] = gram[threadIdx.x] - wb;
+    total[threadIdx.x] = gram[threadIdx.x] - tb;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -452,15 +553,41 @@ int rayleigh_run(Context* ctx, EmbedIO* io, const float* x, double* ray, int row
   return ray_dispatch<void>(ctx, io, x, ray, row, s);
 }
 
-int gram_run(Context* ctx, const EmbedIO* io, float* const* basis, const float* Y, double* partials,
-             int32_t* counter, double* out, hipStream_t s) {
+int gram_run(Context* ctx, const EmbedIO* io, float* const* basis, double* partials, int32_t* counter, double* out,
+             hipStream_t s) {
   Blocks B;
   for (int j = 0; j < 9; ++j) B.b[j] = basis[j];
   const int32_t n = (int32_t)io->g->n;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, ctx->num_cu * 2));
-  hipLaunchKernelGGL(gram_kernel, dim3(grid), dim3(kBlock), 0, s, B, Y, io->deg, n, io->l, io->LH, partials, counter,
-                     out);
+  hipLaunchKernelGGL(gram_kernel, dim3(grid), dim3(kBlock), 0, s, B, io->deg, n, io->l, io->LH, partials, counter, out);
   return check_hip(hipGetLastError(), "gram launch");
+}
+
+// Blocks of the cluster-sums kernel: about 256 rows each, at most kSumsGrid.
+constexpr int kSumsGrid = 512;
+
+static int sums_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, kSumsGrid)); }
+
+size_t scatter_workspace_bytes(int64_t n, int l, int k) {
+  return align_up((size_t)sums_grid(n) * k * (9 * l + 1) * 8);
+}
+
+int scatter_run(const EmbedIO* io, float* const* basis, const int32_t* labels, int k, const double* gram,
+                double* sums, double* within, double* total, hipStream_t s) {
+  Blocks B;
+  for (int j = 0; j < 9; ++j) B.b[j] = basis[j];
+  const int32_t n = (int32_t)io->g->n;
+  const int l = io->l, E = 9 * l + 1;
+  const int grid = sums_grid(n);
+  const int32_t chunk = (n + grid - 1) / grid;
+  // LDS: k * E doubles (at most 64 * 73 * 8 = 37 KB) plus the staged labels
+  hipLaunchKernelGGL(cluster_sums_kernel, dim3(grid), dim3(kBlock), (size_t)k * E * 8, s, B, labels, io->deg, n, l,
+                     io->LH, k, chunk, sums);
+  int rc = check_hip(hipGetLastError(), "cluster sums launch");
+  if (rc) return rc;
+  hipLaunchKernelGGL(scatter_finish_kernel, dim3(1), dim3(kBlock), (size_t)(k + 1) * E * 8, s, sums, grid, l, k, gram,
+                     within, total);
+  return check_hip(hipGetLastError(), "scatter finish launch");
 }
 
 int features_run(Context* ctx, const EmbedIO* io, int k, const double* ray, double* partials, int32_t* counter,

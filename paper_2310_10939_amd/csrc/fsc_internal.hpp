@@ -276,8 +276,11 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
 // ---- learned form (fsc_filter.hip, fsc_mlp.hip) ----
 int cheb_basis_run(Context* ctx, EmbedIO* io, float* const* basis, double* ray, hipStream_t s);
 int rayleigh_run(Context* ctx, EmbedIO* io, const float* x, double* ray, int row, hipStream_t s);
-int gram_run(Context* ctx, const EmbedIO* io, float* const* basis, const float* Y, double* partials,
-             int32_t* counter, double* out, hipStream_t s);
+int gram_run(Context* ctx, const EmbedIO* io, float* const* basis, double* partials, int32_t* counter, double* out,
+             hipStream_t s);
+size_t scatter_workspace_bytes(int64_t n, int l, int k);
+int scatter_run(const EmbedIO* io, float* const* basis, const int32_t* labels, int k, const double* gram,
+                double* sums, double* within, double* total, hipStream_t s);
 int features_run(Context* ctx, const EmbedIO* io, int k, const double* ray, double* partials, int32_t* counter,
                  float* feat, hipStream_t s);
 int combine_run(const EmbedIO* io, float* const* basis, const float* c_rest, float* S, hipStream_t s);
@@ -286,8 +289,8 @@ int fallback_run(const EmbedIO* io, const double* ray, int row_f, int row_ref, c
 int mlp_param_count();
 size_t mlp_workspace_bytes(int B);
 int mlp_forward_run(const float* params, int B, const float* feats, float* acts, float* c_out, hipStream_t s);
-int mlp_loss_grad_run(const float* params, int B, const float* feats, const double* G, const double* h,
-                      const double* yy, float* grad, double* loss_out, char* ws, hipStream_t s);
+int mlp_loss_grad_run(const float* params, int B, const float* feats, const double* W, const double* T,
+                      float* grad, double* loss_out, char* ws, hipStream_t s);
 int mlp_adam_run(float* p, float* m, float* v, const float* g, float lr, int step, hipStream_t s);
 
 // ---- ARI (fsc_ari.hip) ----

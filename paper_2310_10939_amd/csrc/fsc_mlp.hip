@@ -3,10 +3,10 @@
 // backward and Adam kernels.
 //
 // Parameters are one flat FP32 array: for each layer, W (out x in, row-major)
-// then b (out).  The training loss of a graph is the relative error
-// ||S(c) - Y||^2 / ||Y||^2 of the filtered block against the plain
-// PowerMethod output, which is (c^T G c - 2 h^T c + yy) / yy in its FP64
-// Gram statistics (c = (1 - sum c_rest, c_rest)); the batch loss is the mean.
+// then b (out).  The training loss of a graph is the normalised k-means cost
+// (Sec. 2.2) of its filtered embedding under the plain method's labels:
+// within-cluster over total scatter, c^T W c / c^T T c in its FP64 scatter
+// statistics (c = (1 - sum c_rest, c_rest)); the batch loss is the mean.
 // Every reduction runs in a fixed order, so training is deterministic.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
@@ -46,10 +46,13 @@ __global__ void mlp_fwd_kernel(const float* __restrict__ W, const float* __restr
   }
 }
 
-// Per-graph loss and dL/dc_rest / B (FP64 from the FP32 outputs).
-__global__ void mlp_loss_kernel(const float* __restrict__ c_rest, const double* __restrict__ G,
-                                const double* __restrict__ h, const double* __restrict__ yy, int B,
-                                float* __restrict__ delta, double* __restrict__ loss_per) {
+// Per-graph loss L = c^T W c / c^T T c and dL/dc_rest / B (FP64 from the
+// FP32 outputs): dL/dc = 2 (W c - L T c) / c^T T c, and c_0 = 1 - sum c_rest
+// gives dL/dc_j - dL/dc_0.  A graph with c^T T c = 0 (all its rows equal)
+// has no defined ratio and contributes 0 with a zero gradient.
+__global__ void mlp_loss_kernel(const float* __restrict__ c_rest, const double* __restrict__ W,
+                                const double* __restrict__ T, int B, float* __restrict__ delta,
+                                double* __restrict__ loss_per) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   double c[9];
@@ -59,22 +62,31 @@ __global__ void mlp_loss_kernel(const float* __restrict__ c_rest, const double* 
     sum += c[j + 1];
   }
   c[0] = 1.0 - sum;
-  const double* Gb = G + (int64_t)b * 81;
-  const double* hb = h + (int64_t)b * 9;
-  const double y = yy[b];
-  double Gc[9];
-  double quad = 0.0, lin = 0.0;
+  const double* Wb = W + (int64_t)b * 81;
+  const double* Tb = T + (int64_t)b * 81;
+  double Wc[9], Tc[9];
+  double num = 0.0, den = 0.0;
   for (int i = 0; i < 9; ++i) {
-    double s = 0.0;
-    for (int j = 0; j < 9; ++j) s += Gb[i * 9 + j] * c[j];
-    Gc[i] = s;
-    quad += c[i] * s;
-    lin += hb[i] * c[i];
+    double sw = 0.0, st = 0.0;
+    for (int j = 0; j < 9; ++j) {
+      sw += Wb[i * 9 + j] * c[j];
+      st += Tb[i * 9 + j] * c[j];
+    }
+    Wc[i] = sw;
+    Tc[i] = st;
+    num += c[i] * sw;
+    den += c[i] * st;
   }
-  loss_per[b] = (quad - 2.0 * lin + y) / y;
-  const double g0 = 2.0 * (Gc[0] - hb[0]) / y;
+  if (!(den > 0.0)) {
+    loss_per[b] = 0.0;
+    for (int j = 0; j < 8; ++j) delta[b * 8 + j] = 0.f;
+    return;
+  }
+  const double L = num / den;
+  loss_per[b] = L;
+  const double g0 = 2.0 * (Wc[0] - L * Tc[0]) / den;
   for (int j = 0; j < 8; ++j) {
-    const double gj = 2.0 * (Gc[j + 1] - hb[j + 1]) / y;
+    const double gj = 2.0 * (Wc[j + 1] - L * Tc[j + 1]) / den;
     delta[b * 8 + j] = (float)((gj - g0) / (double)B);
   }
 }
@@ -157,8 +169,8 @@ int mlp_forward_run(const float* params, int B, const float* feats, float* acts,
   return check_hip(hipGetLastError(), "mlp forward launch");
 }
 
-int mlp_loss_grad_run(const float* params, int B, const float* feats, const double* G, const double* h,
-                      const double* yy, float* grad, double* loss_out, char* ws, hipStream_t s) {
+int mlp_loss_grad_run(const float* params, int B, const float* feats, const double* W, const double* T,
+                      float* grad, double* loss_out, char* ws, hipStream_t s) {
   Arena a;
   a.base = ws;
   a.size = mlp_workspace_bytes(B);
@@ -170,7 +182,7 @@ int mlp_loss_grad_run(const float* params, int B, const float* feats, const doub
   double* lp = a.take<double>(B);
   int rc = mlp_forward_run(params, B, feats, acts, c, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(mlp_loss_kernel, dim3((B + 255) / 256), dim3(256), 0, s, c, G, h, yy, B, d0, lp);
+  hipLaunchKernelGGL(mlp_loss_kernel, dim3((B + 255) / 256), dim3(256), 0, s, c, W, T, B, d0, lp);
   hipLaunchKernelGGL(mlp_loss_mean_kernel, dim3(1), dim3(256), 0, s, lp, B, loss_out);
   // backward: layer 3 (delta d0 is B x 8) down to layer 0
   float* delta = d0;

@@ -57,11 +57,12 @@ _lib.fsc_cluster_batched.argtypes = [_vp, _i32, ctypes.POINTER(Csr), ctypes.POIN
 _lib.fsc_autotune.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, ctypes.POINTER(Tuning), _vp]
 _f = ctypes.c_float
 _lib.fsc_mlp_param_count.restype = ctypes.c_int
-_lib.fsc_filter_stats.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _i32, _u64, _vp, _vp, _vp, _vp, _vp]
+_lib.fsc_filter_stats.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp,
+                                  _vp, _vp, _vp]
 _lib.fsc_mlp_forward.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
-_lib.fsc_mlp_loss_grad.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.fsc_mlp_loss_grad.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.fsc_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, _f, _i32, _vp]
-_lib.fsc_mlp_train.argtypes = [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i32, _f, _i32, _vp, _vp]
+_lib.fsc_mlp_train.argtypes = [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, _f, _i32, _vp, _vp]
 _lib.fsc_filter_embed.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _u64, _vp, _vp, _vp]
 _lib.fsc_cluster_filtered.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, _vp, _vp, _i32,
                                       ctypes.POINTER(Opts), _vp, _vp, _vp, ctypes.POINTER(_i32), _vp]
@@ -238,18 +239,21 @@ def mlp_param_count():
     return _lib.fsc_mlp_param_count()
 
 
-def filter_stats(indptr, indices, data, k, l, t, seed):
-    """Training statistics of one graph: (features float32[9], G float64[9,9],
-    h float64[9], yy float64[1]) device tensors."""
+def filter_stats(indptr, indices, data, k, l, t, seed, kmeans_iters=30):
+    """Training statistics of one graph: (features float32[9], within
+    float64[9,9], total float64[9,9], labels int32[n]) device tensors; the
+    labels are the plain method's."""
     dev = indptr.device
+    n = indptr.numel() - 1
     feat = torch.empty(9, dtype=torch.float32, device=dev)
-    G = torch.empty((9, 9), dtype=torch.float64, device=dev)
-    h = torch.empty(9, dtype=torch.float64, device=dev)
-    yy = torch.empty(1, dtype=torch.float64, device=dev)
+    W = torch.empty((9, 9), dtype=torch.float64, device=dev)
+    T = torch.empty((9, 9), dtype=torch.float64, device=dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
     g = _csr(indptr, indices, data)
-    _check(_lib.fsc_filter_stats(context(dev.index), ctypes.byref(g), k, l, t, seed, _ptr(feat), _ptr(G), _ptr(h),
-                                 _ptr(yy), _stream()))
-    return feat, G, h, yy
+    o = _opts(kmeans_iters=kmeans_iters)
+    _check(_lib.fsc_filter_stats(context(dev.index), ctypes.byref(g), k, l, t, seed, ctypes.byref(o), _ptr(feat),
+                                 _ptr(W), _ptr(T), _ptr(labels), _stream()))
+    return feat, W, T, labels
 
 
 def mlp_forward(params, feats):
@@ -260,11 +264,11 @@ def mlp_forward(params, feats):
     return out
 
 
-def mlp_loss_grad(params, feats, G, h, yy):
+def mlp_loss_grad(params, feats, W, T):
     grad = torch.empty_like(params)
     loss = torch.empty(1, dtype=torch.float64, device=params.device)
-    _check(_lib.fsc_mlp_loss_grad(context(params.device.index), _ptr(params), feats.shape[0], _ptr(feats), _ptr(G),
-                                  _ptr(h), _ptr(yy), _ptr(grad), _ptr(loss), _stream()))
+    _check(_lib.fsc_mlp_loss_grad(context(params.device.index), _ptr(params), feats.shape[0], _ptr(feats), _ptr(W),
+                                  _ptr(T), _ptr(grad), _ptr(loss), _stream()))
     return loss, grad
 
 
@@ -273,11 +277,11 @@ def mlp_adam(params, m, v, grad, lr, step):
                              _stream()))
 
 
-def mlp_train(params, m, v, feats, G, h, yy, steps, lr, first_step=1):
+def mlp_train(params, m, v, feats, W, T, steps, lr, first_step=1):
     """`steps` full-batch Adam steps on the device; returns the loss trace."""
     trace = torch.empty(steps, dtype=torch.float64, device=params.device)
     _check(_lib.fsc_mlp_train(context(params.device.index), _ptr(params), _ptr(m), _ptr(v), feats.shape[0],
-                              _ptr(feats), _ptr(G), _ptr(h), _ptr(yy), steps, lr, first_step, _ptr(trace), _stream()))
+                              _ptr(feats), _ptr(W), _ptr(T), steps, lr, first_step, _ptr(trace), _stream()))
     return trace
 
 

@@ -3,13 +3,15 @@
 Training data: degree-corrected SBM graphs (n uniform in [1e5, 2e6], k in
 [2, 50], power-law degree propensities with exponent 2.5 and mean degree 20,
 fp32 unit weights), generated on the device.  For each graph the library's
-kernels compute the plain PowerMethod output Y = M^t X0 (t = ceil(3 ln n),
-l = ceil(log2 k) + 1), the Chebyshev basis, the Gram statistics and the
-features (fsc_filter_stats); only these statistics are kept.  The MLP is then
-trained by full-batch Adam with the library's forward/backward/Adam kernels
-(fsc_mlp_train).  Held-out graphs measure the gain: ARI of the learned filter
-against the plain method, next to the fixed filter gamma^8 (8 plain steps, the
-same budget of sparse products), and wall times.
+kernels run the plain method (t = ceil(3 ln n) PowerMethod steps,
+l = ceil(log2 k) + 1, k-means) for its labels, then the Chebyshev basis, the
+within-cluster and total scatter matrices of the filtered embedding under
+those labels, and the features (fsc_filter_stats); only these statistics are
+kept.  The MLP is then trained by full-batch Adam on the normalised k-means
+cost with the library's forward/backward/Adam kernels (fsc_mlp_train).
+Held-out graphs measure the gain: ARI of the learned filter against the plain
+method, next to the fixed filter gamma^8 (8 plain steps, the same budget of
+sparse products) and the per-graph optimum of the loss, and wall times.
 
 Usage: python -m paper_2310_10939_amd.train_filter --graphs 2000 --heldout 100
        --out <params.npy> --report <report.json>
@@ -61,23 +63,22 @@ def collect(specs, device, log=print):
     import torch
     import synth
     from . import fsc
-    F, G, H, YY = [], [], [], []
+    F, W, T = [], [], []
     t0 = time.perf_counter()
     for i, s in enumerate(specs):
         ip, ix, _ = synth.dcsbm_device(s["n"], s["k"], 20.0, s["seed"], device=device)
-        f, g, h, yy = fsc.filter_stats(ip, ix, None, s["k"], s["l"], s["t"], s["seed"])
+        f, w, tt, _ = fsc.filter_stats(ip, ix, None, s["k"], s["l"], s["t"], s["seed"])
         F.append(f)
-        G.append(g)
-        H.append(h)
-        YY.append(yy)
+        W.append(w)
+        T.append(tt)
         del ip, ix
         if (i + 1) % 50 == 0 or i + 1 == len(specs):
             torch.cuda.synchronize()
             log(f"stats {i + 1}/{len(specs)} graphs, {time.perf_counter() - t0:.1f} s")
-    return torch.stack(F), torch.stack(G), torch.stack(H), torch.cat(YY)
+    return torch.stack(F), torch.stack(W), torch.stack(T)
 
 
-def train(F, G, H, YY, steps, lr, seed, log=print):
+def train(F, W, T, steps, lr, seed, log=print):
     import torch
     from . import fsc
     p = torch.from_numpy(init_params(seed)).to(F.device)
@@ -86,7 +87,7 @@ def train(F, G, H, YY, steps, lr, seed, log=print):
     traces = []
     done = 0
     for phase_steps, phase_lr in ((steps * 2 // 3, lr), (steps - steps * 2 // 3, lr * 0.3)):
-        tr = fsc.mlp_train(p, m, v, F, G, H, YY, phase_steps, phase_lr, first_step=done + 1)
+        tr = fsc.mlp_train(p, m, v, F, W, T, phase_steps, phase_lr, first_step=done + 1)
         traces.append(tr)
         done += phase_steps
         torch.cuda.synchronize()
@@ -94,29 +95,27 @@ def train(F, G, H, YY, steps, lr, seed, log=print):
     return p, torch.cat(traces)
 
 
-def ls_optimum(G, h, yy):
-    """Per-graph least-squares coefficients c_1..c_8 of the training loss
-    (the best any degree-8 filter with p(1) = 1 can do on that graph) and the
-    loss there.  Host FP64 solve of the 8 x 8 normal equations."""
-    A = np.eye(9)[:, 1:] - np.outer(np.eye(9)[0], np.ones(8))   # c = e0 + A c_rest
-    e0 = np.eye(9)[0]
-    Gr = A.T @ G @ A
-    rhs = A.T @ (h - G @ e0)
-    c = np.linalg.solve(Gr, rhs)
-    full = e0 + A @ c
-    return c, float((full @ G @ full - 2 * h @ full + yy) / yy)
+def ratio_optimum(W, T):
+    """Per-graph coefficients c_1..c_8 minimising c^T W c / c^T T c (the best
+    any degree-8 filter can do on that graph's loss): the generalised
+    eigenvector of the smallest eigenvalue, scaled so p(1) = sum c = 1, and
+    that eigenvalue.  Host FP64."""
+    Li = np.linalg.inv(np.linalg.cholesky(T))
+    lam, V = np.linalg.eigh(Li @ W @ Li.T)
+    x = Li.T @ V[:, 0]
+    return x[1:] / x.sum(), float(lam[0])
 
 
-def heldout_loss(p, F, G, H, YY):
+def heldout_loss(p, F, W, T):
     from . import fsc
-    loss, _ = fsc.mlp_loss_grad(p, F, G, H, YY)
+    loss, _ = fsc.mlp_loss_grad(p, F, W, T)
     return float(loss[0])
 
 
 def evaluate(p, specs, device, stats=None, log=print):
     """ARI against the plain method (and the planted clusters) of the learned
-    filter, of the fixed gamma^8 filter and of the per-graph least-squares
-    optimum, with wall times."""
+    filter, of the fixed gamma^8 filter and of the per-graph optimum of the
+    loss, with wall times."""
     import torch
     import synth
     from . import fsc
@@ -150,11 +149,14 @@ def evaluate(p, specs, device, stats=None, log=print):
         dg, d8 = diag.cpu().numpy(), diag8.cpu().numpy()
         extra = {}
         if stats is not None:
-            Gi, hi, yi = (x[i].double().cpu().numpy() for x in stats)
-            c_ls, loss_ls = ls_optimum(Gi, hi, float(yi))
+            Fi, Wi, Ti = (x[i].double().cpu().numpy() for x in stats)
+            c_opt, loss_opt = ratio_optimum(Wi, Ti)
             best, _, _ = fsc.cluster_filtered(ip, ix, None, k, l, seed,
-                                              coeffs=torch.tensor(c_ls, dtype=torch.float32, device=device))
-            extra = dict(loss_ls_optimum=loss_ls, ari_lsopt_vs_plain=float(fsc.ari(best, plain, k, k)))
+                                              coeffs=torch.tensor(c_opt, dtype=torch.float32, device=device))
+            c_l = coef.double().cpu().numpy()
+            full = np.concatenate([[1.0 - c_l.sum()], c_l])
+            extra = dict(loss_optimum=loss_opt, loss_learned=float(full @ Wi @ full / (full @ Ti @ full)),
+                         ari_opt_vs_plain=float(fsc.ari(best, plain, k, k)))
         rows.append(dict(n=s["n"], k=k, l=l, t=t, **extra,
                          ari_learned_vs_plain=float(fsc.ari(learned, plain, k, k)),
                          ari_fixed8_vs_plain=float(fsc.ari(fixed, plain, k, k)),
@@ -200,10 +202,10 @@ def main(argv=None):
 
     test_specs = synth.learned_params(args.heldout, 100000)
     if args.eval_only:
-        Ft, Gt, Ht, YYt = collect(test_specs, dev, log)
+        stats_t = collect(test_specs, dev, log)
         p = load_params(args.out, dev)
-        rows = evaluate(p, test_specs, dev, (Gt, Ht, YYt), log)
-        report = {"heldout_graphs": args.heldout, "heldout_loss": heldout_loss(p, Ft, Gt, Ht, YYt),
+        rows = evaluate(p, test_specs, dev, stats_t, log)
+        report = {"heldout_graphs": args.heldout, "heldout_loss": heldout_loss(p, *stats_t),
                   "summary": summarize(rows), "rows": rows}
         if args.report:
             with open(args.report, "w") as fh:
@@ -211,16 +213,16 @@ def main(argv=None):
         log(json.dumps({k: v for k, v in report.items() if k != "rows"}))
         return 0
     train_specs = synth.learned_params(args.graphs, 0)
-    F, G, H, YY = collect(train_specs, dev, log)
-    Ft, Gt, Ht, YYt = collect(test_specs, dev, log)
-    p, trace = train(F, G, H, YY, args.steps, args.lr, args.seed, log)
+    F, W, T = collect(train_specs, dev, log)
+    stats_t = collect(test_specs, dev, log)
+    p, trace = train(F, W, T, args.steps, args.lr, args.seed, log)
     np.save(args.out, p.cpu().numpy())
-    rows = evaluate(p, test_specs, dev, (Gt, Ht, YYt), log)
+    rows = evaluate(p, test_specs, dev, stats_t, log)
     report = {"train_graphs": args.graphs, "heldout_graphs": args.heldout, "steps": args.steps,
               "train_loss_first": float(trace[0]), "train_loss_last": float(trace[-1]),
-              "heldout_loss": heldout_loss(p, Ft, Gt, Ht, YYt),
-              "heldout_loss_identity_init": heldout_loss(torch.from_numpy(init_params(args.seed)).to(dev), Ft, Gt,
-                                                         Ht, YYt),
+              "heldout_loss": heldout_loss(p, *stats_t),
+              "heldout_loss_identity_init": heldout_loss(torch.from_numpy(init_params(args.seed)).to(dev),
+                                                         *stats_t),
               "summary": summarize(rows), "rows": rows}
     if args.report:
         with open(args.report, "w") as fh:

@@ -39,29 +39,66 @@ def test_gamma8_coefficients_equal_eight_power_steps(gpu_lib):
     assert col_rel_err(E8, P8) <= 1e-5
 
 
+def _scatter_oracle(g, data, l, seed, labels):
+    """W, T of the oracle's FP64 basis blocks under the given labels."""
+    X0 = o.gaussian_block(g.n, l, seed)
+    M = o.signless_laplacian(g.n, g.indptr, g.indices, data)
+    d = o.degrees(g.n, g.indptr, g.indices, data)
+    s = o.inv_sqrt_degree(d)
+    B = fl.cheb_basis(M, X0)
+    return fl.scatter_stats([s[:, None] * b for b in B], labels, d > 0)
+
+
 def test_filter_stats_match_oracle(gpu_lib):
     g = synth.sbm(2000, 4, 0.03, 0.002, seed=3)
     ip, ix, _ = to_device(g)
-    feat, G, h, yy = gpu_lib.filter_stats(ip, ix, None, 4, 3, 17, 9)
-    F_o, G_o, h_o, yy_o = fl.graph_stats(g.n, g.indptr, g.indices, None, 4, 3, 17, 9)
-    feat, G, h, yy = feat.cpu().numpy(), G.cpu().numpy(), h.cpu().numpy(), float(yy.cpu()[0])
+    feat, W, T, lab = gpu_lib.filter_stats(ip, ix, None, 4, 3, 17, 9, kmeans_iters=30)
+    F_o, W_o, T_o, lab_o = fl.graph_stats(g.n, g.indptr, g.indices, None, 4, 3, 17, 9, kmeans_iters=30)
+    feat, W, T, lab = feat.cpu().numpy(), W.cpu().numpy(), T.cpu().numpy(), lab.cpu().numpy()
     say("features gpu", np.round(feat, 5), "oracle", np.round(F_o, 5))
     assert np.abs(feat - F_o).max() <= 1e-4
-    assert np.abs(G - G_o).max() <= 1e-5 * np.abs(G_o).max()
-    assert np.abs(h - h_o).max() <= 1e-5 * max(np.abs(h_o).max(), 1e-30)
-    assert abs(yy - yy_o) <= 1e-5 * yy_o
+    # the plain method's labels agree with the oracle's (same partition)
+    assert o.ari(lab, lab_o) == 1.0
+    scale = np.abs(T_o).max()
+    say("  W err", np.abs(W - W_o).max() / scale, "T err", np.abs(T - T_o).max() / scale)
+    assert np.abs(W - W_o).max() <= 1e-5 * scale
+    assert np.abs(T - T_o).max() <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("n,l,k", [(40_000, 1, 2), (150_000, 5, 7), (600_000, 8, 3)])
+def test_scatter_stats_under_gpu_labels(gpu_lib, n, l, k):
+    """W, T against the oracle's blocks under the labels the GPU produced
+    (so k-means ties cannot enter): weighted graphs with hubs and isolated
+    vertices, 256-row chunks up to chunks longer than the 1024 staged rows,
+    l from 1 to 8; the ratio of a few coefficient vectors as well."""
+    g = synth.random_weighted(n, 4 * n, seed=n % 97, hubs=3, hub_degree=700, isolated=11)
+    ip, ix, d = to_device(g, "f32")
+    feat, W, T, lab = gpu_lib.filter_stats(ip, ix, d, k, l, 12, 2, kmeans_iters=10)
+    lab = lab.cpu().numpy()
+    deg = o.degrees(g.n, g.indptr, g.indices, host_weights(d))
+    assert lab[deg > 0].min() >= 0 and lab[deg > 0].max() < k
+    W_o, T_o = _scatter_oracle(g, host_weights(d), l, 2, lab)
+    W, T = W.cpu().numpy(), T.cpu().numpy()
+    scale = np.abs(T_o).max()
+    say(f"scatter n={n} l={l} k={k}: W err", np.abs(W - W_o).max() / scale, "T err", np.abs(T - T_o).max() / scale)
+    assert np.abs(W - W_o).max() <= 1e-5 * scale
+    assert np.abs(T - T_o).max() <= 1e-5 * scale
+    rng = np.random.default_rng(0)
+    for _ in range(4):
+        c = fl.full_coefficients(rng.standard_normal(8) * 0.2)
+        assert abs(fl.ratio(c, W, T) - fl.ratio(c, W_o, T_o)) <= 1e-4
 
 
 def _batch(B=6, seed=0):
     rng = np.random.default_rng(seed)
     F = rng.standard_normal((B, 9)).astype(np.float32)
-    G, h, yy = [], [], []
+    W, T = [], []
     for _ in range(B):
-        A = rng.standard_normal((9, 12))
-        G.append(A @ A.T)
-        h.append(rng.standard_normal(9))
-        yy.append(float(rng.uniform(1, 3)))
-    return F, np.array(G), np.array(h), np.array(yy)
+        A = rng.standard_normal((9, 14))
+        Bm = rng.standard_normal((9, 5))
+        W.append(A @ A.T)
+        T.append(A @ A.T + Bm @ Bm.T)
+    return F, np.array(W), np.array(T)
 
 
 def _dev(*xs):
@@ -72,13 +109,13 @@ def test_mlp_forward_grad_adam_match_oracle(gpu_lib):
     assert gpu_lib.mlp_param_count() == fl.param_count()
     p = fl.init_params(1)
     p[-1000:] *= 50.0
-    F, G, h, yy = _batch()
-    pg, Fg, Gg, hg, yg = _dev(p.astype(np.float32), F, G, h, yy)
+    F, W, T = _batch()
+    pg, Fg, Wg, Tg = _dev(p.astype(np.float32), F, W, T)
     c = gpu_lib.mlp_forward(pg, Fg).cpu().numpy()
     c_o, _ = fl.mlp_forward(p.astype(np.float32).astype(np.float64), F.astype(np.float64))
     assert np.abs(c - c_o).max() <= 1e-5 * max(1.0, np.abs(c_o).max())
-    loss, grad = gpu_lib.mlp_loss_grad(pg, Fg, Gg, hg, yg)
-    L_o, g_o = fl.loss_and_grad(p.astype(np.float32).astype(np.float64), F.astype(np.float64), G, h, yy)
+    loss, grad = gpu_lib.mlp_loss_grad(pg, Fg, Wg, Tg)
+    L_o, g_o = fl.loss_and_grad(p.astype(np.float32).astype(np.float64), F.astype(np.float64), W, T)
     grad = grad.cpu().numpy()
     say("loss gpu", float(loss.cpu()[0]), "oracle", L_o)
     assert abs(float(loss.cpu()[0]) - L_o) <= 1e-5 * abs(L_o)
@@ -91,21 +128,28 @@ def test_mlp_forward_grad_adam_match_oracle(gpu_lib):
     assert np.abs(pg.cpu().numpy() - p1).max() <= 1e-6
 
 
+def _lambda_min(W, T):
+    Li = np.linalg.inv(np.linalg.cholesky(T))
+    return float(np.linalg.eigvalsh(Li @ W @ Li.T).min())
+
+
 def test_mlp_training_descends(gpu_lib):
-    F, G, h, yy = _batch(16, seed=4)
+    F, W, T = _batch(16, seed=4)
     p = fl.init_params(2).astype(np.float32)
-    pg, Fg, Gg, hg, yg = _dev(p, F, G, h, yy)
+    pg, Fg, Wg, Tg = _dev(p, F, W, T)
     m = torch.zeros_like(pg)
     v = torch.zeros_like(pg)
-    trace = gpu_lib.mlp_train(pg, m, v, Fg, Gg, hg, yg, 200, 1e-3).cpu().numpy()
-    say("train loss", trace[0], "->", trace[-1])
-    assert trace[-1] < 0.5 * trace[0]
+    trace = gpu_lib.mlp_train(pg, m, v, Fg, Wg, Tg, 200, 1e-3).cpu().numpy()
+    bound = np.mean([_lambda_min(W[b], T[b]) for b in range(16)])
+    say("train loss", trace[0], "->", trace[-1], "bound", bound)
+    assert trace[-1] < trace[0] - 0.3 * (trace[0] - bound)
+    assert trace[-1] >= bound - 1e-9
     # the same steps in FP64 on the CPU stay close for the first steps
     po = p.astype(np.float64)
     mo = np.zeros_like(po)
     vo = np.zeros_like(po)
     for step in range(1, 6):
-        L, gr = fl.loss_and_grad(po, F.astype(np.float64), G, h, yy)
+        L, gr = fl.loss_and_grad(po, F.astype(np.float64), W, T)
         assert abs(L - trace[step - 1]) <= 1e-4 * abs(L)
         po, mo, vo = fl.adam_step(po, gr, mo, vo, step, 1e-3)
 
