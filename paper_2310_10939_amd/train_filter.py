@@ -191,6 +191,7 @@ def main(argv=None):
     ap.add_argument("--out", default=PARAMS_FILE)
     ap.add_argument("--report", default=None)
     ap.add_argument("--eval-only", action="store_true", help="evaluate the saved parameters (--out)")
+    ap.add_argument("--stats-out", default=None, help="save the collected statistics (.npz) and stop")
     args = ap.parse_args(argv)
     import torch
     import synth
@@ -215,6 +216,11 @@ def main(argv=None):
     train_specs = synth.learned_params(args.graphs, 0)
     F, W, T = collect(train_specs, dev, log)
     stats_t = collect(test_specs, dev, log)
+    if args.stats_out:
+        np.savez(args.stats_out, F=F.cpu().numpy(), W=W.cpu().numpy(), T=T.cpu().numpy(),
+                 Ft=stats_t[0].cpu().numpy(), Wt=stats_t[1].cpu().numpy(), Tt=stats_t[2].cpu().numpy(),
+                 specs=json.dumps(train_specs), test_specs=json.dumps(test_specs))
+        return 0
     p, trace = train(F, W, T, args.steps, args.lr, args.seed, log)
     np.save(args.out, p.cpu().numpy())
     rows = evaluate(p, test_specs, dev, stats_t, log)

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 import scipy.sparse.csgraph as csgraph
 import scipy.sparse as sp
+from numpy.polynomial import Chebyshev as Ch
 from numpy.polynomial import chebyshev as C
 
 import synth
@@ -124,12 +125,67 @@ def test_loss_at_gamma_t_is_the_plain_embeddings_cost():
     n, ip, ix = _stats_graph()
     F, W, T, labels = fl.graph_stats(n, ip, ix, None, 3, 2, 8, seed=6)
     c8 = C.poly2cheb(np.polynomial.polynomial.polypow([0.5, 0.5], 8))
-    L, _ = fl.loss_terms(c8[1:][None], W[None], T[None])
     m = o.degrees(n, ip, ix, None) > 0
     E = o.embed(n, ip, ix, None, 2, 8, seed=6)[m]
     want = o.kmeans_cost(E, labels[m], 3) / o.kmeans_cost(E, np.zeros(m.sum(), dtype=int), 1)
-    assert abs(L[0] - want) < 1e-10
     assert abs(fl.ratio(c8, W, T) - want) < 1e-10
+
+
+def _T8_closed(u):
+    """T_8 by its closed forms: cos(8 arccos u) inside [-1, 1], cosh(8
+    arccosh |u|) outside (T_8 is even)."""
+    u = np.asarray(u, dtype=np.float64)
+    out = np.empty_like(u)
+    inside = np.abs(u) <= 1
+    out[inside] = np.cos(8 * np.arccos(u[inside]))
+    out[~inside] = np.cosh(8 * np.arccosh(np.abs(u[~inside])))
+    return out
+
+
+@pytest.mark.parametrize("alpha,beta", [(np.log(0.52), np.log(0.28)), (0.3, -4.0), (-2.5, -1.0), (-0.7, -0.2)])
+def test_head_is_the_chebyshev_polynomial_of_the_interval(alpha, beta):
+    a, b = fl.interval(alpha, beta)
+    assert a < b < 1
+    c = fl.full_coefficients(fl.coefficients([[alpha, beta]])[0])
+    assert abs(c.sum() - 1.0) < 1e-12                        # p(1) = 1
+    g = np.concatenate([np.linspace(0, 1, 101), np.random.default_rng(0).random(50)])
+    p = C.chebval(2 * g - 1, c)                              # numpy's Chebyshev series at 2g - 1
+    u = lambda x: (2 * x - a - b) / (b - a)
+    want = _T8_closed(u(g)) / _T8_closed(u(np.array([1.0])))[0]
+    assert np.abs(p - want).max() < 1e-10 * max(1.0, np.abs(want).max())
+    # numpy's own change of domain gives the same coefficients
+    q = Ch([0] * 8 + [1], domain=[a, b]).convert(domain=[0, 1], kind=Ch).coef
+    assert np.abs(q / q.sum() - c).max() < 1e-10 * max(1.0, np.abs(c).max())
+    # minimax: on [a, b] |p| reaches its maximum 1 / T_8(u(1)) at the 9
+    # extrema of T_8
+    ext = (a + b) / 2 + (b - a) / 2 * np.cos(np.pi * np.arange(9) / 8)
+    pe = C.chebval(2 * ext - 1, c)
+    bound = 1.0 / _T8_closed(u(np.array([1.0])))[0]
+    inner = np.linspace(a, b, 1001)
+    # rounding: coefficient errors of order eps each, times |T_j(x)| <=
+    # T_j(max(1, |x|)) (large where the interval reaches below 0)
+    tol = 1e-14 * C.chebval(np.maximum(1.0, np.abs(2 * inner - 1)), np.ones(9)).max()
+    assert np.allclose(np.abs(pe), bound, rtol=1e-8, atol=tol)
+    assert np.abs(C.chebval(2 * inner - 1, c)).max() <= bound * (1 + 1e-8) + tol
+
+
+def test_head_derivatives_match_finite_differences():
+    for alpha, beta in [(np.log(0.52), np.log(0.28)), (-1.3, -2.2), (0.2, -0.5)]:
+        q, qa, qb = fl.head(alpha, beta)
+        eps = 1e-6
+        fa = (fl.head(alpha + eps, beta)[0] - fl.head(alpha - eps, beta)[0]) / (2 * eps)
+        fb = (fl.head(alpha, beta + eps)[0] - fl.head(alpha, beta - eps)[0]) / (2 * eps)
+        scale = np.abs(q).max()
+        assert np.abs(qa - fa).max() <= 1e-6 * scale
+        assert np.abs(qb - fb).max() <= 1e-6 * scale
+
+
+def test_initial_parameters_give_the_initial_interval():
+    p = fl.init_params(0)
+    out, _ = fl.mlp_forward(p, np.zeros((1, fl.NFEAT)))
+    a, b = fl.interval(out[0, 0], out[0, 1])
+    assert abs(a - fl.INIT_A) < 1e-12 and abs(b - fl.INIT_B) < 1e-12
+    assert fl.param_count() == 9 * 128 + 128 + 2 * (128 * 128 + 128) + 128 * 2 + 2
 
 
 def _batch(B=5, seed=0):
@@ -153,7 +209,7 @@ def _lambda_min(W, T):
 
 def test_gradient_matches_finite_differences():
     p = fl.init_params(1)
-    p[-1000:] *= 100.0       # a last layer large enough to give the loss curvature
+    p[-258:-2] *= 20.0       # output weights large enough for the features to matter
     F, W, T = _batch()
     L, g = fl.loss_and_grad(p, F, W, T)
     rng = np.random.default_rng(2)
@@ -168,7 +224,7 @@ def test_gradient_matches_finite_differences():
 def test_gradient_matches_torch_autograd():
     torch = pytest.importorskip("torch")
     p = fl.init_params(3)
-    p[-1000:] *= 30.0
+    p[-258:-2] *= 20.0
     F, W, T = _batch(4, seed=5)
     L, g = fl.loss_and_grad(p, F, W, T)
     P = torch.tensor(p, dtype=torch.float64, requires_grad=True)
@@ -179,10 +235,21 @@ def test_gradient_matches_torch_autograd():
         x = x @ Wl.T + b
         if li < len(fl.LAYERS) - 1:
             x = torch.relu(x)
-    c = torch.cat([1 - x.sum(1, keepdim=True), x], 1)
+    # the head in torch: T_8 of the interval at the Chebyshev-Gauss nodes,
+    # projected on T_0..T_8 (autograd through every step)
+    b_ = 1 - torch.exp(x[:, 1:2])
+    a_ = b_ - torch.exp(x[:, 0:1])
+    nodes = torch.cos(torch.pi * (torch.arange(9, dtype=torch.float64) + 0.5) / 9)
+    u = (nodes[None] + 1 - a_ - b_) / (b_ - a_)
+    t0, t1 = torch.ones_like(u), u
+    for _ in range(7):
+        t0, t1 = t1, 2 * u * t1 - t0
+    Tn = torch.cos(torch.outer(torch.arange(9, dtype=torch.float64), torch.arccos(nodes)))
+    q = (2.0 / 9) * t1 @ Tn.T
+    q = torch.cat([q[:, :1] / 2, q[:, 1:]], 1)
     Wt, Tt = torch.tensor(W), torch.tensor(T)
-    num = torch.bmm(torch.bmm(c[:, None, :], Wt), c[:, :, None]).flatten()
-    den = torch.bmm(torch.bmm(c[:, None, :], Tt), c[:, :, None]).flatten()
+    num = torch.bmm(torch.bmm(q[:, None, :], Wt), q[:, :, None]).flatten()
+    den = torch.bmm(torch.bmm(q[:, None, :], Tt), q[:, :, None]).flatten()
     Lt = (num / den).mean()
     Lt.backward()
     assert abs(Lt.item() - L) < 1e-12
@@ -208,9 +275,7 @@ def test_adam_reduces_loss_to_no_less_than_the_bound():
         assert Lb[0] >= lam - 1e-12
         ev, V = np.linalg.eig(np.linalg.solve(T[b], W[b]))
         x = np.real(V[:, np.argmin(np.real(ev))])
-        x = x / x.sum()
-        La, _ = fl.loss_terms(x[1:][None], W[b][None], T[b][None])
-        assert abs(La[0] - lam) < 1e-9
+        assert abs(fl.ratio(x, W[b], T[b]) - lam) < 1e-9
 
 
 def test_adam_matches_torch_optimizer():
