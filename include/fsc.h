@@ -200,18 +200,23 @@ int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, f
  * with T*_j the Chebyshev polynomials shifted to [0, 1] and c_0 = 1 -
  * sum_{j>0} c_j so that p(1) = 1 (gamma_1 = 1 keeps its weight): 8 sparse
  * products instead of t.  A small MLP (9 inputs, 3 hidden layers of 128 with
- * ReLU, 8 outputs c_1..c_8, FP32) maps graph statistics to the coefficients.
- * Its inputs, in order: log n, log k, log mean degree, the degree's
- * coefficient of variation, log(max degree / mean degree) (over non-isolated
- * vertices), and the column-mean Rayleigh quotients <B_j, M B_j> / <B_j,B_j>
- * of the basis blocks B_j = T*_j(M) X0, j = 0..3; each input is then centred
- * and scaled by fixed constants (12, 2, 3, 1, 5, 0, 0, 0, 0) and
- * (2, 1, 1, 1, 2, 1, 1, 1, 1).  Parameters: one flat FP32 array of
- * fsc_mlp_param_count() values, for each layer W (out x in, row-major) then
- * b.  The paper has no learned part; this is built on top of its method.
+ * ReLU, 2 outputs (alpha, beta), FP32) picks the part of the spectrum to
+ * damp, the interval [a, b] with b = 1 - e^beta and a = b - e^alpha, and a
+ * fixed head makes the filter the Chebyshev polynomial of that interval,
+ * p(gamma) = T_8(u(gamma)) / T_8(u(1)) with u = (2 gamma - a - b) / (b - a),
+ * the degree-8 polynomial with p(1) = 1 that is smallest on [a, b]; c_0..c_8
+ * are its coefficients in the T*_j basis.  The MLP's inputs, in order: log n,
+ * log k, log mean degree, log(1 + the degree's coefficient of variation),
+ * log(max degree / mean degree) (over non-isolated vertices), and the
+ * column-mean Rayleigh quotients <B_j, M B_j> / <B_j, B_j> of the basis
+ * blocks B_j = T*_j(M) X0, j = 0..3; each input is then centred and scaled by
+ * fixed constants (12, 2, 3, 1, 5, 0, 0, 0, 0) and (2, 1, 1, 1, 2, 1, 1, 1,
+ * 1).  Parameters: one flat FP32 array of fsc_mlp_param_count() values, for
+ * each layer W (out x in, row-major) then b.  The paper has no learned part;
+ * this is built on top of its method.
  * ------------------------------------------------------------------------- */
 
-/* Number of MLP parameters (35336). */
+/* Number of MLP parameters (34562). */
 int fsc_mlp_param_count(void);
 
 /* Training statistics of one graph (FP32 vectors).  The plain method
@@ -224,22 +229,24 @@ int fsc_mlp_param_count(void);
  * cost of Sec. 2.2) and total scatter c^T T c (its value for one cluster):
  * within and total (device FP64 9 x 9, row-major, symmetric).  features:
  * device float[9].  The MLP's training loss of the graph is the ratio
- * c^T W c / c^T T c, the normalised k-means cost, scale-free and in [0, 1].
+ * c^T W c / c^T T c for the coefficients c its outputs give, the normalised
+ * k-means cost, in [0, 1] and independent of the scale of c.
  * k in [1, min(n, 64)], l in [1, 8], t >= 0. */
 int fsc_filter_stats(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t, uint64_t seed,
                      const fsc_opts* opts, float* features, double* within, double* total, int32_t* labels,
                      void* stream);
 
-/* Coefficients c_1..c_8 (device float[count][8]) for `count` feature rows
- * (device float[count][9]). */
+/* Filter coefficients c_1..c_8 (device float[count][8]) for `count` feature
+ * rows (device float[count][9]): the MLP's outputs through the head. */
 int fsc_mlp_forward(fsc_context* ctx, const float* params, int32_t count, const float* features,
                     float* coeffs, void* stream);
 
 /* Mean training loss over `count` graphs (device double[1]) and its gradient
  * in the parameters (device float[param_count]); features (float[count][9]),
  * within and total (double[count][81]) as produced by fsc_filter_stats,
- * stacked.  A graph whose total scatter c^T T c is 0 contributes 0 with a
- * zero gradient. */
+ * stacked.  The gradient runs through the head (FP64) and the MLP (FP32).
+ * A graph whose total scatter c^T T c is 0 contributes 0 with a zero
+ * gradient. */
 int fsc_mlp_loss_grad(fsc_context* ctx, const float* params, int32_t count, const float* features,
                       const double* within, const double* total, float* grad, double* loss, void* stream);
 

@@ -488,8 +488,7 @@ int fsc_mlp_forward(fsc_context* ctx, const float* params, int32_t count, const 
   if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
   Arena arena;
   if ((rc = reserve_arena(&ctx->c, mlp_workspace_bytes(count), &arena))) return rc;
-  float* acts = arena.take<float>((size_t)count * 3 * 128);
-  return mlp_forward_run(params, count, features, acts, coeffs, s);
+  return mlp_coefficients_run(params, count, features, arena.base, coeffs, s);
 }
 
 int fsc_mlp_loss_grad(fsc_context* ctx, const float* params, int32_t count, const float* features,
@@ -608,8 +607,7 @@ int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t 
   if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
   const float* c_rest = coeffs;
   if (!c_rest) {
-    float* acts = reinterpret_cast<float*>(w.mlp);
-    if ((rc = mlp_forward_run(params, 1, w.feat, acts, w.coef, s))) return rc;
+    if ((rc = mlp_coefficients_run(params, 1, w.feat, w.mlp, w.coef, s))) return rc;
     c_rest = w.coef;
   }
   if ((rc = combine_run(&io, w.basis, c_rest, w.S, s))) return rc;

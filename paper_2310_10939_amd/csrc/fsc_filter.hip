@@ -313,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void scatter_finish_kernel(const double* __
 }
 
 // ---------------------------------------------------------------------------
-// Features: log n, log k, log mean degree, degree CV, log(max/mean degree)
+// Features: log n, log k, log mean degree, log(1 + degree CV), log(max/mean degree)
 // (over non-isolated vertices) and the column-mean Rayleigh quotients of
 // B_0..B_3, centred and scaled by fixed constants.
 // ---------------------------------------------------------------------------
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void features_kernel(const double* __restri
   raw[0] = log((double)n);
   raw[1] = log((double)k);
   raw[2] = log(mean);
-  raw[3] = sqrt(var) / mean;
+  raw[3] = log1p(sqrt(var) / mean);
   raw[4] = log(fmax(m, 1e-300) / mean);
   for (int j = 0; j < 4; ++j) {
     double s = 0.0;

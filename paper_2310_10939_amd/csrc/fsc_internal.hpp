@@ -288,7 +288,8 @@ int fallback_run(const EmbedIO* io, const double* ray, int row_f, int row_ref, c
                  const float* c_rest, int32_t* used, double* diag, hipStream_t s);
 int mlp_param_count();
 size_t mlp_workspace_bytes(int B);
-int mlp_forward_run(const float* params, int B, const float* feats, float* acts, float* c_out, hipStream_t s);
+int mlp_forward_run(const float* params, int B, const float* feats, float* acts, float* raw, hipStream_t s);
+int mlp_coefficients_run(const float* params, int B, const float* feats, char* ws, float* c_out, hipStream_t s);
 int mlp_loss_grad_run(const float* params, int B, const float* feats, const double* W, const double* T,
                       float* grad, double* loss_out, char* ws, hipStream_t s);
 int mlp_adam_run(float* p, float* m, float* v, const float* g, float lr, int step, hipStream_t s);

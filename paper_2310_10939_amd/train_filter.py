@@ -31,25 +31,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PARAMS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "filter_mlp_params.npy")
-LAYERS = [(9, 128), (128, 128), (128, 128), (128, 8)]
+LAYERS = [(9, 128), (128, 128), (128, 128), (128, 2)]
 # Chebyshev coefficients c_1..c_8 of gamma^8 on [0, 1]: C(16, 8 - j) / 2^15
 GAMMA8 = [11440 / 32768, 8008 / 32768, 4368 / 32768, 1820 / 32768, 560 / 32768, 120 / 32768, 16 / 32768,
           1 / 32768]
+# the interval [a, b] the training starts from (about 0.5 +- 1/sqrt(20), the
+# bulk of M for a random graph of mean degree 20)
+INIT_A, INIT_B = 0.2, 0.72
 
 
 def init_params(seed):
-    """He-uniform weights, zero biases; the output layer scaled by 0.01 so
-    training starts near p = 1 (the identity filter)."""
+    """He-uniform weights, zero biases; the output layer's weights scaled by
+    0.01 and its biases set so that every graph starts near the filter of
+    [INIT_A, INIT_B] (alpha = log(b - a), beta = log(1 - b))."""
     rng = np.random.default_rng(seed)
     parts = []
-    for i, o in LAYERS:
+    for li, (i, o) in enumerate(LAYERS):
         lim = np.sqrt(6.0 / i)
-        parts.append(rng.uniform(-lim, lim, size=(o, i)).ravel())
-        parts.append(np.zeros(o))
-    p = np.concatenate(parts)
-    last = LAYERS[-1][0] * LAYERS[-1][1] + LAYERS[-1][1]
-    p[-last:] *= 0.01
-    return p.astype(np.float32)
+        w = rng.uniform(-lim, lim, size=(o, i))
+        b = np.zeros(o)
+        if li == len(LAYERS) - 1:
+            w *= 0.01
+            b = np.array([np.log(INIT_B - INIT_A), np.log(1.0 - INIT_B)])
+        parts += [w.ravel(), b]
+    return np.concatenate(parts).astype(np.float32)
 
 
 def load_params(path=PARAMS_FILE, device="cuda"):
@@ -185,7 +190,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--graphs", type=int, default=2000)
     ap.add_argument("--heldout", type=int, default=100)
-    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=PARAMS_FILE)
