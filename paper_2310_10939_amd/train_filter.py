@@ -15,6 +15,8 @@ sparse products) and the per-graph optimum of the loss, and wall times.
 
 Usage: python -m paper_2310_10939_amd.train_filter --graphs 2000 --heldout 100
        --out <params.npy> --report <report.json>
+The shipped parameters (filter_mlp_params.npy) come from this command with
+its defaults; filter_mlp_report.json is their report.
 """
 from __future__ import annotations
 
@@ -169,6 +171,7 @@ def evaluate(p, specs, device, stats=None, log=print):
                          ari_learned_vs_planted=float(fsc.ari(learned, lab, k, k)),
                          ari_fixed8_vs_planted=float(fsc.ari(fixed, lab, k, k)),
                          ari_guarded_vs_plain=float(fsc.ari(guarded, plain, k, k)),
+                         ari_guarded_vs_planted=float(fsc.ari(guarded, lab, k, k)),
                          fallback=used, ms_plain=(t1 - t0) * 1e3, ms_learned=(t2 - t1) * 1e3,
                          ms_fixed8=(t3 - t2) * 1e3, ms_guarded=(t4 - t3) * 1e3,
                          rho_learned=float(dg[0]), rho_8=float(dg[1]), cost_learned=float(dg[2]),

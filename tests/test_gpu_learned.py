@@ -196,3 +196,31 @@ def test_cluster_filtered_and_fallback(gpu_lib):
                               gpu_lib.filter_stats(ip, ix, None, 5, 4, 1, 7)[0].cpu().numpy()[None].astype(np.float64))
     c_o = fl.coefficients(out_o)
     assert np.abs(cout.cpu().numpy() - c_o[0]).max() <= 1e-4 * max(1.0, np.abs(c_o).max())
+
+
+def test_shipped_parameters_on_heldout_graphs(gpu_lib):
+    """The trained parameters shipped with the package on the first four
+    held-out DC-SBM graphs of the learned-form workload (seeds 100000..3):
+    the learned filter's labels against the planted clusters come close to
+    the plain method's (t = ceil(3 ln n) steps), far above the fixed gamma^8
+    filter with the same 8 sparse products, with no fallback."""
+    from paper_2310_10939_amd.train_filter import GAMMA8, load_params
+    p = load_params()
+    assert p.numel() == gpu_lib.mlp_param_count()
+    g8 = torch.tensor(GAMMA8, dtype=torch.float32, device="cuda")
+    learned, plain, fixed = [], [], []
+    for s in synth.learned_params(4, 100000):
+        ip, ix, lab = synth.dcsbm_device(s["n"], s["k"], 20.0, s["seed"])
+        k, l, t, seed = s["k"], s["l"], s["t"], s["seed"]
+        lf, _, used = gpu_lib.cluster_filtered(ip, ix, None, k, l, seed, params=p)
+        lp = gpu_lib.cluster(ip, ix, None, k, l, t, seed)
+        l8, _, _ = gpu_lib.cluster_filtered(ip, ix, None, k, l, seed, coeffs=g8)
+        learned.append(float(gpu_lib.ari(lf, lab, k, k)))
+        plain.append(float(gpu_lib.ari(lp, lab, k, k)))
+        fixed.append(float(gpu_lib.ari(l8, lab, k, k)))
+        say(f"n={s['n']} k={k}: ARI learned {learned[-1]:.3f} plain {plain[-1]:.3f} gamma^8 {fixed[-1]:.3f} "
+            f"fallback {used}")
+        assert not used
+    assert np.mean(learned) >= np.mean(plain) - 0.1
+    assert min(learned) >= 0.7
+    assert np.mean(learned) >= np.mean(fixed) + 0.5
