@@ -232,23 +232,34 @@ def kmeans_cost(B, labels, k):
     return total
 
 
-def kmeanspp(P, k, seed, eligible=None):
-    """k-means++ seeding (Arthur and Vassilvitskii, as cited in Sec. 2.2).
+def kmeanspp_trials(k):
+    """Candidates per round of the greedy seeding: 2 + floor(ln k)."""
+    return 2 + int(np.floor(np.log(k)))
+
+
+def kmeanspp(P, k, seed, eligible=None, trials=None):
+    """k-means++ seeding (Arthur and Vassilvitskii, as cited in Sec. 2.2), in
+    its greedy form: each round draws several candidates by D^2 sampling and
+    keeps the one that lowers the potential sum_v min(D2(v), ||P_v - c||^2)
+    most.
 
     Reading of the sampling, with the Philox uniforms of this module:
       * centre 0: with u from stream 1, the row v whose inclusive running
         count of eligible rows first exceeds u * n_eligible;
       * centre r >= 1: D2(v) = min over chosen centres of ||P_v - c||^2 on
-        eligible rows (0 on the others); with u from stream 2, counter r, the
-        smallest v whose inclusive float64 running sum of D2 exceeds
-        u * sum(D2);
-      * if sum(D2) == 0: the smallest eligible row not chosen yet, else the
-        smallest row not chosen yet.
-    Returns the chosen row indices.
+        eligible rows (0 on the others); candidate j (0 <= j < L, L = trials,
+        by default 2 + floor(ln k)) takes u from stream 3, counter r * L + j,
+        and is the smallest v whose inclusive float64 running sum of D2
+        exceeds u * sum(D2); the candidate with the smallest potential over
+        the eligible rows wins, ties to the lower j;
+      * if sum(D2) == 0: every candidate is the smallest eligible row not
+        chosen yet, else the smallest row not chosen yet.
+    trials = 1 is plain D^2 sampling.  Returns the chosen row indices.
     """
     P = np.asarray(P, dtype=np.float64)
     n = P.shape[0]
     elig = np.ones(n, dtype=bool) if eligible is None else np.asarray(eligible, dtype=bool)
+    L = kmeanspp_trials(k) if trials is None else int(trials)
     chosen = []
 
     def pick(weights, u):
@@ -270,11 +281,15 @@ def kmeanspp(P, k, seed, eligible=None):
     chosen.append(pick(elig.astype(np.float64), uniform_draw(seed, 0, 1)))
     d2 = np.full(n, np.inf)
     for r in range(1, k):
-        c = P[chosen[-1]]
-        dist = ((P - c) ** 2).sum(axis=1)
-        d2 = np.minimum(d2, dist)
+        d2 = np.minimum(d2, ((P - P[chosen[-1]]) ** 2).sum(axis=1))
         w = np.where(elig, d2, 0.0)
-        chosen.append(pick(w, uniform_draw(seed, r, 2)))
+        best, best_pot = None, None
+        for j in range(L):
+            v = pick(w, uniform_draw(seed, r * L + j, 3))
+            pot = float(np.where(elig, np.minimum(d2, ((P - P[v]) ** 2).sum(axis=1)), 0.0).sum())
+            if best is None or pot < best_pot:
+                best, best_pot = v, pot
+        chosen.append(best)
     return chosen
 
 

@@ -270,7 +270,7 @@ def test_kmeanspp_samples_proportional_to_d2():
     first = np.zeros(5)
     second = np.zeros((5, 5))
     for s in range(trials):
-        c = o.kmeanspp(P, 2, seed=s)
+        c = o.kmeanspp(P, 2, seed=s, trials=1)
         first[c[0]] += 1
         second[c[0], c[1]] += 1
     assert stats.chisquare(first).pvalue > 1e-4
@@ -280,6 +280,45 @@ def test_kmeanspp_samples_proportional_to_d2():
         m = exp > 0
         assert second[a, ~m].sum() == 0                # the centre itself never again
         assert stats.chisquare(second[a, m], exp[m]).pvalue > 1e-4
+
+
+def test_greedy_kmeanspp_keeps_the_best_candidate():
+    """Each round's winner is the candidate (drawn by D^2 sampling, checked
+    by rerunning the plain sampling with the same uniforms) whose potential,
+    recomputed here by brute force over the rows, is smallest."""
+    rng = np.random.default_rng(5)
+    P = rng.standard_normal((40, 3))
+    elig = np.ones(40, dtype=bool)
+    elig[[3, 17]] = False
+    k = 5
+    L = o.kmeanspp_trials(k)
+    assert L == 2 + int(np.floor(np.log(k)))
+    for seed in range(10):
+        c = o.kmeanspp(P, k, seed, eligible=elig)
+        for r in range(1, k):
+            d2 = np.array([min(((P[v] - P[x]) ** 2).sum() for x in c[:r]) for v in range(40)])
+            w = np.where(elig, d2, 0.0)
+            cands = []
+            for j in range(L):
+                u = o.uniform_draw(seed, r * L + j, 3)
+                run = np.cumsum(w)
+                cands.append(int(np.searchsorted(run, u * run[-1], side="right")))
+            pots = [sum(min(w[v], ((P[v] - P[x]) ** 2).sum()) for v in range(40) if elig[v]) for x in cands]
+            assert c[r] == cands[int(np.argmin(pots))]
+            assert elig[c[r]]
+
+
+def test_greedy_kmeanspp_separates_well_spread_blobs():
+    """Five tight blobs far apart: the greedy seeding puts one centre in
+    each blob for every seed (plain D^2 sampling may put two in one)."""
+    rng = np.random.default_rng(1)
+    means = np.array([[0, 0], [10, 0], [0, 10], [10, 10], [5, 25]], dtype=float)
+    sizes = [400, 30, 30, 200, 10]
+    P = np.concatenate([m + 0.1 * rng.standard_normal((s_, 2)) for m, s_ in zip(means, sizes)])
+    blob = np.repeat(np.arange(5), sizes)
+    for seed in range(30):
+        c = o.kmeanspp(P, 5, seed)
+        assert sorted(blob[c]) == [0, 1, 2, 3, 4]
 
 
 def test_kmeanspp_respects_eligibility_and_degenerate_case():
