@@ -23,9 +23,12 @@
  *   - Labels are 0..k-1 and meaningful up to a permutation of the clusters.
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by `seed`.
  *     Start-block entry (i, j) uses counter (i_lo, i_hi, j, 0) and the
- *     Box-Muller transform of the two 53-bit uniforms it yields; k-means++
- *     draw r uses counter (r_lo, r_hi, 0, 1) for r = 0 and (r, 0, 0, 2) for
- *     r >= 1.
+ *     Box-Muller transform of the two 53-bit uniforms it yields.  k-means++
+ *     seeding is greedy: centre 0 is a uniform draw over the eligible rows
+ *     (counter (0, 0, 0, 1)); centre r >= 1 is the best of L = 2 + floor(ln k)
+ *     candidates drawn with probability proportional to D^2, candidate j
+ *     with counter (r L + j, 0, 0, 3), the one that lowers
+ *     sum_v min(D^2(v), ||x_v - c||^2) most (ties to the lower j).
  *   - An isolated vertex (degree 0) has no D^{-1/2} (Sec. 2); it is given
  *     D^{-1/2} := 0, so its embedding row is 0.  It takes no part in k-means
  *     seeding or centre updates and is labelled by its nearest final centre.

@@ -436,7 +436,10 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     if (x.LH != x.KD) add(4 * x.n * x.KD);
     int pp, ll, tpw;
     kmeans_shape(x.n, ctx->num_cu, &pp, &ll, &tpw);
-    add(4 * x.n + 8 * pp + 4 * 64 * x.KD + 8 * (size_t)ll * 64 * (x.KD + 1) + 4 * 64 + 4 * 256);
+    // d2, bsum, cand, cand_row, centres, cpart, chosen: 7 takes, each padded
+    // to 256 bytes
+    add(4 * x.n + 8 * 6 * pp + 4 * 6 * x.KD + 4 * 6 + 4 * 64 * x.KD + 8 * (size_t)ll * 64 * (x.KD + 1) + 4 * 64 +
+        8 * 256);
   }
   bytes += 64 * 1024;
   if (bytes > ctx->barena_size) {
@@ -514,7 +517,10 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     J.k = x.k;
     kmeans_shape(x.n, ctx->num_cu, &J.nblk_pp, &J.nblk_ll, &J.tpw);
     J.d2 = a.take<float>(x.n);
-    J.bsum = a.take<double>(J.nblk_pp);
+    J.bsum = a.take<double>((size_t)J.nblk_pp * 6);
+    J.cand = a.take<float>(6 * x.KD);
+    J.cand_row = a.take<int32_t>(6);
+    J.trials = kpp_trials(x.k);
     J.centres = a.take<float>(64 * x.KD);
     J.cpart = a.take<double>((size_t)J.nblk_ll * 64 * (x.KD + 1));
     J.chosen = a.take<int32_t>(64);

@@ -221,7 +221,9 @@ struct KmeansIO {
   float* centres_out;      // optional k x l
   // workspace
   float* d2;               // n
-  double* bsum;            // blocks
+  double* bsum;            // blocks x 6
+  float* cand;             // 6 x KD: the seeding round's candidates
+  int32_t* cand_row;       // 6
   float* centres;          // 64 x KD (padded)
   double* cpart;           // blocks x 64 x (KD+1)
   int32_t* chosen;         // 64
@@ -236,6 +238,9 @@ struct KmJob {
   int KD, k;
   float* d2;
   double* bsum;
+  float* cand;
+  int32_t* cand_row;
+  int trials;              // candidates per seeding round
   int32_t* counter;
   float* centres;          // 64 x KD
   int32_t* chosen;
@@ -245,6 +250,7 @@ struct KmJob {
   int nblk_pp, nblk_ll, tpw;
 };
 void kmeans_shape(int64_t n, int num_cu, int* nblk_pp, int* nblk_ll, int* tpw);
+int kpp_trials(int k);
 KmJob make_job(Context* ctx, const KmeansIO* io);
 int kmeans_run_batched(Context* ctx, const KmJob* jobs_dev, const int32_t* pp_off_dev, int pp_total,
                        const int32_t* ll_off_dev, int ll_total, int njobs, int kmax, int iters, hipStream_t s);

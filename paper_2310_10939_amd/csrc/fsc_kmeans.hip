@@ -5,11 +5,16 @@
 // single-graph entry points launch one job, the batched form launches many in
 // one grid (blocks map to (job, local block) through a prefix table).
 //
-// Seeding: one launch per centre.  Each block owns a contiguous run of rows,
-// updates D2(v) = min(D2(v), ||p_v - c_{r-1}||^2) and writes the FP64 sum of
-// its weights; the last block of the job to finish scans the block sums,
-// locates the block holding the sample u * sum(D2) and rescans that block's
-// rows (same summation order) to find the sampled row.  No host round trip.
+// Seeding (greedy k-means++): two launches per centre r >= 1.  In the first,
+// each block owns a contiguous run of rows, updates
+// D2(v) = min(D2(v), ||p_v - c_{r-1}||^2) and writes the FP64 sum of its
+// weights; the last block of the job to finish draws L = 2 + floor(ln k)
+// candidates: for each it scans the block sums, locates the block holding the
+// sample u_j * sum(D2) and rescans that block's rows (same summation order)
+// to find the sampled row.  In the second, each block sums, per candidate,
+// min(D2(v), ||p_v - cand_j||^2) over its eligible rows, and the last block
+// keeps the candidate with the smallest total (ties to the lower j).  Centre
+// 0 is one uniform draw over the eligible rows.  No host round trip.
 //
 // Lloyd: one launch per step.  Distances come from MFMA
 // (v_mfma_f32_16x16x4_f32): a 16-centre tile of C times a 16-point tile of
@@ -25,6 +30,7 @@
 #include "fsc_internal.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 namespace fsc {
@@ -34,6 +40,7 @@ constexpr int kRPT = 8;     // rows per thread in the seeding kernel
 constexpr int kLB = 1024;   // threads per Lloyd block (16 waves)
 constexpr int kLW = kLB / FSC_WAVE;
 constexpr int kMaxK = 64;
+constexpr int kMaxTrials = 6;  // 2 + floor(ln 64)
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -65,13 +72,123 @@ __device__ __forceinline__ double seed_weight(int first, const uint8_t* elig, in
   return first ? 1.0 : (double)d2v;
 }
 
+// The row holding `target` in the inclusive running sum of the seeding
+// weights (last block of the job; every thread returns it).  The block sums
+// are scanned in chunks, then the found block's rows are rescanned in the
+// order of phase A, so the prefixes are bit-identical to phase A's.
+template <int KD>
+__device__ int64_t kpp_sample(const KmJob& J, int first, double target, KppShared& sh) {
+  double* sbuf = sh.sbuf;
+  const int64_t n = J.n;
+  const int64_t rpb = (int64_t)kKB * kRPT;
+  const int nblk = J.nblk_pp;
+  if (threadIdx.x == 0) {
+    sh.block = -1;
+    sh.base = 0.0;
+  }
+  __syncthreads();
+  double carry = 0.0;
+  for (int base = 0; base < nblk; base += kKB) {
+    const int b = base + threadIdx.x;
+    double ct;
+    const double inc = block_scan_inclusive<kKB>(b < nblk ? J.bsum[b] : 0.0, sbuf, &ct) + carry;
+    sh.inc[threadIdx.x] = inc;
+    if (threadIdx.x == 0) sh.found = INT32_MAX;
+    __syncthreads();
+    if (b < nblk && inc > target) atomicMin(&sh.found, b);
+    __syncthreads();
+    if (sh.found != INT32_MAX) {
+      // the prefix before the block, exactly as the scan computed it
+      if (threadIdx.x == 0) {
+        sh.block = sh.found;
+        sh.base = sh.found == base ? carry : sh.inc[sh.found - base - 1];
+      }
+      __syncthreads();
+      break;
+    }
+    carry += ct;  // equals the chunk's last inclusive value bit for bit
+  }
+  if (sh.block < 0 && threadIdx.x == 0) {  // rounding at the very end
+    for (int b = nblk - 1; b >= 0; --b)
+      if (J.bsum[b] > 0.0) {
+        sh.block = b;
+        sh.base = 0.0;  // the in-block search below falls back to the last row
+        break;
+      }
+  }
+  __syncthreads();
+  const int B = sh.block;
+  const double before = sh.base;
+  const int64_t v0 = (int64_t)B * rpb + (int64_t)threadIdx.x * kRPT;
+  double w[kRPT];
+  double ts = 0.0;
+#pragma unroll
+  for (int i = 0; i < kRPT; ++i) {
+    const int64_t v = v0 + i;
+    w[i] = v < n ? seed_weight(first, J.elig, v, first ? 0.f : J.d2[v]) : 0.0;
+    ts += w[i];
+  }
+  double bt;
+  const double inc = block_scan_inclusive<kKB>(ts, sbuf, &bt);
+  if (threadIdx.x == 0) sh.found = INT32_MAX;
+  __syncthreads();
+  double run = before + (inc - ts);
+#pragma unroll
+  for (int i = 0; i < kRPT; ++i) {
+    run += w[i];
+    if (w[i] > 0.0 && run > target) {
+      atomicMin(&sh.found, (int32_t)(threadIdx.x * kRPT + i));
+      break;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && sh.found == INT32_MAX) {  // rounding: last positive row of B
+    for (int i = kKB * kRPT - 1; i >= 0; --i) {
+      const int64_t v = (int64_t)B * rpb + i;
+      if (v < n && seed_weight(first, J.elig, v, first ? 0.f : J.d2[v]) > 0.0) {
+        sh.found = i;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t pick = (int64_t)B * rpb + sh.found;
+  __syncthreads();  // sh is reused by the next search
+  return pick;
+}
+
+// Every weight is 0: the smallest eligible row not chosen yet, else the
+// smallest row not chosen yet (every thread returns it).
+__device__ int64_t kpp_unchosen(const KmJob& J, int r, KppShared& sh) {
+  const int64_t n = J.n;
+  if (threadIdx.x == 0) sh.found = INT32_MAX;
+  __syncthreads();
+  for (int pass = 0; pass < 2 && sh.found == INT32_MAX; ++pass) {
+    for (int64_t base = 0; base < n; base += kKB) {
+      const int64_t v = base + threadIdx.x;
+      bool ok = v < n;
+      if (ok && pass == 0 && J.elig) ok = J.elig[v] != 0;
+      if (ok)
+        for (int j = 0; j < r; ++j)
+          if (J.chosen[j] == v) {
+            ok = false;
+            break;
+          }
+      if (ok) atomicMin(&sh.found, (int32_t)v);
+      __syncthreads();
+      if (sh.found != INT32_MAX) break;
+    }
+    __syncthreads();
+  }
+  const int64_t pick = sh.found;
+  __syncthreads();
+  return pick;
+}
+
 template <int KD>
 __device__ void kpp_block(const KmJob& J, int blk, int r, KppShared& sh) {
   double* sbuf = sh.sbuf;
   int& is_last = sh.is_last;
-  int32_t& found = sh.found;
-  double& sh_base = sh.base;
-  int32_t& sh_block = sh.block;
   const int64_t n = J.n;
   const int first = (r == 0);
   const int64_t rpb = (int64_t)kKB * kRPT;
@@ -136,11 +253,8 @@ __device__ void kpp_block(const KmJob& J, int blk, int r, KppShared& sh) {
   if (!is_last) return;
   __threadfence();
 
-  // phase B (last block): sample u * sum(weights) over the block sums, then
-  // inside the block that holds it.  Both passes over the block sums use the
-  // same chunked scan, so the prefixes they see are bit-identical.
-  const u32x4 rr = philox4x32_10(u32x4{first ? 0u : (uint32_t)r, 0u, 0u, first ? 1u : 2u}, J.k0, J.k1);
-  const double u = uniform53(rr.x, rr.y);
+  // phase B (last block): the total weight, then each draw u * total located
+  // by kpp_sample.
   double total = 0.0;
   for (int base = 0; base < nblk; base += kKB) {
     const int b = base + threadIdx.x;
@@ -148,110 +262,94 @@ __device__ void kpp_block(const KmJob& J, int blk, int r, KppShared& sh) {
     block_scan_inclusive<kKB>(b < nblk ? J.bsum[b] : 0.0, sbuf, &ct);
     total += ct;
   }
-  const double target = u * total;
+  const int ntrial = first ? 1 : J.trials;
   int64_t pick = -1;
-  if (total > 0.0) {
-    if (threadIdx.x == 0) {
-      sh_block = -1;
-      sh_base = 0.0;
+  for (int j = 0; j < ntrial; ++j) {
+    if (total > 0.0) {
+      // centre 0: stream 1, counter 0; candidate j of round r: stream 3,
+      // counter r * L + j
+      const uint32_t ctr = first ? 0u : (uint32_t)(r * J.trials + j);
+      const u32x4 rr = philox4x32_10(u32x4{ctr, 0u, 0u, first ? 1u : 3u}, J.k0, J.k1);
+      pick = kpp_sample<KD>(J, first, uniform53(rr.x, rr.y) * total, sh);
+    } else {
+      if (j == 0) pick = kpp_unchosen(J, r, sh);  // every candidate is this row
     }
-    __syncthreads();
-    double carry = 0.0;
-    for (int base = 0; base < nblk; base += kKB) {
-      const int b = base + threadIdx.x;
-      double ct;
-      const double inc = block_scan_inclusive<kKB>(b < nblk ? J.bsum[b] : 0.0, sbuf, &ct) + carry;
-      sh.inc[threadIdx.x] = inc;
-      if (threadIdx.x == 0) found = INT32_MAX;
-      __syncthreads();
-      if (b < nblk && inc > target) atomicMin(&found, b);
-      __syncthreads();
-      if (found != INT32_MAX) {
-        // the prefix before the block, exactly as the scan computed it
-        if (threadIdx.x == 0) {
-          sh_block = found;
-          sh_base = found == base ? carry : sh.inc[found - base - 1];
-        }
-        __syncthreads();
-        break;
-      }
-      carry += ct;  // equals the chunk's last inclusive value bit for bit
+    if (first) {
+      if (threadIdx.x == 0) J.chosen[r] = (int32_t)pick;
+      if (threadIdx.x < KD) J.centres[r * KD + threadIdx.x] = pts[pick * KD + threadIdx.x];
+    } else {
+      if (threadIdx.x == 0) J.cand_row[j] = (int32_t)pick;
+      if (threadIdx.x < KD) J.cand[j * KD + threadIdx.x] = pts[pick * KD + threadIdx.x];
     }
-    if (sh_block < 0 && threadIdx.x == 0) {  // rounding at the very end
-      for (int b = nblk - 1; b >= 0; --b)
-        if (J.bsum[b] > 0.0) {
-          sh_block = b;
-          sh_base = 0.0;  // the in-block search below falls back to the last row
-          break;
-        }
-    }
-    __syncthreads();
-    const int B = sh_block;
-    const double before = sh_base;
-    // rescan block B's rows in the order of phase A
-    const int64_t v0 = (int64_t)B * rpb + (int64_t)threadIdx.x * kRPT;
-    double w[kRPT];
-    double ts = 0.0;
+  }
+  if (threadIdx.x == 0) *J.counter = 0;
+}
+
+// Round r >= 1, second launch: the potential of each candidate over this
+// block's rows; the last block keeps the best candidate as centre r.
+template <int KD>
+__device__ void kpp_pick_block(const KmJob& J, int blk, int r, KppShared& sh) {
+  const int64_t n = J.n;
+  const int L = J.trials;
+  const int64_t rpb = (int64_t)kKB * kRPT;
+  const int nblk = J.nblk_pp;
+  float c[kMaxTrials][KD];
 #pragma unroll
-    for (int i = 0; i < kRPT; ++i) {
-      const int64_t v = v0 + i;
-      w[i] = v < n ? seed_weight(first, elig, v, first ? 0.f : d2[v]) : 0.0;
-      ts += w[i];
-    }
-    double bt;
-    const double inc = block_scan_inclusive<kKB>(ts, sbuf, &bt);
-    if (threadIdx.x == 0) found = INT32_MAX;
-    __syncthreads();
-    double run = before + (inc - ts);
+  for (int j = 0; j < kMaxTrials; ++j)
 #pragma unroll
-    for (int i = 0; i < kRPT; ++i) {
-      run += w[i];
-      if (w[i] > 0.0 && run > target) {
-        atomicMin(&found, (int32_t)(threadIdx.x * kRPT + i));
-        break;
+    for (int q = 0; q < KD; ++q) c[j][q] = j < L ? J.cand[j * KD + q] : 0.f;
+  double pot[kMaxTrials];
+#pragma unroll
+  for (int j = 0; j < kMaxTrials; ++j) pot[j] = 0.0;
+  const int64_t v0 = (int64_t)blk * rpb + (int64_t)threadIdx.x * kRPT;
+#pragma unroll 2
+  for (int i = 0; i < kRPT; ++i) {
+    const int64_t v = v0 + i;
+    if (v >= n || (J.elig && !J.elig[v])) continue;
+    float p[KD];
+    rowio<float, KD>::load(J.pts + v * KD, p);
+    const float dv = J.d2[v];
+#pragma unroll
+    for (int j = 0; j < kMaxTrials; ++j) {
+      float dist = 0.f;
+#pragma unroll
+      for (int q = 0; q < KD; ++q) {
+        const float e = p[q] - c[j][q];
+        dist += e * e;
       }
+      pot[j] += (double)fminf(dv, dist);
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && found == INT32_MAX) {  // rounding: last positive row of B
-      for (int i = kKB * kRPT - 1; i >= 0; --i) {
-        const int64_t v = (int64_t)B * rpb + i;
-        if (v < n && seed_weight(first, elig, v, first ? 0.f : d2[v]) > 0.0) {
-          found = i;
-          break;
-        }
-      }
-    }
-    __syncthreads();
-    pick = (int64_t)B * rpb + found;
-  } else {
-    // every weight is 0: the smallest eligible row not chosen yet, else the
-    // smallest row not chosen yet
-    if (threadIdx.x == 0) found = INT32_MAX;
-    __syncthreads();
-    for (int pass = 0; pass < 2 && found == INT32_MAX; ++pass) {
-      for (int64_t base = 0; base < n; base += kKB) {
-        const int64_t v = base + threadIdx.x;
-        bool ok = v < n;
-        if (ok && pass == 0 && elig) ok = elig[v] != 0;
-        if (ok)
-          for (int j = 0; j < r; ++j)
-            if (J.chosen[j] == v) {
-              ok = false;
-              break;
-            }
-        if (ok) atomicMin(&found, (int32_t)v);
-        __syncthreads();
-        if (found != INT32_MAX) break;
-      }
-      __syncthreads();
-    }
-    pick = found;
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxTrials; ++j) {
+    if (j >= L) break;
+    const double t = block_sum<kKB>(pot[j], sh.sbuf);
+    if (threadIdx.x == 0) J.bsum[(int64_t)blk * kMaxTrials + j] = t;
   }
   if (threadIdx.x == 0) {
-    J.chosen[r] = (int32_t)pick;
+    __threadfence();
+    sh.is_last = atomicAdd(J.counter, 1) == nblk - 1;
+  }
+  __syncthreads();
+  if (!sh.is_last) return;
+  __threadfence();
+  double best = 0.0;
+  int bj = 0;
+  for (int j = 0; j < L; ++j) {
+    double part = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kKB) part += J.bsum[(int64_t)b * kMaxTrials + j];
+    const double t = block_sum<kKB>(part, sh.sbuf);
+    if (j == 0 || t < best) {
+      best = t;
+      bj = j;
+    }
+  }
+  const int32_t row = J.cand_row[bj];
+  if (threadIdx.x == 0) {
+    J.chosen[r] = row;
     *J.counter = 0;
   }
-  if (threadIdx.x < KD) J.centres[r * KD + threadIdx.x] = pts[pick * KD + threadIdx.x];
+  if (threadIdx.x < KD) J.centres[r * KD + threadIdx.x] = J.cand[bj * KD + threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -482,6 +580,12 @@ __global__ __launch_bounds__(kKB) void kpp_kernel(KmJob J, int r) {
   kpp_block<KD>(J, blockIdx.x, r, sh);
 }
 
+template <int KD>
+__global__ __launch_bounds__(kKB) void kpp_pick_kernel(KmJob J, int r) {
+  __shared__ KppShared sh;
+  kpp_pick_block<KD>(J, blockIdx.x, r, sh);
+}
+
 template <int KD, int KT, bool UPDATE>
 __global__ __launch_bounds__(kLB) void lloyd_kernel(KmJob J) {
   __shared__ LloydShared sh;
@@ -506,6 +610,17 @@ __global__ __launch_bounds__(kKB) void kpp_kernel_seg(const KmJob* __restrict__ 
   const int b = blockIdx.x - off[g];
   if (J.KD == 4) kpp_block<4>(J, b, r, sh);
   else kpp_block<8>(J, b, r, sh);
+}
+
+__global__ __launch_bounds__(kKB) void kpp_pick_kernel_seg(const KmJob* __restrict__ jobs,
+                                                           const int32_t* __restrict__ off, int njobs, int r) {
+  __shared__ KppShared sh;
+  const int g = find_job(off, njobs, blockIdx.x);
+  const KmJob J = jobs[g];
+  if (r >= J.k) return;
+  const int b = blockIdx.x - off[g];
+  if (J.KD == 4) kpp_pick_block<4>(J, b, r, sh);
+  else kpp_pick_block<8>(J, b, r, sh);
 }
 
 template <bool UPDATE>
@@ -602,6 +717,8 @@ __global__ void zero_i32(int32_t* p, int count) {
 // ===========================================================================
 // Lloyd launch shape for n points: tiles of 16 rows, blocks of 16 waves, about
 // one block per CU and at least one tile per wave.
+int kpp_trials(int k) { return std::min(kMaxTrials, 2 + (int)std::floor(std::log((double)std::max(k, 1)))); }
+
 void kmeans_shape(int64_t n, int num_cu, int* nblk_pp, int* nblk_ll, int* tpw) {
   *nblk_pp = (int)((n + kKB * kRPT - 1) / (kKB * kRPT));
   const int64_t tiles = (n + 15) / 16;
@@ -620,7 +737,8 @@ size_t kmeans_workspace_bytes(int64_t n, int KD) {
   const int64_t nblk_ll = (n + 15) / 16 / kLW + 1;  // upper bound
   size_t b = 0;
   b += align_up(n * 4);                                   // d2
-  b += align_up(nblk_pp * 8);                             // bsum
+  b += align_up(nblk_pp * kMaxTrials * 8);                // bsum: block sums, or per-candidate potentials
+  b += align_up(kMaxTrials * KD * 4) + align_up(kMaxTrials * 4);  // candidates
   b += align_up(kMaxK * KD * 4);                          // centres
   b += align_up((size_t)nblk_ll * kMaxK * (KD + 1) * 8);  // cpart
   b += align_up(kMaxK * 4) + align_up(16);                // chosen, counter
@@ -631,7 +749,9 @@ int kmeans_bind_workspace(Arena* a, KmeansIO* io) {
   const int64_t n = io->n;
   io->nblk_pp = (int)((n + kKB * kRPT - 1) / (kKB * kRPT));
   io->d2 = a->take<float>(n);
-  io->bsum = a->take<double>(io->nblk_pp);
+  io->bsum = a->take<double>((size_t)io->nblk_pp * kMaxTrials);
+  io->cand = a->take<float>(kMaxTrials * io->KD);
+  io->cand_row = a->take<int32_t>(kMaxTrials);
   io->centres = a->take<float>(kMaxK * io->KD);
   io->cpart = a->take<double>((size_t)((n + 15) / 16 / kLW + 1) * kMaxK * (io->KD + 1));
   io->chosen = a->take<int32_t>(kMaxK);
@@ -649,6 +769,9 @@ KmJob make_job(Context* ctx, const KmeansIO* io) {
   J.k = io->k;
   J.d2 = io->d2;
   J.bsum = io->bsum;
+  J.cand = io->cand;
+  J.cand_row = io->cand_row;
+  J.trials = kpp_trials(io->k);
   J.counter = io->counter;
   J.centres = io->centres;
   J.chosen = io->chosen;
@@ -672,8 +795,10 @@ template <int KD>
 static int kmeans_typed(Context* ctx, KmeansIO* io, hipStream_t s) {
   hipLaunchKernelGGL(zero_i32, dim3(1), dim3(64), 0, s, io->counter, 4);
   const KmJob J = make_job(ctx, io);
-  for (int r = 0; r < io->k; ++r)
+  for (int r = 0; r < io->k; ++r) {
     hipLaunchKernelGGL(kpp_kernel<KD>, dim3(J.nblk_pp), dim3(kKB), 0, s, J, r);
+    if (r > 0) hipLaunchKernelGGL(kpp_pick_kernel<KD>, dim3(J.nblk_pp), dim3(kKB), 0, s, J, r);
+  }
   int rc = check_hip(hipGetLastError(), "kpp_kernel launch");
   if (rc) return rc;
   const int KT = (io->k + 15) / 16;
@@ -700,8 +825,11 @@ int kmeans_run(Context* ctx, KmeansIO* io, hipStream_t s) {
 
 int kmeans_run_batched(Context* ctx, const KmJob* jobs_dev, const int32_t* pp_off_dev, int pp_total,
                        const int32_t* ll_off_dev, int ll_total, int njobs, int kmax, int iters, hipStream_t s) {
-  for (int r = 0; r < kmax; ++r)
+  for (int r = 0; r < kmax; ++r) {
     hipLaunchKernelGGL(kpp_kernel_seg, dim3(pp_total), dim3(kKB), 0, s, jobs_dev, pp_off_dev, njobs, r);
+    if (r > 0)
+      hipLaunchKernelGGL(kpp_pick_kernel_seg, dim3(pp_total), dim3(kKB), 0, s, jobs_dev, pp_off_dev, njobs, r);
+  }
   for (int it = 0; it < iters; ++it)
     hipLaunchKernelGGL(lloyd_kernel_seg<true>, dim3(ll_total), dim3(kLB), 0, s, jobs_dev, ll_off_dev, njobs);
   hipLaunchKernelGGL(lloyd_kernel_seg<false>, dim3(ll_total), dim3(kLB), 0, s, jobs_dev, ll_off_dev, njobs);

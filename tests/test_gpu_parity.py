@@ -152,6 +152,22 @@ def test_kmeans_parity(gpu_lib, k, l):
     assert _valid_assignment(X.astype(np.float64), lab, C.astype(np.float64), 1e-4)
 
 
+@pytest.mark.parametrize("n,l,k", [(700, 3, 2), (5000, 3, 7), (40000, 8, 33), (20000, 4, 64)])
+def test_kmeanspp_seeds_match_oracle_exactly(gpu_lib, n, l, k):
+    """Greedy k-means++ on points of an integer grid: every squared distance
+    and every running sum is exact on both sides, so the GPU must choose the
+    oracle's rows, candidate for candidate (0 Lloyd steps leave the seeds as
+    the centres).  Some rows are ineligible."""
+    rng = np.random.default_rng(n + k)
+    X = rng.integers(-100, 101, size=(n, l)).astype(np.float32)
+    elig = (np.arange(n) % 5 != 2)
+    idx = o.kmeanspp(X.astype(np.float64), k, 11, eligible=elig)
+    _, C = gpu_lib.kmeans(torch.from_numpy(X).cuda(), k, 0, seed=11,
+                          eligible=torch.from_numpy(elig.astype(np.uint8)).cuda())
+    say(f"kmeans++ n={n} l={l} k={k}")
+    assert np.array_equal(C.cpu().numpy(), X[idx])
+
+
 def test_kmeans_eligibility_and_fp64_points(gpu_lib):
     X, _ = synth.gaussian_mixture(300, 4, 3, seed=1, mean_scale=5.0)
     X = X.astype(np.float64)
