@@ -131,8 +131,10 @@ typedef struct {
    * summation order. */
   int32_t slab_kb;
   /* Which slab form (0 keeps the current one): 1 phases -- every block walks
-   * all slabs, one at a time; 2 per-XCD -- 8 slabs, one per XCD, whose
-   * per-row partial sums a second kernel adds in slab order; 3 automatic
+   * all slabs, one at a time, its rows' sums in LDS; 2 per-XCD -- 8 slabs,
+   * one per XCD, whose per-row partial sums a second kernel adds in slab
+   * order; 4 waves -- every wave takes its 64 rows through all slabs with the
+   * sums in registers (same results as phases, bit for bit); 3 automatic
    * (default: phases). */
   int32_t slab_mode;
 } fsc_tuning;

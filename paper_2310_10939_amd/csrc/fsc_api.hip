@@ -662,7 +662,7 @@ int fsc_tuning_set(fsc_context* ctx, fsc_tuning* t) {
   }
   if (t->slab_kb > 65536) return fail(FSC_E_ARG, "slab_kb must be <= 65536");
   if (t->slab_kb != 0) nt.slab_kb = t->slab_kb > 0 ? t->slab_kb : -1;
-  if (t->slab_mode < 0 || t->slab_mode > 3) return fail(FSC_E_ARG, "slab_mode must be in [0, 3]");
+  if (t->slab_mode < 0 || t->slab_mode > 4) return fail(FSC_E_ARG, "slab_mode must be in [0, 4]");
   if (t->slab_mode != 0) nt.slab_mode = t->slab_mode == 3 ? 0 : t->slab_mode;
   ctx->c.tune = nt;
   t->tile_nnz = nt.tile_nnz;

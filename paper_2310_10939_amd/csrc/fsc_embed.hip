@@ -284,7 +284,15 @@ static int launch_tiles(const Op& op, const TileArgs& ta, const StatsArgs& sa, i
 template <class Op>
 static int launch_slab(const Op& op, const TileArgs& ta, const SlabArgs& sb, const StatsArgs& sa, int grid,
                        int rgrid, hipStream_t s) {
-  if (sb.xcd) {
+  if (sb.wave) {
+    SlabWaveArgs sw;
+    sw.nslab = sb.nslab;
+    sw.wlen = sb.wlen;
+    sw.gbase = sb.gbase;
+    sw.gunit = sb.gunit;
+    sw.scol = sb.scol;
+    hipLaunchKernelGGL((slab_wave_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sw, sa);
+  } else if (sb.xcd) {
     hipLaunchKernelGGL((slab_xcd_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb);
     hipLaunchKernelGGL((slab_reduce_kernel<Op>), dim3(rgrid), dim3(kBlock), 0, s, op, ta, sb, sa);
   } else {
@@ -451,8 +459,13 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
   sb.sbase = sp.sbase;
   sb.smax = sp.smax;
   sb.sreg = sp.sreg;
-  io->grid = sp.xcd ? persistent_grid(ctx, (int64_t)sp.ntiles * sp.nslab, ctx->tune.slab_xcd_bpc)
-                    : persistent_grid(ctx, sp.ntiles, ctx->tune.slab_bpc);
+  sb.wave = sp.wave;
+  sb.wlen = sp.wlen;
+  sb.gbase = sp.gbase;
+  sb.gunit = sp.gunit;
+  io->grid = sp.wave  ? persistent_grid(ctx, ((int64_t)n + 4 * FSC_WAVE - 1) / (4 * FSC_WAVE), ctx->tune.slab_wave_bpc)
+             : sp.xcd ? persistent_grid(ctx, (int64_t)sp.ntiles * sp.nslab, ctx->tune.slab_xcd_bpc)
+                      : persistent_grid(ctx, sp.ntiles, ctx->tune.slab_bpc);
   return run_steps<S, W, LH>(ctx, io, ts, &sb, ss, s, stats);
 }
 

@@ -54,7 +54,7 @@ constexpr int kMaxGrid = 4096;
 
 // Column-slab form of the sparse product (fsc_slab.hpp, fsc_slab.hip).
 constexpr int kSlabRows = 1024;   // rows per slab tile
-constexpr int kSlabLong = 256;    // longer rows are summed by long-row chunks
+constexpr int kSlabLong = 255;    // longer rows are summed by long-row chunks (a length fits a byte)
 constexpr int kSlabMax = 16;      // most slabs per graph
 constexpr int kSlabChunk = 2048;  // nonzeros per long-row chunk
 
@@ -69,7 +69,8 @@ struct Tune {
   int slab_kb = 1024;      // column-slab size (KiB of the start block); <= 0: off
   int slab_bpc = 6;        // resident blocks per CU of the column-slab kernel (phases)
   int slab_xcd_bpc = 7;    // the same for the per-XCD form
-  int slab_mode = 0;       // 0 automatic, 1 phases, 2 per-XCD slabs
+  int slab_mode = 0;       // 0 automatic, 1 phases, 2 per-XCD slabs, 4 waves
+  int slab_wave_bpc = 8;   // resident blocks per CU of the wave form
 };
 
 // Tile plan of one graph for the sparse product (built on the device).
@@ -90,6 +91,10 @@ struct SlabPlan {
   int enabled = 0;
   int32_t S = 0, nslab = 0, ntiles = 0, rows = 0;  // slabs of S columns
   int xcd = 0;                 // 1: per-XCD slabs with partial sums
+  int wave = 0;                // 1: wave form (each wave owns 64 rows through all slabs)
+  uint8_t* wlen = nullptr;     // wave form: [nslab][n] segment length of each row in each slab
+  int64_t* gbase = nullptr;    // wave form: [ceil(n/64)] start of each 64-row group's nonzeros
+  uint8_t* gunit = nullptr;    // wave form: [ceil(n/64)] 1: the group's weights are all 1
   float* part = nullptr;       // per-XCD form: [n/64][nslab][64][LH] partial sums
   uint8_t* tunit = nullptr;    // [ntiles] 1: every weight of the tile's short rows is 1
   int64_t max_long = 0, max_chunks = 0;

@@ -9,6 +9,8 @@
 //                      starts, the scatter of the nonzeros into slab order
 //                      (assembled in LDS, written out coalesced), and the
 //                      long-row chunks.
+// The wave form replaces the last kernel by slab_wave_build_kernel (no sort:
+// each 64-row group's nonzeros slab by slab, row by row).
 // The layout is a function of the CSR alone: rows are sorted stably, and a
 // row's nonzeros keep their CSR order within its segment.
 #include "fsc_device.hpp"
@@ -19,7 +21,8 @@
 
 namespace fsc {
 
-static_assert(kSlabLong == 256, "the diagonal scan uses one 256-thread block pass");
+static_assert(kSlabLong < 1024, "the length and diagonal scans use one block pass");
+static_assert(kSlabLong <= 255, "the wave form stores segment lengths in a byte");
 static_assert(kSlabRows == 1024, "one build thread per row of a tile");
 
 // Slab of column c: slabs are S consecutive columns.
@@ -293,6 +296,126 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   }
 }
 
+// Wave form: per tile, one thread per row.  Each 64-row group (one wave)
+// lays out its nonzeros slab by slab; within a slab, row by row in row order,
+// each row's segment in CSR order.  Stored per row and slab: the segment
+// length (a byte); per group: the start of its nonzeros and a unit-weight
+// flag.  The positions within a group come from wave scans, so no sort is
+// needed.
+template <typename W>
+__global__ __launch_bounds__(kBuild) void slab_wave_build_kernel(
+    const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const W* __restrict__ val, int32_t n,
+    int32_t rows, int32_t S, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
+    const int32_t* __restrict__ coff, int32_t* __restrict__ scol, W* __restrict__ sval, uint8_t* __restrict__ wlen,
+    int64_t* __restrict__ gbase, uint8_t* __restrict__ gunit, LongChunk* __restrict__ chunks) {
+  __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
+  __shared__ uint16_t spos[kSlabMax * kSlabRows];  // start of each (row, slab) segment within its group
+  __shared__ int32_t scan32[kBuild / FSC_WAVE];
+  __shared__ int64_t scan64[kBuild / FSC_WAVE];
+  const int32_t T = blockIdx.x;
+  const int32_t r0 = T * rows;  // rows is a multiple of 64: groups do not straddle tiles
+  const int32_t R = min(rows, n - r0);
+  const int last = nslab - 1;
+  const int rl = threadIdx.x;
+  const int lane = rl % FSC_WAVE;
+  int64_t a = 0, b = 0;
+  if (rl < R) {
+    a = row_ptr[r0 + rl];
+    b = row_ptr[r0 + rl + 1];
+  }
+  const bool shortrow = rl < R && b - a <= kSlabLong;
+  for (int i = threadIdx.x; i < nslab * R; i += kBuild) cnt[i] = 0;
+  __syncthreads();
+  if (shortrow) {
+    for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
+      int32_t c[kBuildU];
+#pragma unroll
+      for (int u = 0; u < kBuildU; ++u) c[u] = j0 + u < b ? col[j0 + u] : 0;
+#pragma unroll
+      for (int u = 0; u < kBuildU; ++u)
+        if (j0 + u < b) cnt[slab_of(c[u], S, last) * R + rl] += 1;
+    }
+  }
+  // start of this row's group: the short-row nonzeros before the group
+  int64_t gb;
+  {
+    int64_t tot;
+    const int64_t len = shortrow ? b - a : 0;
+    const int64_t excl = block_scan_inclusive<kBuild, int64_t>(len, scan64, &tot) - len;
+    gb = toff[T] + __shfl(excl, 0, FSC_WAVE);
+    if (lane == 0 && rl < R) gbase[(r0 + rl) / FSC_WAVE] = gb;
+  }
+  __syncthreads();  // the counts above are complete
+  // per slab, the group's rows in row order: segment starts by a wave scan
+  int32_t phoff = 0;
+  for (int p = 0; p < nslab; ++p) {
+    const int len = rl < R ? (int)cnt[p * R + rl] : 0;
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < FSC_WAVE; o <<= 1) {
+      const int x = __shfl_up(incl, o, FSC_WAVE);
+      if (lane >= o) incl += x;
+    }
+    if (rl < R) {
+      spos[p * R + rl] = (uint16_t)(phoff + incl - len);
+      wlen[(int64_t)p * n + r0 + rl] = (uint8_t)len;
+    }
+    phoff += __shfl(incl, FSC_WAVE - 1, FSC_WAVE);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nslab * R; i += kBuild) cnt[i] = 0;
+  __syncthreads();
+  int unit = 1;  // every weight of this thread's row is exactly 1
+  if (shortrow) {
+    for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
+      int32_t c[kBuildU];
+#pragma unroll
+      for (int u = 0; u < kBuildU; ++u) c[u] = j0 + u < b ? col[j0 + u] : 0;
+#pragma unroll
+      for (int u = 0; u < kBuildU; ++u) {
+        if (j0 + u >= b) continue;
+        const int p = slab_of(c[u], S, last);
+        const int kk = cnt[p * R + rl]++;
+        const int64_t dst = gb + spos[p * R + rl] + kk;
+        scol[dst] = c[u];
+        if constexpr (!std::is_void<W>::value) {
+          const W w = val[j0 + u];
+          sval[dst] = w;
+          if (weight<W, float>::get(&w, 0) != 1.0f) unit = 0;
+        }
+      }
+    }
+  }
+  {
+    const bool all_unit = __all(unit);
+    if (lane == 0 && rl < R) gunit[(r0 + rl) / FSC_WAVE] = all_unit ? 1 : 0;
+  }
+  // long rows: chunks of kSlabChunk nonzeros of the original CSR
+  {
+    const int32_t isl = rl < R && !shortrow ? 1 : 0;
+    const int32_t nc = isl ? (int32_t)((b - a + kSlabChunk - 1) / kSlabChunk) : 0;
+    int32_t tl, tc;
+    const int32_t il = block_scan_inclusive<kBuild, int32_t>(isl, scan32, &tl);
+    const int32_t ic = block_scan_inclusive<kBuild, int32_t>(nc, scan32, &tc);
+    if (isl) {
+      const int32_t lid = loff[T] + il - 1;
+      const int32_t first = coff[T] + ic - nc;
+      for (int32_t c = 0; c < nc; ++c) {
+        LongChunk ch;
+        ch.start = a + (int64_t)c * kSlabChunk;
+        ch.end = min<int64_t>(ch.start + kSlabChunk, b);
+        ch.row = r0 + rl;
+        ch.lid = lid;
+        ch.index = c;
+        ch.count = nc;
+        ch.first = first;
+        ch.pad = 0;
+        chunks[first + c] = ch;
+      }
+    }
+  }
+}
+
 __global__ void slab_fill_i32(int32_t* p, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
@@ -302,7 +425,8 @@ __global__ void slab_fill_i32(int32_t* p, int64_t count) {
 // Host side
 // ===========================================================================
 // Which slab form a block of n rows x LH columns takes (slab_kb of the
-// context's tuning, slab_mode 0 automatic, 1 phases, 2 per-XCD):
+// context's tuning, slab_mode 0 automatic, 1 phases, 2 per-XCD, 4 waves; the
+// wave form has the phase form's slabs):
 //   - none when the block fits one slab (FP64 blocks never take one);
 //   - phases (automatic): slabs of a power of two rows of at most slab_kb
 //     KiB, no more than kSlabMax of them (larger slabs if needed);
@@ -337,9 +461,10 @@ static size_t weight_bytes(const fsc_csr* g) {
 
 // Rows per tile.  Phase form: about one tile per resident block, a multiple
 // of 64 in [256, kSlabRows], so blocks move through the slabs together.
-// Per-XCD form: kSlabRows (each (tile, slab) region is a work item).
+// Per-XCD form: kSlabRows (each (tile, slab) region is a work item).  Wave
+// form: kSlabRows (tiles only group the build).
 int32_t slab_rows(const Context* ctx, int64_t n, int xcd) {
-  if (xcd) return kSlabRows;
+  if (xcd || ctx->tune.slab_mode == 4) return kSlabRows;
   const int64_t blocks = (int64_t)ctx->num_cu * ctx->tune.slab_bpc;
   int64_t r = (n + blocks - 1) / std::max<int64_t>(blocks, 1);
   r = (r + 63) / 64 * 64;
@@ -357,8 +482,12 @@ size_t slab_workspace_bytes(const Context* ctx, const fsc_csr* g, int LH, int ve
   const int64_t mc = nnz / kSlabChunk + ml + 1;
   size_t b = 0;
   b += align_up(nnz * 4) + align_up(nnz * weight_bytes(g));
-  b += align_up(n * nslab * 2);
-  b += align_up(nt * nslab * (kSlabLong + 1) * 4) + align_up(nt * nslab * 4) + align_up(nt * nslab * 8);
+  if (ctx->tune.slab_mode == 4) {
+    b += align_up(n * nslab) + align_up((n + 63) / 64 * 8) + align_up((n + 63) / 64);
+  } else {
+    b += align_up(n * nslab * 2);
+    b += align_up(nt * nslab * (kSlabLong + 1) * 4) + align_up(nt * nslab * 4) + align_up(nt * nslab * 8);
+  }
   b += align_up(nt * 8) + align_up((nt + 1) * 8) + 4 * align_up((nt + 1) * 4);
   b += align_up(mc * sizeof(LongChunk)) + align_up(16);
   b += align_up(ml * 2 * LH * 8) + align_up(mc * LH * 4) + align_up(ml * 4);
@@ -382,10 +511,17 @@ int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
   sp.max_chunks = nnz / kSlabChunk + sp.max_long + 1;
   sp.scol = a->take<int32_t>(nnz);
   sp.sval = g->val ? (void*)a->take<char>(nnz * weight_bytes(g)) : nullptr;
-  sp.sperm = a->take<uint16_t>(n * sp.nslab);
-  sp.sbase = a->take<int32_t>(nt * sp.nslab * (kSlabLong + 1));
-  sp.smax = a->take<int32_t>(nt * sp.nslab);
-  sp.sreg = a->take<int64_t>(nt * sp.nslab);
+  sp.wave = !sp.xcd && ctx->tune.slab_mode == 4;
+  if (sp.wave) {
+    sp.wlen = a->take<uint8_t>(n * sp.nslab);
+    sp.gbase = a->take<int64_t>((n + 63) / 64);
+    sp.gunit = a->take<uint8_t>((n + 63) / 64);
+  } else {
+    sp.sperm = a->take<uint16_t>(n * sp.nslab);
+    sp.sbase = a->take<int32_t>(nt * sp.nslab * (kSlabLong + 1));
+    sp.smax = a->take<int32_t>(nt * sp.nslab);
+    sp.sreg = a->take<int64_t>(nt * sp.nslab);
+  }
   sp.tshort = a->take<int64_t>(nt);
   sp.toff = a->take<int64_t>(nt + 1);
   sp.tlong = a->take<int32_t>(nt + 1);
@@ -405,6 +541,12 @@ int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
 
 template <typename W>
 static void launch_build(const fsc_csr* g, SlabPlan& sp, hipStream_t s) {
+  if (sp.wave) {
+    hipLaunchKernelGGL((slab_wave_build_kernel<W>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
+                       reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
+                       sp.coff, sp.scol, reinterpret_cast<W*>(sp.sval), sp.wlen, sp.gbase, sp.gunit, sp.chunks);
+    return;
+  }
   hipLaunchKernelGGL((slab_build_kernel<W>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
                      reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
                      sp.coff, sp.scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax, sp.sreg,

@@ -36,6 +36,10 @@ struct SlabArgs {
   const int32_t* sbase;   // [ntiles*nslab][kSlabLong+1]: start of diagonal k within the region
   const int32_t* smax;    // [ntiles*nslab]: longest segment of the (tile, phase)
   const int64_t* sreg;    // [ntiles*nslab]: start of the (tile, phase) region
+  int32_t wave;           // 1: wave form (slab_wave_kernel), with the three arrays below
+  const uint8_t* wlen;
+  const int64_t* gbase;
+  const uint8_t* gunit;
 };
 
 
@@ -228,6 +232,94 @@ __global__ __launch_bounds__(kBlock) void slab_reduce_kernel(Op op_in, TileArgs 
     op.prefetch(r, pre);
     op.finish(r, sum, pre, st);
   }
+  if constexpr (Op::STATS) op.epilogue(sa, st);
+}
+
+// ---------------------------------------------------------------------------
+// Wave form: each wave owns a group of 64 consecutive rows, one per lane, and
+// takes them through the slabs in order with the row sums in registers, so
+// no wave waits for another.  Waves start together and run at about the same
+// pace, so the XCDs still gather from about one slab at a time.  Layout
+// (slab_wave_build_kernel): the group's nonzeros slab by slab, within a slab
+// row by row, each row's segment in CSR order; per row and slab the segment
+// length (a byte).  A row's sum is built in the phase form's order (per slab
+// a partial sum over the segment, added to the row's total slab by slab), so
+// the two forms give the same bits.
+// ---------------------------------------------------------------------------
+struct SlabWaveArgs {
+  int32_t nslab;
+  const uint8_t* wlen;    // [nslab][n] segment length of row r in slab p (0 for long rows)
+  const int64_t* gbase;   // [ceil(n/64)] start of group g's nonzeros in scol
+  const uint8_t* gunit;   // [ceil(n/64)] 1: the group's weights are all 1
+  const int32_t* scol;
+};
+
+template <int kU, bool UNIT, class Op>
+__device__ __forceinline__ void wave_group(const Op& op, const TileArgs& ta, const SlabWaveArgs& sw, int32_t g,
+                                           double* st) {
+  constexpr int LH = Op::LH;
+  using A = typename Op::A;
+  const int lane = threadIdx.x % FSC_WAVE;
+  const int32_t n = ta.n;
+  const int32_t r = g * FSC_WAVE + lane;
+  const bool in = r < n;
+  const uint8_t* lp = sw.wlen + (in ? r : 0);
+  A acc[LH];
+#pragma unroll
+  for (int q = 0; q < LH; ++q) acc[q] = A(0);
+  int64_t base = sw.gbase[g];
+  int len_next = in ? (int)lp[0] : 0;
+  for (int p = 0; p < sw.nslab; ++p) {
+    const int len = len_next;
+    len_next = in && p + 1 < sw.nslab ? (int)lp[(int64_t)(p + 1) * n] : 0;  // in flight during this slab
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < FSC_WAVE; o <<= 1) {
+      const int x = __shfl_up(incl, o, FSC_WAVE);
+      if (lane >= o) incl += x;
+    }
+    const int total = __shfl(incl, FSC_WAVE - 1, FSC_WAVE);
+    int mx = len;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o, FSC_WAVE));
+    const int start = incl - len;
+    A a[LH];
+#pragma unroll
+    for (int q = 0; q < LH; ++q) a[q] = A(0);
+    for (int k = 0; k < mx; k += kU) {
+      int32_t off[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) off[u] = k + u < len ? start + k + u : -1;
+      op.template accumulate_at<kU, UNIT>(sw.scol, base, off, a);
+    }
+#pragma unroll
+    for (int q = 0; q < LH; ++q) acc[q] += a[q];
+    base += total;
+  }
+  if (in && ta.row_ptr[r + 1] - ta.row_ptr[r] <= kSlabLong) {  // long rows: finished by their chunks
+    typename Op::Pre pre;
+    op.prefetch(r, pre);
+    op.finish(r, acc, pre, st);
+  }
+}
+
+template <int kU, class Op>
+__global__ __launch_bounds__(kBlock) void slab_wave_kernel(Op op_in, TileArgs ta, SlabWaveArgs sw, StatsArgs sa) {
+  constexpr int LH = Op::LH;
+  constexpr int WPB = kBlock / FSC_WAVE;
+  Op op = op_in;
+  op.init();
+  double st[2 * LH];
+#pragma unroll
+  for (int q = 0; q < 2 * LH; ++q) st[q] = 0.0;
+  const int wave = threadIdx.x / FSC_WAVE;
+  const int32_t ng = (ta.n + FSC_WAVE - 1) / FSC_WAVE;
+  for (int32_t g = blockIdx.x * WPB + wave; g < ng; g += gridDim.x * WPB) {
+    if (sw.gunit[g]) wave_group<kU, true>(op, ta, sw, g, st);
+    else wave_group<kU, false>(op, ta, sw, g, st);
+  }
+  const int32_t nch = ta.meta[0];
+  for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) long_chunk<kU>(op, ta, c);
   if constexpr (Op::STATS) op.epilogue(sa, st);
 }
 

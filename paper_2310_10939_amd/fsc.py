@@ -339,8 +339,8 @@ def ari(a, b, ka, kb):
 
 def tuning(tile_nnz=0, blocks_per_cu=0, xcd_order=0, unroll=0, slab_kb=0, slab_mode=0, device=None):
     """Sets the sparse-product launch shape (0 keeps a field; slab_kb < 0
-    turns the column-slab form off; slab_mode 1 phases, 2 per-XCD, 3
-    automatic) and returns the current one as a dict (xcd_order: 1 contiguous
+    turns the column-slab form off; slab_mode 1 phases, 2 per-XCD, 4 waves,
+    3 automatic) and returns the current one as a dict (xcd_order: 1 contiguous
     per XCD, 2 round robin)."""
     t = Tuning(tile_nnz, blocks_per_cu, xcd_order, unroll, slab_kb, slab_mode)
     _check(_lib.fsc_tuning_set(context(device), ctypes.byref(t)))

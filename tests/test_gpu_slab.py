@@ -1,8 +1,9 @@
 """Column-slab form of the sparse product: parity with the FP64 oracle and
 with the plain tile kernel.
 
-Both forms are checked: phases (every block walks the slabs) and per-XCD
-(8 slabs, partial sums added by a second kernel).  Small graphs are cut into
+All three forms are checked: phases (every block walks the slabs), per-XCD
+(8 slabs, partial sums added by a second kernel) and waves (every wave takes
+its 64 rows through the slabs, sums in registers; bit-identical to phases).  Small graphs are cut into
 many slabs by a small slab size (4 KiB of the block), with long rows (hubs, summed by chunks of the original CSR),
 isolated vertices and a ragged last tile of rows.  The full-size test runs
 the 1M-vertex SBM (vertex ids permuted, as the benchmark's default workload)
@@ -38,11 +39,12 @@ def test_slab_size_is_reported(gpu_lib, slab):
     assert slab(0, 1)["slab_mode"] == 1
     assert slab(0, 2)["slab_mode"] == 2
     assert slab(0, 3)["slab_mode"] == 3
+    assert slab(0, 4)["slab_mode"] == 4
     with pytest.raises(RuntimeError):
-        slab(0, 4)
+        slab(0, 5)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 4])
 @pytest.mark.parametrize("l", [1, 2, 3, 4, 6, 8])
 @pytest.mark.parametrize("vec,wt", [("f32", "f32"), ("f32", "none"), ("bf16", "bf16")])
 def test_slab_matches_oracle_and_tiles(gpu_lib, slab, l, vec, wt, mode):
@@ -64,7 +66,7 @@ def test_slab_matches_oracle_and_tiles(gpu_lib, slab, l, vec, wt, mode):
         assert col_rel_err(E, plain) <= 1e-5
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 4])
 def test_slab_traces_and_renorm(gpu_lib, slab, mode):
     g = synth.random_weighted(4000, 20000, seed=11, hubs=3, hub_degree=900, isolated=5)
     ip, ix, d = to_device(g, "f32")
@@ -79,7 +81,7 @@ def test_slab_traces_and_renorm(gpu_lib, slab, mode):
     assert np.abs(sqn.cpu().numpy() - sq_o).max() <= 1e-4 * np.abs(sq_o).max()
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 4])
 def test_slab_unit_weight_tiles(gpu_lib, slab, mode):
     """Tiles whose weights are all exactly 1 skip the weight loads: stored
     unit weights give the same bits as no weights, and a graph where one
@@ -104,7 +106,7 @@ def test_slab_unit_weight_tiles(gpu_lib, slab, mode):
     assert col_rel_err(E, want) <= TOL["f32"]
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 4])
 def test_slab_deterministic(gpu_lib, slab, mode):
     g = synth.random_weighted(6000, 50000, seed=2, hubs=3, hub_degree=3000)
     ip, ix, d = to_device(g, "f32")
@@ -115,7 +117,7 @@ def test_slab_deterministic(gpu_lib, slab, mode):
         assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 4])
 def test_slab_cluster_small(gpu_lib, slab, mode):
     g = synth.sbm_by_degree(20000, 6, 24, 3, seed=5, permute=True)
     ip, ix, _ = to_device(g)
@@ -125,6 +127,26 @@ def test_slab_cluster_small(gpu_lib, slab, mode):
     ari = float(gpu_lib.ari(lab, torch.from_numpy(np.asarray(lab_o, dtype=np.int32)).cuda(), 6, 6))
     say("slab cluster ARI vs oracle", ari)
     assert ari >= 0.99
+
+
+@pytest.mark.parametrize("kb", [4, 64])
+@pytest.mark.parametrize("l", [1, 3, 4, 8])
+@pytest.mark.parametrize("wt", ["f32", "none", "bf16"])
+def test_wave_form_equals_phase_form(gpu_lib, slab, kb, l, wt):
+    """The wave form sums every row in the phase form's order, so the two
+    give the same bits (the statistics are summed in another order and are
+    compared to 1e-12)."""
+    g = synth.random_weighted(9000, 60000, seed=40 + l, hubs=4, hub_degree=1500, isolated=9)
+    ip, ix, d = to_device(g, wt)
+    vec = "bf16" if wt == "bf16" else "f32"
+    slab(kb, 1)
+    a, sqa, raa = gpu_lib.embed(ip, ix, d, l, 9, seed=5, vec_dtype=vec, traces=True)
+    slab(kb, 4)
+    b, sqb, rab = gpu_lib.embed(ip, ix, d, l, 9, seed=5, vec_dtype=vec, traces=True)
+    say(f"wave vs phases kb={kb} l={l} weights={wt}")
+    assert torch.equal(a, b)
+    assert torch.allclose(sqa, sqb, rtol=1e-12, atol=0)
+    assert torch.allclose(raa, rab, rtol=1e-12, atol=1e-15)
 
 
 def test_full_size_sbm_matches_oracle(gpu_lib):
