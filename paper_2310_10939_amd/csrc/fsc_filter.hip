@@ -141,7 +141,7 @@ struct ChebOp {
     float out[LH_];
 #pragma unroll
     for (int q = 0; q < LH_; ++q) {
-      const float m = 0.5f * p.z[q] + p.h * acc[q];
+      const float m = fma_acc(p.h, acc[q], 0.5f * p.z[q]);
       out[q] = first ? 2.f * m - p.z[q] : 4.f * m - 2.f * p.z[q] - p.zm[q];
       st[q] += p.d * (double)p.z[q] * (double)p.z[q];
       st[LH_ + q] += p.d * (double)p.z[q] * (double)m;

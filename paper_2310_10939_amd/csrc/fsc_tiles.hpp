@@ -110,6 +110,10 @@ struct DegreeOp {
   }
 };
 
+// a * b + c with one rounding, for the accumulation type
+__device__ __forceinline__ float fma_acc(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_acc(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // One PowerMethod step in z-space with a per-column scale c (1 unless the
 // iterate is re-normalised):
 //   Z'_r = c (.) (Z_r / 2 + hinv_r (A Z)_r).
@@ -186,7 +190,9 @@ struct StepOp {
     A zn[LH_];
 #pragma unroll
     for (int q = 0; q < LH_; ++q) {
-      const A m = A(0.5) * p.z[q] + p.h * acc[q];
+      // one explicit fused multiply-add, so every kernel that inlines this
+      // rounds the same way
+      const A m = fma_acc(p.h, acc[q], A(0.5) * p.z[q]);
       zn[q] = cs[q] * m;
       if constexpr (STATS_) {
         // statistics of the value that is actually stored

@@ -134,8 +134,8 @@ def test_slab_cluster_small(gpu_lib, slab, mode):
 @pytest.mark.parametrize("wt", ["f32", "none", "bf16"])
 def test_wave_form_equals_phase_form(gpu_lib, slab, kb, l, wt):
     """The wave form sums every row in the phase form's order, so the two
-    give the same bits (the statistics are summed in another order and are
-    compared to 1e-12)."""
+    give the same bits (the FP64 statistics are summed over the rows in
+    another order and are compared to 1e-10)."""
     g = synth.random_weighted(9000, 60000, seed=40 + l, hubs=4, hub_degree=1500, isolated=9)
     ip, ix, d = to_device(g, wt)
     vec = "bf16" if wt == "bf16" else "f32"
@@ -145,8 +145,8 @@ def test_wave_form_equals_phase_form(gpu_lib, slab, kb, l, wt):
     b, sqb, rab = gpu_lib.embed(ip, ix, d, l, 9, seed=5, vec_dtype=vec, traces=True)
     say(f"wave vs phases kb={kb} l={l} weights={wt}")
     assert torch.equal(a, b)
-    assert torch.allclose(sqa, sqb, rtol=1e-12, atol=0)
-    assert torch.allclose(raa, rab, rtol=1e-12, atol=1e-15)
+    assert torch.allclose(sqa, sqb, rtol=1e-10, atol=0)
+    assert torch.allclose(raa, rab, rtol=1e-10, atol=1e-12)
 
 
 def test_full_size_sbm_matches_oracle(gpu_lib):
