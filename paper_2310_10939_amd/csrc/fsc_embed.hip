@@ -281,6 +281,10 @@ static int launch_tiles(const Op& op, const TileArgs& ta, const StatsArgs& sa, i
   return check_hip(hipGetLastError(), "tile_kernel launch");
 }
 
+// Phase-form kernel shape: nonzeros in flight per row, rows per lane.
+constexpr int kSlabU = 8;
+constexpr int kSlabJ = 1;
+
 template <class Op>
 static int launch_slab(const Op& op, const TileArgs& ta, const SlabArgs& sb, const StatsArgs& sa, int grid,
                        int rgrid, hipStream_t s) {
@@ -296,7 +300,7 @@ static int launch_slab(const Op& op, const TileArgs& ta, const SlabArgs& sb, con
     hipLaunchKernelGGL((slab_xcd_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb);
     hipLaunchKernelGGL((slab_reduce_kernel<Op>), dim3(rgrid), dim3(kBlock), 0, s, op, ta, sb, sa);
   } else {
-    hipLaunchKernelGGL((slab_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb, sa);
+    hipLaunchKernelGGL((slab_kernel<kSlabU, kSlabJ, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb, sa);
   }
   return check_hip(hipGetLastError(), "slab_kernel launch");
 }
@@ -359,6 +363,12 @@ static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta, const SlabAr
     }
     timing_stop(ev, s);
     if (rc) return rc;
+    if (stats) {
+      // the partials come from the per-XCD form's reduce kernel, else from the step kernel
+      const bool reduce = sb && sb->xcd && !std::is_same<A, double>::value;
+      hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kBlock), 0, s, sa, reduce ? sb->rgrid : io->grid);
+      if ((rc = check_hip(hipGetLastError(), "stats_finish launch"))) return rc;
+    }
   }
   io->zt = io->z[io->t & 1];
   return FSC_OK;
@@ -430,6 +440,10 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
                        (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), io->x0, io->isq, io->deg,
                        reinterpret_cast<S*>(io->z[0]), sa, stats ? 1 : 0);
     if ((rc = check_hip(hipGetLastError(), "start_block launch"))) return rc;
+    if (stats) {
+      hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kBlock), 0, s, sa, grid);
+      if ((rc = check_hip(hipGetLastError(), "stats_finish launch"))) return rc;
+    }
   }
   if (!io->slab.enabled || std::is_same<A, double>::value)
     return run_steps<S, W, LH>(ctx, io, ta, nullptr, sa, s, stats);

@@ -29,31 +29,29 @@
 
 namespace fsc {
 
-// Rayleigh-quotient epilogue: the last block writes, per column q,
-// rayleigh[step * LH + q] = sum d z m / sum d z z.
+// Rayleigh-quotient statistics: each block writes its partial sums; the
+// one-block cheb_stats_finish kernel, launched after the step on the same
+// stream, writes per column q rayleigh[step * LH + q] = sum d z m / sum d z z
+// (no block of the step waits on a device-scope fence).
 template <int LH>
 __device__ __forceinline__ void cheb_stats_epilogue(const StatsArgs& sa, const double* st) {
   __shared__ double red[kBlock / FSC_WAVE];
-  __shared__ double tot[2 * LH];
-  __shared__ int is_last;
 #pragma unroll
   for (int q = 0; q < 2 * LH; ++q) {
     const double v = block_sum<kBlock>(st[q], red);
     if (threadIdx.x == 0) sa.partials[(int64_t)blockIdx.x * 2 * LH + q] = v;
   }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(sa.counter, 1);
-    is_last = (prev == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
+
+template <int LH>
+__global__ __launch_bounds__(kBlock) void cheb_stats_finish(StatsArgs sa, int grid) {
+  __shared__ double red[kBlock / FSC_WAVE];
+  __shared__ double tot[2 * LH];
   const int32_t nlong = sa.meta[1];
   double v[2 * LH];
 #pragma unroll
   for (int q = 0; q < 2 * LH; ++q) v[q] = 0.0;
-  for (int32_t g = threadIdx.x; g < (int32_t)gridDim.x; g += kBlock)
+  for (int32_t g = threadIdx.x; g < grid; g += kBlock)
 #pragma unroll
     for (int q = 0; q < 2 * LH; ++q) v[q] += sa.partials[(int64_t)g * 2 * LH + q];
   for (int32_t g = threadIdx.x; g < nlong; g += kBlock)
@@ -69,7 +67,6 @@ __device__ __forceinline__ void cheb_stats_epilogue(const StatsArgs& sa, const d
     const int q = threadIdx.x;
     sa.rayleigh[(int64_t)sa.step * LH + q] = tot[q] > 0.0 ? tot[LH + q] / tot[q] : 0.0;
   }
-  if (threadIdx.x == 0) *sa.counter = 0;
 }
 
 // One Chebyshev step: zout = first ? 2 M_z z - z : 4 M_z z - 2 z - zprev.
@@ -482,6 +479,7 @@ static int cheb_steps_typed(Context* ctx, EmbedIO* io, float* const* basis, int 
     else
       hipLaunchKernelGGL((tile_kernel<8, ChebOp<W, LH>>), dim3(io->grid), dim3(kBlock), 0, s, op, ta, sa);
     timing_stop(ev, s);
+    hipLaunchKernelGGL((cheb_stats_finish<LH>), dim3(1), dim3(kBlock), 0, s, sa, io->grid);
   }
   return check_hip(hipGetLastError(), "chebyshev step launch");
 }
@@ -519,6 +517,7 @@ static int rayleigh_typed(Context* ctx, EmbedIO* io, const float* x, double* ray
   op.deg = io->deg;
   op.first = 1;
   hipLaunchKernelGGL((tile_kernel<4, ChebOp<W, LH>>), dim3(io->grid), dim3(kBlock), 0, s, op, ta, sa);
+  hipLaunchKernelGGL((cheb_stats_finish<LH>), dim3(1), dim3(kBlock), 0, s, sa, io->grid);
   return check_hip(hipGetLastError(), "rayleigh launch");
 }
 

@@ -5,16 +5,17 @@
 // single-graph entry points launch one job, the batched form launches many in
 // one grid (blocks map to (job, local block) through a prefix table).
 //
-// Seeding (greedy k-means++): two launches per centre r >= 1.  In the first,
-// each block owns a contiguous run of rows, updates
-// D2(v) = min(D2(v), ||p_v - c_{r-1}||^2) and writes the FP64 sum of its
-// weights; the last block of the job to finish draws L = 2 + floor(ln k)
-// candidates: for each it scans the block sums, locates the block holding the
-// sample u_j * sum(D2) and rescans that block's rows (same summation order)
-// to find the sampled row.  In the second, each block sums, per candidate,
-// min(D2(v), ||p_v - cand_j||^2) over its eligible rows, and the last block
-// keeps the candidate with the smallest total (ties to the lower j).  Centre
-// 0 is one uniform draw over the eligible rows.  No host round trip.
+// Seeding (greedy k-means++): per centre r >= 1, a pass over the rows and a
+// one-block kernel, twice.  First each block owns a contiguous run of rows,
+// updates D2(v) = min(D2(v), ||p_v - c_{r-1}||^2) and writes the FP64 sum of
+// its weights; then one block draws L = 2 + floor(ln k) candidates: for each
+// it scans the block sums, locates the block holding the sample
+// u_j * sum(D2) and rescans that block's rows (same summation order) to find
+// the sampled row.  Second, each block sums, per candidate,
+// min(D2(v), ||p_v - cand_j||^2) over its eligible rows, and one block keeps
+// the candidate with the smallest total (ties to the lower j).  Centre 0 is
+// one uniform draw over the eligible rows.  No host round trip, and no block
+// waits on a device-scope fence (the stream orders the kernels).
 //
 // Lloyd: one launch per step.  Distances come from MFMA
 // (v_mfma_f32_16x16x4_f32): a 16-centre tile of C times a 16-point tile of
@@ -24,8 +25,9 @@
 // update is a second contraction on the same unit: the one-hot matrix of the
 // labels (transposed) times the point tile, with a ones column for the
 // counts, accumulated over the wave's tiles.  The 16 waves of a block are
-// summed in FP64 in wave order, and the per-block sums are combined by the
-// last block of the job in a fixed order, so results are deterministic.
+// summed in FP64 in wave order, and the per-block sums are combined in a fixed
+// order by a one-block kernel per job after the step, so results are
+// deterministic.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
 
@@ -58,9 +60,6 @@ struct LloydShared {
   float cn[kMaxK];  // ||c_j||^2, +inf past k
   float wsum[kLW][kMaxK][9];
   int lab[kLW][16];
-  double tot[kMaxK * 9];
-  double part[kLB];
-  int is_last;
 };
 
 // ---------------------------------------------------------------------------
@@ -188,11 +187,9 @@ __device__ int64_t kpp_unchosen(const KmJob& J, int r, KppShared& sh) {
 template <int KD>
 __device__ void kpp_block(const KmJob& J, int blk, int r, KppShared& sh) {
   double* sbuf = sh.sbuf;
-  int& is_last = sh.is_last;
   const int64_t n = J.n;
   const int first = (r == 0);
   const int64_t rpb = (int64_t)kKB * kRPT;
-  const int nblk = J.nblk_pp;
   const float* pts = J.pts;
   const uint8_t* elig = J.elig;
   float* d2 = J.d2;
@@ -243,18 +240,16 @@ __device__ void kpp_block(const KmJob& J, int blk, int r, KppShared& sh) {
     block_scan_inclusive<kKB>(ts, sbuf, &total);
     if (threadIdx.x == 0) J.bsum[blk] = total;
   }
-  // hand-off to the last block of the job
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(J.counter, 1);
-    is_last = (prev == nblk - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
 
-  // phase B (last block): the total weight, then each draw u * total located
-  // by kpp_sample.
+// Phase B of round r (one block per job, after phase A on the same stream):
+// the total weight, then each draw u * total located by kpp_sample.
+template <int KD>
+__device__ void kpp_sample_block(const KmJob& J, int r, KppShared& sh) {
+  double* sbuf = sh.sbuf;
+  const int first = (r == 0);
+  const int nblk = J.nblk_pp;
+  const float* pts = J.pts;
   double total = 0.0;
   for (int base = 0; base < nblk; base += kKB) {
     const int b = base + threadIdx.x;
@@ -282,7 +277,6 @@ __device__ void kpp_block(const KmJob& J, int blk, int r, KppShared& sh) {
       if (threadIdx.x < KD) J.cand[j * KD + threadIdx.x] = pts[pick * KD + threadIdx.x];
     }
   }
-  if (threadIdx.x == 0) *J.counter = 0;
 }
 
 // Round r >= 1, second launch: the potential of each candidate over this
@@ -326,13 +320,14 @@ __device__ void kpp_pick_block(const KmJob& J, int blk, int r, KppShared& sh) {
     const double t = block_sum<kKB>(pot[j], sh.sbuf);
     if (threadIdx.x == 0) J.bsum[(int64_t)blk * kMaxTrials + j] = t;
   }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    sh.is_last = atomicAdd(J.counter, 1) == nblk - 1;
-  }
-  __syncthreads();
-  if (!sh.is_last) return;
-  __threadfence();
+}
+
+// Round r >= 1 (one block per job, after the potentials): the candidate with
+// the smallest total potential becomes centre r.
+__device__ void kpp_select_block(const KmJob& J, int r, KppShared& sh) {
+  const int L = J.trials;
+  const int nblk = J.nblk_pp;
+  const int KD = J.KD;
   double best = 0.0;
   int bj = 0;
   for (int j = 0; j < L; ++j) {
@@ -345,10 +340,7 @@ __device__ void kpp_pick_block(const KmJob& J, int blk, int r, KppShared& sh) {
     }
   }
   const int32_t row = J.cand_row[bj];
-  if (threadIdx.x == 0) {
-    J.chosen[r] = row;
-    *J.counter = 0;
-  }
+  if (threadIdx.x == 0) J.chosen[r] = row;
   if (threadIdx.x < KD) J.centres[r * KD + threadIdx.x] = J.cand[bj * KD + threadIdx.x];
 }
 
@@ -369,7 +361,6 @@ template <int KD, int KT, bool UPDATE>
 __device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh) {
   auto& wsum = sh.wsum;
   auto& lab_s = sh.lab;
-  int& is_last = sh.is_last;
   const int64_t n = J.n;
   const int k = J.k;
   const float* pts = J.pts;
@@ -522,52 +513,50 @@ __device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh) {
       for (int w = 0; w < kLW; ++w) s += (double)wsum[w][j][d];
       cpart[(int64_t)blk * O + o] = s;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const int prev = atomicAdd(J.counter, 1);
-      is_last = (prev == J.nblk_ll - 1);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    double* tot = sh.tot;
-    double* part = sh.part;
-    // outputs o < O; each summed by S threads over interleaved block subsets,
-    // the S partial sums then combined in subset order
-    const int nblk = J.nblk_ll;
-    for (int o0 = 0; o0 < O; o0 += kLB) {
-      const int cnt = min(kLB, O - o0);
-      const int S = kLB / cnt;
-      const int o = o0 + threadIdx.x % cnt, sidx = threadIdx.x / cnt;
-      double acc = 0.0;
-      if (sidx < S) {
-        int b = sidx;
-        for (; b + 3 * S < nblk; b += 4 * S) {
-          const double x0 = cpart[(int64_t)b * O + o], x1 = cpart[(int64_t)(b + S) * O + o];
-          const double x2 = cpart[(int64_t)(b + 2 * S) * O + o], x3 = cpart[(int64_t)(b + 3 * S) * O + o];
-          acc += x0;
-          acc += x1;
-          acc += x2;
-          acc += x3;
-        }
-        for (; b < nblk; b += S) acc += cpart[(int64_t)b * O + o];
+  }
+}
+
+// Centre update of a Lloyd step: the per-block sums of the step's kernel,
+// added in a fixed order, then the means (one block per job, launched after
+// the step on the same stream, so no block of the step waits on a
+// device-scope fence).
+__device__ void lloyd_finish(const KmJob& J, double* tot, double* part) {
+  const int KD = J.KD, k = J.k;
+  const int O = k * (KD + 1);
+  const double* cpart = J.cpart;
+  // outputs o < O; each summed by S threads over interleaved block subsets,
+  // the S partial sums then combined in subset order
+  const int nblk = J.nblk_ll;
+  for (int o0 = 0; o0 < O; o0 += kLB) {
+    const int cnt = min(kLB, O - o0);
+    const int S = kLB / cnt;
+    const int o = o0 + threadIdx.x % cnt, sidx = threadIdx.x / cnt;
+    double acc = 0.0;
+    if (sidx < S) {
+      int b = sidx;
+      for (; b + 3 * S < nblk; b += 4 * S) {
+        const double x0 = cpart[(int64_t)b * O + o], x1 = cpart[(int64_t)(b + S) * O + o];
+        const double x2 = cpart[(int64_t)(b + 2 * S) * O + o], x3 = cpart[(int64_t)(b + 3 * S) * O + o];
+        acc += x0;
+        acc += x1;
+        acc += x2;
+        acc += x3;
       }
-      part[threadIdx.x] = acc;
-      __syncthreads();
-      if (threadIdx.x < cnt) {
-        double s2 = 0.0;
-        for (int i = 0; i < S; ++i) s2 += part[i * cnt + threadIdx.x];
-        tot[o0 + threadIdx.x] = s2;
-      }
-      __syncthreads();
+      for (; b < nblk; b += S) acc += cpart[(int64_t)b * O + o];
     }
-    for (int o = threadIdx.x; o < k * KD; o += kLB) {
-      const int j = o / KD, d = o % KD;
-      const double cnt = tot[j * (KD + 1) + KD];
-      if (cnt > 0.0) J.centres[j * KD + d] = (float)(tot[j * (KD + 1) + d] / cnt);
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+      double s2 = 0.0;
+      for (int i = 0; i < S; ++i) s2 += part[i * cnt + threadIdx.x];
+      tot[o0 + threadIdx.x] = s2;
     }
-    if (threadIdx.x == 0) *J.counter = 0;
+    __syncthreads();
+  }
+  for (int o = threadIdx.x; o < k * KD; o += kLB) {
+    const int j = o / KD, d = o % KD;
+    const double cnt = tot[j * (KD + 1) + KD];
+    if (cnt > 0.0) J.centres[j * KD + d] = (float)(tot[j * (KD + 1) + d] / cnt);
   }
 }
 
@@ -586,10 +575,27 @@ __global__ __launch_bounds__(kKB) void kpp_pick_kernel(KmJob J, int r) {
   kpp_pick_block<KD>(J, blockIdx.x, r, sh);
 }
 
+template <int KD>
+__global__ __launch_bounds__(kKB) void kpp_sample_kernel(KmJob J, int r) {
+  __shared__ KppShared sh;
+  kpp_sample_block<KD>(J, r, sh);
+}
+
+__global__ __launch_bounds__(kKB) void kpp_select_kernel(KmJob J, int r) {
+  __shared__ KppShared sh;
+  kpp_select_block(J, r, sh);
+}
+
 template <int KD, int KT, bool UPDATE>
 __global__ __launch_bounds__(kLB) void lloyd_kernel(KmJob J) {
   __shared__ LloydShared sh;
   lloyd_block<KD, KT, UPDATE>(J, blockIdx.x, sh);
+}
+
+__global__ __launch_bounds__(kLB) void lloyd_finish_kernel(KmJob J) {
+  __shared__ double tot[kMaxK * 9];
+  __shared__ double part[kLB];
+  lloyd_finish(J, tot, part);
 }
 
 __device__ __forceinline__ int find_job(const int32_t* off, int njobs, int b) {
@@ -610,6 +616,22 @@ __global__ __launch_bounds__(kKB) void kpp_kernel_seg(const KmJob* __restrict__ 
   const int b = blockIdx.x - off[g];
   if (J.KD == 4) kpp_block<4>(J, b, r, sh);
   else kpp_block<8>(J, b, r, sh);
+}
+
+// One block per job.
+__global__ __launch_bounds__(kKB) void kpp_sample_kernel_seg(const KmJob* __restrict__ jobs, int r) {
+  __shared__ KppShared sh;
+  const KmJob J = jobs[blockIdx.x];
+  if (r >= J.k) return;
+  if (J.KD == 4) kpp_sample_block<4>(J, r, sh);
+  else kpp_sample_block<8>(J, r, sh);
+}
+
+__global__ __launch_bounds__(kKB) void kpp_select_kernel_seg(const KmJob* __restrict__ jobs, int r) {
+  __shared__ KppShared sh;
+  const KmJob J = jobs[blockIdx.x];
+  if (r >= J.k) return;
+  kpp_select_block(J, r, sh);
 }
 
 __global__ __launch_bounds__(kKB) void kpp_pick_kernel_seg(const KmJob* __restrict__ jobs,
@@ -640,6 +662,13 @@ __global__ __launch_bounds__(kLB) void lloyd_kernel_seg(const KmJob* __restrict_
     else if (KT == 2) lloyd_block<8, 2, UPDATE>(J, b, sh);
     else lloyd_block<8, 4, UPDATE>(J, b, sh);
   }
+}
+
+// One block per job.
+__global__ __launch_bounds__(kLB) void lloyd_finish_kernel_seg(const KmJob* __restrict__ jobs) {
+  __shared__ double tot[kMaxK * 9];
+  __shared__ double part[kLB];
+  lloyd_finish(jobs[blockIdx.x], tot, part);
 }
 
 // Normalised k-means cost of the final assignment over the eligible rows:
@@ -785,8 +814,10 @@ KmJob make_job(Context* ctx, const KmeansIO* io) {
 
 template <int KD, int KT>
 static int lloyd_all(const KmJob& J, int iters, hipStream_t s) {
-  for (int it = 0; it < iters; ++it)
+  for (int it = 0; it < iters; ++it) {
     hipLaunchKernelGGL((lloyd_kernel<KD, KT, true>), dim3(J.nblk_ll), dim3(kLB), 0, s, J);
+    hipLaunchKernelGGL(lloyd_finish_kernel, dim3(1), dim3(kLB), 0, s, J);
+  }
   hipLaunchKernelGGL((lloyd_kernel<KD, KT, false>), dim3(J.nblk_ll), dim3(kLB), 0, s, J);
   return check_hip(hipGetLastError(), "lloyd_kernel launch");
 }
@@ -797,7 +828,11 @@ static int kmeans_typed(Context* ctx, KmeansIO* io, hipStream_t s) {
   const KmJob J = make_job(ctx, io);
   for (int r = 0; r < io->k; ++r) {
     hipLaunchKernelGGL(kpp_kernel<KD>, dim3(J.nblk_pp), dim3(kKB), 0, s, J, r);
-    if (r > 0) hipLaunchKernelGGL(kpp_pick_kernel<KD>, dim3(J.nblk_pp), dim3(kKB), 0, s, J, r);
+    hipLaunchKernelGGL(kpp_sample_kernel<KD>, dim3(1), dim3(kKB), 0, s, J, r);
+    if (r > 0) {
+      hipLaunchKernelGGL(kpp_pick_kernel<KD>, dim3(J.nblk_pp), dim3(kKB), 0, s, J, r);
+      hipLaunchKernelGGL(kpp_select_kernel, dim3(1), dim3(kKB), 0, s, J, r);
+    }
   }
   int rc = check_hip(hipGetLastError(), "kpp_kernel launch");
   if (rc) return rc;
@@ -827,11 +862,16 @@ int kmeans_run_batched(Context* ctx, const KmJob* jobs_dev, const int32_t* pp_of
                        const int32_t* ll_off_dev, int ll_total, int njobs, int kmax, int iters, hipStream_t s) {
   for (int r = 0; r < kmax; ++r) {
     hipLaunchKernelGGL(kpp_kernel_seg, dim3(pp_total), dim3(kKB), 0, s, jobs_dev, pp_off_dev, njobs, r);
-    if (r > 0)
+    hipLaunchKernelGGL(kpp_sample_kernel_seg, dim3(njobs), dim3(kKB), 0, s, jobs_dev, r);
+    if (r > 0) {
       hipLaunchKernelGGL(kpp_pick_kernel_seg, dim3(pp_total), dim3(kKB), 0, s, jobs_dev, pp_off_dev, njobs, r);
+      hipLaunchKernelGGL(kpp_select_kernel_seg, dim3(njobs), dim3(kKB), 0, s, jobs_dev, r);
+    }
   }
-  for (int it = 0; it < iters; ++it)
+  for (int it = 0; it < iters; ++it) {
     hipLaunchKernelGGL(lloyd_kernel_seg<true>, dim3(ll_total), dim3(kLB), 0, s, jobs_dev, ll_off_dev, njobs);
+    hipLaunchKernelGGL(lloyd_finish_kernel_seg, dim3(njobs), dim3(kLB), 0, s, jobs_dev);
+  }
   hipLaunchKernelGGL(lloyd_kernel_seg<false>, dim3(ll_total), dim3(kLB), 0, s, jobs_dev, ll_off_dev, njobs);
   return check_hip(hipGetLastError(), "batched k-means launch");
 }

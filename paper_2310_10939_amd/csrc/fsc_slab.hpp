@@ -50,8 +50,11 @@ __device__ __forceinline__ int32_t diag_start(const int32_t* base, int32_t lane_
 }
 
 // Adds the (tile T, slab p) region's per-row sums to acc (LDS, R x LH): one
-// lane per sorted row, kU nonzeros in flight per lane.
-template <int kU, bool UNIT, class Op>
+// lane per sorted row, kU nonzeros in flight per row.  With J = 2 a lane takes
+// two rows at once, positions s0 + lane and s0 + kBlock + lane, whose loads
+// are all issued together (rows are sorted by length, so the first is never
+// shorter); each row's sum is built in the same order either way.
+template <int kU, int J, bool UNIT, class Op>
 __device__ __forceinline__ void slab_region_as(const Op& op, const SlabArgs& sb, int32_t T, int p, int32_t r0,
                                                int32_t R, typename Op::A* acc) {
   constexpr int LH = Op::LH;
@@ -66,49 +69,57 @@ __device__ __forceinline__ void slab_region_as(const Op& op, const SlabArgs& sb,
   // diagonal starts 0..63 live in the lanes of every wave
   const int32_t bl = lane <= maxlen ? base[lane] : 0;
   const int32_t active = diag_start(base, bl, 1);  // rows with a nonempty segment
-  for (int32_t s0 = wave * FSC_WAVE; s0 < active; s0 += kBlock) {
-    const int32_t i = s0 + lane;
-    const int rl = i < active ? (int)perm[i] : 0;
-    A a[LH];
+  for (int32_t s0 = wave * FSC_WAVE; s0 < active; s0 += J * kBlock) {
+    const int32_t i0 = s0 + lane;
+    const int32_t i1 = i0 + kBlock;
+    const int rl0 = i0 < active ? (int)perm[i0] : 0;
+    const int rl1 = J == 2 && i1 < active ? (int)perm[i1] : 0;
+    A a0[LH], a1[LH];
 #pragma unroll
-    for (int q = 0; q < LH; ++q) a[q] = A(0);
+    for (int q = 0; q < LH; ++q) a0[q] = a1[q] = A(0);
     int32_t b0 = 0;
     for (int32_t k = 0; k < maxlen; k += kU) {
-      int32_t off[kU];
+      int32_t off0[kU], off1[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int32_t kk = k + u;
-        off[u] = -1;
+        off0[u] = off1[u] = -1;
         if (kk < maxlen) {
-          const int32_t b1 = diag_start(base, bl, kk + 1);
-          if (i < b1 - b0) off[u] = b0 + i;
+          const int32_t b1 = diag_start(base, bl, kk + 1);  // diagonal kk holds positions [0, b1 - b0)
+          if (i0 < b1 - b0) off0[u] = b0 + i0;
+          if (J == 2 && i1 < b1 - b0) off1[u] = b0 + i1;
           b0 = b1;
         }
       }
-      op.template accumulate_at<kU, UNIT>(sb.scol, reg, off, a);
+      if constexpr (J == 2) op.template accumulate_at2<kU, UNIT>(sb.scol, reg, off0, off1, a0, a1);
+      else op.template accumulate_at<kU, UNIT>(sb.scol, reg, off0, a0);
       // rows are sorted by length: once diagonal k+kU is no longer than s0
       // rows, the whole slice is done
       const int32_t kn = k + kU;
       if (kn < maxlen && s0 >= diag_start(base, bl, kn + 1) - b0) break;
     }
-    if (i < active) {
+    if (i0 < active) {
 #pragma unroll
-      for (int q = 0; q < LH; ++q) acc[rl * LH + q] += a[q];
+      for (int q = 0; q < LH; ++q) acc[rl0 * LH + q] += a0[q];
+    }
+    if (J == 2 && i1 < active) {
+#pragma unroll
+      for (int q = 0; q < LH; ++q) acc[rl1 * LH + q] += a1[q];
     }
   }
 }
 
 // A tile whose weights are all 1 takes the code path without weight loads.
-template <int kU, class Op>
+template <int kU, int J, class Op>
 __device__ __forceinline__ void slab_region(const Op& op, const SlabArgs& sb, int32_t T, int p, int32_t r0,
                                             int32_t R, typename Op::A* acc) {
-  if (sb.tunit[T]) slab_region_as<kU, true>(op, sb, T, p, r0, R, acc);
-  else slab_region_as<kU, false>(op, sb, T, p, r0, R, acc);
+  if (sb.tunit[T]) slab_region_as<kU, J, true>(op, sb, T, p, r0, R, acc);
+  else slab_region_as<kU, J, false>(op, sb, T, p, r0, R, acc);
 }
 
 // Phase form: each block takes whole tiles and walks the slabs in order, so
 // at any time the blocks gather from about one slab.
-template <int kU, class Op>
+template <int kU, int J, class Op>
 __global__ __launch_bounds__(kBlock) void slab_kernel(Op op_in, TileArgs ta, SlabArgs sb, StatsArgs sa) {
   constexpr int LH = Op::LH;
   using A = typename Op::A;
@@ -125,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void slab_kernel(Op op_in, TileArgs ta, Sla
     for (int i = threadIdx.x; i < R * LH; i += kBlock) acc[i] = A(0);
     __syncthreads();
     for (int p = 0; p < sb.nslab; ++p) {
-      slab_region<kU>(op, sb, T, p, r0, R, acc);
+      slab_region<kU, J>(op, sb, T, p, r0, R, acc);
       __syncthreads();  // the next phase may give a row to another wave
     }
     // statistics stay out of registers during the phases: each tile's are
@@ -182,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void slab_xcd_kernel(Op op_in, TileArgs ta,
       const int32_t R = min(sb.rows, n - r0);
       for (int i = threadIdx.x; i < R * LH; i += kBlock) acc[i] = A(0);
       __syncthreads();
-      slab_region<kU>(op, sb, T, p, r0, R, acc);
+      slab_region<kU, 1>(op, sb, T, p, r0, R, acc);
       __syncthreads();
       // part: groups of 64 rows, each holding its nslab slabs' 64 x LH sums
       // in a row, so every write here and every read of the reduce is

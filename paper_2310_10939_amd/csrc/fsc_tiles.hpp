@@ -177,6 +177,53 @@ struct StepOp {
       gather_rows<S, W, LH_, U>(zin, c, w, acc);
     }
   }
+  // Two rows at once (offsets off0 into acc0, off1 into acc1): every index,
+  // weight and row load of both is issued before the first use; each row's
+  // sum is built in the same order as by accumulate_at.
+  template <int U, bool UNIT>
+  __device__ __forceinline__ void accumulate_at2(const int32_t* scol, int64_t reg, const int32_t* off0,
+                                                 const int32_t* off1, A* acc0, A* acc1) const {
+    const int32_t* cp = scol + reg;
+    int32_t c[2 * U];
+    A w[2 * U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = off0[u] >= 0 ? nt_load(cp + off0[u]) : -1;
+      c[U + u] = off1[u] >= 0 ? nt_load(cp + off1[u]) : -1;
+    }
+    if constexpr (std::is_void<W>::value || UNIT) {
+#pragma unroll
+      for (int u = 0; u < 2 * U; ++u) w[u] = A(1);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        w[u] = off0[u] >= 0 ? load_weight<W, A>(sval + reg, off0[u]) : A(0);
+        w[U + u] = off1[u] >= 0 ? load_weight<W, A>(sval + reg, off1[u]) : A(0);
+      }
+    }
+    A zr[2 * U][LH_];
+#pragma unroll
+    for (int u = 0; u < 2 * U; ++u) {
+      if (c[u] >= 0) {
+        rowio<S, LH_>::load(zin + (int64_t)c[u] * LH_, zr[u]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < LH_; ++q) zr[u][q] = A(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < LH_; ++q) {
+        if constexpr (std::is_void<W>::value || UNIT) {
+          acc0[q] += zr[u][q];
+          acc1[q] += zr[U + u][q];
+        } else {
+          acc0[q] += w[u] * zr[u][q];
+          acc1[q] += w[U + u] * zr[U + u][q];
+        }
+      }
+  }
   __device__ __forceinline__ void prefetch(int32_t r, Pre& p) const {
     rowio<S, LH_>::load(zin + (int64_t)r * LH_, p.z);
     p.h = hinv[r];
@@ -255,7 +302,7 @@ __device__ __forceinline__ void short_tile(const Op& op, const TileArgs& ta, con
 }
 
 // ---------------------------------------------------------------------------
-// Column statistics, finished by the last block of a step.
+// Column statistics of a step, finished by one block after the step.
 // state: [0..LH) prev_sq, [LH..2LH) cum (product of applied scales),
 //        [2LH..3LH) next scale (FP64), [3LH..4LH) next scale in the step's
 //        accumulation type.
@@ -320,28 +367,26 @@ __device__ void stats_finish(const StatsArgs& sa, int grid) {
   }
 }
 
-// Writes this block's partial statistics; the last block to arrive finishes
-// them.  Called by every thread of every block.
+// Writes this block's partial statistics.  They are finished by
+// stats_finish_kernel, launched after the kernel on the same stream: a
+// last-block finish inside the kernel would need a device-scope release by
+// every block, which writes back its XCD's L2 and cost 15% of a power step.
+// Called by every thread of every block.
 template <int LH>
 __device__ __forceinline__ void stats_epilogue(const StatsArgs& sa, const double* st) {
   __shared__ double red[kBlock / FSC_WAVE];
-  __shared__ int is_last;
 #pragma unroll
   for (int q = 0; q < 2 * LH; ++q) {
     const double v = block_sum<kBlock>(st[q], red);
     if (threadIdx.x == 0) sa.partials[(int64_t)blockIdx.x * 2 * LH + q] = v;
   }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(sa.counter, 1);
-    is_last = (prev == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (is_last) {
-    __threadfence();
-    stats_finish<LH>(sa, gridDim.x);
-    if (threadIdx.x == 0) *sa.counter = 0;
-  }
+}
+
+// One block: the statistics of a step from the `grid` partials of the kernel
+// that wrote them (in a fixed order, so deterministic).
+template <int LH>
+__global__ __launch_bounds__(kBlock) void stats_finish_kernel(StatsArgs sa, int grid) {
+  stats_finish<LH>(sa, grid);
 }
 
 // ---------------------------------------------------------------------------
