@@ -8,10 +8,10 @@
 // Seeding (greedy k-means++): per centre r >= 1, a pass over the rows and a
 // one-block kernel, twice.  First each block owns a contiguous run of rows,
 // updates D2(v) = min(D2(v), ||p_v - c_{r-1}||^2) and writes the FP64 sum of
-// its weights; then one block draws L = 2 + floor(ln k) candidates: for each
-// it scans the block sums, locates the block holding the sample
-// u_j * sum(D2) and rescans that block's rows (same summation order) to find
-// the sampled row.  Second, each block sums, per candidate,
+// its weights; then L = 2 + floor(ln k) blocks draw one candidate each: each
+// scans the block sums, locates the block holding the sample u_j * sum(D2)
+// and rescans that block's rows (same summation order) to find the sampled
+// row.  Second, each block sums, per candidate,
 // min(D2(v), ||p_v - cand_j||^2) over its eligible rows, and one block keeps
 // the candidate with the smallest total (ties to the lower j).  Centre 0 is
 // one uniform draw over the eligible rows.  No host round trip, and no block
@@ -242,12 +242,14 @@ __device__ void kpp_block(const KmJob& J, int blk, int r, KppShared& sh) {
   }
 }
 
-// Phase B of round r (one block per job, after phase A on the same stream):
-// the total weight, then each draw u * total located by kpp_sample.
+// Phase B of round r (one block per candidate j of each job, after phase A on
+// the same stream): the total weight, then the draw u_j * total located by
+// kpp_sample.
 template <int KD>
-__device__ void kpp_sample_block(const KmJob& J, int r, KppShared& sh) {
+__device__ void kpp_sample_block(const KmJob& J, int r, int j, KppShared& sh) {
   double* sbuf = sh.sbuf;
   const int first = (r == 0);
+  if (j >= (first ? 1 : J.trials)) return;
   const int nblk = J.nblk_pp;
   const float* pts = J.pts;
   double total = 0.0;
@@ -257,25 +259,22 @@ __device__ void kpp_sample_block(const KmJob& J, int r, KppShared& sh) {
     block_scan_inclusive<kKB>(b < nblk ? J.bsum[b] : 0.0, sbuf, &ct);
     total += ct;
   }
-  const int ntrial = first ? 1 : J.trials;
-  int64_t pick = -1;
-  for (int j = 0; j < ntrial; ++j) {
-    if (total > 0.0) {
-      // centre 0: stream 1, counter 0; candidate j of round r: stream 3,
-      // counter r * L + j
-      const uint32_t ctr = first ? 0u : (uint32_t)(r * J.trials + j);
-      const u32x4 rr = philox4x32_10(u32x4{ctr, 0u, 0u, first ? 1u : 3u}, J.k0, J.k1);
-      pick = kpp_sample<KD>(J, first, uniform53(rr.x, rr.y) * total, sh);
-    } else {
-      if (j == 0) pick = kpp_unchosen(J, r, sh);  // every candidate is this row
-    }
-    if (first) {
-      if (threadIdx.x == 0) J.chosen[r] = (int32_t)pick;
-      if (threadIdx.x < KD) J.centres[r * KD + threadIdx.x] = pts[pick * KD + threadIdx.x];
-    } else {
-      if (threadIdx.x == 0) J.cand_row[j] = (int32_t)pick;
-      if (threadIdx.x < KD) J.cand[j * KD + threadIdx.x] = pts[pick * KD + threadIdx.x];
-    }
+  int64_t pick;
+  if (total > 0.0) {
+    // centre 0: stream 1, counter 0; candidate j of round r: stream 3,
+    // counter r * L + j
+    const uint32_t ctr = first ? 0u : (uint32_t)(r * J.trials + j);
+    const u32x4 rr = philox4x32_10(u32x4{ctr, 0u, 0u, first ? 1u : 3u}, J.k0, J.k1);
+    pick = kpp_sample<KD>(J, first, uniform53(rr.x, rr.y) * total, sh);
+  } else {
+    pick = kpp_unchosen(J, r, sh);  // every candidate is this row
+  }
+  if (first) {
+    if (threadIdx.x == 0) J.chosen[r] = (int32_t)pick;
+    if (threadIdx.x < KD) J.centres[r * KD + threadIdx.x] = pts[pick * KD + threadIdx.x];
+  } else {
+    if (threadIdx.x == 0) J.cand_row[j] = (int32_t)pick;
+    if (threadIdx.x < KD) J.cand[j * KD + threadIdx.x] = pts[pick * KD + threadIdx.x];
   }
 }
 
@@ -578,7 +577,7 @@ __global__ __launch_bounds__(kKB) void kpp_pick_kernel(KmJob J, int r) {
 template <int KD>
 __global__ __launch_bounds__(kKB) void kpp_sample_kernel(KmJob J, int r) {
   __shared__ KppShared sh;
-  kpp_sample_block<KD>(J, r, sh);
+  kpp_sample_block<KD>(J, r, blockIdx.x, sh);
 }
 
 __global__ __launch_bounds__(kKB) void kpp_select_kernel(KmJob J, int r) {
@@ -618,13 +617,15 @@ __global__ __launch_bounds__(kKB) void kpp_kernel_seg(const KmJob* __restrict__ 
   else kpp_block<8>(J, b, r, sh);
 }
 
-// One block per job.
+// One block per (job, candidate): block b is candidate b % kMaxTrials of job
+// b / kMaxTrials.
 __global__ __launch_bounds__(kKB) void kpp_sample_kernel_seg(const KmJob* __restrict__ jobs, int r) {
   __shared__ KppShared sh;
-  const KmJob J = jobs[blockIdx.x];
+  const KmJob J = jobs[blockIdx.x / kMaxTrials];
   if (r >= J.k) return;
-  if (J.KD == 4) kpp_sample_block<4>(J, r, sh);
-  else kpp_sample_block<8>(J, r, sh);
+  const int j = blockIdx.x % kMaxTrials;
+  if (J.KD == 4) kpp_sample_block<4>(J, r, j, sh);
+  else kpp_sample_block<8>(J, r, j, sh);
 }
 
 __global__ __launch_bounds__(kKB) void kpp_select_kernel_seg(const KmJob* __restrict__ jobs, int r) {
@@ -828,7 +829,7 @@ static int kmeans_typed(Context* ctx, KmeansIO* io, hipStream_t s) {
   const KmJob J = make_job(ctx, io);
   for (int r = 0; r < io->k; ++r) {
     hipLaunchKernelGGL(kpp_kernel<KD>, dim3(J.nblk_pp), dim3(kKB), 0, s, J, r);
-    hipLaunchKernelGGL(kpp_sample_kernel<KD>, dim3(1), dim3(kKB), 0, s, J, r);
+    hipLaunchKernelGGL(kpp_sample_kernel<KD>, dim3(r == 0 ? 1 : J.trials), dim3(kKB), 0, s, J, r);
     if (r > 0) {
       hipLaunchKernelGGL(kpp_pick_kernel<KD>, dim3(J.nblk_pp), dim3(kKB), 0, s, J, r);
       hipLaunchKernelGGL(kpp_select_kernel, dim3(1), dim3(kKB), 0, s, J, r);
@@ -862,7 +863,7 @@ int kmeans_run_batched(Context* ctx, const KmJob* jobs_dev, const int32_t* pp_of
                        const int32_t* ll_off_dev, int ll_total, int njobs, int kmax, int iters, hipStream_t s) {
   for (int r = 0; r < kmax; ++r) {
     hipLaunchKernelGGL(kpp_kernel_seg, dim3(pp_total), dim3(kKB), 0, s, jobs_dev, pp_off_dev, njobs, r);
-    hipLaunchKernelGGL(kpp_sample_kernel_seg, dim3(njobs), dim3(kKB), 0, s, jobs_dev, r);
+    hipLaunchKernelGGL(kpp_sample_kernel_seg, dim3(njobs * kMaxTrials), dim3(kKB), 0, s, jobs_dev, r);
     if (r > 0) {
       hipLaunchKernelGGL(kpp_pick_kernel_seg, dim3(pp_total), dim3(kKB), 0, s, jobs_dev, pp_off_dev, njobs, r);
       hipLaunchKernelGGL(kpp_select_kernel_seg, dim3(njobs), dim3(kKB), 0, s, jobs_dev, r);

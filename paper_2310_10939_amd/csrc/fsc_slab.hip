@@ -99,7 +99,7 @@ __global__ __launch_bounds__(1024) void slab_scan_kernel(const int64_t* __restri
 
 constexpr int kBuild = 1024;  // threads of the build kernel: one per row of a tile
 constexpr int kBuildU = 8;    // nonzeros of a row loaded at once
-constexpr int kStage = 6144;  // entries of the LDS staging buffer
+constexpr int kStageWords = 12288;  // 48 KiB of LDS staging: column indices, then weights when loaded
 
 template <typename W>
 __global__ __launch_bounds__(kBuild) void slab_build_kernel(
@@ -117,8 +117,8 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   __shared__ int64_t regL[kSlabMax + 1];
   __shared__ int32_t scan32[kBuild / FSC_WAVE];
   using WS = typename std::conditional<std::is_void<W>::value, char, W>::type;
-  __shared__ int32_t stcol[kStage];                // staging of a group of regions
-  __shared__ WS stval[std::is_void<W>::value ? 1 : kStage];
+  __shared__ int32_t stage[kStageWords];           // staging of a group of regions
+  __shared__ int tile_unit;
   const int32_t T = blockIdx.x;
   const int32_t r0 = T * rows;
   const int32_t R = min(rows, n - r0);
@@ -132,15 +132,30 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   const bool shortrow = rl < R && b - a <= kSlabLong;
   for (int i = threadIdx.x; i < nslab * R; i += kBuild) cnt[i] = 0;
   __syncthreads();
-  // segment length of every short row in every slab
+  // segment length of every short row in every slab, and whether every
+  // weight of the tile's short rows is exactly 1
+  int unit = 1;
   if (shortrow) {
     for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
       int32_t c[kBuildU];
 #pragma unroll
       for (int u = 0; u < kBuildU; ++u) c[u] = j0 + u < b ? col[j0 + u] : 0;
+      if constexpr (!std::is_void<W>::value) {
+#pragma unroll
+        for (int u = 0; u < kBuildU; ++u)
+          if (j0 + u < b && weight<W, float>::get(val, j0 + u) != 1.0f) unit = 0;
+      }
 #pragma unroll
       for (int u = 0; u < kBuildU; ++u)
         if (j0 + u < b) cnt[slab_of(c[u], S, last) * R + rl] += 1;
+    }
+  }
+  {
+    int32_t nonunit;
+    block_scan_inclusive<kBuild, int32_t>(unit ? 0 : 1, scan32, &nonunit);
+    if (threadIdx.x == 0) {
+      tile_unit = nonunit == 0;
+      tunit[T] = nonunit == 0 ? 1 : 0;  // such a tile skips the weight stream, so its weights are not copied
     }
   }
   __syncthreads();
@@ -221,14 +236,18 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   // row's segment), a group of consecutive slabs at a time: the group's
   // regions are contiguous, so they are assembled in LDS and written out in
   // one coalesced pass.  A region too large for the buffer is written
-  // directly.
-  int unit = 1;  // every weight of this thread's row is exactly 1
+  // directly.  Weights are copied only for a tile that loads them, so a
+  // unit-weight tile stages twice the column indices per pass.
+  const bool copy_w = !std::is_void<W>::value && !tile_unit;
+  const int32_t cap = copy_w ? (int32_t)(kStageWords * 4 / (4 + sizeof(WS))) : kStageWords;
+  int32_t* stcol = stage;
+  WS* stval = reinterpret_cast<WS*>(stage + cap);
   for (int p0 = 0; p0 < nslab;) {
     int p1 = p0 + 1;
-    while (p1 < nslab && regL[p1 + 1] - regL[p0] <= kStage) ++p1;
+    while (p1 < nslab && regL[p1 + 1] - regL[p0] <= cap) ++p1;
     const int64_t g0 = regL[p0];
     const int32_t gsz = (int32_t)(regL[p1] - g0);
-    const bool staged = gsz <= kStage;
+    const bool staged = gsz <= cap;
     for (int i = p0 * R + threadIdx.x; i < p1 * R; i += kBuild) cnt[i] = 0;
     __syncthreads();
     if (shortrow) {
@@ -246,10 +265,11 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
           if (staged) stcol[off] = c[u];
           else scol[g0 + off] = c[u];
           if constexpr (!std::is_void<W>::value) {
-            const W w = val[j0 + u];
-            if (staged) stval[off] = w;
-            else sval[g0 + off] = w;
-            if (weight<W, float>::get(&w, 0) != 1.0f) unit = 0;
+            if (copy_w) {
+              const W w = val[j0 + u];
+              if (staged) stval[off] = w;
+              else sval[g0 + off] = w;
+            }
           }
         }
       }
@@ -258,17 +278,13 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     if (staged) {
       for (int32_t e = threadIdx.x; e < gsz; e += kBuild) {
         scol[g0 + e] = stcol[e];
-        if constexpr (!std::is_void<W>::value) sval[g0 + e] = stval[e];
+        if constexpr (!std::is_void<W>::value) {
+          if (copy_w) sval[g0 + e] = stval[e];
+        }
       }
     }
     __syncthreads();
     p0 = p1;
-  }
-  // a tile whose short rows all have unit weights skips the weight stream
-  {
-    int32_t tu;
-    block_scan_inclusive<kBuild, int32_t>(unit ? 0 : 1, scan32, &tu);
-    if (threadIdx.x == 0) tunit[T] = tu == 0 ? 1 : 0;
   }
   // long rows: chunks of kSlabChunk nonzeros of the original CSR
   {
