@@ -541,6 +541,7 @@ static int filter_front(Context* ctx, const fsc_csr* g, int k, int l, uint64_t s
                         size_t extra, EmbedIO* io, Arena* arena, FilterWS* w, hipStream_t s) {
   int rc;
   if ((rc = prepare_embed(ctx, g, l, 0, seed, o, filter_extra_bytes(ctx, g, l) + extra, io, arena))) return rc;
+  io->need_tiles = 1;  // the Chebyshev steps run the tile kernel
   filter_bind(ctx, arena, io, w);
   if (arena->used > arena->size) return fail(FSC_E_NOMEM, "workspace layout overflow");
   if ((rc = embed_run(ctx, io, s))) return rc;

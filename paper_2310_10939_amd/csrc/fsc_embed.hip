@@ -382,8 +382,12 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
   const int32_t nb = io->plan.nb;
   const int32_t NB = io->plan.tile_nnz;
   int rc;
+  // Graphs whose steps take the slab form get their degrees from the slab
+  // builder (it reads every weight anyway) and need no tile plan unless a
+  // later tile kernel asks for one.
+  const bool slab_steps = io->slab.enabled && !std::is_same<A, double>::value;
   // tile plan
-  {
+  if (!slab_steps || io->need_tiles) {
     const int blocks = (nb + 255) / 256;
     hipLaunchKernelGGL(plan_buckets, dim3(blocks), dim3(256), 0, s, g->row_ptr, n, nb, NB, io->plan.desc,
                        io->plan.nch);
@@ -423,7 +427,10 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
   sa.renorm = io->renorm;
   sa.acc_is_double = std::is_same<A, double>::value ? 1 : 0;
   // degrees (FP64), 1/(2d), d^{-1/2}, eligibility
-  {
+  if (slab_steps) {
+    // column-slab plan: its own tiles and long-row chunks for the steps
+    if ((rc = slab_build(ctx, io, s))) return rc;
+  } else {
     DegreeOp<W, A> op;
     op.val = reinterpret_cast<const W*>(g->val);
     op.deg = io->deg;
@@ -445,10 +452,7 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
       if ((rc = check_hip(hipGetLastError(), "stats_finish launch"))) return rc;
     }
   }
-  if (!io->slab.enabled || std::is_same<A, double>::value)
-    return run_steps<S, W, LH>(ctx, io, ta, nullptr, sa, s, stats);
-  // column-slab plan: its own tiles and long-row chunks for the steps
-  if ((rc = slab_build(ctx, io, s))) return rc;
+  if (!slab_steps) return run_steps<S, W, LH>(ctx, io, ta, nullptr, sa, s, stats);
   const SlabPlan& sp = io->slab;
   TileArgs ts = ta;
   ts.nb = 0;

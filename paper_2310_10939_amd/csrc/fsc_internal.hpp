@@ -167,6 +167,7 @@ struct EmbedIO {
   const double* x0;
   double* sqnorm_trace;
   double* rayleigh_trace;
+  int need_tiles;   // 1: build the tile plan even when the steps take the slab form (later tile kernels use it)
   // workspace (filled by embed_workspace)
   double* deg;
   void* hinv;       // float[n] or double[n]

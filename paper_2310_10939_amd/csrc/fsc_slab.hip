@@ -31,6 +31,44 @@ __device__ __forceinline__ int slab_of(int32_t c, int32_t S, int last) {
   return p > last ? last : p;
 }
 
+// The per-vertex quantities of the degree pass (Sec. 2), written by the
+// builders for the short rows (which they read anyway) and by
+// slab_long_degree_kernel for the long ones: d = sum of the row's weights
+// (FP64), 1/(2d), d^{-1/2} (0 for an isolated vertex) and the k-means
+// eligibility d > 0.
+struct DegreeOut {
+  double* deg;
+  float* hinv;
+  double* isq;
+  uint8_t* elig;
+};
+
+__device__ __forceinline__ void write_degree(const DegreeOut& o, int32_t r, double d) {
+  o.deg[r] = d;
+  o.hinv[r] = d > 0.0 ? static_cast<float>(0.5 / d) : 0.f;
+  o.isq[r] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  o.elig[r] = d > 0.0 ? 1 : 0;
+}
+
+// Degrees of the long rows: one block per row (its first chunk names it).
+template <typename W>
+__global__ __launch_bounds__(256) void slab_long_degree_kernel(const int64_t* __restrict__ row_ptr,
+                                                               const W* __restrict__ val,
+                                                               const LongChunk* __restrict__ chunks,
+                                                               const int32_t* __restrict__ meta, DegreeOut o) {
+  __shared__ double red[256 / FSC_WAVE];
+  const int32_t nch = meta[0];
+  for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const LongChunk ch = chunks[c];
+    if (ch.index != 0) continue;
+    const int64_t a = row_ptr[ch.row], b = row_ptr[ch.row + 1];
+    double sum = 0.0;
+    for (int64_t j = a + threadIdx.x; j < b; j += 256) sum += weight<W, double>::get(val, j);
+    sum = block_sum<256>(sum, red);
+    if (threadIdx.x == 0) write_degree(o, ch.row, sum);
+  }
+}
+
 __global__ __launch_bounds__(256) void slab_count_kernel(const int64_t* __restrict__ row_ptr, int32_t n,
                                                          int32_t rows, int64_t* __restrict__ tshort,
                                                          int32_t* __restrict__ tlong, int32_t* __restrict__ tchunks) {
@@ -107,7 +145,7 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     int32_t rows, int32_t S, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
     const int32_t* __restrict__ coff, int32_t* __restrict__ scol, W* __restrict__ sval, uint16_t* __restrict__ sperm,
     int32_t* __restrict__ sbase, int32_t* __restrict__ smax, int64_t* __restrict__ sreg,
-    LongChunk* __restrict__ chunks, uint8_t* __restrict__ tunit) {
+    LongChunk* __restrict__ chunks, uint8_t* __restrict__ tunit, DegreeOut dout) {
   __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
   __shared__ uint16_t spos[kSlabMax * kSlabRows];  // sorted position of each row per slab
   __shared__ int32_t wcnt[kBuild / FSC_WAVE * (kSlabLong + 1)];  // per wave and length
@@ -134,21 +172,26 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   __syncthreads();
   // segment length of every short row in every slab, and whether every
   // weight of the tile's short rows is exactly 1
+  // (and the row's degree: its weights are read here anyway)
   int unit = 1;
   if (shortrow) {
+    double dsum = 0.0;
     for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
       int32_t c[kBuildU];
 #pragma unroll
       for (int u = 0; u < kBuildU; ++u) c[u] = j0 + u < b ? col[j0 + u] : 0;
-      if constexpr (!std::is_void<W>::value) {
 #pragma unroll
-        for (int u = 0; u < kBuildU; ++u)
-          if (j0 + u < b && weight<W, float>::get(val, j0 + u) != 1.0f) unit = 0;
+      for (int u = 0; u < kBuildU; ++u) {
+        if (j0 + u >= b) continue;
+        const float w = weight<W, float>::get(val, j0 + u);
+        if (w != 1.0f) unit = 0;
+        dsum += (double)w;
       }
 #pragma unroll
       for (int u = 0; u < kBuildU; ++u)
         if (j0 + u < b) cnt[slab_of(c[u], S, last) * R + rl] += 1;
     }
+    write_degree(dout, r0 + rl, dsum);
   }
   {
     int32_t nonunit;
@@ -323,7 +366,7 @@ __global__ __launch_bounds__(kBuild) void slab_wave_build_kernel(
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const W* __restrict__ val, int32_t n,
     int32_t rows, int32_t S, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
     const int32_t* __restrict__ coff, int32_t* __restrict__ scol, W* __restrict__ sval, uint8_t* __restrict__ wlen,
-    int64_t* __restrict__ gbase, uint8_t* __restrict__ gunit, LongChunk* __restrict__ chunks) {
+    int64_t* __restrict__ gbase, uint8_t* __restrict__ gunit, LongChunk* __restrict__ chunks, DegreeOut dout) {
   __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
   __shared__ uint16_t spos[kSlabMax * kSlabRows];  // start of each (row, slab) segment within its group
   __shared__ int32_t scan32[kBuild / FSC_WAVE];
@@ -343,14 +386,19 @@ __global__ __launch_bounds__(kBuild) void slab_wave_build_kernel(
   for (int i = threadIdx.x; i < nslab * R; i += kBuild) cnt[i] = 0;
   __syncthreads();
   if (shortrow) {
+    double dsum = 0.0;
     for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
       int32_t c[kBuildU];
 #pragma unroll
       for (int u = 0; u < kBuildU; ++u) c[u] = j0 + u < b ? col[j0 + u] : 0;
 #pragma unroll
-      for (int u = 0; u < kBuildU; ++u)
-        if (j0 + u < b) cnt[slab_of(c[u], S, last) * R + rl] += 1;
+      for (int u = 0; u < kBuildU; ++u) {
+        if (j0 + u >= b) continue;
+        dsum += weight<W, double>::get(val, j0 + u);
+        cnt[slab_of(c[u], S, last) * R + rl] += 1;
+      }
     }
+    write_degree(dout, r0 + rl, dsum);
   }
   // start of this row's group: the short-row nonzeros before the group
   int64_t gb;
@@ -556,33 +604,40 @@ int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
 }
 
 template <typename W>
-static void launch_build(const fsc_csr* g, SlabPlan& sp, hipStream_t s) {
+static void launch_build(const fsc_csr* g, SlabPlan& sp, const DegreeOut& dout, hipStream_t s) {
   if (sp.wave) {
     hipLaunchKernelGGL((slab_wave_build_kernel<W>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
                        reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
-                       sp.coff, sp.scol, reinterpret_cast<W*>(sp.sval), sp.wlen, sp.gbase, sp.gunit, sp.chunks);
-    return;
-  }
+                       sp.coff, sp.scol, reinterpret_cast<W*>(sp.sval), sp.wlen, sp.gbase, sp.gunit, sp.chunks, dout);
+  } else {
   hipLaunchKernelGGL((slab_build_kernel<W>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
                      reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
                      sp.coff, sp.scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax, sp.sreg,
-                     sp.chunks, sp.tunit);
+                     sp.chunks, sp.tunit, dout);
+  }
+  hipLaunchKernelGGL((slab_long_degree_kernel<W>), dim3(256), dim3(256), 0, s, g->row_ptr,
+                     reinterpret_cast<const W*>(g->val), sp.chunks, sp.meta, dout);
 }
 
 int slab_build(Context*, EmbedIO* io, hipStream_t s) {
   SlabPlan& sp = io->slab;
   const fsc_csr* g = io->g;
+  DegreeOut dout;
+  dout.deg = io->deg;
+  dout.hinv = reinterpret_cast<float*>(io->hinv);
+  dout.isq = io->isq;
+  dout.elig = io->elig;
   const int32_t n = (int32_t)g->n;
   hipLaunchKernelGGL(slab_count_kernel, dim3(sp.ntiles), dim3(256), 0, s, g->row_ptr, n, sp.rows, sp.tshort,
                      sp.tlong, sp.tchunks);
   hipLaunchKernelGGL(slab_scan_kernel, dim3(1), dim3(1024), 0, s, sp.tshort, sp.tlong, sp.tchunks, sp.ntiles,
                      sp.toff, sp.loff, sp.coff, sp.meta);
   if (!g->val) {
-    launch_build<void>(g, sp, s);
+    launch_build<void>(g, sp, dout, s);
   } else if (g->val_dtype == FSC_F32) {
-    launch_build<float>(g, sp, s);
+    launch_build<float>(g, sp, dout, s);
   } else if (g->val_dtype == FSC_BF16) {
-    launch_build<bf16_t>(g, sp, s);
+    launch_build<bf16_t>(g, sp, dout, s);
   } else {
     return fail(FSC_E_UNSUPPORTED, "the slab form takes f32 or bf16 weights");
   }
