@@ -232,11 +232,6 @@ __global__ __launch_bounds__(kBlock) void bpoints_kernel(const BGraph* __restric
   }
 }
 
-__global__ void bfill_i32(int32_t* p, int64_t count) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0;
-}
-
 // ===========================================================================
 // Host side
 // ===========================================================================
@@ -426,7 +421,6 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   add(8 * (G2 + 4) * 4);             // boff, noff, toffs (per class), toff
   add(4 * (G2 + 1));                 // order
   add(4 * (G2 + 1) * 2);             // pp_off, ll_off
-  add(4 * 4 * (G2 + 1));             // counters
   for (int g : bl) {
     const Host& x = h[g];
     add(sizeof(TileDesc) * x.nb);
@@ -474,7 +468,6 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   int32_t* d_order = a.take<int32_t>(G2 + 1);
   int32_t* d_ppoff = a.take<int32_t>(G2 + 1);
   int32_t* d_lloff = a.take<int32_t>(G2 + 1);
-  int32_t* d_counters = a.take<int32_t>(4 * (G2 + 1));
 
   std::vector<BGraph> bg(G2);
   std::vector<KmJob> jobs(G2);
@@ -524,7 +517,6 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     J.centres = a.take<float>(64 * x.KD);
     J.cpart = a.take<double>((size_t)J.nblk_ll * 64 * (x.KD + 1));
     J.chosen = a.take<int32_t>(64);
-    J.counter = d_counters + 4 * bi;
     J.labels = labels + loff[g];
     J.k0 = b.k0;
     J.k1 = b.k1;
@@ -591,8 +583,6 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   const int cap = ctx->num_cu * ctx->tune.blocks_per_cu;
   // the shared per-level launches of the smaller graphs
   auto shared = [&](hipStream_t s) -> int {
-    hipLaunchKernelGGL(bfill_i32, dim3(grid_for((4 * G2 + 255) / 256, 1024)), dim3(256), 0, s, d_counters,
-                       (int64_t)4 * G2);
     hipLaunchKernelGGL(bplan_kernel, dim3(grid_for((boff[G2] + 255) / 256, 8192)), dim3(256), 0, s, d_graphs,
                        d_boff, G2);
     hipLaunchKernelGGL(bdegree_kernel, dim3(grid_for(toff[G2], cap)), dim3(kBlock), 0, s, d_graphs, d_toff, G2);

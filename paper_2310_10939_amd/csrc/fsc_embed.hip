@@ -227,7 +227,7 @@ size_t embed_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, int ve
   b += align_up(n * 8) * 2 + align_up(n * ae) + align_up(n);        // deg, isq, hinv, elig
   b += 2 * align_up(n * LH * se);                                   // z ping-pong
   b += align_up((size_t)kMaxGrid * 2 * LH * 8);                     // partials
-  b += align_up((5 * LH + 8) * 8);                                  // state + counter
+  b += align_up((5 * LH + 8) * 8);                                  // state
   b += align_up(nb * 2 * LH * 8);                                   // lnorm
   b += align_up((2 * nb + 1) * std::max<size_t>(LH * ae, 8));       // lpart (FP64 for degrees)
   b += align_up(nb * 4);                                            // lcount
@@ -255,7 +255,6 @@ int embed_bind_workspace(Context* ctx, Arena* a, EmbedIO* io) {
   io->z[1] = a->take<char>(n * LH * se);
   io->partials = a->take<double>((size_t)kMaxGrid * 2 * LH);
   io->state = a->take<double>(5 * LH + 8);
-  io->counter = reinterpret_cast<int32_t*>(io->state + 5 * LH);
   io->lnorm = a->take<double>(nb * 2 * LH);
   io->lpart = a->take<char>((2 * nb + 1) * std::max<size_t>(LH * ae, 8));
   io->lcount = a->take<int32_t>(nb);
@@ -396,7 +395,6 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
     hipLaunchKernelGGL(plan_chunks, dim3(blocks), dim3(256), 0, s, g->row_ptr, nb, NB, io->plan.desc,
                        io->plan.nch, io->plan.choff, io->plan.lid, io->plan.chunks);
     hipLaunchKernelGGL(fill_i32, dim3((nb + 255) / 256), dim3(256), 0, s, io->lcount, (int64_t)nb, 0);
-    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, io->counter, (int64_t)1, 0);
     if ((rc = check_hip(hipGetLastError(), "plan kernels"))) return rc;
   }
   io->grid = persistent_grid(ctx, nb, ctx->tune.blocks_per_cu);
@@ -418,7 +416,6 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
   sa.lnorm = io->lnorm;
   sa.meta = io->plan.meta;
   sa.state = io->state;
-  sa.counter = io->counter;
   sa.sqnorm = io->sqnorm_trace;
   sa.rayleigh = io->rayleigh_trace;
   sa.step = 0;

@@ -461,7 +461,6 @@ static int cheb_steps_typed(Context* ctx, EmbedIO* io, float* const* basis, int 
   sa.partials = io->partials;
   sa.lnorm = io->lnorm;
   sa.meta = io->plan.meta;
-  sa.counter = io->counter;
   sa.rayleigh = ray;
   for (int j = 0; j < nsteps; ++j) {
     ChebOp<W, LH> op;
@@ -505,7 +504,6 @@ static int rayleigh_typed(Context* ctx, EmbedIO* io, const float* x, double* ray
   sa.partials = io->partials;
   sa.lnorm = io->lnorm;
   sa.meta = io->plan.meta;
-  sa.counter = io->counter;
   sa.rayleigh = ray;
   sa.step = row;
   ChebOp<W, LH> op;

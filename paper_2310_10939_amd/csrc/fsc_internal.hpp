@@ -176,7 +176,6 @@ struct EmbedIO {
   void* z[2];       // S[n*LH] ping-pong
   double* partials; // [grid][2*LH]
   double* state;    // [5][LH]: prev_sq, cum, scale, scale as A, spare
-  int32_t* counter; // arrival counter of the statistics epilogue
   double* lnorm;    // [max long rows][2*LH]
   void* lpart;      // A[max chunks][LH]
   int32_t* lcount;  // [max long rows]
@@ -233,7 +232,6 @@ struct KmeansIO {
   float* centres;          // 64 x KD (padded)
   double* cpart;           // blocks x 64 x (KD+1)
   int32_t* chosen;         // 64
-  int32_t* counter;        // 4
   int nblk_pp, nblk_ll;
 };
 // One k-means problem as the kernels see it.
@@ -247,7 +245,6 @@ struct KmJob {
   float* cand;
   int32_t* cand_row;
   int trials;              // candidates per seeding round
-  int32_t* counter;
   float* centres;          // 64 x KD
   int32_t* chosen;
   int32_t* labels;

@@ -52,7 +52,6 @@ struct KppShared {
   double sbuf[kKB / FSC_WAVE + 1];
   double inc[kKB];
   double base;
-  int is_last;
   int32_t found;
   int32_t block;
 };
@@ -72,7 +71,7 @@ __device__ __forceinline__ double seed_weight(int first, const uint8_t* elig, in
 }
 
 // The row holding `target` in the inclusive running sum of the seeding
-// weights (last block of the job; every thread returns it).  The block sums
+// weights (run by one whole block; every thread returns it).  The block sums
 // are scanned in chunks, then the found block's rows are rescanned in the
 // order of phase A, so the prefixes are bit-identical to phase A's.
 template <int KD>
@@ -278,8 +277,8 @@ __device__ void kpp_sample_block(const KmJob& J, int r, int j, KppShared& sh) {
   }
 }
 
-// Round r >= 1, second launch: the potential of each candidate over this
-// block's rows; the last block keeps the best candidate as centre r.
+// Round r >= 1, second pass: the potential of each candidate over this
+// block's rows (kpp_select_block then keeps the best candidate as centre r).
 template <int KD>
 __device__ void kpp_pick_block(const KmJob& J, int blk, int r, KppShared& sh) {
   const int64_t n = J.n;
@@ -737,11 +736,6 @@ __global__ void pad_points(const T* __restrict__ in, int64_t n, int l, int KD, f
   }
 }
 
-__global__ void zero_i32(int32_t* p, int count) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = 0;
-}
-
 // ===========================================================================
 // Host side
 // ===========================================================================
@@ -771,7 +765,7 @@ size_t kmeans_workspace_bytes(int64_t n, int KD) {
   b += align_up(kMaxTrials * KD * 4) + align_up(kMaxTrials * 4);  // candidates
   b += align_up(kMaxK * KD * 4);                          // centres
   b += align_up((size_t)nblk_ll * kMaxK * (KD + 1) * 8);  // cpart
-  b += align_up(kMaxK * 4) + align_up(16);                // chosen, counter
+  b += align_up(kMaxK * 4);                               // chosen
   return b + 8 * 256;
 }
 
@@ -785,7 +779,6 @@ int kmeans_bind_workspace(Arena* a, KmeansIO* io) {
   io->centres = a->take<float>(kMaxK * io->KD);
   io->cpart = a->take<double>((size_t)((n + 15) / 16 / kLW + 1) * kMaxK * (io->KD + 1));
   io->chosen = a->take<int32_t>(kMaxK);
-  io->counter = a->take<int32_t>(4);
   if (a->used > a->size) return fail(FSC_E_NOMEM, "workspace arena too small");
   return FSC_OK;
 }
@@ -802,7 +795,6 @@ KmJob make_job(Context* ctx, const KmeansIO* io) {
   J.cand = io->cand;
   J.cand_row = io->cand_row;
   J.trials = kpp_trials(io->k);
-  J.counter = io->counter;
   J.centres = io->centres;
   J.chosen = io->chosen;
   J.labels = io->labels;
@@ -825,7 +817,6 @@ static int lloyd_all(const KmJob& J, int iters, hipStream_t s) {
 
 template <int KD>
 static int kmeans_typed(Context* ctx, KmeansIO* io, hipStream_t s) {
-  hipLaunchKernelGGL(zero_i32, dim3(1), dim3(64), 0, s, io->counter, 4);
   const KmJob J = make_job(ctx, io);
   for (int r = 0; r < io->k; ++r) {
     hipLaunchKernelGGL(kpp_kernel<KD>, dim3(J.nblk_pp), dim3(kKB), 0, s, J, r);

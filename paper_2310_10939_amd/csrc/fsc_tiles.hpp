@@ -312,7 +312,6 @@ struct StatsArgs {
   const double* lnorm;  // [long rows][2*LH]
   const int32_t* meta;  // meta[1] = long rows
   double* state;
-  int32_t* counter;
   double* sqnorm;       // optional (t+1) x l
   double* rayleigh;     // optional t x l
   int step, t, l, renorm;
