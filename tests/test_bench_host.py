@@ -1,0 +1,69 @@
+"""Host-side logic of bench.py (no GPU): the algorithmic byte count of a
+power step, the single-GPU guard, and the workload table."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_step_bytes_of_the_large_sbm():
+    # col (4) + weight (4) per nonzero, row pointer, read + write of the
+    # 1M x 4 FP32 block, 1/(2d) (FP32) and the FP64 degree
+    n, nnz = 1_000_000, 39_988_154
+    want = nnz * 8 + (n + 1) * 8 + 2 * n * 4 * 4 + n * 4 + n * 8
+    assert bench.spmm_bytes(n, nnz, 4, "f32", "f32") == want == 371_905_240
+
+
+def test_step_bytes_follow_the_storage_types():
+    n, nnz = 70_000, 1_283_232
+    bf = bench.spmm_bytes(n, nnz, 4, "bf16", "bf16")
+    assert bf == nnz * 6 + (n + 1) * 8 + 2 * n * 4 * 2 + n * 4 + n * 8
+    # l = 3 pads to 4 columns; no weights stored
+    assert bench.spmm_bytes(10, 20, 3, "f32", None) == 20 * 4 + 11 * 8 + 2 * 10 * 4 * 4 + 10 * 4 + 10 * 8
+    assert bench.spmm_bytes(10, 20, 3, "f32", None, stats=False) == 20 * 4 + 11 * 8 + 2 * 10 * 4 * 4 + 10 * 4
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("name", sorted(bench.WORKLOADS))
+def test_workload_table_is_consistent(name):
+    n, k, din, dout, l, t, lloyd, vec, wdt, permute = bench.WORKLOADS[name]
+    assert n > 0 and 1 <= k <= 64 and 1 <= l <= 8 and t > 0 and lloyd >= 0
+    assert vec in ("f64", "f32", "bf16") and wdt in (None, "f64", "f32", "bf16")
+
+
+def test_trainer_host_pieces():
+    """train_filter's host-side helpers: the per-graph optimum of the loss is
+    the smallest generalised eigenvalue (checked against the oracle's ratio
+    and a dense solve), and the initial parameters give the initial
+    interval through the oracle's head."""
+    import numpy as np
+    from oracle import fsc_learned as fl
+    from paper_2310_10939_amd import train_filter as tf
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((9, 14))
+    Bm = rng.standard_normal((9, 5))
+    W, T = A @ A.T, A @ A.T + Bm @ Bm.T
+    c_rest, lam = tf.ratio_optimum(W, T)
+    c = np.concatenate([[1 - c_rest.sum()], c_rest])
+    assert abs(fl.ratio(c, W, T) - lam) < 1e-10
+    ev = np.linalg.eigvals(np.linalg.solve(T, W))
+    assert abs(np.real(ev).min() - lam) < 1e-10
+    p = tf.init_params(0).astype(np.float64)
+    assert p.size == fl.param_count()
+    out, _ = fl.mlp_forward(p, np.zeros((1, fl.NFEAT)))
+    a, b = fl.interval(*out[0])
+    assert abs(a - tf.INIT_A) < 1e-6 and abs(b - tf.INIT_B) < 1e-6
+    # the gamma^8 table of the trainer is the Chebyshev series of gamma^8
+    want = np.polynomial.chebyshev.poly2cheb(np.polynomial.polynomial.polypow([0.5, 0.5], 8))
+    assert np.allclose(tf.GAMMA8, want[1:], rtol=0, atol=1e-15)
