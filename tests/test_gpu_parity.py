@@ -152,7 +152,7 @@ def test_kmeans_parity(gpu_lib, k, l):
     assert _valid_assignment(X.astype(np.float64), lab, C.astype(np.float64), 1e-4)
 
 
-@pytest.mark.parametrize("n,l,k", [(700, 3, 2), (5000, 3, 7), (40000, 8, 33), (20000, 4, 64)])
+@pytest.mark.parametrize("n,l,k", [(5, 2, 1), (64, 1, 64), (700, 3, 2), (5000, 3, 7), (40000, 8, 33), (20000, 4, 64)])
 def test_kmeanspp_seeds_match_oracle_exactly(gpu_lib, n, l, k):
     """Greedy k-means++ on points of an integer grid: every squared distance
     and every running sum is exact on both sides, so the GPU must choose the
@@ -166,6 +166,20 @@ def test_kmeanspp_seeds_match_oracle_exactly(gpu_lib, n, l, k):
                           eligible=torch.from_numpy(elig.astype(np.uint8)).cuda())
     say(f"kmeans++ n={n} l={l} k={k}")
     assert np.array_equal(C.cpu().numpy(), X[idx])
+
+
+def test_kmeanspp_with_fewer_distinct_points_than_k(gpu_lib):
+    """Three distinct points repeated, k = 6: after three centres every D^2
+    is 0 and the seeding takes unchosen rows; the centres are the oracle's
+    and every label is valid."""
+    X = np.repeat(np.array([[0, 0], [5, 1], [-3, 7]], dtype=np.float32), [40, 25, 35], axis=0)
+    idx = o.kmeanspp(X.astype(np.float64), 6, 2)
+    lab, C = gpu_lib.kmeans(torch.from_numpy(X).cuda(), 6, 5, seed=2)
+    lab = lab.cpu().numpy()
+    assert lab.min() >= 0 and lab.max() < 6
+    _, C0 = gpu_lib.kmeans(torch.from_numpy(X).cuda(), 6, 0, seed=2)
+    assert np.array_equal(C0.cpu().numpy(), X[idx])
+    assert _valid_assignment(X.astype(np.float64), lab, C.cpu().numpy().astype(np.float64), 1e-6)
 
 
 def test_kmeans_eligibility_and_fp64_points(gpu_lib):
