@@ -344,8 +344,38 @@ def fast_spectral_cluster(n, indptr, indices, data, k, l, t, seed, kmeans_iters,
 
 
 # ----------------------------------------------------------------------------
-# Adjusted Rand index (Hubert and Arabie; the score of Sec. 4.2)
+# Accuracy scores of Sec. 4.2: normalised mutual information and the
+# adjusted Rand index (Hubert and Arabie)
 # ----------------------------------------------------------------------------
+def nmi(a, b):
+    """Normalised mutual information (the second accuracy score of Sec. 4.2)
+    from the contingency table, natural logarithms:
+    I(A; B) / ((H(A) + H(B)) / 2).  Readings: the paper cites the score
+    without fixing its normalisation; this is the arithmetic mean of the two
+    entropies.  When both entropies are 0 (each labeling one cluster) the
+    score is 1; I is clipped at 0 against rounding."""
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    n = a.size
+    if n == 0:
+        return 1.0
+    _, ai = np.unique(a, return_inverse=True)
+    _, bi = np.unique(b, return_inverse=True)
+    table = np.zeros((ai.max() + 1, bi.max() + 1))
+    np.add.at(table, (ai, bi), 1.0)
+    pa = table.sum(axis=1) / n
+    pb = table.sum(axis=0) / n
+    ha = -float(np.sum(pa * np.log(pa)))
+    hb = -float(np.sum(pb * np.log(pb)))
+    nz = table > 0
+    pij = table[nz] / n
+    mi = float(np.sum(pij * np.log(pij / np.outer(pa, pb)[nz])))
+    mi = max(mi, 0.0)
+    if ha + hb == 0.0:
+        return 1.0
+    return mi / (0.5 * (ha + hb))
+
+
 def _comb2(x):
     x = np.asarray(x, dtype=np.float64)
     return x * (x - 1.0) / 2.0

@@ -366,3 +366,18 @@ def test_pipeline_recovers_cliques_and_small_sbm():
     g = synth.sbm(1000, 5, 0.5, 0.01, seed=0)
     lab, C, E = o.fast_spectral_cluster(g.n, g.indptr, g.indices, None, 5, 3, 20, 0, 20)
     assert o.ari(lab, g.labels) > 0.99
+
+
+def test_nmi_matches_scikit_learn_and_closed_forms():
+    from sklearn.metrics import normalized_mutual_info_score as sk_nmi
+    rng = np.random.default_rng(4)
+    for n, ka, kb in [(50, 3, 4), (1000, 10, 10), (333, 2, 7)]:
+        a = rng.integers(0, ka, n)
+        b = np.where(rng.random(n) < 0.6, a % kb, rng.integers(0, kb, n))
+        assert abs(o.nmi(a, b) - sk_nmi(a, b, average_method="arithmetic")) < 1e-12
+    a = rng.integers(0, 5, 200)
+    assert abs(o.nmi(a, (a + 3) % 5) - 1.0) < 1e-12          # a relabelling
+    i = np.arange(9 * 40)
+    assert abs(o.nmi(i % 3, (i // 3) % 3)) < 1e-12              # independent: I = 0
+    assert o.nmi(np.zeros(7), np.zeros(7)) == 1.0                # both one cluster
+    assert o.nmi(np.zeros(8), np.arange(8) % 2) == 0.0           # one trivial labeling
