@@ -301,6 +301,17 @@ int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t 
 int fsc_ari(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int32_t ka,
             int32_t kb, double* out, void* stream);
 
+/* Normalised mutual information (the second accuracy score of Sec. 4.2)
+ * between labelings a (values in [0, ka)) and b (values in [0, kb)) of n
+ * items, written as one FP64 value to device memory `out`:
+ * I(A; B) / ((H(A) + H(B)) / 2), natural logarithms, the arithmetic-mean
+ * normalisation (the paper names no other).  Only pairs with both labels in
+ * range are counted (N of them).  The value is 1 when both entropies are 0 or
+ * N = 0.  Needs ka*kb <= 2^22; the table and margins come from the context's
+ * workspace. */
+int fsc_nmi(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int32_t ka,
+            int32_t kb, double* out, void* stream);
+
 /* Sets (fields > 0; slab_kb < 0 turns the slab form off) and then reports in
  * *t the sparse-product launch shape used by later calls on this context
  * (slab_kb reported as -1 when off).  t is a host pointer.  Returns FSC_E_ARG

@@ -350,6 +350,23 @@ int fsc_ari(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int
   return ari_run(&ctx->c, a, b, n, ka, kb, out, table, s);
 }
 
+int fsc_nmi(fsc_context* ctx, const int32_t* a, const int32_t* b, int64_t n, int32_t ka, int32_t kb, double* out,
+            void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (!out || (n > 0 && (!a || !b))) return fail(FSC_E_ARG, "null pointer");
+  if (n < 0) return fail(FSC_E_ARG, "n must be >= 0");
+  if (ka < 1 || kb < 1 || (int64_t)ka * kb > (1 << 22)) return fail(FSC_E_ARG, "need ka, kb >= 1 and ka*kb <= 2^22");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  Arena arena;
+  if ((rc = reserve_arena(&ctx->c, align_up((size_t)ka * kb * 8) + align_up(((size_t)ka + kb) * 8) + 512, &arena)))
+    return rc;
+  unsigned long long* table = arena.take<unsigned long long>((size_t)ka * kb);
+  double* margin = arena.take<double>((size_t)ka + kb);
+  return nmi_run(&ctx->c, a, b, n, ka, kb, out, table, margin, s);
+}
+
 int fsc_cluster_batched(fsc_context* ctx, int32_t count, const fsc_csr* graphs, const int32_t* k,
                         const int32_t* l, const int32_t* t, uint64_t seed, const fsc_opts* opts,
                         int32_t* labels, float* emb, void* stream) {

@@ -1,7 +1,8 @@
-// Adjusted Rand index (Hubert and Arabie), the accuracy score of Sec. 4.2.
-// The contingency table is built with integer atomics (exact, so the result
-// does not depend on the order of the updates); the index is then formed in
-// FP64 by one block.  C(x, 2) of integer counts below 2^26 is exact in FP64.
+// Accuracy scores of Sec. 4.2: the adjusted Rand index (Hubert and Arabie)
+// and normalised mutual information.  The contingency table is built with
+// integer atomics (exact, so the result does not depend on the order of the
+// updates); each score is then formed in FP64 by one block.  C(x, 2) of
+// integer counts below 2^26 is exact in FP64.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
 
@@ -50,15 +51,76 @@ __global__ __launch_bounds__(256) void ari_finish(const unsigned long long* __re
   }
 }
 
-int ari_run(Context*, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,
-            unsigned long long* table, hipStream_t s) {
+// NMI = I(A; B) / ((H(A) + H(B)) / 2) with natural logarithms, over the N
+// pairs whose labels are both in range.  The block first writes the table's
+// row and column sums to `margin` (ka + kb doubles), then sums the entropies
+// and the information.  Both entropies 0 (or N = 0) gives 1; I is clipped at
+// 0 against rounding.
+__global__ __launch_bounds__(256) void nmi_finish(const unsigned long long* __restrict__ table, int ka, int kb,
+                                                  double* __restrict__ margin, double* __restrict__ out) {
+  __shared__ double red[4];
+  double* ra = margin;
+  double* cb = margin + ka;
+  double cnt = 0.0;
+  for (int x = threadIdx.x; x < ka; x += blockDim.x) {
+    double row = 0.0;
+    for (int y = 0; y < kb; ++y) row += (double)table[(int64_t)x * kb + y];
+    ra[x] = row;
+    cnt += row;
+  }
+  for (int y = threadIdx.x; y < kb; y += blockDim.x) {
+    double colsum = 0.0;
+    for (int x = 0; x < ka; ++x) colsum += (double)table[(int64_t)x * kb + y];
+    cb[y] = colsum;
+  }
+  const double N = block_sum<256>(cnt, red);  // ends in a barrier: the margins are visible
+  if (N == 0.0) {
+    if (threadIdx.x == 0) *out = 1.0;
+    return;
+  }
+  const double logN = log(N);
+  double ha = 0.0, hb = 0.0, mi = 0.0;
+  for (int x = threadIdx.x; x < ka; x += blockDim.x)
+    if (ra[x] > 0.0) ha -= (ra[x] / N) * (log(ra[x]) - logN);
+  for (int y = threadIdx.x; y < kb; y += blockDim.x)
+    if (cb[y] > 0.0) hb -= (cb[y] / N) * (log(cb[y]) - logN);
+  for (int64_t c = threadIdx.x; c < (int64_t)ka * kb; c += blockDim.x) {
+    const double nij = (double)table[c];
+    if (nij > 0.0) {
+      const int x = (int)(c / kb), y = (int)(c % kb);
+      mi += (nij / N) * (log(nij) + logN - log(ra[x]) - log(cb[y]));
+    }
+  }
+  ha = block_sum<256>(ha, red);
+  hb = block_sum<256>(hb, red);
+  mi = block_sum<256>(mi, red);
+  if (threadIdx.x == 0) {
+    const double h = ha + hb;
+    *out = h == 0.0 ? 1.0 : fmax(mi, 0.0) / (0.5 * h);
+  }
+}
+
+static void contingency(const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, unsigned long long* table,
+                        hipStream_t s) {
   const int64_t cells = (int64_t)ka * kb;
   hipLaunchKernelGGL(ari_zero, dim3((int)std::min<int64_t>((cells + 255) / 256, 4096)), dim3(256), 0, s, table, cells);
   if (n > 0)
     hipLaunchKernelGGL(ari_count, dim3((int)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s, a, b, n, ka,
                        kb, table);
+}
+
+int ari_run(Context*, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,
+            unsigned long long* table, hipStream_t s) {
+  contingency(a, b, n, ka, kb, table, s);
   hipLaunchKernelGGL(ari_finish, dim3(1), dim3(256), 0, s, table, n, ka, kb, out);
   return check_hip(hipGetLastError(), "ari launch");
+}
+
+int nmi_run(Context*, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,
+            unsigned long long* table, double* margin, hipStream_t s) {
+  contingency(a, b, n, ka, kb, table, s);
+  hipLaunchKernelGGL(nmi_finish, dim3(1), dim3(256), 0, s, table, ka, kb, margin, out);
+  return check_hip(hipGetLastError(), "nmi launch");
 }
 
 }  // namespace fsc

@@ -303,8 +303,10 @@ int mlp_loss_grad_run(const float* params, int B, const float* feats, const doub
                       float* grad, double* loss_out, char* ws, hipStream_t s);
 int mlp_adam_run(float* p, float* m, float* v, const float* g, float lr, int step, hipStream_t s);
 
-// ---- ARI (fsc_ari.hip) ----
+// ---- ARI and NMI (fsc_ari.hip) ----
 int ari_run(Context* ctx, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,
             unsigned long long* table, hipStream_t s);
+int nmi_run(Context* ctx, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,
+            unsigned long long* table, double* margin, hipStream_t s);
 
 }  // namespace fsc

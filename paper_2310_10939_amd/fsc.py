@@ -67,13 +67,14 @@ _lib.fsc_filter_embed.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _u64, _vp, _vp
 _lib.fsc_cluster_filtered.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, _vp, _vp, _i32,
                                       ctypes.POINTER(Opts), _vp, _vp, _vp, ctypes.POINTER(_i32), _vp]
 _lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
+_lib.fsc_nmi.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
 _lib.fsc_tuning_set.argtypes = [_vp, ctypes.POINTER(Tuning)]
 _lib.fsc_timing_enable.argtypes = [_vp, ctypes.c_int]
 _lib.fsc_timing_read.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
 _lib.fsc_last_error.restype = ctypes.c_char_p
 _lib.fsc_version.restype = ctypes.c_int
 
-EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari",
+EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari", "fsc_nmi",
            "fsc_cluster_batched", "fsc_autotune", "fsc_mlp_param_count", "fsc_filter_stats",
            "fsc_mlp_forward", "fsc_mlp_loss_grad", "fsc_mlp_adam", "fsc_mlp_train", "fsc_filter_embed",
            "fsc_cluster_filtered",
@@ -334,6 +335,14 @@ def ari(a, b, ka, kb):
     """Adjusted Rand index of two int32 device labelings (an FP64 0-d tensor)."""
     out = torch.empty((), dtype=torch.float64, device=a.device)
     _check(_lib.fsc_ari(context(a.device.index), _ptr(a), _ptr(b), a.numel(), ka, kb, _ptr(out), _stream()))
+    return out
+
+
+def nmi(a, b, ka, kb):
+    """Normalised mutual information (arithmetic-mean normalisation) of two
+    int32 device labelings (an FP64 0-d tensor)."""
+    out = torch.empty((), dtype=torch.float64, device=a.device)
+    _check(_lib.fsc_nmi(context(a.device.index), _ptr(a), _ptr(b), a.numel(), ka, kb, _ptr(out), _stream()))
     return out
 
 

@@ -67,3 +67,10 @@ def test_trainer_host_pieces():
     # the gamma^8 table of the trainer is the Chebyshev series of gamma^8
     want = np.polynomial.chebyshev.poly2cheb(np.polynomial.polynomial.polypow([0.5, 0.5], 8))
     assert np.allclose(tf.GAMMA8, want[1:], rtol=0, atol=1e-15)
+
+
+def test_trial_report_summary_is_mean_and_population_std():
+    from paper_2310_10939_amd.report import summary
+    res = {"workload": "w", "methods": {"fsc": {"ari": [1.0, 0.5], "nmi": [0.9, 0.7], "ms": [2.0, 4.0]}}}
+    row = summary(res).splitlines()[-1]
+    assert row == "| w | fsc | 0.7500 ± 0.2500 | 0.8000 ± 0.1000 | 3.00 ± 1.00 |"

@@ -201,6 +201,32 @@ def test_ari_kernel(gpu_lib):
         assert abs(got - o.ari(a, b)) < 1e-12
 
 
+def test_nmi_kernel(gpu_lib):
+    rng = np.random.default_rng(1)
+    for n, ka, kb in [(1, 6, 9), (7, 6, 9), (1000, 6, 9), (100000, 10, 10), (300000, 2048, 2048)]:
+        a = rng.integers(0, ka, n).astype(np.int32)
+        b = np.where(rng.random(n) < 0.6, a % kb, rng.integers(0, kb, n)).astype(np.int32)
+        got = float(gpu_lib.nmi(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), ka, kb))
+        assert abs(got - o.nmi(a, b)) < 1e-12, (n, ka, kb)
+
+
+def test_nmi_degenerate_cases(gpu_lib):
+    z = torch.zeros(50, dtype=torch.int32, device="cuda")
+    assert float(gpu_lib.nmi(z, z, 1, 1)) == 1.0                       # both one cluster
+    assert float(gpu_lib.nmi(z[:0], z[:0], 3, 3)) == 1.0               # no items
+    alt = torch.arange(50, dtype=torch.int32, device="cuda") % 2
+    assert float(gpu_lib.nmi(z, alt, 1, 2)) == 0.0                     # one trivial labeling
+    # out-of-range labels drop their pair
+    rng = np.random.default_rng(2)
+    a = rng.integers(0, 5, 4000).astype(np.int32)
+    b = np.where(rng.random(4000) < 0.7, a, rng.integers(0, 5, 4000)).astype(np.int32)
+    a[::13] = -1
+    b[5::17] = 5
+    keep = (a >= 0) & (b < 5)
+    got = float(gpu_lib.nmi(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), 5, 5))
+    assert abs(got - o.nmi(a[keep], b[keep])) < 1e-12
+
+
 # --------------------------------------------------------------------------
 # Whole pipeline
 # --------------------------------------------------------------------------
