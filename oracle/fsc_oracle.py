@@ -17,7 +17,8 @@ Sections of the paper referenced below:
   * Sec. 2.3, Algorithm 1 (PowerMethod): x_i = M x_{i-1}, no normalisation.
   * Sec. 3.2, Algorithm 2 (FastSpectralCluster): l Gaussian vectors, each run
     through PowerMethod for t steps, k-means on D^{-1/2} Y.
-  * Sec. 4.2: ARI as the accuracy score.
+  * Sec. 4: PM with k vectors, the comparison method of Boutsidis et al.
+  * Sec. 4.2: ARI and NMI as the accuracy scores.
 """
 from __future__ import annotations
 
@@ -338,6 +339,53 @@ def fast_spectral_cluster(n, indptr, indices, data, k, l, t, seed, kmeans_iters,
     Isolated vertices (reading: d = 0) take no part in the k-means fit and are
     labelled by their nearest final centre.  Returns (labels, centres, E)."""
     E = embed(n, indptr, indices, data, l, t, seed=seed, x0=x0)
+    d = degrees(n, indptr, indices, data)
+    labels, C = kmeans(E, k, kmeans_iters, seed, eligible=d > 0)
+    return labels, C, E
+
+
+# ----------------------------------------------------------------------------
+# PM with k vectors: the comparison method of Sec. 4 (Boutsidis et al.), which
+# Sec. 1.1 describes as the power method on k vectors plus a singular value
+# decomposition
+# ----------------------------------------------------------------------------
+def pm_k_embed(n, indptr, indices, data, k, t, seed=None, x0=None):
+    """Y = M^t X0 for k Gaussian columns (Algorithm 1 on each), then the left
+    singular vectors U of Y, and the embedding D^{-1/2} U.
+
+    Readings: the orthonormalisation is one SVD at the end (the span is the
+    one a QR after every step gives, in exact arithmetic); the SVD runs over
+    the non-isolated rows (an isolated vertex has no D^{-1/2}, and its row
+    stays 0); columns come in descending order of singular value, a column
+    whose singular value is at most 1e-12 of the largest is 0, and each
+    column's sign makes the largest-magnitude entry of its right singular
+    vector positive (the first such entry on a tie)."""
+    if x0 is None:
+        x0 = gaussian_block(n, k, seed)
+    x0 = np.asarray(x0, dtype=np.float64).reshape(n, k)
+    M = signless_laplacian(n, indptr, indices, data)
+    d = degrees(n, indptr, indices, data)
+    Y = power_method(M, x0, t)
+    rows = d > 0
+    U = np.zeros((n, k))
+    if rows.any():
+        u, sv, vh = np.linalg.svd(Y[rows], full_matrices=False)
+        for j in range(len(sv)):
+            if not (sv[0] > 0 and sv[j] > 1e-12 * sv[0]):
+                u[:, j] = 0.0
+                continue
+            v = vh[j]
+            if v[int(np.argmax(np.abs(v)))] < 0:
+                u[:, j] = -u[:, j]
+        U[np.flatnonzero(rows)[:, None], np.arange(len(sv))[None, :]] = u
+    return inv_sqrt_degree(d)[:, None] * U
+
+
+def pm_k_cluster(n, indptr, indices, data, k, t, seed, kmeans_iters, x0=None):
+    """PM with k vectors end to end: pm_k_embed, then k-means exactly as in
+    fast_spectral_cluster (isolated vertices out of the fit).  Returns
+    (labels, centres, E)."""
+    E = pm_k_embed(n, indptr, indices, data, k, t, seed=seed, x0=x0)
     d = degrees(n, indptr, indices, data)
     labels, C = kmeans(E, k, kmeans_iters, seed, eligible=d > 0)
     return labels, C, E

@@ -381,3 +381,70 @@ def test_nmi_matches_scikit_learn_and_closed_forms():
     assert abs(o.nmi(i % 3, (i // 3) % 3)) < 1e-12              # independent: I = 0
     assert o.nmi(np.zeros(7), np.zeros(7)) == 1.0                # both one cluster
     assert o.nmi(np.zeros(8), np.arange(8) % 2) == 0.0           # one trivial labeling
+
+
+# ---- PM with k vectors (the comparison method of Sec. 4) ----
+def _dense_M(g):
+    """M = (I + D^{-1/2} A D^{-1/2}) / 2 built densely from the edge list, an
+    isolated vertex's D^{-1/2} taken as 0 (its row of M is e_v / 2)."""
+    A = np.zeros((g.n, g.n))
+    rows = np.repeat(np.arange(g.n), np.diff(g.indptr))
+    A[rows, g.indices] = 1.0 if g.data is None else g.data
+    d = A.sum(axis=1)
+    s = np.where(d > 0, 1.0 / np.sqrt(np.where(d > 0, d, 1.0)), 0.0)
+    return 0.5 * (np.eye(g.n) + s[:, None] * A * s[None, :]), d
+
+
+def test_pm_k_on_disjoint_cliques_spans_the_cluster_indicators():
+    g = synth.disjoint_cliques(4, 6)
+    E = o.pm_k_embed(g.n, g.indptr, g.indices, g.data, 4, 80, seed=3)
+    d = np.full(g.n, 5.0)
+    U = np.sqrt(d)[:, None] * E
+    B = np.zeros((g.n, 4))
+    B[np.arange(g.n), g.labels] = 1.0 / np.sqrt(6.0)      # orthonormal cluster indicators
+    cos = np.linalg.svd(B.T @ U, compute_uv=False)
+    assert cos.min() > 1 - 1e-12
+    lab, _, _ = o.pm_k_cluster(g.n, g.indptr, g.indices, g.data, 4, 80, 3, 10)
+    assert o.ari(lab, g.labels) == 1.0
+
+
+def test_pm_k_columns_are_orthonormal_and_span_the_power_iterate():
+    g = synth.random_weighted(60, 150, seed=5, isolated=3)
+    k, t, seed = 5, 7, 11
+    E = o.pm_k_embed(g.n, g.indptr, g.indices, g.data, k, t, seed=seed)
+    M, d = _dense_M(g)
+    live = d > 0
+    assert np.all(E[~live] == 0.0)
+    U = np.sqrt(d[live])[:, None] * E[live]
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-12
+    # M^t X0 from the dense eigendecomposition, not from repeated products
+    gam, F = np.linalg.eigh(M)
+    Y = (F * gam ** t) @ F.T @ o.gaussian_block(g.n, k, seed)
+    Yl = Y[live]
+    assert np.linalg.norm(Yl - U @ (U.T @ Yl)) < 1e-10 * np.linalg.norm(Yl)
+    # the sign convention: U^T Y = Sigma V^T, each row's largest entry positive
+    P = U.T @ Yl
+    assert all(P[j, np.argmax(np.abs(P[j]))] > 0 for j in range(k))
+    sv = np.linalg.svd(Yl, compute_uv=False)
+    assert np.allclose(np.linalg.norm(P, axis=1), sv, rtol=1e-10)   # descending order
+
+
+def test_pm_k_converges_to_the_top_eigenvectors():
+    g = synth.sbm(300, 3, 0.5, 0.02, seed=2)
+    E = o.pm_k_embed(g.n, g.indptr, g.indices, g.data, 3, 300, seed=1)
+    M, d = _dense_M(g)
+    gam, F = np.linalg.eigh(M)
+    assert gam[-3] - gam[-4] > 0.1                       # a clear gap below the top 3
+    U = np.sqrt(d)[:, None] * E
+    cos = np.linalg.svd(F[:, -3:].T @ U, compute_uv=False)
+    assert cos.min() > 1 - 1e-8
+
+
+def test_pm_k_rank_deficient_block_leaves_zero_columns():
+    # a triangle and four isolated vertices: Y has rank at most 3
+    g = synth.csr_from_edges(7, np.array([0, 1, 2]), np.array([1, 2, 0]))
+    E = o.pm_k_embed(g.n, g.indptr, g.indices, g.data, 5, 3, seed=4)
+    assert np.all(E[3:] == 0.0)
+    assert np.all(E[:, 3:] == 0.0)
+    U = np.sqrt(2.0) * E[:3, :3]
+    assert np.abs(U.T @ U - np.eye(3)).max() < 1e-12
