@@ -293,6 +293,22 @@ int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t 
                          int32_t* labels, float* coeffs_out, double* diagnostics, int32_t* used_fallback,
                          void* stream);
 
+/* PM with k vectors, the comparison method of Sec. 4 (Boutsidis et al.; the
+ * power method on k vectors followed by a singular value decomposition, as
+ * Sec. 1.1 describes it).  Y = M^t X0 for k start vectors (the start block
+ * and steps of fsc_embed with l = k), then U = the left singular vectors of Y
+ * over the non-isolated rows, taken through the FP64 Gram matrix Y^T Y (cyclic
+ * Jacobi), and k-means exactly as fsc_cluster on the rows of D^{-1/2} U.
+ * Columns of U come in descending order of singular value; a column whose
+ * singular value is at most 1e-6 of the largest is 0; each column's sign
+ * makes the largest-magnitude entry of its right singular vector positive.
+ * `labels` receives int32[n].  Optional outputs (NULL to skip): `emb` (FP32
+ * n x k, the rows k-means sees) and `sigma` (FP64 [k], the singular values of
+ * Y, descending).  1 <= k <= min(n, 8); opts as for fsc_cluster (x0, when
+ * given, is n x k). */
+int fsc_cluster_pmk(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t t, uint64_t seed,
+                    const fsc_opts* opts, int32_t* labels, float* emb, double* sigma, void* stream);
+
 /* Adjusted Rand index (Hubert and Arabie; the accuracy score of Sec. 4.2)
  * between labelings a (values in [0, ka)) and b (values in [0, kb)) of n
  * items, written as one FP64 value to device memory `out`.  If both labelings

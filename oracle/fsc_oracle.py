@@ -357,7 +357,8 @@ def pm_k_embed(n, indptr, indices, data, k, t, seed=None, x0=None):
     one a QR after every step gives, in exact arithmetic); the SVD runs over
     the non-isolated rows (an isolated vertex has no D^{-1/2}, and its row
     stays 0); columns come in descending order of singular value, a column
-    whose singular value is at most 1e-12 of the largest is 0, and each
+    whose singular value is at most 1e-6 of the largest is 0 (a direction
+    that FP32 rows, which the device path stores, cannot resolve), and each
     column's sign makes the largest-magnitude entry of its right singular
     vector positive (the first such entry on a tie)."""
     if x0 is None:
@@ -371,7 +372,7 @@ def pm_k_embed(n, indptr, indices, data, k, t, seed=None, x0=None):
     if rows.any():
         u, sv, vh = np.linalg.svd(Y[rows], full_matrices=False)
         for j in range(len(sv)):
-            if not (sv[0] > 0 and sv[j] > 1e-12 * sv[0]):
+            if not (sv[0] > 0 and sv[j] > 1e-6 * sv[0]):
                 u[:, j] = 0.0
                 continue
             v = vh[j]

@@ -211,6 +211,40 @@ int cluster_run(Context* c, const fsc_csr* g, int k, int l, int t, uint64_t seed
   return kmeans_run(c, &km, s);
 }
 
+// PM with k vectors: the plain path's power steps on k columns, the
+// orthonormalisation of fsc_pmk.hip, then the same k-means.
+static int pmk_cluster_run(Context* c, const fsc_csr* g, int k, int t, uint64_t seed, const fsc_opts& o,
+                           int32_t* labels, float* emb, double* sigma, hipStream_t s) {
+  int rc;
+  const int iters = o.kmeans_iters > 0 ? o.kmeans_iters : 30;
+  const int KD = kmeans_width(k);
+  const size_t extra =
+      kmeans_workspace_bytes(g->n, KD) + align_up(g->n * KD * 4) + pmk_workspace_bytes(g->n, KD) + 2048;
+  EmbedIO io;
+  Arena arena;
+  if ((rc = prepare_embed(c, g, k, t, seed, o, extra, &io, &arena))) return rc;
+  KmeansIO km;
+  std::memset(&km, 0, sizeof(km));
+  km.n = g->n;
+  km.l = k;
+  km.KD = KD;
+  km.k = k;
+  km.iters = iters;
+  km.seed = seed;
+  km.labels = labels;
+  float* pts = arena.take<float>(g->n * KD);
+  double* partials = arena.take<double>((size_t)pmk_grid(g->n) * KD * (KD + 1) / 2);
+  float* W = arena.take<float>((size_t)KD * KD);
+  if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
+  if (o.validate && (rc = validate_csr(c, g, s))) return rc;
+  if ((rc = embed_run(c, &io, s))) return rc;
+  if ((rc = embed_to_points(c, &io, pts, s))) return rc;
+  if ((rc = pmk_run(&io, pts, KD, k, partials, W, sigma, emb, s))) return rc;
+  km.pts = pts;
+  km.elig = io.elig;
+  return kmeans_run(c, &km, s);
+}
+
 }  // namespace fsc
 
 using namespace fsc;
@@ -300,6 +334,18 @@ int fsc_cluster(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_
   const fsc_opts o = opts ? *opts : default_opts();
   if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
   return cluster_run(&ctx->c, g, k, l, t, seed, o, labels, emb, centres, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int fsc_cluster_pmk(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t t, uint64_t seed, const fsc_opts* opts,
+                    int32_t* labels, float* emb, double* sigma, void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (!labels) return fail(FSC_E_ARG, "labels is NULL");
+  int rc;
+  if ((rc = check_csr(g))) return rc;
+  if (k < 1 || k > 8 || k > g->n) return fail(FSC_E_ARG, "k must be in [1, min(n, 8)]");
+  const fsc_opts o = opts ? *opts : default_opts();
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  return pmk_cluster_run(&ctx->c, g, k, t, seed, o, labels, emb, sigma, static_cast<hipStream_t>(stream));
 }
 
 int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, int32_t l, int32_t k, int32_t iters,

@@ -303,6 +303,12 @@ int mlp_loss_grad_run(const float* params, int B, const float* feats, const doub
                       float* grad, double* loss_out, char* ws, hipStream_t s);
 int mlp_adam_run(float* p, float* m, float* v, const float* g, float lr, int step, hipStream_t s);
 
+// ---- PM with k vectors (fsc_pmk.hip) ----
+int pmk_grid(int64_t n);
+size_t pmk_workspace_bytes(int64_t n, int KD);
+int pmk_run(const EmbedIO* io, float* pts, int KD, int k, double* partials, float* W, double* sigma, float* emb,
+            hipStream_t s);
+
 // ---- ARI and NMI (fsc_ari.hip) ----
 int ari_run(Context* ctx, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,
             unsigned long long* table, hipStream_t s);

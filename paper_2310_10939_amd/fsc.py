@@ -68,6 +68,7 @@ _lib.fsc_cluster_filtered.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64
                                       ctypes.POINTER(Opts), _vp, _vp, _vp, ctypes.POINTER(_i32), _vp]
 _lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
 _lib.fsc_nmi.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
+_lib.fsc_cluster_pmk.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp, _vp, _vp]
 _lib.fsc_tuning_set.argtypes = [_vp, ctypes.POINTER(Tuning)]
 _lib.fsc_timing_enable.argtypes = [_vp, ctypes.c_int]
 _lib.fsc_timing_read.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
@@ -77,7 +78,7 @@ _lib.fsc_version.restype = ctypes.c_int
 EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari", "fsc_nmi",
            "fsc_cluster_batched", "fsc_autotune", "fsc_mlp_param_count", "fsc_filter_stats",
            "fsc_mlp_forward", "fsc_mlp_loss_grad", "fsc_mlp_adam", "fsc_mlp_train", "fsc_filter_embed",
-           "fsc_cluster_filtered",
+           "fsc_cluster_filtered", "fsc_cluster_pmk",
            "fsc_tuning_set", "fsc_timing_enable", "fsc_timing_read", "fsc_last_error", "fsc_version")
 
 
@@ -192,6 +193,21 @@ def cluster(indptr, indices, data, k, l, t, seed, kmeans_iters=30, vec_dtype="f3
     if traces:
         res += [sq, ray[:t]]
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def cluster_pmk(indptr, indices, data, k, t, seed, kmeans_iters=30, vec_dtype="f32", x0=None, validate=False):
+    """PM with k vectors (k <= 8): (labels int32 [n], embedding FP32 n x k,
+    singular values FP64 [k])."""
+    n = indptr.numel() - 1
+    dev = indptr.device
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    emb = torch.empty((n, k), dtype=torch.float32, device=dev)
+    sv = torch.empty(k, dtype=torch.float64, device=dev)
+    g = _csr(indptr, indices, data)
+    o = _opts(vec_dtype, kmeans_iters, validate, False, x0)
+    _check(_lib.fsc_cluster_pmk(context(dev.index), ctypes.byref(g), k, t, seed, ctypes.byref(o), _ptr(labels),
+                                _ptr(emb), _ptr(sv), _stream()))
+    return labels, emb, sv
 
 
 def cluster_batched(graphs, ks, ls, ts, seed, kmeans_iters=30, return_embedding=False, use_graph=True):

@@ -11,6 +11,8 @@ Methods:
   fsc        the plain method (Algorithm 2), l = ceil(log2 k), t as named by
              the workload
   fsc-l+1    the same with one more vector than log2 k
+  pm-k       PM with k vectors (the comparison method of Sec. 4: k power
+             vectors and one SVD), for k <= 8, same t
   learned    the learned polynomial filter with the shipped parameters and the
              plain method as its fallback (SBM workloads only: the filter was
              trained on SBM graphs)
@@ -32,10 +34,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# name: (n, k, mean in-cluster degree, mean cross degree, t, permuted) for
+# name: (kind, n, k, mean in-cluster degree, mean cross degree, t, permuted) for
 # SBM graphs; the kNN entry is 70,000 points of 10 Gaussians in 784 dims
 WORKLOADS = {
     "sbm1m": ("sbm", 1_000_000, 10, 36, 4, 30, True),
+    "sbm1m-k8": ("sbm", 1_000_000, 8, 36, 4, 30, True),
     "sbm100k": ("sbm", 100_000, 10, 36, 4, 25, True),
     "sbm100k-k50": ("sbm", 100_000, 50, 36, 4, 25, True),
     "knn70k": ("knn", 70_000, 10, None, None, 40, False),
@@ -66,6 +69,8 @@ def run(name, trials, methods=None):
         "fsc": lambda s: fsc.cluster(ip, ix, w, k, l, t, s),
         "fsc-l+1": lambda s: fsc.cluster(ip, ix, w, k, l + 1, t, s),
     }
+    if k <= 8:
+        runs["pm-k"] = lambda s: fsc.cluster_pmk(ip, ix, w, k, t, s)[0]
     if WORKLOADS[name][0] == "sbm":
         from paper_2310_10939_amd.train_filter import PARAMS_FILE
         params = torch.from_numpy(np.load(PARAMS_FILE)).to(dev)
