@@ -345,6 +345,33 @@ def fast_spectral_cluster(n, indptr, indices, data, k, l, t, seed, kmeans_iters,
 
 
 # ----------------------------------------------------------------------------
+# k nearest neighbours: the pre-processing of the real-world data (Sec. 4.2)
+# ----------------------------------------------------------------------------
+def knn_rows(X, rows, knn):
+    """The knn nearest other points of each listed row of X by squared
+    Euclidean distance, brute force in float64 from the coordinate
+    differences; ties to the lower index.  Returns (indices, squared
+    distances), each len(rows) x knn, nearest first."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    rows = np.asarray(rows, dtype=np.int64)
+    nbr = np.empty((len(rows), knn), dtype=np.int64)
+    dist = np.empty((len(rows), knn))
+    for i, q in enumerate(rows):
+        d = ((X - X[q]) ** 2).sum(axis=1)
+        d[q] = np.inf
+        order = np.lexsort((np.arange(n), d))[:knn]
+        nbr[i] = order
+        dist[i] = d[order]
+    return nbr, dist
+
+
+def knn(X, knn):
+    """knn_rows over every row."""
+    return knn_rows(X, np.arange(np.asarray(X).shape[0]), knn)
+
+
+# ----------------------------------------------------------------------------
 # PM with k vectors: the comparison method of Sec. 4 (Boutsidis et al.), which
 # Sec. 1.1 describes as the power method on k vectors plus a singular value
 # decomposition

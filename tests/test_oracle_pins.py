@@ -450,3 +450,36 @@ def test_pm_k_rank_deficient_block_leaves_zero_columns():
     assert np.all(E[:, 3:] == 0.0)
     U = np.sqrt(2.0) * E[:3, :3]
     assert np.abs(U.T @ U - np.eye(3)).max() < 1e-12
+
+
+# ---- k nearest neighbours (the pre-processing of Sec. 4.2) ----
+def test_knn_on_a_line_is_the_closed_form():
+    # x_i = i on the first axis: the neighbours of i are i-1, i+1, i-2, i+2, ...
+    # (each equal pair to the lower index first), clipped at the ends
+    n = 40
+    X = np.zeros((n, 4))
+    X[:, 0] = np.arange(n)
+    nbr, dist = o.knn(X, 6)
+    for i in range(n):
+        want = sorted((j for j in range(n) if j != i), key=lambda j: ((j - i) ** 2, j))[:6]
+        assert list(nbr[i]) == want
+        assert np.array_equal(dist[i], [(j - i) ** 2 for j in want])
+    assert list(nbr[10]) == [9, 11, 8, 12, 7, 13]
+
+
+def test_knn_matches_a_kd_tree():
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((500, 12))
+    nbr, dist = o.knn(X, 10)
+    dd, ii = cKDTree(X).query(X, k=11)
+    assert np.array_equal(nbr, ii[:, 1:])
+    assert np.allclose(dist, dd[:, 1:] ** 2, rtol=1e-12)
+
+
+def test_knn_ties_and_duplicates_go_to_the_lower_index():
+    X = np.zeros((6, 4))
+    X[3:] = 1.0                      # two groups of three identical points
+    nbr, dist = o.knn(X, 4)
+    assert list(nbr[0]) == [1, 2, 3, 4] and list(dist[0]) == [0, 0, 4, 4]
+    assert list(nbr[4]) == [3, 5, 0, 1]
