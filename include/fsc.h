@@ -309,6 +309,19 @@ int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t 
 int fsc_cluster_pmk(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t t, uint64_t seed,
                     const fsc_opts* opts, int32_t* labels, float* emb, double* sigma, void* stream);
 
+/* Exact k nearest neighbours of every point, the pre-processing of the
+ * real-world data in Sec. 4.2 (each point joined to its 10 nearest).  X is a
+ * device FP32 matrix of n rows of dim values (row-major, 16-byte aligned).
+ * For each row q, nbr[q*knn + j] (int32, device) receives the index of its
+ * j-th nearest other row by squared Euclidean distance, and dist[q*knn + j]
+ * (FP32, device) that squared distance, |x_q|^2 + |x_c|^2 - 2 x_q.x_c with
+ * the dot product on FP32 matrix cores (clamped at 0).  Self is excluded;
+ * ties go to the lower index; the list is in ascending order.  Needs
+ * 2 <= n <= 2^30, dim a multiple of 4 in [4, 1024], 1 <= knn <= min(16, n-1).
+ * Symmetrisation and edge weights are the caller's. */
+int fsc_knn(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int32_t knn, int32_t* nbr,
+            float* dist, void* stream);
+
 /* Adjusted Rand index (Hubert and Arabie; the accuracy score of Sec. 4.2)
  * between labelings a (values in [0, ka)) and b (values in [0, kb)) of n
  * items, written as one FP64 value to device memory `out`.  If both labelings

@@ -348,6 +348,23 @@ int fsc_cluster_pmk(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t t, ui
   return pmk_cluster_run(&ctx->c, g, k, t, seed, o, labels, emb, sigma, static_cast<hipStream_t>(stream));
 }
 
+int fsc_knn(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int32_t knn, int32_t* nbr, float* dist,
+            void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (!X || !nbr || !dist) return fail(FSC_E_ARG, "null pointer");
+  if (n < 2 || n > (1 << 30)) return fail(FSC_E_ARG, "n must be in [2, 2^30]");
+  if (dim < 4 || dim > 1024 || dim % 4 != 0) return fail(FSC_E_ARG, "dim must be a multiple of 4 in [4, 1024]");
+  if (knn < 1 || knn > 16 || knn > n - 1) return fail(FSC_E_ARG, "knn must be in [1, min(16, n - 1)]");
+  if (reinterpret_cast<uintptr_t>(X) % 16 != 0) return fail(FSC_E_ARG, "X must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  Arena arena;
+  if ((rc = reserve_arena(&ctx->c, align_up((size_t)n * 4) + 256, &arena))) return rc;
+  float* norms = arena.take<float>((size_t)n);
+  return knn_run(X, n, dim, knn, norms, nbr, dist, s);
+}
+
 int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, int32_t l, int32_t k, int32_t iters,
                uint64_t seed, const uint8_t* eligible, int32_t* labels, float* centres, void* stream) {
   if (!ctx) return fail(FSC_E_ARG, "context is NULL");

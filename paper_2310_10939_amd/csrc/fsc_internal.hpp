@@ -309,6 +309,9 @@ size_t pmk_workspace_bytes(int64_t n, int KD);
 int pmk_run(const EmbedIO* io, float* pts, int KD, int k, double* partials, float* W, double* sigma, float* emb,
             hipStream_t s);
 
+// ---- k-nearest neighbours (fsc_knn.hip) ----
+int knn_run(const float* X, int64_t n, int dim, int knn, float* norms, int32_t* nbr, float* dist, hipStream_t s);
+
 // ---- ARI and NMI (fsc_ari.hip) ----
 int ari_run(Context* ctx, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,
             unsigned long long* table, hipStream_t s);

@@ -68,6 +68,7 @@ _lib.fsc_cluster_filtered.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64
                                       ctypes.POINTER(Opts), _vp, _vp, _vp, ctypes.POINTER(_i32), _vp]
 _lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
 _lib.fsc_nmi.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
+_lib.fsc_knn.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]
 _lib.fsc_cluster_pmk.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp, _vp, _vp]
 _lib.fsc_tuning_set.argtypes = [_vp, ctypes.POINTER(Tuning)]
 _lib.fsc_timing_enable.argtypes = [_vp, ctypes.c_int]
@@ -78,7 +79,7 @@ _lib.fsc_version.restype = ctypes.c_int
 EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari", "fsc_nmi",
            "fsc_cluster_batched", "fsc_autotune", "fsc_mlp_param_count", "fsc_filter_stats",
            "fsc_mlp_forward", "fsc_mlp_loss_grad", "fsc_mlp_adam", "fsc_mlp_train", "fsc_filter_embed",
-           "fsc_cluster_filtered", "fsc_cluster_pmk",
+           "fsc_cluster_filtered", "fsc_cluster_pmk", "fsc_knn",
            "fsc_tuning_set", "fsc_timing_enable", "fsc_timing_read", "fsc_last_error", "fsc_version")
 
 
@@ -331,6 +332,17 @@ def cluster_filtered(indptr, indices, data, k, l, seed, params=None, coeffs=None
     if diagnostics:
         return labels, cout, bool(used.value), diag
     return labels, cout, bool(used.value)
+
+
+def knn(X, k):
+    """Exact k nearest neighbours (k <= 16) of the rows of a contiguous FP32
+    device matrix: (indices int32 [n, k], squared distances FP32 [n, k])."""
+    assert X.dtype == torch.float32 and X.is_contiguous() and X.dim() == 2
+    n, dim = X.shape
+    nbr = torch.empty((n, k), dtype=torch.int32, device=X.device)
+    dist = torch.empty((n, k), dtype=torch.float32, device=X.device)
+    _check(_lib.fsc_knn(context(X.device.index), _ptr(X), n, dim, k, _ptr(nbr), _ptr(dist), _stream()))
+    return nbr, dist
 
 
 def kmeans(points, k, iters, seed, eligible=None):
