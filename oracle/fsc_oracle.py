@@ -371,6 +371,33 @@ def knn(X, knn):
     return knn_rows(X, np.arange(np.asarray(X).shape[0]), knn)
 
 
+def knn_graph(X, k):
+    """The symmetrised kNN graph (Sec. 4.2 joins each point to its k
+    nearest).  Readings: the union of the directed edges; weight
+    exp(-d / sigma^2) with sigma^2 the median of the directed squared
+    distances and d taken from the list of the pair's lower-indexed endpoint
+    when it holds the pair (all weights 1 if sigma^2 = 0).  Returns CSR
+    (indptr, indices, weights) with both directions, rows sorted by column."""
+    nbr, dist = knn(X, k)
+    n = nbr.shape[0]
+    sigma2 = float(np.median(dist))
+    pairs = {}
+    for u in range(n):
+        for j in range(k):
+            v = int(nbr[u, j])
+            key = (min(u, v), max(u, v))
+            if key not in pairs:
+                pairs[key] = np.exp(-dist[u, j] / sigma2) if sigma2 > 0 else 1.0
+    rows, cols, ws = [], [], []
+    for (a, b), w in pairs.items():
+        rows += [a, b]
+        cols += [b, a]
+        ws += [w, w]
+    A = sp.csr_matrix((ws, (rows, cols)), shape=(n, n))
+    A.sort_indices()
+    return A.indptr.astype(np.int64), A.indices.astype(np.int64), A.data
+
+
 # ----------------------------------------------------------------------------
 # PM with k vectors: the comparison method of Sec. 4 (Boutsidis et al.), which
 # Sec. 1.1 describes as the power method on k vectors plus a singular value

@@ -483,3 +483,34 @@ def test_knn_ties_and_duplicates_go_to_the_lower_index():
     nbr, dist = o.knn(X, 4)
     assert list(nbr[0]) == [1, 2, 3, 4] and list(dist[0]) == [0, 0, 4, 4]
     assert list(nbr[4]) == [3, 5, 0, 1]
+
+
+def test_knn_graph_on_a_line_is_the_closed_form():
+    # x_i = i, 2 neighbours: the path plus the pairs {0, 2} and {n-3, n-1};
+    # directed distances are 1 except the two ends' second neighbours (4), so
+    # sigma^2 = 1
+    n = 30
+    X = np.zeros((n, 4))
+    X[:, 0] = np.arange(n)
+    indptr, indices, w = o.knn_graph(X, 2)
+    A = sp.csr_matrix((w, indices, indptr), shape=(n, n)).toarray()
+    want = np.zeros((n, n))
+    for i in range(n - 1):
+        want[i, i + 1] = want[i + 1, i] = np.exp(-1.0)
+    want[0, 2] = want[2, 0] = want[n - 3, n - 1] = want[n - 1, n - 3] = np.exp(-4.0)
+    assert np.array_equal(A, want)
+    assert all(np.all(np.diff(indices[indptr[r]:indptr[r + 1]]) > 0) for r in range(n))
+
+
+def test_knn_graph_is_the_union_of_the_directed_lists():
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((200, 8))
+    nbr, dist = o.knn(X, 5)
+    indptr, indices, w = o.knn_graph(X, 5)
+    A = sp.csr_matrix((w, indices, indptr), shape=(200, 200))
+    assert (A != A.T).nnz == 0
+    D = np.zeros((200, 200), dtype=bool)
+    D[np.repeat(np.arange(200), 5), nbr.ravel()] = True
+    assert np.array_equal(A.toarray() > 0, D | D.T)
+    s2 = np.median(dist)
+    assert np.allclose(A[0, nbr[0, 0]], np.exp(-dist[0, 0] / s2), rtol=1e-15)
