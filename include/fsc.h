@@ -322,6 +322,20 @@ int fsc_cluster_pmk(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t t, ui
 int fsc_knn(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int32_t knn, int32_t* nbr,
             float* dist, void* stream);
 
+/* The symmetrised kNN graph of the rows of X (the pre-processing of the
+ * real-world data in Sec. 4.2), built on the device: the neighbours of
+ * fsc_knn; sigma^2 = the median of the n*knn directed squared distances (the
+ * mean of the two middle values when n*knn is even); the union of the
+ * directed edges, each undirected pair {a, b} weighted exp(-d / sigma^2)
+ * with d the squared distance in the list of min(a, b) if that list holds the
+ * pair, else in the other's (all weights 1 when sigma^2 = 0).  Output CSR on
+ * the device, both directions stored, rows sorted by column: indptr (int64
+ * [n+1]; indptr[n] is the number of stored entries, between n*knn and
+ * 2*n*knn), indices (int32) and weights (FP32), each with room for 2*n*knn
+ * entries.  Same limits as fsc_knn, and 2*n*knn < 2^31. */
+int fsc_knn_graph(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int32_t knn, int64_t* indptr,
+                  int32_t* indices, float* weights, void* stream);
+
 /* Adjusted Rand index (Hubert and Arabie; the accuracy score of Sec. 4.2)
  * between labelings a (values in [0, ka)) and b (values in [0, kb)) of n
  * items, written as one FP64 value to device memory `out`.  If both labelings

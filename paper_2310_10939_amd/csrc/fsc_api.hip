@@ -365,6 +365,23 @@ int fsc_knn(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int32_t kn
   return knn_run(X, n, dim, knn, norms, nbr, dist, s);
 }
 
+int fsc_knn_graph(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int32_t knn, int64_t* indptr,
+                  int32_t* indices, float* weights, void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (!X || !indptr || !indices || !weights) return fail(FSC_E_ARG, "null pointer");
+  if (n < 2 || n > (1 << 30)) return fail(FSC_E_ARG, "n must be in [2, 2^30]");
+  if (dim < 4 || dim > 1024 || dim % 4 != 0) return fail(FSC_E_ARG, "dim must be a multiple of 4 in [4, 1024]");
+  if (knn < 1 || knn > 16 || knn > n - 1) return fail(FSC_E_ARG, "knn must be in [1, min(16, n - 1)]");
+  if (2 * n * (int64_t)knn > INT32_MAX) return fail(FSC_E_ARG, "2 n knn must be below 2^31");
+  if (reinterpret_cast<uintptr_t>(X) % 16 != 0) return fail(FSC_E_ARG, "X must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  Arena arena;
+  if ((rc = reserve_arena(&ctx->c, knn_graph_workspace_bytes(n, knn), &arena))) return rc;
+  return knn_graph_run(&arena, X, n, dim, knn, indptr, indices, weights, s);
+}
+
 int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, int32_t l, int32_t k, int32_t iters,
                uint64_t seed, const uint8_t* eligible, int32_t* labels, float* centres, void* stream) {
   if (!ctx) return fail(FSC_E_ARG, "context is NULL");

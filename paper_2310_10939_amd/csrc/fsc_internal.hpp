@@ -311,6 +311,9 @@ int pmk_run(const EmbedIO* io, float* pts, int KD, int k, double* partials, floa
 
 // ---- k-nearest neighbours (fsc_knn.hip) ----
 int knn_run(const float* X, int64_t n, int dim, int knn, float* norms, int32_t* nbr, float* dist, hipStream_t s);
+size_t knn_graph_workspace_bytes(int64_t n, int knn);
+int knn_graph_run(Arena* a, const float* X, int64_t n, int dim, int knn, int64_t* indptr, int32_t* indices,
+                  float* weights, hipStream_t s);
 
 // ---- ARI and NMI (fsc_ari.hip) ----
 int ari_run(Context* ctx, const int32_t* a, const int32_t* b, int64_t n, int ka, int kb, double* out,

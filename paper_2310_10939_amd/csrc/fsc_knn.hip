@@ -7,6 +7,8 @@
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
 
+#include <hipcub/hipcub.hpp>
+
 #include <algorithm>
 #include <climits>
 
@@ -168,6 +170,151 @@ int knn_run(const float* X, int64_t n, int dim, int knn, float* norms, int32_t* 
   const int grid = (int)((n + kKnnQ - 1) / kKnnQ);
   hipLaunchKernelGGL(knn_kernel, dim3(grid), dim3(256), 0, s, X, norms, (int)n, dim, knn, nbr, dist);
   return check_hip(hipGetLastError(), "knn launch");
+}
+
+// ---- the symmetrised kNN graph ----
+// Directed edge e = u * knn + j (u -> nbr[e]) becomes the pair key
+// min * n + max.  After a stable sort of the keys, the first entry of each run
+// (the lower-indexed endpoint's list, which comes first in e) emits both
+// directions of the pair with weight exp(-d / sigma^2); the other entries emit
+// sentinels n * n, which sort after every real entry.  A second sort by
+// row * n + col orders the CSR, and a binary search per row finds its start.
+__global__ void kg_pair_kernel(const int32_t* __restrict__ nbr, int64_t E, int knn, int64_t n,
+                               unsigned long long* __restrict__ key, int32_t* __restrict__ val) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = e / knn, v = nbr[e];
+    key[e] = (unsigned long long)(u < v ? u * n + v : v * n + u);
+    val[e] = (int32_t)e;
+  }
+}
+
+// sigma^2: the median of the E sorted directed distances (the mean of the two
+// middle values when E is even).
+__global__ void kg_median_kernel(const float* __restrict__ sorted, int64_t E, float* __restrict__ sigma2) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int64_t m = E / 2;
+    *sigma2 = (E % 2) ? sorted[m] : 0.5f * (sorted[m - 1] + sorted[m]);
+  }
+}
+
+__global__ void kg_emit_kernel(const unsigned long long* __restrict__ key_s, const int32_t* __restrict__ val_s,
+                               const float* __restrict__ dist, const float* __restrict__ sigma2, int64_t E,
+                               int64_t n, unsigned long long* __restrict__ key2, float* __restrict__ w2) {
+  const float s2 = *sigma2;
+  const unsigned long long sentinel = (unsigned long long)n * (unsigned long long)n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long k = key_s[i];
+    if (i == 0 || key_s[i - 1] != k) {
+      const float d = dist[val_s[i]];
+      const float w = s2 > 0.f ? expf(-d / s2) : 1.f;
+      const unsigned long long a = k / (unsigned long long)n, b = k % (unsigned long long)n;
+      key2[2 * i] = a * (unsigned long long)n + b;
+      key2[2 * i + 1] = b * (unsigned long long)n + a;
+      w2[2 * i] = w;
+      w2[2 * i + 1] = w;
+    } else {
+      key2[2 * i] = sentinel;
+      key2[2 * i + 1] = sentinel;
+      w2[2 * i] = 0.f;
+      w2[2 * i + 1] = 0.f;
+    }
+  }
+}
+
+// indptr[r] = first sorted entry with key >= r * n (r = 0..n; indptr[n] = nnz);
+// the real entries' columns and weights.
+__global__ void kg_csr_kernel(const unsigned long long* __restrict__ key2_s, const float* __restrict__ w2_s,
+                              int64_t M, int64_t n, int64_t* __restrict__ indptr, int32_t* __restrict__ indices,
+                              float* __restrict__ weights) {
+  const unsigned long long nn = (unsigned long long)n;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n; r += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long target = (unsigned long long)r * nn;
+    int64_t lo = 0, hi = M;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (key2_s[mid] < target) lo = mid + 1;
+      else hi = mid;
+    }
+    indptr[r] = lo;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long k = key2_s[i];
+    if (k < nn * nn) {
+      indices[i] = (int32_t)(k % nn);
+      weights[i] = w2_s[i];
+    }
+  }
+}
+
+static int key_bits(unsigned long long maxkey) {
+  int b = 1;
+  while (b < 64 && (maxkey >> b) != 0) ++b;
+  return b;
+}
+
+// Scratch of the three radix sorts, queried with the counts and key widths
+// the run uses.
+static size_t kg_temp_bytes(int64_t n, int knn) {
+  const int64_t E = n * knn, M = 2 * E;
+  const unsigned long long nn = (unsigned long long)n * (unsigned long long)n;
+  size_t t1 = 0, t2 = 0, t3 = 0;
+  hipcub::DeviceRadixSort::SortKeys(nullptr, t1, (const float*)nullptr, (float*)nullptr, (int)E, 0, 32);
+  hipcub::DeviceRadixSort::SortPairs(nullptr, t2, (const unsigned long long*)nullptr, (unsigned long long*)nullptr,
+                                     (const int32_t*)nullptr, (int32_t*)nullptr, (int)E, 0, key_bits(nn - 1));
+  hipcub::DeviceRadixSort::SortPairs(nullptr, t3, (const unsigned long long*)nullptr, (unsigned long long*)nullptr,
+                                     (const float*)nullptr, (float*)nullptr, (int)M, 0, key_bits(nn));
+  return std::max(t1, std::max(t2, t3));
+}
+
+size_t knn_graph_workspace_bytes(int64_t n, int knn) {
+  const int64_t E = n * knn, M = 2 * E;
+  return align_up((size_t)n * 4) +                                    // norms
+         align_up((size_t)E * 4) * 3 +                                // nbr, dist, sorted distances
+         align_up((size_t)E * 8) * 2 + align_up((size_t)E * 4) * 2 +  // pair keys and edge ids, sorted
+         align_up((size_t)M * 8) * 2 + align_up((size_t)M * 4) * 2 +  // CSR keys and weights, sorted
+         align_up(64 * 4) + align_up(kg_temp_bytes(n, knn)) + 4096;
+}
+
+int knn_graph_run(Arena* a, const float* X, int64_t n, int dim, int knn, int64_t* indptr, int32_t* indices,
+                  float* weights, hipStream_t s) {
+  const int64_t E = n * knn, M = 2 * E;
+  float* norms = a->take<float>((size_t)n);
+  int32_t* nbr = a->take<int32_t>((size_t)E);
+  float* dist = a->take<float>((size_t)E);
+  float* dsort = a->take<float>((size_t)E);
+  unsigned long long* key = a->take<unsigned long long>((size_t)E);
+  unsigned long long* key_s = a->take<unsigned long long>((size_t)E);
+  int32_t* val = a->take<int32_t>((size_t)E);
+  int32_t* val_s = a->take<int32_t>((size_t)E);
+  unsigned long long* key2 = a->take<unsigned long long>((size_t)M);
+  unsigned long long* key2_s = a->take<unsigned long long>((size_t)M);
+  float* w2 = a->take<float>((size_t)M);
+  float* w2_s = a->take<float>((size_t)M);
+  float* sigma2 = a->take<float>(64);
+  size_t temp_bytes = kg_temp_bytes(n, knn);
+  void* temp = a->take<char>(temp_bytes);
+  if (a->used > a->size) return fail(FSC_E_NOMEM, "knn graph workspace too small");
+  int rc;
+  if ((rc = knn_run(X, n, dim, knn, norms, nbr, dist, s))) return rc;
+  const int blocks = (int)std::min<int64_t>((M + 255) / 256, 8192);
+  const unsigned long long nn = (unsigned long long)n * (unsigned long long)n;
+  if ((rc = check_hip(hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, dist, dsort, (int)E, 0, 32, s),
+                      "sort distances")))
+    return rc;
+  hipLaunchKernelGGL(kg_median_kernel, dim3(1), dim3(64), 0, s, dsort, E, sigma2);
+  hipLaunchKernelGGL(kg_pair_kernel, dim3(blocks), dim3(256), 0, s, nbr, E, knn, n, key, val);
+  if ((rc = check_hip(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, key, key_s, val, val_s, (int)E, 0,
+                                                         key_bits(nn - 1), s),
+                      "sort pairs")))
+    return rc;
+  hipLaunchKernelGGL(kg_emit_kernel, dim3(blocks), dim3(256), 0, s, key_s, val_s, dist, sigma2, E, n, key2, w2);
+  if ((rc = check_hip(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, key2, key2_s, w2, w2_s, (int)M, 0,
+                                                         key_bits(nn), s),
+                      "sort entries")))
+    return rc;
+  const int cblocks = (int)std::min<int64_t>((std::max<int64_t>(M, n + 1) + 255) / 256, 8192);
+  hipLaunchKernelGGL(kg_csr_kernel, dim3(cblocks), dim3(256), 0, s, key2_s, w2_s, M, n, indptr, indices, weights);
+  return check_hip(hipGetLastError(), "knn graph launch");
 }
 
 }  // namespace fsc

@@ -69,6 +69,7 @@ _lib.fsc_cluster_filtered.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64
 _lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
 _lib.fsc_nmi.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
 _lib.fsc_knn.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]
+_lib.fsc_knn_graph.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp]
 _lib.fsc_cluster_pmk.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp, _vp, _vp]
 _lib.fsc_tuning_set.argtypes = [_vp, ctypes.POINTER(Tuning)]
 _lib.fsc_timing_enable.argtypes = [_vp, ctypes.c_int]
@@ -79,7 +80,7 @@ _lib.fsc_version.restype = ctypes.c_int
 EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari", "fsc_nmi",
            "fsc_cluster_batched", "fsc_autotune", "fsc_mlp_param_count", "fsc_filter_stats",
            "fsc_mlp_forward", "fsc_mlp_loss_grad", "fsc_mlp_adam", "fsc_mlp_train", "fsc_filter_embed",
-           "fsc_cluster_filtered", "fsc_cluster_pmk", "fsc_knn",
+           "fsc_cluster_filtered", "fsc_cluster_pmk", "fsc_knn", "fsc_knn_graph",
            "fsc_tuning_set", "fsc_timing_enable", "fsc_timing_read", "fsc_last_error", "fsc_version")
 
 
@@ -343,6 +344,21 @@ def knn(X, k):
     dist = torch.empty((n, k), dtype=torch.float32, device=X.device)
     _check(_lib.fsc_knn(context(X.device.index), _ptr(X), n, dim, k, _ptr(nbr), _ptr(dist), _stream()))
     return nbr, dist
+
+
+def knn_graph(X, k):
+    """The symmetrised kNN graph of the rows of a contiguous FP32 device
+    matrix: device (indptr int64 [n+1], indices int32, weights FP32), trimmed
+    to the stored entries."""
+    assert X.dtype == torch.float32 and X.is_contiguous() and X.dim() == 2
+    n, dim = X.shape
+    indptr = torch.empty(n + 1, dtype=torch.int64, device=X.device)
+    indices = torch.empty(2 * n * k, dtype=torch.int32, device=X.device)
+    weights = torch.empty(2 * n * k, dtype=torch.float32, device=X.device)
+    _check(_lib.fsc_knn_graph(context(X.device.index), _ptr(X), n, dim, k, _ptr(indptr), _ptr(indices),
+                              _ptr(weights), _stream()))
+    nnz = int(indptr[-1])
+    return indptr, indices[:nnz], weights[:nnz]
 
 
 def kmeans(points, k, iters, seed, eligible=None):

@@ -95,3 +95,43 @@ def test_knn_full_size_sampled_rows(gpu_lib):
     say(f"  knn 70000 x 784, k=10: {ms:.1f} ms, {flops / ms / 1e9:.1f} TFLOP/s (FP32)")
     rows = np.concatenate([[0, 1, 69999], np.random.default_rng(4).integers(0, 70000, 29)])
     _check(gpu_lib, X, 10, rows=rows)
+
+
+def _graph(fsc, X, k):
+    ip, ix, w = fsc.knn_graph(torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda(), k)
+    return ip.cpu().numpy(), ix.cpu().numpy().astype(np.int64), w.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("case", ["line", "integer"])
+def test_knn_graph_exact_structure(gpu_lib, case):
+    rng = np.random.default_rng(5)
+    if case == "line":
+        X = np.zeros((301, 4), dtype=np.float32)
+        X[:, 0] = np.arange(301)
+        k = 2
+    else:
+        X = rng.integers(-2, 3, (1203, 12)).astype(np.float32)
+        k = 10
+    say(f"knn graph {case} n={X.shape[0]} k={k}")
+    ip, ix, w = _graph(gpu_lib, X, k)
+    oip, oix, ow = o.knn_graph(X, k)
+    assert np.array_equal(ip, oip) and np.array_equal(ix, oix)
+    assert np.all(np.abs(w - ow) <= 1e-6 * ow)
+
+
+def test_knn_graph_gaussian_mixture(gpu_lib):
+    X, _ = synth.gaussian_mixture(200, 5, 784, seed=2)
+    n, k = X.shape[0], 10
+    ip, ix, w = _graph(gpu_lib, X, k)
+    oip, oix, ow = o.knn_graph(X, k)
+    say(f"knn graph mixture n={n}: nnz {ip[-1]} vs oracle {oip[-1]}")
+    import scipy.sparse as sp
+    A = sp.csr_matrix((w, ix, ip), shape=(n, n))
+    B = sp.csr_matrix((ow, oix, oip), shape=(n, n))
+    assert (A != A.T).nnz == 0
+    assert np.all(np.diff(ip) >= k)
+    assert all(np.all(np.diff(ix[ip[r]:ip[r + 1]]) > 0) for r in range(n))
+    common = A.multiply(B > 0)
+    assert common.nnz >= 0.999 * B.nnz
+    rel = np.abs(common - B.multiply(A > 0)).max() / ow.min()
+    assert rel <= 1e-5
