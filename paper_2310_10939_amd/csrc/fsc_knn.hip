@@ -37,18 +37,24 @@ __global__ __launch_bounds__(256) void knn_norms_kernel(const float* __restrict_
   }
 }
 
-// Block b takes queries 32b .. 32b + 31.  Wave w computes the dot products of
+// Block b takes queries 32b .. 32b + 31, held in LDS for the whole run.
+// Candidates stream through LDS in chunks of 64 rows x 64 dimensions, loaded
+// once per block with coalesced 16-byte loads (the next chunk's loads are in
+// flight while the current one is used).  Wave w computes the dot products of
 // queries 16 (w & 1) + 0..15 with candidates 32 (w >> 1) + 0..31 of each tile
-// of 64: lane (col, kk) supplies dimensions k0 + 4 kk + s (s = 0..3) of query
+// of 64: lane (col, kk) supplies dimensions k + 4 kk + s (s = 0..3) of query
 // col and of candidate col, and receives the products of queries 4 kk + r
 // with candidate col.  The tile's products go through LDS to the selection:
 // thread t keeps the 16 nearest of the candidates 8 (t % 8) + 0..7 of every
 // tile for query t / 8, sorted by (distance, index).  At the end the 8 lists
 // of a query are merged.
+constexpr int kKnnLdc = kKnnC + 4;  // padded row of the candidate chunk
+
 __global__ __launch_bounds__(256) void knn_kernel(const float* __restrict__ X, const float* __restrict__ nrm,
                                                   int n, int dim, int knn, int32_t* __restrict__ nbr,
                                                   float* __restrict__ dist) {
   __shared__ __align__(16) float qs[kKnnQ * (kKnnMaxDim + 4)];
+  __shared__ __align__(16) float cs[kKnnC * kKnnLdc];
   __shared__ float dt[kKnnQ][kKnnC + 1];
   const int dim16 = (dim + 15) & ~15;
   const int ldq = dim16 + 4;
@@ -57,7 +63,6 @@ __global__ __launch_bounds__(256) void knn_kernel(const float* __restrict__ X, c
     const int r = i / dim16, c = i - r * dim16;
     qs[r * ldq + c] = (q0 + r < n && c < dim) ? X[(int64_t)(q0 + r) * dim + c] : 0.f;
   }
-  __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kk = lane >> 4;
@@ -74,29 +79,57 @@ __global__ __launch_bounds__(256) void knn_kernel(const float* __restrict__ X, c
     bi[j] = INT_MAX;
   }
   const float* qrow = qs + (qw + col) * ldq + 4 * kk;
+  const float* crow0 = cs + (cw + col) * kKnnLdc + 4 * kk;
+  const float* crow1 = crow0 + 16 * kKnnLdc;
   const knn_f4 zero = {0.f, 0.f, 0.f, 0.f};
 
-  for (int c0 = 0; c0 < n; c0 += kKnnC) {
-    const int ra = c0 + cw + col, rb = ra + 16;
-    const bool va = ra < n, vb = rb < n;
-    // rows and offsets are clamped into the matrix, so that even a load the
-    // compiler issues ahead of its condition stays inside X
-    const float* pa = X + (int64_t)(va ? ra : 0) * dim;
-    const float* pb = X + (int64_t)(vb ? rb : 0) * dim;
-    knn_f4 acc0 = zero, acc1 = zero;
-#pragma unroll 4
-    for (int k0 = 0; k0 < dim; k0 += 16) {
-      const bool kin = k0 + 4 * kk < dim;
-      const int ko = kin ? k0 + 4 * kk : 0;
-      const knn_f4 a = *reinterpret_cast<const knn_f4*>(qrow + k0);
-      const knn_f4 b0 = (va && kin) ? *reinterpret_cast<const knn_f4*>(pa + ko) : zero;
-      const knn_f4 b1 = (vb && kin) ? *reinterpret_cast<const knn_f4*>(pb + ko) : zero;
+  // chunk ci covers candidates 64 (ci / nkc) + 0..63, dimensions 64 (ci % nkc) + 0..63;
+  // thread t loads 16-byte pieces t + 256 i (i = 0..3): row piece / 16, dims 4 (piece % 16)
+  const int nkc = (dim + 63) / 64;
+  const int64_t total = (int64_t)((n + kKnnC - 1) / kKnnC) * nkc;
+  knn_f4 pre[4];
+  auto load = [&](int64_t ci) {
+    const int c0 = (int)(ci / nkc) * kKnnC, kc = (int)(ci % nkc) * 64;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b0[s], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b1[s], acc1, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) {
+      const int piece = threadIdx.x + 256 * i;
+      const int r = c0 + (piece >> 4), d = kc + 4 * (piece & 15);
+      const bool ok = r < n && d < dim;
+      // the address stays inside X even where the load is not wanted
+      const knn_f4 v = *reinterpret_cast<const knn_f4*>(X + (int64_t)(ok ? r : 0) * dim + (ok ? d : 0));
+      pre[i] = ok ? v : zero;
+    }
+  };
+  load(0);
+  knn_f4 acc0 = zero, acc1 = zero;
+  for (int64_t ci = 0; ci < total; ++ci) {
+    const int c0 = (int)(ci / nkc) * kKnnC, kc = (int)(ci % nkc) * 64;
+    __syncthreads();  // every wave is done with the previous chunk (and the query staging)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int piece = threadIdx.x + 256 * i;
+      *reinterpret_cast<knn_f4*>(cs + (piece >> 4) * kKnnLdc + 4 * (piece & 15)) = pre[i];
+    }
+    __syncthreads();
+    if (ci + 1 < total) load(ci + 1);
+    if (kc == 0) {
+      acc0 = zero;
+      acc1 = zero;
+    }
+#pragma unroll
+    for (int k = 0; k < 64; k += 16) {
+      if (kc + k < dim) {
+        const knn_f4 a = *reinterpret_cast<const knn_f4*>(qrow + kc + k);
+        const knn_f4 b0 = *reinterpret_cast<const knn_f4*>(crow0 + k);
+        const knn_f4 b1 = *reinterpret_cast<const knn_f4*>(crow1 + k);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b0[s], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b1[s], acc1, 0, 0, 0);
+        }
       }
     }
+    if (kc + 64 < dim) continue;  // more dimensions of this tile to come
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       dt[qw + 4 * kk + r][cw + col] = acc0[r];
@@ -126,8 +159,8 @@ __global__ __launch_bounds__(256) void knn_kernel(const float* __restrict__ X, c
         }
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
 
   // merge: the query buffer is free now
   float* ld = qs;                                          // [32][8][16] distances
