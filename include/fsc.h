@@ -309,6 +309,24 @@ int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t 
 int fsc_cluster_pmk(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t t, uint64_t seed,
                     const fsc_opts* opts, int32_t* labels, float* emb, double* sigma, void* stream);
 
+/* The eigenvector baselines of Sec. 4 ("k Eigenvectors" with m = k,
+ * "log(k) Eigenvectors" with m = log k): the m leading eigenvectors of M
+ * (the m smallest of the normalised Laplacian), computed by subspace
+ * iteration -- `cycles` rounds of `steps` power steps on m columns (the
+ * kernels of fsc_embed, the first round from the seeded Gaussian block),
+ * each round restarted from the orthonormal basis U of the last one (the
+ * orthonormalisation of fsc_cluster_pmk) -- then k-means exactly as
+ * fsc_cluster on the rows of D^{-1/2} U.  The span converges to the leading
+ * eigenvectors at the rate (gamma_{m+1} / gamma_m)^(cycles*steps).
+ * `labels` receives int32[n].  Optional outputs (NULL to skip): `emb` (FP32
+ * n x m, the rows k-means sees) and `gamma` (FP64 [m], the eigenvalue
+ * estimates sigma_j^(1/steps) of the last round, meaningful for cycles >= 2).
+ * 1 <= k <= min(n, 64), 1 <= m <= min(n, 8), cycles, steps >= 1; opts as for
+ * fsc_cluster (x0 and the traces are ignored). */
+int fsc_cluster_eigs(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t m, int32_t cycles, int32_t steps,
+                     uint64_t seed, const fsc_opts* opts, int32_t* labels, float* emb, double* gamma,
+                     void* stream);
+
 /* Exact k nearest neighbours of every point, the pre-processing of the
  * real-world data in Sec. 4.2 (each point joined to its 10 nearest).  X is a
  * device FP32 matrix of n rows of dim values (row-major, 16-byte aligned).

@@ -345,6 +345,29 @@ def fast_spectral_cluster(n, indptr, indices, data, k, l, t, seed, kmeans_iters,
 
 
 # ----------------------------------------------------------------------------
+# The eigenvector baselines of Sec. 4 ("k Eigenvectors", "log(k) Eigenvectors")
+# ----------------------------------------------------------------------------
+def eigs_embed(n, indptr, indices, data, m):
+    """The m leading eigenvectors F of M (the m smallest of the normalised
+    Laplacian, Sec. 2) from a dense symmetric eigendecomposition, embedded as
+    D^{-1/2} F like Algorithm 2's D^{-1/2} Y (isolated rows 0).  Returns
+    (E, gamma) with gamma the m largest eigenvalues, descending."""
+    M = signless_laplacian(n, indptr, indices, data).toarray()
+    gam, F = np.linalg.eigh(M)
+    F = F[:, ::-1][:, :m]
+    d = degrees(n, indptr, indices, data)
+    return inv_sqrt_degree(d)[:, None] * F, gam[::-1][:m].copy()
+
+
+def eigs_cluster(n, indptr, indices, data, k, m, seed, kmeans_iters):
+    """k-means (as in fast_spectral_cluster) on eigs_embed."""
+    E, _ = eigs_embed(n, indptr, indices, data, m)
+    d = degrees(n, indptr, indices, data)
+    labels, C = kmeans(E, k, kmeans_iters, seed, eligible=d > 0)
+    return labels, C, E
+
+
+# ----------------------------------------------------------------------------
 # k nearest neighbours: the pre-processing of the real-world data (Sec. 4.2)
 # ----------------------------------------------------------------------------
 def knn_rows(X, rows, knn):

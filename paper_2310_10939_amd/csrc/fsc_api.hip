@@ -245,6 +245,63 @@ static int pmk_cluster_run(Context* c, const fsc_csr* g, int k, int t, uint64_t 
   return kmeans_run(c, &km, s);
 }
 
+// Leading eigenvectors by subspace iteration: `cycles` rounds of `steps`
+// power steps on m columns, each round restarted from the orthonormalised
+// block of the last; then the same k-means as the plain method on
+// D^{-1/2} U.
+static int eigs_cluster_run(Context* c, const fsc_csr* g, int k, int m, int cycles, int steps, uint64_t seed,
+                            const fsc_opts& o, int32_t* labels, float* emb, double* gamma, hipStream_t s) {
+  int rc;
+  const int iters = o.kmeans_iters > 0 ? o.kmeans_iters : 30;
+  const int KD = kmeans_width(m);
+  const size_t extra = kmeans_workspace_bytes(g->n, KD) + align_up(g->n * KD * 4) + pmk_workspace_bytes(g->n, KD) +
+                       align_up((size_t)g->n * m * 8) + align_up(8 * 8) + 2048;
+  fsc_opts oc = o;
+  oc.x0 = nullptr;
+  oc.sqnorm_trace = nullptr;
+  oc.rayleigh_trace = nullptr;
+  EmbedIO io;
+  Arena arena;
+  if ((rc = prepare_embed(c, g, m, steps, seed, oc, extra, &io, &arena))) return rc;
+  KmeansIO km;
+  std::memset(&km, 0, sizeof(km));
+  km.n = g->n;
+  km.l = m;
+  km.KD = KD;
+  km.k = k;
+  km.iters = iters;
+  km.seed = seed;
+  km.labels = labels;
+  float* pts = arena.take<float>(g->n * KD);
+  double* partials = arena.take<double>((size_t)pmk_grid(g->n) * KD * (KD + 1) / 2);
+  float* W = arena.take<float>((size_t)KD * KD);
+  double* x0 = arena.take<double>((size_t)g->n * m);
+  double* sigma = arena.take<double>(8);
+  if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
+  if (arena.used > arena.size) return fail(FSC_E_NOMEM, "eigenvector workspace too small");
+  if (o.validate && (rc = validate_csr(c, g, s))) return rc;
+  for (int cy = 0; cy < cycles; ++cy) {
+    // the same arena layout every cycle: x0, pts and the k-means workspace
+    // sit after the embedding's region and survive the rebinding
+    if (cy > 0) {
+      oc.x0 = x0;
+      EmbedIO next;
+      Arena again;
+      if ((rc = prepare_embed(c, g, m, steps, seed, oc, extra, &next, &again))) return rc;
+      if (again.base != arena.base) return fail(FSC_E_HIP, "workspace moved between cycles");
+      io = next;
+    }
+    if ((rc = embed_run(c, &io, s))) return rc;
+    if ((rc = embed_to_points(c, &io, pts, s))) return rc;
+    if ((rc = pmk_run(&io, pts, KD, m, partials, W, sigma, cy + 1 == cycles ? emb : nullptr, s))) return rc;
+    if (cy + 1 < cycles && (rc = eig_restart_run(pts, io.deg, g->n, KD, m, x0, s))) return rc;
+  }
+  if (gamma && (rc = eig_gamma_run(sigma, m, steps, gamma, s))) return rc;
+  km.pts = pts;
+  km.elig = io.elig;
+  return kmeans_run(c, &km, s);
+}
+
 }  // namespace fsc
 
 using namespace fsc;
@@ -380,6 +437,21 @@ int fsc_knn_graph(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int3
   Arena arena;
   if ((rc = reserve_arena(&ctx->c, knn_graph_workspace_bytes(n, knn), &arena))) return rc;
   return knn_graph_run(&arena, X, n, dim, knn, indptr, indices, weights, s);
+}
+
+int fsc_cluster_eigs(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t m, int32_t cycles, int32_t steps,
+                     uint64_t seed, const fsc_opts* opts, int32_t* labels, float* emb, double* gamma, void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (!labels) return fail(FSC_E_ARG, "labels is NULL");
+  int rc;
+  if ((rc = check_csr(g))) return rc;
+  if (k < 1 || k > 64 || k > g->n) return fail(FSC_E_ARG, "k must be in [1, min(n, 64)]");
+  if (m < 1 || m > 8 || m > g->n) return fail(FSC_E_ARG, "m must be in [1, min(n, 8)]");
+  if (cycles < 1 || steps < 1) return fail(FSC_E_ARG, "cycles and steps must be >= 1");
+  const fsc_opts o = opts ? *opts : default_opts();
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  return eigs_cluster_run(&ctx->c, g, k, m, cycles, steps, seed, o, labels, emb, gamma,
+                          static_cast<hipStream_t>(stream));
 }
 
 int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, int32_t l, int32_t k, int32_t iters,

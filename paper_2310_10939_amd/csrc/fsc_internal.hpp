@@ -308,6 +308,8 @@ int pmk_grid(int64_t n);
 size_t pmk_workspace_bytes(int64_t n, int KD);
 int pmk_run(const EmbedIO* io, float* pts, int KD, int k, double* partials, float* W, double* sigma, float* emb,
             hipStream_t s);
+int eig_restart_run(const float* pts, const double* deg, int64_t n, int KD, int m, double* x0, hipStream_t s);
+int eig_gamma_run(const double* sigma, int m, int steps, double* gamma, hipStream_t s);
 
 // ---- k-nearest neighbours (fsc_knn.hip) ----
 int knn_run(const float* X, int64_t n, int dim, int knn, float* norms, int32_t* nbr, float* dist, hipStream_t s);

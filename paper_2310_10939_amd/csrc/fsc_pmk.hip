@@ -191,4 +191,36 @@ int pmk_run(const EmbedIO* io, float* pts, int KD, int k, double* partials, floa
   return check_hip(hipGetLastError(), "pmk launch");
 }
 
+// ---- subspace iteration for the leading eigenvectors of M ----
+// After each cycle of power steps the orthonormalised block restarts the
+// next: x0 = D^{1/2} (Z_t W) = U (y-space), in FP64 n x m.
+__global__ __launch_bounds__(kPmkBlock) void eig_restart_kernel(const float* __restrict__ pts,
+                                                                const double* __restrict__ deg, int64_t n,
+                                                                int KD, int m, double* __restrict__ x0) {
+  for (int64_t i = (int64_t)blockIdx.x * kPmkBlock + threadIdx.x; i < n * m; i += (int64_t)gridDim.x * kPmkBlock) {
+    const int64_t v = i / m;
+    const int j = (int)(i - v * m);
+    const double d = deg[v];
+    x0[i] = d > 0.0 ? sqrt(d) * (double)pts[v * KD + j] : 0.0;
+  }
+}
+
+// Eigenvalue estimates from the last cycle: its start block U is
+// orthonormal, so the singular values of M^s U tend to gamma_j^s.
+__global__ void eig_gamma_kernel(const double* __restrict__ sigma, int m, int steps, double* __restrict__ gamma) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    for (int j = 0; j < m; ++j) gamma[j] = steps > 0 && sigma[j] > 0.0 ? pow(sigma[j], 1.0 / steps) : 0.0;
+}
+
+int eig_restart_run(const float* pts, const double* deg, int64_t n, int KD, int m, double* x0, hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n * m + kPmkBlock - 1) / kPmkBlock, 8192));
+  hipLaunchKernelGGL(eig_restart_kernel, dim3(grid), dim3(kPmkBlock), 0, s, pts, deg, n, KD, m, x0);
+  return check_hip(hipGetLastError(), "eig restart launch");
+}
+
+int eig_gamma_run(const double* sigma, int m, int steps, double* gamma, hipStream_t s) {
+  hipLaunchKernelGGL(eig_gamma_kernel, dim3(1), dim3(64), 0, s, sigma, m, steps, gamma);
+  return check_hip(hipGetLastError(), "eig gamma launch");
+}
+
 }  // namespace fsc

@@ -69,6 +69,8 @@ _lib.fsc_cluster_filtered.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64
 _lib.fsc_ari.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
 _lib.fsc_nmi.argtypes = [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp]
 _lib.fsc_knn.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]
+_lib.fsc_cluster_eigs.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp,
+                                  _vp, _vp]
 _lib.fsc_knn_graph.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp]
 _lib.fsc_cluster_pmk.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp, _vp, _vp]
 _lib.fsc_tuning_set.argtypes = [_vp, ctypes.POINTER(Tuning)]
@@ -80,7 +82,7 @@ _lib.fsc_version.restype = ctypes.c_int
 EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari", "fsc_nmi",
            "fsc_cluster_batched", "fsc_autotune", "fsc_mlp_param_count", "fsc_filter_stats",
            "fsc_mlp_forward", "fsc_mlp_loss_grad", "fsc_mlp_adam", "fsc_mlp_train", "fsc_filter_embed",
-           "fsc_cluster_filtered", "fsc_cluster_pmk", "fsc_knn", "fsc_knn_graph",
+           "fsc_cluster_filtered", "fsc_cluster_pmk", "fsc_cluster_eigs", "fsc_knn", "fsc_knn_graph",
            "fsc_tuning_set", "fsc_timing_enable", "fsc_timing_read", "fsc_last_error", "fsc_version")
 
 
@@ -210,6 +212,22 @@ def cluster_pmk(indptr, indices, data, k, t, seed, kmeans_iters=30, vec_dtype="f
     _check(_lib.fsc_cluster_pmk(context(dev.index), ctypes.byref(g), k, t, seed, ctypes.byref(o), _ptr(labels),
                                 _ptr(emb), _ptr(sv), _stream()))
     return labels, emb, sv
+
+
+def cluster_eigs(indptr, indices, data, k, m, cycles, steps, seed, kmeans_iters=30, vec_dtype="f32"):
+    """Eigenvector baseline (m <= 8 leading eigenvectors by subspace
+    iteration): (labels int32 [n], embedding FP32 n x m, eigenvalue
+    estimates FP64 [m])."""
+    n = indptr.numel() - 1
+    dev = indptr.device
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    emb = torch.empty((n, m), dtype=torch.float32, device=dev)
+    gam = torch.empty(m, dtype=torch.float64, device=dev)
+    g = _csr(indptr, indices, data)
+    o = _opts(vec_dtype, kmeans_iters)
+    _check(_lib.fsc_cluster_eigs(context(dev.index), ctypes.byref(g), k, m, cycles, steps, seed, ctypes.byref(o),
+                                 _ptr(labels), _ptr(emb), _ptr(gam), _stream()))
+    return labels, emb, gam
 
 
 def cluster_batched(graphs, ks, ls, ts, seed, kmeans_iters=30, return_embedding=False, use_graph=True):

@@ -13,6 +13,9 @@ Methods:
   fsc-l+1    the same with one more vector than log2 k
   pm-k       PM with k vectors (the comparison method of Sec. 4: k power
              vectors and one SVD), for k <= 8, same t
+  k-eigs     the k leading eigenvectors of M (Sec. 4's "k Eigenvectors"), by
+             subspace iteration: 4 rounds of t steps, for k <= 8
+  logk-eigs  the same with l = ceil(log2 k) eigenvectors ("log(k) Eigenvectors")
   learned    the learned polynomial filter with the shipped parameters and the
              plain method as its fallback (SBM workloads only: the filter was
              trained on SBM graphs)
@@ -36,6 +39,8 @@ if ROOT not in sys.path:
 
 # name: (kind, n, k, mean in-cluster degree, mean cross degree, t, permuted) for
 # SBM graphs; the kNN entry is 70,000 points of 10 Gaussians in 784 dims
+EIG_CYCLES = 4
+
 WORKLOADS = {
     "sbm1m": ("sbm", 1_000_000, 10, 36, 4, 30, True),
     "sbm1m-k8": ("sbm", 1_000_000, 8, 36, 4, 30, True),
@@ -71,6 +76,8 @@ def run(name, trials, methods=None):
     }
     if k <= 8:
         runs["pm-k"] = lambda s: fsc.cluster_pmk(ip, ix, w, k, t, s)[0]
+        runs["k-eigs"] = lambda s: fsc.cluster_eigs(ip, ix, w, k, k, EIG_CYCLES, t, s)[0]
+    runs["logk-eigs"] = lambda s: fsc.cluster_eigs(ip, ix, w, k, min(l, 8), EIG_CYCLES, t, s)[0]
     if WORKLOADS[name][0] == "sbm":
         from paper_2310_10939_amd.train_filter import PARAMS_FILE
         params = torch.from_numpy(np.load(PARAMS_FILE)).to(dev)

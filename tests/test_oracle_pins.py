@@ -514,3 +514,27 @@ def test_knn_graph_is_the_union_of_the_directed_lists():
     assert np.array_equal(A.toarray() > 0, D | D.T)
     s2 = np.median(dist)
     assert np.allclose(A[0, nbr[0, 0]], np.exp(-dist[0, 0] / s2), rtol=1e-15)
+
+
+# ---- eigenvector baselines (Sec. 4) ----
+def test_eigs_on_disjoint_cliques_spans_the_cluster_indicators():
+    g = synth.disjoint_cliques(3, 7)
+    E, gam = o.eigs_embed(g.n, g.indptr, g.indices, g.data, 3)
+    assert np.allclose(gam, 1.0, atol=1e-12)                 # eigenvalue 1 once per component
+    U = np.sqrt(6.0) * E
+    B = np.zeros((g.n, 3))
+    B[np.arange(g.n), g.labels] = 1.0 / np.sqrt(7.0)
+    assert np.linalg.svd(B.T @ U, compute_uv=False).min() > 1 - 1e-12
+
+
+def test_eigs_satisfy_the_eigen_equation_and_match_a_sparse_solver():
+    from scipy.sparse.linalg import eigsh
+    g = synth.sbm(400, 4, 0.2, 0.01, seed=3)
+    E, gam = o.eigs_embed(g.n, g.indptr, g.indices, g.data, 4)
+    M, d = _dense_M(g)
+    F = np.sqrt(d)[:, None] * E
+    assert np.abs(M @ F - F * gam).max() < 1e-12
+    assert np.abs(F.T @ F - np.eye(4)).max() < 1e-12
+    w, V = eigsh(M, k=4, which="LA", tol=1e-14)
+    assert np.allclose(np.sort(w)[::-1], gam, atol=1e-10)
+    assert np.linalg.svd(V.T @ F, compute_uv=False).min() > 1 - 1e-10
