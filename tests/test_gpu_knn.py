@@ -95,6 +95,16 @@ def test_knn_full_size_sampled_rows(gpu_lib):
     say(f"  knn 70000 x 784, k=10: {ms:.1f} ms, {flops / ms / 1e9:.1f} TFLOP/s (FP32)")
     rows = np.concatenate([[0, 1, 69999], np.random.default_rng(4).integers(0, 70000, 29)])
     _check(gpu_lib, X, 10, rows=rows)
+    # the whole graph builder at this size: timing and the CSR's invariants
+    gpu_lib.knn_graph(Xt, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ip, ix, w = gpu_lib.knn_graph(Xt, 10)
+    torch.cuda.synchronize()
+    say(f"  knn graph 70000 x 784, k=10: {(time.perf_counter() - t0) * 1e3:.1f} ms, nnz {int(ip[-1])}")
+    deg = torch.diff(ip)
+    assert int(deg.min()) >= 10 and 700000 <= int(ip[-1]) <= 1400000
+    assert float(w.min()) > 0.0 and float(w.max()) <= 1.0
 
 
 def _graph(fsc, X, k):
