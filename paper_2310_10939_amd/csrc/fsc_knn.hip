@@ -17,10 +17,8 @@ namespace fsc {
 typedef float knn_f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kKnnQ = 32;         // queries per block
-constexpr int kKnnC = 64;         // candidates per tile
-constexpr int kKnnMaxDim = 1024;  // longest point the query buffer holds
 constexpr int kKnnList = 16;      // entries of each partial list
-constexpr int kKnnParts = 8;      // partial lists per query
+constexpr int kKnnPerPart = 8;    // candidates of a tile per partial list
 
 // |x_v|^2 in FP64, one wave per row, rounded to FP32.
 __global__ __launch_bounds__(256) void knn_norms_kernel(const float* __restrict__ X, int64_t n, int dim,
@@ -38,28 +36,36 @@ __global__ __launch_bounds__(256) void knn_norms_kernel(const float* __restrict_
 }
 
 // Block b takes queries 32b .. 32b + 31, held in LDS for the whole run.
-// Candidates stream through LDS in chunks of 64 rows x 64 dimensions, loaded
-// once per block with coalesced 16-byte loads (the next chunk's loads are in
-// flight while the current one is used).  Wave w computes the dot products of
-// queries 16 (w & 1) + 0..15 with candidates 32 (w >> 1) + 0..31 of each tile
-// of 64: lane (col, kk) supplies dimensions k + 4 kk + s (s = 0..3) of query
-// col and of candidate col, and receives the products of queries 4 kk + r
-// with candidate col.  The tile's products go through LDS to the selection:
-// thread t keeps the 16 nearest of the candidates 8 (t % 8) + 0..7 of every
-// tile for query t / 8, sorted by (distance, index).  At the end the 8 lists
-// of a query are merged.
-constexpr int kKnnLdc = kKnnC + 4;  // padded row of the candidate chunk
-
-__global__ __launch_bounds__(256) void knn_kernel(const float* __restrict__ X, const float* __restrict__ nrm,
-                                                  int n, int dim, int knn, int32_t* __restrict__ nbr,
-                                                  float* __restrict__ dist) {
-  __shared__ __align__(16) float qs[kKnnQ * (kKnnMaxDim + 4)];
-  __shared__ __align__(16) float cs[kKnnC * kKnnLdc];
-  __shared__ float dt[kKnnQ][kKnnC + 1];
+// Candidates stream through LDS in chunks of C = 16 NW rows x 64 dimensions
+// (NW waves per block), loaded once per block with coalesced 16-byte loads
+// (the next chunk's loads are in flight while the current one is used).
+// Wave w computes the dot products of queries 16 (w & 1) + 0..15 with
+// candidates 32 (w >> 1) + 0..31 of each tile of C: lane (col, kk) supplies
+// dimensions k + 4 kk + s (s = 0..3) of query col and of candidate col, and
+// receives the products of queries 4 kk + r with candidate col.  The tile's
+// products go through LDS to the selection: thread t keeps the 16 nearest of
+// the candidates 8 (t % P) + 0..7 of every tile for query t / P (P = 2 NW
+// partial lists per query), sorted by (distance, index).  At the end the P
+// lists of a query are merged.  MAXD bounds the dimension the query buffer
+// holds: 8 waves with MAXD = 800 and 4 waves with MAXD = 1024 both fit LDS.
+template <int NW, int MAXD>
+__global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ X, const float* __restrict__ nrm,
+                                                      int n, int dim, int knn, int32_t* __restrict__ nbr,
+                                                      float* __restrict__ dist) {
+  constexpr int NT = 64 * NW;          // threads
+  constexpr int C = 16 * NW;           // candidates per tile
+  constexpr int LDC = 64 + 4;          // padded row of the candidate chunk
+  constexpr int P = NT / kKnnQ;        // partial lists per query
+  static_assert(C == P * kKnnPerPart, "each tile candidate belongs to one list");
+  static_assert(C * 16 == 4 * NT, "four 16-byte pieces per thread per chunk");
+  static_assert(kKnnQ * P * kKnnList * 2 <= kKnnQ * (MAXD + 4), "the merge fits the query buffer");
+  __shared__ __align__(16) float qs[kKnnQ * (MAXD + 4)];
+  __shared__ __align__(16) float cs[C * LDC];
+  __shared__ float dt[kKnnQ][C + 1];
   const int dim16 = (dim + 15) & ~15;
   const int ldq = dim16 + 4;
   const int q0 = blockIdx.x * kKnnQ;
-  for (int i = threadIdx.x; i < kKnnQ * dim16; i += 256) {
+  for (int i = threadIdx.x; i < kKnnQ * dim16; i += NT) {
     const int r = i / dim16, c = i - r * dim16;
     qs[r * ldq + c] = (q0 + r < n && c < dim) ? X[(int64_t)(q0 + r) * dim + c] : 0.f;
   }
@@ -68,7 +74,7 @@ __global__ __launch_bounds__(256) void knn_kernel(const float* __restrict__ X, c
   const int col = lane & 15, kk = lane >> 4;
   const int qw = (wave & 1) * 16;
   const int cw = (wave >> 1) * 32;
-  const int tq = threadIdx.x >> 3, te = threadIdx.x & 7;
+  const int tq = threadIdx.x / P, te = threadIdx.x % P;
   const int gq = q0 + tq;
   const float qn = gq < n ? nrm[gq] : 0.f;
   float bd[kKnnList];
@@ -79,20 +85,20 @@ __global__ __launch_bounds__(256) void knn_kernel(const float* __restrict__ X, c
     bi[j] = INT_MAX;
   }
   const float* qrow = qs + (qw + col) * ldq + 4 * kk;
-  const float* crow0 = cs + (cw + col) * kKnnLdc + 4 * kk;
-  const float* crow1 = crow0 + 16 * kKnnLdc;
+  const float* crow0 = cs + (cw + col) * LDC + 4 * kk;
+  const float* crow1 = crow0 + 16 * LDC;
   const knn_f4 zero = {0.f, 0.f, 0.f, 0.f};
 
-  // chunk ci covers candidates 64 (ci / nkc) + 0..63, dimensions 64 (ci % nkc) + 0..63;
-  // thread t loads 16-byte pieces t + 256 i (i = 0..3): row piece / 16, dims 4 (piece % 16)
+  // chunk ci covers candidates C (ci / nkc) + 0..C-1, dimensions 64 (ci % nkc) + 0..63;
+  // thread t loads 16-byte pieces t + NT i (i = 0..3): row piece / 16, dims 4 (piece % 16)
   const int nkc = (dim + 63) / 64;
-  const int64_t total = (int64_t)((n + kKnnC - 1) / kKnnC) * nkc;
+  const int64_t total = (int64_t)((n + C - 1) / C) * nkc;
   knn_f4 pre[4];
   auto load = [&](int64_t ci) {
-    const int c0 = (int)(ci / nkc) * kKnnC, kc = (int)(ci % nkc) * 64;
+    const int c0 = (int)(ci / nkc) * C, kc = (int)(ci % nkc) * 64;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int piece = threadIdx.x + 256 * i;
+      const int piece = threadIdx.x + NT * i;
       const int r = c0 + (piece >> 4), d = kc + 4 * (piece & 15);
       const bool ok = r < n && d < dim;
       // the address stays inside X even where the load is not wanted
@@ -103,12 +109,12 @@ __global__ __launch_bounds__(256) void knn_kernel(const float* __restrict__ X, c
   load(0);
   knn_f4 acc0 = zero, acc1 = zero;
   for (int64_t ci = 0; ci < total; ++ci) {
-    const int c0 = (int)(ci / nkc) * kKnnC, kc = (int)(ci % nkc) * 64;
+    const int c0 = (int)(ci / nkc) * C, kc = (int)(ci % nkc) * 64;
     __syncthreads();  // every wave is done with the previous chunk (and the query staging)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int piece = threadIdx.x + 256 * i;
-      *reinterpret_cast<knn_f4*>(cs + (piece >> 4) * kKnnLdc + 4 * (piece & 15)) = pre[i];
+      const int piece = threadIdx.x + NT * i;
+      *reinterpret_cast<knn_f4*>(cs + (piece >> 4) * LDC + 4 * (piece & 15)) = pre[i];
     }
     __syncthreads();
     if (ci + 1 < total) load(ci + 1);
@@ -137,8 +143,8 @@ __global__ __launch_bounds__(256) void knn_kernel(const float* __restrict__ X, c
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kKnnC / kKnnParts; ++j) {
-      const int cl = te * (kKnnC / kKnnParts) + j;
+    for (int j = 0; j < kKnnPerPart; ++j) {
+      const int cl = te * kKnnPerPart + j;
       const int c = c0 + cl;
       if (c < n && c != gq) {
         const float d = fmaxf(qn + nrm[c] - 2.f * dt[tq][cl], 0.f);
@@ -163,33 +169,33 @@ __global__ __launch_bounds__(256) void knn_kernel(const float* __restrict__ X, c
   __syncthreads();
 
   // merge: the query buffer is free now
-  float* ld = qs;                                          // [32][8][16] distances
-  int* li = reinterpret_cast<int*>(qs + kKnnQ * kKnnParts * kKnnList);  // and indices
+  float* ld = qs;                                                 // [32][P][16] distances
+  int* li = reinterpret_cast<int*>(qs + kKnnQ * P * kKnnList);     // and indices
 #pragma unroll
   for (int j = 0; j < kKnnList; ++j) {
-    ld[(tq * kKnnParts + te) * kKnnList + j] = bd[j];
-    li[(tq * kKnnParts + te) * kKnnList + j] = bi[j];
+    ld[(tq * P + te) * kKnnList + j] = bd[j];
+    li[(tq * P + te) * kKnnList + j] = bi[j];
   }
   __syncthreads();
   if (threadIdx.x < kKnnQ && q0 + (int)threadIdx.x < n) {
     const int q = threadIdx.x;
-    int head[kKnnParts];
-    for (int e = 0; e < kKnnParts; ++e) head[e] = 0;
+    int head[P];
+    for (int e = 0; e < P; ++e) head[e] = 0;
     for (int o = 0; o < knn; ++o) {
       int be = -1;
       float bdv = __builtin_inff();
       int biv = INT_MAX;
-      for (int e = 0; e < kKnnParts; ++e) {
+      for (int e = 0; e < P; ++e) {
         if (head[e] >= kKnnList) continue;
-        const float d = ld[(q * kKnnParts + e) * kKnnList + head[e]];
-        const int i = li[(q * kKnnParts + e) * kKnnList + head[e]];
+        const float d = ld[(q * P + e) * kKnnList + head[e]];
+        const int i = li[(q * P + e) * kKnnList + head[e]];
         if (be < 0 || d < bdv || (d == bdv && i < biv)) {
           be = e;
           bdv = d;
           biv = i;
         }
       }
-      if (be < 0) break;  // cannot happen: 128 entries cover knn <= 16
+      if (be < 0) break;  // cannot happen: P * 16 entries cover knn <= 16
       head[be] += 1;
       nbr[(int64_t)(q0 + q) * knn + o] = biv;
       dist[(int64_t)(q0 + q) * knn + o] = bdv;
@@ -201,7 +207,10 @@ int knn_run(const float* X, int64_t n, int dim, int knn, float* norms, int32_t* 
   const int nb = (int)std::min<int64_t>((n + 3) / 4, 8192);
   hipLaunchKernelGGL(knn_norms_kernel, dim3(nb), dim3(256), 0, s, X, n, dim, norms);
   const int grid = (int)((n + kKnnQ - 1) / kKnnQ);
-  hipLaunchKernelGGL(knn_kernel, dim3(grid), dim3(256), 0, s, X, norms, (int)n, dim, knn, nbr, dist);
+  if (dim <= 800)
+    hipLaunchKernelGGL((knn_kernel<8, 800>), dim3(grid), dim3(512), 0, s, X, norms, (int)n, dim, knn, nbr, dist);
+  else
+    hipLaunchKernelGGL((knn_kernel<4, 1024>), dim3(grid), dim3(256), 0, s, X, norms, (int)n, dim, knn, nbr, dist);
   return check_hip(hipGetLastError(), "knn launch");
 }
 

@@ -58,6 +58,13 @@ def test_knn_ragged_dim_and_largest_k(gpu_lib):
     _check(gpu_lib, X, 16)
 
 
+@pytest.mark.parametrize("dim", [800, 804, 1024])
+def test_knn_both_block_shapes(gpu_lib, dim):
+    # up to 800 dimensions the 8-wave block, above it the 4-wave one
+    X = np.random.default_rng(dim).standard_normal((700, dim)).astype(np.float32)
+    _check(gpu_lib, X, 10)
+
+
 def test_knn_smallest_case(gpu_lib):
     X = np.array([[0, 0, 0, 0], [1, 2, 3, 4]], dtype=np.float32)
     _check(gpu_lib, X, 1, exact=True)
