@@ -422,41 +422,68 @@ def knn_graph(X, k):
 
 
 # ----------------------------------------------------------------------------
-# PM with k vectors: the comparison method of Sec. 4 (Boutsidis et al.), which
-# Sec. 1.1 describes as the power method on k vectors plus a singular value
-# decomposition
+# PM with k vectors: the comparison method of Sec. 4, whose embedding is k
+# mutually orthogonal vectors obtained by the power method (the algorithm of
+# Boutsidis et al.; Sec. 1.1 notes its extra singular value decomposition)
 # ----------------------------------------------------------------------------
-def pm_k_embed(n, indptr, indices, data, k, t, seed=None, x0=None):
-    """Y = M^t X0 for k Gaussian columns (Algorithm 1 on each), then the left
-    singular vectors U of Y, and the embedding D^{-1/2} U.
+PMK_CUT = 1e-12
 
-    Readings: the orthonormalisation is one SVD at the end (the span is the
-    one a QR after every step gives, in exact arithmetic); the SVD runs over
-    the non-isolated rows (an isolated vertex has no D^{-1/2}, and its row
-    stays 0); columns come in descending order of singular value, a column
-    whose singular value is at most 1e-6 of the largest is 0 (a direction
-    that FP32 rows, which the device path stores, cannot resolve), and each
-    column's sign makes the largest-magnitude entry of its right singular
-    vector positive (the first such entry on a tie)."""
+
+def orthonormal_basis(Y):
+    """An orthonormal basis of the columns of Y (rows x k): the left singular
+    vectors (LAPACK's SVD in float64), in descending order of singular value,
+    a column whose singular value is at most PMK_CUT of the largest set to 0
+    (float64 cannot tell that direction from none).  Fewer rows than k leave
+    the trailing columns 0.  Returns (U, sigma), both padded to k columns."""
+    rows, k = Y.shape
+    U = np.zeros((rows, k))
+    sigma = np.zeros(k)
+    if rows == 0:
+        return U, sigma
+    u, sv, _ = np.linalg.svd(Y, full_matrices=False)
+    r = len(sv)
+    sigma[:r] = sv
+    keep = (sv > 0) & (sv > PMK_CUT * sv[0])
+    U[:, :r] = np.where(keep[None, :], u, 0.0)
+    return U, sigma
+
+
+def pm_k_iterate(n, indptr, indices, data, k, t, seed=None, x0=None):
+    """Orthogonal (subspace) iteration on k vectors, over the non-isolated
+    rows: Q_0 = basis(X0), then for i = 1..t, Y_i = M Q_{i-1} and
+    Q_i = basis(Y_i), with basis() the orthonormalisation above after every
+    step.  In exact arithmetic span(Q_t) = span(M^t X0), so this is the power
+    method on k vectors kept orthogonal; the per-step orthonormalisation keeps
+    every direction that float64 resolves at any t (without it the columns of
+    M^t X0 all turn towards the leading eigenvector).
+
+    Returns (U, sigma): U = Q_t (n x k, isolated rows 0), sigma the singular
+    values of Y_t (of X0 when t = 0), descending.  Reading: each column's sign
+    makes its largest-magnitude entry positive (the first such entry on a
+    tie); an isolated vertex has no D^{-1/2} and takes no part."""
     if x0 is None:
         x0 = gaussian_block(n, k, seed)
     x0 = np.asarray(x0, dtype=np.float64).reshape(n, k)
-    M = signless_laplacian(n, indptr, indices, data)
     d = degrees(n, indptr, indices, data)
-    Y = power_method(M, x0, t)
-    rows = d > 0
+    rows = np.flatnonzero(d > 0)
+    M = signless_laplacian(n, indptr, indices, data)[rows][:, rows]
+    Q, sigma = orthonormal_basis(x0[rows])
+    for _ in range(t):
+        Q, sigma = orthonormal_basis(M @ Q)
+    for j in range(k):
+        if Q.shape[0] and Q[int(np.argmax(np.abs(Q[:, j]))), j] < 0:
+            Q[:, j] = -Q[:, j]
     U = np.zeros((n, k))
-    if rows.any():
-        u, sv, vh = np.linalg.svd(Y[rows], full_matrices=False)
-        for j in range(len(sv)):
-            if not (sv[0] > 0 and sv[j] > 1e-6 * sv[0]):
-                u[:, j] = 0.0
-                continue
-            v = vh[j]
-            if v[int(np.argmax(np.abs(v)))] < 0:
-                u[:, j] = -u[:, j]
-        U[np.flatnonzero(rows)[:, None], np.arange(len(sv))[None, :]] = u
-    return inv_sqrt_degree(d)[:, None] * U
+    U[rows] = Q
+    return U, sigma
+
+
+def pm_k_embed(n, indptr, indices, data, k, t, seed=None, x0=None):
+    """The embedding of PM with k vectors: D^{-1/2} U with U = pm_k_iterate's
+    orthonormal basis, the rows k-means sees (as Algorithm 2 embeds
+    D^{-1/2} Y)."""
+    U, _ = pm_k_iterate(n, indptr, indices, data, k, t, seed=seed, x0=x0)
+    return inv_sqrt_degree(degrees(n, indptr, indices, data))[:, None] * U
 
 
 def pm_k_cluster(n, indptr, indices, data, k, t, seed, kmeans_iters, x0=None):

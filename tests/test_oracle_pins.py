@@ -412,34 +412,73 @@ def test_pm_k_columns_are_orthonormal_and_span_the_power_iterate():
     g = synth.random_weighted(60, 150, seed=5, isolated=3)
     k, t, seed = 5, 7, 11
     E = o.pm_k_embed(g.n, g.indptr, g.indices, g.data, k, t, seed=seed)
+    U_all, sigma = o.pm_k_iterate(g.n, g.indptr, g.indices, g.data, k, t, seed=seed)
     M, d = _dense_M(g)
     live = d > 0
     assert np.all(E[~live] == 0.0)
     U = np.sqrt(d[live])[:, None] * E[live]
+    assert np.abs(U - U_all[live]).max() < 1e-14
     assert np.abs(U.T @ U - np.eye(k)).max() < 1e-12
     # M^t X0 from the dense eigendecomposition, not from repeated products
     gam, F = np.linalg.eigh(M)
-    Y = (F * gam ** t) @ F.T @ o.gaussian_block(g.n, k, seed)
+    X0 = o.gaussian_block(g.n, k, seed)
+    Y = (F * gam ** t) @ F.T @ X0
     Yl = Y[live]
     assert np.linalg.norm(Yl - U @ (U.T @ Yl)) < 1e-10 * np.linalg.norm(Yl)
-    # the sign convention: U^T Y = Sigma V^T, each row's largest entry positive
-    P = U.T @ Yl
-    assert all(P[j, np.argmax(np.abs(P[j]))] > 0 for j in range(k))
-    sv = np.linalg.svd(Yl, compute_uv=False)
-    assert np.allclose(np.linalg.norm(P, axis=1), sv, rtol=1e-10)   # descending order
+    # sigma: the singular values of M applied to an orthonormal basis of
+    # M^(t-1) X0 (a Householder QR of the dense expansion)
+    B = np.linalg.qr(((F * gam ** (t - 1)) @ F.T @ X0)[live])[0]
+    sv = np.linalg.svd(M[np.ix_(live, live)] @ B, compute_uv=False)
+    assert np.allclose(sigma, sv, rtol=1e-10)
+    assert np.all(np.diff(sigma) <= 0)
+    # the sign rule: each column's largest-magnitude entry is positive
+    assert all(U[np.argmax(np.abs(U[:, j])), j] > 0 for j in range(k))
 
 
 def test_pm_k_converges_to_the_top_eigenvectors():
+    # three planted clusters: gamma_2, gamma_3 ~ 0.95, the rest of the
+    # spectrum below 0.6; at t = 300 gamma_3^t ~ 1e-7, yet all three
+    # orthogonal vectors survive and span the leading eigenvectors
     g = synth.sbm(300, 3, 0.5, 0.02, seed=2)
-    t = 60
+    t = 300
     E = o.pm_k_embed(g.n, g.indptr, g.indices, g.data, 3, t, seed=1)
+    _, sigma = o.pm_k_iterate(g.n, g.indptr, g.indices, g.data, 3, t, seed=1)
     M, d = _dense_M(g)
     gam, F = np.linalg.eigh(M)
-    # the rest of the spectrum has died out, the top three have not
-    assert (gam[-4] / gam[-3]) ** t < 1e-6 and gam[-3] ** t > 1e-3
+    assert (gam[-4] / gam[-3]) ** t < 1e-30 and gam[-3] ** t < 1e-6
     U = np.sqrt(d)[:, None] * E
+    assert np.abs(U.T @ U - np.eye(3)).max() < 1e-12
     cos = np.linalg.svd(F[:, -3:].T @ U, compute_uv=False)
-    assert cos.min() > 1 - 1e-8
+    assert cos.min() > 1 - 1e-12
+    # once converged, M Q = Q diag(gamma): the singular values are the
+    # leading eigenvalues
+    assert np.allclose(sigma, gam[::-1][:3], rtol=1e-12, atol=0)
+
+
+def test_pm_k_keeps_every_direction_where_the_plain_iterate_underflows():
+    # distinct leading eigenvalues, t large enough that gamma_4^t underflows
+    # to 0 in float64: M^t X0 itself has lost columns 2..4, the orthogonal
+    # iteration has not
+    g = synth.random_weighted(40, 160, seed=3)
+    M, d = _dense_M(g)
+    assert np.all(d > 0)
+    gam, F = np.linalg.eigh(M)
+    k, t = 4, 3000
+    assert gam[-4] - gam[-5] > 1e-3 and gam[-4] ** t == 0.0
+    E = o.pm_k_embed(g.n, g.indptr, g.indices, g.data, k, t, seed=2)
+    _, sigma = o.pm_k_iterate(g.n, g.indptr, g.indices, g.data, k, t, seed=2)
+    U = np.sqrt(d)[:, None] * E
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-12
+    cos = np.linalg.svd(F[:, -k:].T @ U, compute_uv=False)
+    assert cos.min() > 1 - 1e-12
+    assert np.allclose(sigma, gam[::-1][:k], rtol=1e-12, atol=0)
+    # where the gaps between the leading eigenvalues are wide, every column is
+    # the eigenvector itself (up to the sign rule)
+    gaps = np.abs(np.diff(gam[::-1][: k + 1]))
+    for j in range(k):
+        if min(gaps[max(j - 1, 0)], gaps[j]) > 1e-2:
+            f = F[:, -1 - j]
+            assert abs(abs(f @ U[:, j]) - 1.0) < 1e-10
 
 
 def test_pm_k_rank_deficient_block_leaves_zero_columns():
