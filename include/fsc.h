@@ -293,36 +293,43 @@ int fsc_cluster_filtered(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t 
                          int32_t* labels, float* coeffs_out, double* diagnostics, int32_t* used_fallback,
                          void* stream);
 
-/* PM with k vectors, the comparison method of Sec. 4 (Boutsidis et al.; the
- * power method on k vectors followed by a singular value decomposition, as
- * Sec. 1.1 describes it).  Y = M^t X0 for k start vectors (the start block
- * and steps of fsc_embed with l = k), then U = the left singular vectors of Y
- * over the non-isolated rows, taken through the FP64 Gram matrix Y^T Y (cyclic
- * Jacobi), and k-means exactly as fsc_cluster on the rows of D^{-1/2} U.
- * Columns of U come in descending order of singular value; a column whose
- * singular value is at most 1e-6 of the largest is 0; each column's sign
- * makes the largest-magnitude entry of its right singular vector positive.
+/* PM with k vectors, the comparison method of Sec. 4 (k mutually orthogonal
+ * vectors computed with the power method, the algorithm of Boutsidis et al.;
+ * Sec. 1.1 notes its singular value decomposition), as orthogonal iteration:
+ * the start block and power steps of fsc_embed with l = k, the block
+ * orthonormalised after the start block and after every step, so that
+ * D^{1/2} Z_i holds the left singular vectors of Y_i = M (D^{1/2} Z_{i-1})
+ * over the non-isolated rows.  Each orthonormalisation takes the FP64 Gram
+ * matrix Y^T Y = sum_v d_v z_v z_v^T and its cyclic Jacobi eigenvectors.  In
+ * exact arithmetic the span after t steps is that of M^t X0; every direction
+ * stays resolved at any t.  k-means then runs exactly as in fsc_cluster on
+ * the rows of D^{-1/2} U, U = D^{1/2} Z_t.  Columns of U come in descending
+ * order of singular value; a column whose singular value within one step is
+ * at most 1e-6 of the largest is set to 0 (the Gram matrix of the stored rows
+ * cannot resolve it; it stays 0); after the last step each column's sign
+ * makes its largest-magnitude entry positive (the first such row on a tie).
  * `labels` receives int32[n].  Optional outputs (NULL to skip): `emb` (FP32
  * n x k, the rows k-means sees) and `sigma` (FP64 [k], the singular values of
- * Y, descending).  1 <= k <= min(n, 8); opts as for fsc_cluster (x0, when
- * given, is n x k). */
+ * the last step's Y, descending; Y = X0 when t = 0).  1 <= k <= min(n, 8);
+ * vec_dtype FSC_F32 or FSC_F64 (else FSC_E_UNSUPPORTED); opts as for
+ * fsc_cluster otherwise (x0, when given, is n x k; the traces and renorm are
+ * ignored). */
 int fsc_cluster_pmk(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t t, uint64_t seed,
                     const fsc_opts* opts, int32_t* labels, float* emb, double* sigma, void* stream);
 
 /* The eigenvector baselines of Sec. 4 ("k Eigenvectors" with m = k,
  * "log(k) Eigenvectors" with m = log k): the m leading eigenvectors of M
- * (the m smallest of the normalised Laplacian), computed by subspace
- * iteration -- `cycles` rounds of `steps` power steps on m columns (the
- * kernels of fsc_embed, the first round from the seeded Gaussian block),
- * each round restarted from the orthonormal basis U of the last one (the
- * orthonormalisation of fsc_cluster_pmk) -- then k-means exactly as
- * fsc_cluster on the rows of D^{-1/2} U.  The span converges to the leading
- * eigenvectors at the rate (gamma_{m+1} / gamma_m)^(cycles*steps).
- * `labels` receives int32[n].  Optional outputs (NULL to skip): `emb` (FP32
- * n x m, the rows k-means sees) and `gamma` (FP64 [m], the eigenvalue
- * estimates sigma_j^(1/steps) of the last round, meaningful for cycles >= 2).
- * 1 <= k <= min(n, 64), 1 <= m <= min(n, 8), cycles, steps >= 1; opts as for
- * fsc_cluster (x0 and the traces are ignored). */
+ * (the m smallest of the normalised Laplacian), reached by the orthogonal
+ * iteration of fsc_cluster_pmk on m columns for cycles * steps steps from the
+ * seeded Gaussian block, then k-means exactly as fsc_cluster on the rows of
+ * D^{-1/2} U.  The span converges to the leading eigenvectors at the rate
+ * (gamma_{m+1} / gamma_m)^(cycles*steps).  `labels` receives int32[n].
+ * Optional outputs (NULL to skip): `emb` (FP32 n x m, the rows k-means sees)
+ * and `gamma` (FP64 [m], the eigenvalue estimates: the singular values of
+ * M U for the orthonormal U of the second-to-last step, which equal the
+ * eigenvalues once U has converged).  1 <= k <= min(n, 64),
+ * 1 <= m <= min(n, 8), cycles, steps >= 1 with cycles * steps < 2^31;
+ * opts as for fsc_cluster_pmk (x0 is ignored). */
 int fsc_cluster_eigs(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t m, int32_t cycles, int32_t steps,
                      uint64_t seed, const fsc_opts* opts, int32_t* labels, float* emb, double* gamma,
                      void* stream);

@@ -211,58 +211,29 @@ int cluster_run(Context* c, const fsc_csr* g, int k, int l, int t, uint64_t seed
   return kmeans_run(c, &km, s);
 }
 
-// PM with k vectors: the plain path's power steps on k columns, the
-// orthonormalisation of fsc_pmk.hip, then the same k-means.
-static int pmk_cluster_run(Context* c, const fsc_csr* g, int k, int t, uint64_t seed, const fsc_opts& o,
-                           int32_t* labels, float* emb, double* sigma, hipStream_t s) {
+// Orthogonal iteration on m columns for t steps (fsc_pmk.hip): the plain
+// path's start block and power steps with the block orthonormalised after
+// each, then the same k-means (k clusters) on the rows of D^{-1/2} U.  PM
+// with k vectors has m = k; the eigenvector baselines run it long enough for
+// U to reach the m leading eigenvectors, and the last step's singular values
+// (sigma_out) then estimate their eigenvalues.
+static int ortho_cluster_run(Context* c, const fsc_csr* g, int k, int m, int t, uint64_t seed, const fsc_opts& o,
+                             int32_t* labels, float* emb, double* sigma_out, hipStream_t s) {
   int rc;
-  const int iters = o.kmeans_iters > 0 ? o.kmeans_iters : 30;
-  const int KD = kmeans_width(k);
-  const size_t extra =
-      kmeans_workspace_bytes(g->n, KD) + align_up(g->n * KD * 4) + pmk_workspace_bytes(g->n, KD) + 2048;
-  EmbedIO io;
-  Arena arena;
-  if ((rc = prepare_embed(c, g, k, t, seed, o, extra, &io, &arena))) return rc;
-  KmeansIO km;
-  std::memset(&km, 0, sizeof(km));
-  km.n = g->n;
-  km.l = k;
-  km.KD = KD;
-  km.k = k;
-  km.iters = iters;
-  km.seed = seed;
-  km.labels = labels;
-  float* pts = arena.take<float>(g->n * KD);
-  double* partials = arena.take<double>((size_t)pmk_grid(g->n) * KD * (KD + 1) / 2);
-  float* W = arena.take<float>((size_t)KD * KD);
-  if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
-  if (o.validate && (rc = validate_csr(c, g, s))) return rc;
-  if ((rc = embed_run(c, &io, s))) return rc;
-  if ((rc = embed_to_points(c, &io, pts, s))) return rc;
-  if ((rc = pmk_run(&io, pts, KD, k, partials, W, sigma, emb, s))) return rc;
-  km.pts = pts;
-  km.elig = io.elig;
-  return kmeans_run(c, &km, s);
-}
-
-// Leading eigenvectors by subspace iteration: `cycles` rounds of `steps`
-// power steps on m columns, each round restarted from the orthonormalised
-// block of the last; then the same k-means as the plain method on
-// D^{-1/2} U.
-static int eigs_cluster_run(Context* c, const fsc_csr* g, int k, int m, int cycles, int steps, uint64_t seed,
-                            const fsc_opts& o, int32_t* labels, float* emb, double* gamma, hipStream_t s) {
-  int rc;
+  if (o.vec_dtype != FSC_F32 && o.vec_dtype != FSC_F64)
+    return fail(FSC_E_UNSUPPORTED, "orthogonal iteration takes FP32 or FP64 vectors");
   const int iters = o.kmeans_iters > 0 ? o.kmeans_iters : 30;
   const int KD = kmeans_width(m);
-  const size_t extra = kmeans_workspace_bytes(g->n, KD) + align_up(g->n * KD * 4) + pmk_workspace_bytes(g->n, KD) +
-                       align_up((size_t)g->n * m * 8) + align_up(8 * 8) + 2048;
+  const int LH = padded_width(m);
+  const size_t extra =
+      kmeans_workspace_bytes(g->n, KD) + align_up(g->n * KD * 4) + ortho_workspace_bytes(g->n, LH) + 2048;
   fsc_opts oc = o;
-  oc.x0 = nullptr;
+  oc.renorm = 0;
   oc.sqnorm_trace = nullptr;
   oc.rayleigh_trace = nullptr;
   EmbedIO io;
   Arena arena;
-  if ((rc = prepare_embed(c, g, m, steps, seed, oc, extra, &io, &arena))) return rc;
+  if ((rc = prepare_embed(c, g, m, t, seed, oc, extra, &io, &arena))) return rc;
   KmeansIO km;
   std::memset(&km, 0, sizeof(km));
   km.n = g->n;
@@ -273,30 +244,16 @@ static int eigs_cluster_run(Context* c, const fsc_csr* g, int k, int m, int cycl
   km.seed = seed;
   km.labels = labels;
   float* pts = arena.take<float>(g->n * KD);
-  double* partials = arena.take<double>((size_t)pmk_grid(g->n) * KD * (KD + 1) / 2);
-  float* W = arena.take<float>((size_t)KD * KD);
-  double* x0 = arena.take<double>((size_t)g->n * m);
-  double* sigma = arena.take<double>(8);
+  OrthoArgs oa;
+  ortho_bind(&arena, g->n, LH, m, &oa);
+  oa.sigma_out = sigma_out;
+  io.ortho = &oa;
   if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
-  if (arena.used > arena.size) return fail(FSC_E_NOMEM, "eigenvector workspace too small");
+  if (arena.used > arena.size) return fail(FSC_E_NOMEM, "orthogonal iteration workspace too small");
   if (o.validate && (rc = validate_csr(c, g, s))) return rc;
-  for (int cy = 0; cy < cycles; ++cy) {
-    // the same arena layout every cycle: x0, pts and the k-means workspace
-    // sit after the embedding's region and survive the rebinding
-    if (cy > 0) {
-      oc.x0 = x0;
-      EmbedIO next;
-      Arena again;
-      if ((rc = prepare_embed(c, g, m, steps, seed, oc, extra, &next, &again))) return rc;
-      if (again.base != arena.base) return fail(FSC_E_HIP, "workspace moved between cycles");
-      io = next;
-    }
-    if ((rc = embed_run(c, &io, s))) return rc;
-    if ((rc = embed_to_points(c, &io, pts, s))) return rc;
-    if ((rc = pmk_run(&io, pts, KD, m, partials, W, sigma, cy + 1 == cycles ? emb : nullptr, s))) return rc;
-    if (cy + 1 < cycles && (rc = eig_restart_run(pts, io.deg, g->n, KD, m, x0, s))) return rc;
-  }
-  if (gamma && (rc = eig_gamma_run(sigma, m, steps, gamma, s))) return rc;
+  if ((rc = embed_run(c, &io, s))) return rc;
+  if ((rc = embed_to_points(c, &io, pts, s))) return rc;
+  if (emb && (rc = points_cols_run(pts, g->n, KD, m, emb, s))) return rc;
   km.pts = pts;
   km.elig = io.elig;
   return kmeans_run(c, &km, s);
@@ -402,7 +359,7 @@ int fsc_cluster_pmk(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t t, ui
   if (k < 1 || k > 8 || k > g->n) return fail(FSC_E_ARG, "k must be in [1, min(n, 8)]");
   const fsc_opts o = opts ? *opts : default_opts();
   if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
-  return pmk_cluster_run(&ctx->c, g, k, t, seed, o, labels, emb, sigma, static_cast<hipStream_t>(stream));
+  return ortho_cluster_run(&ctx->c, g, k, k, t, seed, o, labels, emb, sigma, static_cast<hipStream_t>(stream));
 }
 
 int fsc_knn(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int32_t knn, int32_t* nbr, float* dist,
@@ -450,8 +407,11 @@ int fsc_cluster_eigs(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t m, i
   if (cycles < 1 || steps < 1) return fail(FSC_E_ARG, "cycles and steps must be >= 1");
   const fsc_opts o = opts ? *opts : default_opts();
   if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
-  return eigs_cluster_run(&ctx->c, g, k, m, cycles, steps, seed, o, labels, emb, gamma,
-                          static_cast<hipStream_t>(stream));
+  if ((int64_t)cycles * steps > INT32_MAX) return fail(FSC_E_ARG, "cycles * steps must fit 32 bits");
+  fsc_opts oc = o;
+  oc.x0 = nullptr;
+  return ortho_cluster_run(&ctx->c, g, k, m, cycles * steps, seed, oc, labels, emb, gamma,
+                           static_cast<hipStream_t>(stream));
 }
 
 int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, int32_t l, int32_t k, int32_t iters,

@@ -368,6 +368,7 @@ static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta, const SlabAr
       hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kBlock), 0, s, sa, reduce ? sb->rgrid : io->grid);
       if ((rc = check_hip(hipGetLastError(), "stats_finish launch"))) return rc;
     }
+    if (io->ortho && (rc = ortho_run(io, zout, step == io->t, s))) return rc;
   }
   io->zt = io->z[io->t & 1];
   return FSC_OK;
@@ -448,6 +449,7 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
       hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kBlock), 0, s, sa, grid);
       if ((rc = check_hip(hipGetLastError(), "stats_finish launch"))) return rc;
     }
+    if (io->ortho && (rc = ortho_run(io, io->z[0], io->t == 0, s))) return rc;
   }
   if (!slab_steps) return run_steps<S, W, LH>(ctx, io, ta, nullptr, sa, s, stats);
   const SlabPlan& sp = io->slab;

@@ -156,6 +156,18 @@ void timing_stop(std::pair<hipEvent_t, hipEvent_t>* ev, hipStream_t s);
 int reserve_arena(Context* ctx, size_t bytes, Arena* out);
 
 // ---- embedding pipeline (fsc_embed.hip) ----
+// Orthogonal iteration (fsc_pmk.hip): the block is orthonormalised after the
+// start block and after every power step.
+struct OrthoArgs {
+  int k;               // live columns
+  int grid;            // blocks of the Gram and sign passes
+  double* partials;    // [grid][LH*(LH+1)/2]
+  double* W;           // [LH*LH] the current transform
+  double* pmax;        // [grid][LH] sign pass: largest |D^{1/2} z| per column
+  int64_t* prow;       // [grid][LH] and its row
+  double* sigma_out;   // FP64[k]: the last step's singular values (optional)
+};
+
 struct EmbedIO {
   // inputs
   const fsc_csr* g;
@@ -168,6 +180,7 @@ struct EmbedIO {
   double* sqnorm_trace;
   double* rayleigh_trace;
   int need_tiles;   // 1: build the tile plan even when the steps take the slab form (later tile kernels use it)
+  OrthoArgs* ortho; // non-null: orthogonal iteration (fsc_pmk.hip)
   // workspace (filled by embed_workspace)
   double* deg;
   void* hinv;       // float[n] or double[n]
@@ -304,12 +317,13 @@ int mlp_loss_grad_run(const float* params, int B, const float* feats, const doub
 int mlp_adam_run(float* p, float* m, float* v, const float* g, float lr, int step, hipStream_t s);
 
 // ---- PM with k vectors (fsc_pmk.hip) ----
-int pmk_grid(int64_t n);
-size_t pmk_workspace_bytes(int64_t n, int KD);
-int pmk_run(const EmbedIO* io, float* pts, int KD, int k, double* partials, float* W, double* sigma, float* emb,
-            hipStream_t s);
-int eig_restart_run(const float* pts, const double* deg, int64_t n, int KD, int m, double* x0, hipStream_t s);
-int eig_gamma_run(const double* sigma, int m, int steps, double* gamma, hipStream_t s);
+size_t ortho_workspace_bytes(int64_t n, int LH);
+void ortho_bind(Arena* a, int64_t n, int LH, int k, OrthoArgs* oa);
+// Orthonormalises the block z (n x LH, the io's vector dtype) in place; on
+// the last step also fixes the column signs and writes sigma_out.
+int ortho_run(const EmbedIO* io, void* z, bool last, hipStream_t s);
+// Copies the first k values of each FP32 point row (width KD) to n x k.
+int points_cols_run(const float* pts, int64_t n, int KD, int k, float* out, hipStream_t s);
 
 // ---- k-nearest neighbours (fsc_knn.hip) ----
 int knn_run(const float* X, int64_t n, int dim, int knn, float* norms, int32_t* nbr, float* dist, hipStream_t s);

@@ -1,15 +1,19 @@
-// PM with k vectors, the comparison method of Sec. 4 (Boutsidis et al.),
-// which the paper describes as the power method on k vectors followed by a
-// singular value decomposition.  The power steps are the plain path's with
-// l = k columns; this file adds the orthonormalisation of Y = D^{1/2} Z_t
-// (Z_t the embedding rows) through its Gram matrix:
-//   G = Y^T Y = sum_v d_v z_v z_v^T           (FP64, over non-isolated rows)
-//   G = V diag(sigma^2) V^T                    (cyclic Jacobi, FP64, one lane)
-//   D^{-1/2} U = Z_t V diag(1 / sigma)         (the embedding k-means gets)
-// Columns come in descending order of sigma; a column with sigma at most
-// 1e-6 of the largest is set to 0 (FP32 rows cannot resolve it); each
-// column's sign makes the largest-magnitude entry of its column of V
-// positive (the first such entry on a tie).
+// PM with k vectors, the comparison method of Sec. 4 (k mutually orthogonal
+// vectors computed with the power method; the algorithm of Boutsidis et al.,
+// whose singular value decomposition Sec. 1.1 mentions), and the eigenvector
+// baselines of Sec. 4, both as orthogonal iteration on the plain path's power
+// steps.  The block is orthonormalised after the start block and after every
+// step.  With Y = D^{1/2} Z (Z the z-space rows the step kernels keep):
+//   G = Y^T Y = sum_v d_v z_v z_v^T           (FP64, non-isolated rows)
+//   G = V diag(sigma^2) V^T                    (cyclic Jacobi, FP64)
+//   Z <- Z V diag(1 / sigma)                   (D^{1/2} Z orthonormal)
+// so that D^{1/2} Z holds the left singular vectors of Y in descending order
+// of sigma.  The step is linear, so each step acts on the orthonormal block
+// of the last one, and every direction stays resolved at any number of
+// steps.  A direction whose sigma within one step is at most 1e-6 of the
+// largest is set to 0: the Gram matrix of stored rows cannot resolve it.
+// After the last step each column's sign makes its largest-magnitude entry
+// of D^{1/2} Z positive (the first such row on a tie).
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
 
@@ -17,32 +21,35 @@
 
 namespace fsc {
 
-constexpr int kPmkBlock = 256;
-constexpr int kPmkMaxGrid = 1024;
+constexpr int kOrthoBlock = 256;
+constexpr int kOrthoMaxGrid = 1024;
 
-int pmk_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kPmkBlock - 1) / kPmkBlock, kPmkMaxGrid)); }
+int ortho_grid(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + kOrthoBlock - 1) / kOrthoBlock, kOrthoMaxGrid));
+}
 
 // Per-block partial sums of the upper triangle of G (row-major a <= b).
-template <int KD>
-__global__ __launch_bounds__(kPmkBlock) void pmk_gram_kernel(const float* __restrict__ pts,
-                                                             const double* __restrict__ deg, int64_t n,
-                                                             double* __restrict__ partials) {
-  constexpr int NT = KD * (KD + 1) / 2;
-  __shared__ double red[kPmkBlock / FSC_WAVE][NT];
+template <typename S, int LH>
+__global__ __launch_bounds__(kOrthoBlock) void ortho_gram_kernel(const S* __restrict__ z,
+                                                                 const double* __restrict__ deg, int64_t n,
+                                                                 double* __restrict__ partials) {
+  using A = typename elem<S>::acc;
+  constexpr int NT = LH * (LH + 1) / 2;
+  __shared__ double red[kOrthoBlock / FSC_WAVE][NT];
   double g[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) g[i] = 0.0;
-  for (int64_t v = (int64_t)blockIdx.x * kPmkBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kPmkBlock) {
+  for (int64_t v = (int64_t)blockIdx.x * kOrthoBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kOrthoBlock) {
     const double d = deg[v];
     if (d > 0.0) {
-      float p[KD];
-      rowio<float, KD>::load(pts + v * KD, p);
+      A p[LH];
+      rowio<S, LH>::load(z + v * LH, p);
       int i = 0;
 #pragma unroll
-      for (int a = 0; a < KD; ++a) {
+      for (int a = 0; a < LH; ++a) {
         const double da = d * (double)p[a];
 #pragma unroll
-        for (int b = a; b < KD; ++b) g[i++] += da * (double)p[b];
+        for (int b = a; b < LH; ++b) g[i++] += da * (double)p[b];
       }
     }
   }
@@ -56,21 +63,22 @@ __global__ __launch_bounds__(kPmkBlock) void pmk_gram_kernel(const float* __rest
   if (threadIdx.x < NT) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < kPmkBlock / FSC_WAVE; ++q) s += red[q][threadIdx.x];
+    for (int q = 0; q < kOrthoBlock / FSC_WAVE; ++q) s += red[q][threadIdx.x];
     partials[(int64_t)blockIdx.x * NT + threadIdx.x] = s;
   }
 }
 
 // One block: sums the partials in block order (deterministic), then one lane
 // diagonalises the leading k x k block of G and writes W = V diag(1/sigma)
-// (KD x KD, row a = input column, zero outside k x k) and the singular values.
-template <int KD>
-__global__ __launch_bounds__(64) void pmk_finish_kernel(const double* __restrict__ partials, int grid, int k,
-                                                        float* __restrict__ W, double* __restrict__ sigma) {
-  constexpr int NT = KD * (KD + 1) / 2;
+// (LH x LH, row a = input column, zero outside k x k, columns in descending
+// order of sigma) and, when sigma_out is given, the k singular values.
+template <int LH>
+__global__ __launch_bounds__(64) void ortho_finish_kernel(const double* __restrict__ partials, int grid, int k,
+                                                          double* __restrict__ W, double* __restrict__ sigma_out) {
+  constexpr int NT = LH * (LH + 1) / 2;
   __shared__ double gs[NT];
-  __shared__ double G[KD][KD];
-  __shared__ double V[KD][KD];
+  __shared__ double G[LH][LH];
+  __shared__ double V[LH][LH];
   if (threadIdx.x < NT) {
     double s = 0.0;
     for (int b = 0; b < grid; ++b) s += partials[(int64_t)b * NT + threadIdx.x];
@@ -78,11 +86,13 @@ __global__ __launch_bounds__(64) void pmk_finish_kernel(const double* __restrict
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  for (int a = 0, i = 0; a < KD; ++a)
-    for (int b = a; b < KD; ++b, ++i) G[a][b] = G[b][a] = gs[i];
-  for (int a = 0; a < KD; ++a)
-    for (int b = 0; b < KD; ++b) V[a][b] = a == b ? 1.0 : 0.0;
-  // cyclic Jacobi (Golub and Van Loan, the symmetric Schur rotation)
+  for (int a = 0, i = 0; a < LH; ++a)
+    for (int b = a; b < LH; ++b, ++i) G[a][b] = G[b][a] = gs[i];
+  for (int a = 0; a < LH; ++a)
+    for (int b = 0; b < LH; ++b) V[a][b] = a == b ? 1.0 : 0.0;
+  // cyclic Jacobi (Golub and Van Loan, the symmetric Schur rotation); a
+  // block orthonormalised one step earlier gives a nearly diagonal G after
+  // the first few steps, which takes one or two sweeps
   for (int sweep = 0; sweep < 64; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int p = 0; p < k; ++p)
@@ -117,9 +127,9 @@ __global__ __launch_bounds__(64) void pmk_finish_kernel(const double* __restrict
       }
   }
   // descending order of eigenvalue, ties to the lower index
-  int order[KD];
-  bool used[KD];
-  for (int j = 0; j < KD; ++j) used[j] = false;
+  int order[LH];
+  bool used[LH];
+  for (int j = 0; j < LH; ++j) used[j] = false;
   double lmax = 0.0;
   for (int j = 0; j < k; ++j) {
     int best = -1;
@@ -129,98 +139,197 @@ __global__ __launch_bounds__(64) void pmk_finish_kernel(const double* __restrict
     order[j] = best;
     if (j == 0) lmax = fmax(G[best][best], 0.0);
   }
-  for (int a = 0; a < KD; ++a)
-    for (int j = 0; j < KD; ++j) W[a * KD + j] = 0.f;
+  for (int a = 0; a < LH; ++a)
+    for (int j = 0; j < LH; ++j) W[a * LH + j] = 0.0;
   for (int j = 0; j < k; ++j) {
     const int src = order[j];
     const double lam = fmax(G[src][src], 0.0);
     const double sv = sqrt(lam);
-    if (sigma) sigma[j] = sv;
-    if (!(lmax > 0.0 && lam > 1e-12 * lmax)) continue;  // sigma <= 1e-6 sigma_max
-    int rmax = 0;
-    for (int r = 1; r < k; ++r)
-      if (fabs(V[r][src]) > fabs(V[rmax][src])) rmax = r;
-    const double sg = V[rmax][src] < 0.0 ? -1.0 : 1.0;
-    for (int a = 0; a < k; ++a) W[a * KD + j] = (float)(sg * V[a][src] / sv);
+    if (sigma_out) sigma_out[j] = sv;
+    if (!(lmax > 0.0 && lam > 1e-12 * lmax)) continue;  // sigma <= 1e-6 sigma_max: 0
+    for (int a = 0; a < k; ++a) W[a * LH + j] = V[a][src] / sv;
   }
 }
 
-// p_v <- p_v W in place; the first k values of each row also go to emb.
-template <int KD>
-__global__ __launch_bounds__(kPmkBlock) void pmk_apply_kernel(float* __restrict__ pts, int64_t n, int k,
-                                                              const float* __restrict__ W, float* __restrict__ emb) {
-  __shared__ float w[KD * KD];
-  for (int i = threadIdx.x; i < KD * KD; i += kPmkBlock) w[i] = W[i];
+// z_v <- z_v W in place (every row; isolated rows are 0 and stay 0).
+template <typename S, int LH>
+__global__ __launch_bounds__(kOrthoBlock) void ortho_apply_kernel(S* __restrict__ z, int64_t n,
+                                                                  const double* __restrict__ W) {
+  using A = typename elem<S>::acc;
+  __shared__ A w[LH * LH];
+  for (int i = threadIdx.x; i < LH * LH; i += kOrthoBlock) w[i] = (A)W[i];
   __syncthreads();
-  for (int64_t v = (int64_t)blockIdx.x * kPmkBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kPmkBlock) {
-    float p[KD], o[KD];
-    rowio<float, KD>::load(pts + v * KD, p);
+  for (int64_t v = (int64_t)blockIdx.x * kOrthoBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kOrthoBlock) {
+    A p[LH], o[LH];
+    rowio<S, LH>::load(z + v * LH, p);
 #pragma unroll
-    for (int j = 0; j < KD; ++j) {
-      float acc = 0.f;
+    for (int j = 0; j < LH; ++j) {
+      A acc = A(0);
 #pragma unroll
-      for (int a = 0; a < KD; ++a) acc = fmaf(p[a], w[a * KD + j], acc);
+      for (int a = 0; a < LH; ++a) acc = fma(p[a], w[a * LH + j], acc);
       o[j] = acc;
     }
-    rowio<float, KD>::store(pts + v * KD, o);
-    if (emb)
-      for (int j = 0; j < k; ++j) emb[v * k + j] = o[j];
+    rowio<S, LH>::store(z + v * LH, o);
   }
 }
 
-size_t pmk_workspace_bytes(int64_t n, int KD) {
-  return align_up((size_t)pmk_grid(n) * KD * (KD + 1) / 2 * 8) + align_up((size_t)KD * KD * 4);
-}
-
-int pmk_run(const EmbedIO* io, float* pts, int KD, int k, double* partials, float* W, double* sigma, float* emb,
-            hipStream_t s) {
-  const int64_t n = io->g->n;
-  const int grid = pmk_grid(n);
-  const int agrid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kPmkBlock - 1) / kPmkBlock, 8192));
-  if (KD == 4) {
-    hipLaunchKernelGGL(pmk_gram_kernel<4>, dim3(grid), dim3(kPmkBlock), 0, s, pts, io->deg, n, partials);
-    hipLaunchKernelGGL(pmk_finish_kernel<4>, dim3(1), dim3(64), 0, s, partials, grid, k, W, sigma);
-    hipLaunchKernelGGL(pmk_apply_kernel<4>, dim3(agrid), dim3(kPmkBlock), 0, s, pts, n, k, W, emb);
-  } else if (KD == 8) {
-    hipLaunchKernelGGL(pmk_gram_kernel<8>, dim3(grid), dim3(kPmkBlock), 0, s, pts, io->deg, n, partials);
-    hipLaunchKernelGGL(pmk_finish_kernel<8>, dim3(1), dim3(64), 0, s, partials, grid, k, W, sigma);
-    hipLaunchKernelGGL(pmk_apply_kernel<8>, dim3(agrid), dim3(kPmkBlock), 0, s, pts, n, k, W, emb);
-  } else {
-    return fail(FSC_E_ARG, "point width must be 4 or 8");
+// (|value|, row) pairs: the larger value wins, the lower row on a tie.
+__device__ __forceinline__ void absmax_merge(double& m, int64_t& r, double m2, int64_t r2) {
+  if (m2 > m || (m2 == m && r2 >= 0 && (r < 0 || r2 < r))) {
+    m = m2;
+    r = r2;
   }
-  return check_hip(hipGetLastError(), "pmk launch");
 }
 
-// ---- subspace iteration for the leading eigenvectors of M ----
-// After each cycle of power steps the orthonormalised block restarts the
-// next: x0 = D^{1/2} (Z_t W) = U (y-space), in FP64 n x m.
-__global__ __launch_bounds__(kPmkBlock) void eig_restart_kernel(const float* __restrict__ pts,
-                                                                const double* __restrict__ deg, int64_t n,
-                                                                int KD, int m, double* __restrict__ x0) {
-  for (int64_t i = (int64_t)blockIdx.x * kPmkBlock + threadIdx.x; i < n * m; i += (int64_t)gridDim.x * kPmkBlock) {
-    const int64_t v = i / m;
-    const int j = (int)(i - v * m);
+// Per-block largest |sqrt(d_v) z_vj| of each column and its first row.
+template <typename S, int LH>
+__global__ __launch_bounds__(kOrthoBlock) void ortho_sign_partial_kernel(const S* __restrict__ z,
+                                                                         const double* __restrict__ deg,
+                                                                         int64_t n, double* __restrict__ pmax,
+                                                                         int64_t* __restrict__ prow) {
+  using A = typename elem<S>::acc;
+  __shared__ double sm[kOrthoBlock / FSC_WAVE][LH];
+  __shared__ int64_t sr[kOrthoBlock / FSC_WAVE][LH];
+  double m[LH];
+  int64_t r[LH];
+#pragma unroll
+  for (int j = 0; j < LH; ++j) {
+    m[j] = -1.0;
+    r[j] = -1;
+  }
+  for (int64_t v = (int64_t)blockIdx.x * kOrthoBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kOrthoBlock) {
     const double d = deg[v];
-    x0[i] = d > 0.0 ? sqrt(d) * (double)pts[v * KD + j] : 0.0;
+    if (!(d > 0.0)) continue;
+    const double sd = sqrt(d);
+    A p[LH];
+    rowio<S, LH>::load(z + v * LH, p);
+#pragma unroll
+    for (int j = 0; j < LH; ++j) {
+      const double q = fabs(sd * (double)p[j]);
+      if (q > m[j]) {  // rows ascend within a thread: the first row keeps a tie
+        m[j] = q;
+        r[j] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < LH; ++j) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double m2 = __shfl_xor(m[j], off, FSC_WAVE);
+      const int64_t r2 = __shfl_xor(r[j], off, FSC_WAVE);
+      absmax_merge(m[j], r[j], m2, r2);
+    }
+  }
+  const int w = threadIdx.x / FSC_WAVE;
+  if ((threadIdx.x & (FSC_WAVE - 1)) == 0)
+#pragma unroll
+    for (int j = 0; j < LH; ++j) {
+      sm[w][j] = m[j];
+      sr[w][j] = r[j];
+    }
+  __syncthreads();
+  if (threadIdx.x < LH) {
+    const int j = threadIdx.x;
+    double bm = -1.0;
+    int64_t br = -1;
+    for (int q = 0; q < kOrthoBlock / FSC_WAVE; ++q) absmax_merge(bm, br, sm[q][j], sr[q][j]);
+    pmax[(int64_t)blockIdx.x * LH + j] = bm;
+    prow[(int64_t)blockIdx.x * LH + j] = br;
   }
 }
 
-// Eigenvalue estimates from the last cycle: its start block U is
-// orthonormal, so the singular values of M^s U tend to gamma_j^s.
-__global__ void eig_gamma_kernel(const double* __restrict__ sigma, int m, int steps, double* __restrict__ gamma) {
-  if (threadIdx.x == 0 && blockIdx.x == 0)
-    for (int j = 0; j < m; ++j) gamma[j] = steps > 0 && sigma[j] > 0.0 ? pow(sigma[j], 1.0 / steps) : 0.0;
+// One block: W = diag(sign_j), sign_j = -1 when the entry at column j's
+// largest-magnitude row is negative.
+template <typename S, int LH>
+__global__ __launch_bounds__(64) void ortho_sign_finish_kernel(const S* __restrict__ z,
+                                                               const double* __restrict__ pmax,
+                                                               const int64_t* __restrict__ prow, int grid,
+                                                               double* __restrict__ W) {
+  using A = typename elem<S>::acc;
+  if (threadIdx.x >= LH) return;
+  const int j = threadIdx.x;
+  double bm = -1.0;
+  int64_t br = -1;
+  for (int b = 0; b < grid; ++b) absmax_merge(bm, br, pmax[(int64_t)b * LH + j], prow[(int64_t)b * LH + j]);
+  double sg = 1.0;
+  if (br >= 0) {
+    A p[LH];
+    rowio<S, LH>::load(z + br * LH, p);
+    if (p[j] < A(0)) sg = -1.0;
+  }
+  for (int a = 0; a < LH; ++a) W[a * LH + j] = a == j ? sg : 0.0;
 }
 
-int eig_restart_run(const float* pts, const double* deg, int64_t n, int KD, int m, double* x0, hipStream_t s) {
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n * m + kPmkBlock - 1) / kPmkBlock, 8192));
-  hipLaunchKernelGGL(eig_restart_kernel, dim3(grid), dim3(kPmkBlock), 0, s, pts, deg, n, KD, m, x0);
-  return check_hip(hipGetLastError(), "eig restart launch");
+size_t ortho_workspace_bytes(int64_t n, int LH) {
+  const size_t grid = (size_t)ortho_grid(n);
+  return align_up(grid * LH * (LH + 1) / 2 * 8) + align_up((size_t)LH * LH * 8) + align_up(grid * LH * 8) +
+         align_up(grid * LH * 8);
 }
 
-int eig_gamma_run(const double* sigma, int m, int steps, double* gamma, hipStream_t s) {
-  hipLaunchKernelGGL(eig_gamma_kernel, dim3(1), dim3(64), 0, s, sigma, m, steps, gamma);
-  return check_hip(hipGetLastError(), "eig gamma launch");
+void ortho_bind(Arena* a, int64_t n, int LH, int k, OrthoArgs* oa) {
+  oa->k = k;
+  oa->grid = ortho_grid(n);
+  oa->partials = a->take<double>((size_t)oa->grid * LH * (LH + 1) / 2);
+  oa->W = a->take<double>((size_t)LH * LH);
+  oa->pmax = a->take<double>((size_t)oa->grid * LH);
+  oa->prow = a->take<int64_t>((size_t)oa->grid * LH);
+  oa->sigma_out = nullptr;
+}
+
+template <typename S, int LH>
+static int ortho_typed(const EmbedIO* io, void* zv, bool last, hipStream_t s) {
+  const OrthoArgs* oa = io->ortho;
+  const int64_t n = io->g->n;
+  S* z = reinterpret_cast<S*>(zv);
+  const int agrid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kOrthoBlock - 1) / kOrthoBlock, 8192));
+  hipLaunchKernelGGL((ortho_gram_kernel<S, LH>), dim3(oa->grid), dim3(kOrthoBlock), 0, s, z, io->deg, n,
+                     oa->partials);
+  hipLaunchKernelGGL(ortho_finish_kernel<LH>, dim3(1), dim3(64), 0, s, oa->partials, oa->grid, oa->k, oa->W,
+                     last ? oa->sigma_out : nullptr);
+  hipLaunchKernelGGL((ortho_apply_kernel<S, LH>), dim3(agrid), dim3(kOrthoBlock), 0, s, z, n, oa->W);
+  if (last) {
+    hipLaunchKernelGGL((ortho_sign_partial_kernel<S, LH>), dim3(oa->grid), dim3(kOrthoBlock), 0, s, z, io->deg, n,
+                       oa->pmax, oa->prow);
+    hipLaunchKernelGGL((ortho_sign_finish_kernel<S, LH>), dim3(1), dim3(64), 0, s, z, oa->pmax, oa->prow, oa->grid,
+                       oa->W);
+    hipLaunchKernelGGL((ortho_apply_kernel<S, LH>), dim3(agrid), dim3(kOrthoBlock), 0, s, z, n, oa->W);
+  }
+  return check_hip(hipGetLastError(), "orthonormalisation launch");
+}
+
+template <typename S>
+static int ortho_lh(const EmbedIO* io, void* z, bool last, hipStream_t s) {
+  switch (io->LH) {
+    case 1: return ortho_typed<S, 1>(io, z, last, s);
+    case 2: return ortho_typed<S, 2>(io, z, last, s);
+    case 4: return ortho_typed<S, 4>(io, z, last, s);
+    case 8: return ortho_typed<S, 8>(io, z, last, s);
+  }
+  return fail(FSC_E_UNSUPPORTED, "unsupported block width");
+}
+
+int ortho_run(const EmbedIO* io, void* z, bool last, hipStream_t s) {
+  switch (io->vec_dtype) {
+    case FSC_F64: return ortho_lh<double>(io, z, last, s);
+    case FSC_F32: return ortho_lh<float>(io, z, last, s);
+  }
+  return fail(FSC_E_UNSUPPORTED, "orthogonal iteration takes FP32 or FP64 vectors");
+}
+
+// The first k values of each FP32 point row to an n x k array.
+__global__ __launch_bounds__(kOrthoBlock) void points_cols_kernel(const float* __restrict__ pts, int64_t n, int KD,
+                                                                  int k, float* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * kOrthoBlock + threadIdx.x; i < n * k; i += (int64_t)gridDim.x * kOrthoBlock) {
+    const int64_t v = i / k;
+    out[i] = pts[v * KD + (i - v * k)];
+  }
+}
+
+int points_cols_run(const float* pts, int64_t n, int KD, int k, float* out, hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n * k + kOrthoBlock - 1) / kOrthoBlock, 8192));
+  hipLaunchKernelGGL(points_cols_kernel, dim3(grid), dim3(kOrthoBlock), 0, s, pts, n, KD, k, out);
+  return check_hip(hipGetLastError(), "points_cols launch");
 }
 
 }  // namespace fsc

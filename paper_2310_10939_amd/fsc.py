@@ -200,8 +200,8 @@ def cluster(indptr, indices, data, k, l, t, seed, kmeans_iters=30, vec_dtype="f3
 
 
 def cluster_pmk(indptr, indices, data, k, t, seed, kmeans_iters=30, vec_dtype="f32", x0=None, validate=False):
-    """PM with k vectors (k <= 8): (labels int32 [n], embedding FP32 n x k,
-    singular values FP64 [k])."""
+    """PM with k orthogonal vectors (k <= 8): (labels int32 [n], embedding
+    FP32 n x k, the last step's singular values FP64 [k])."""
     n = indptr.numel() - 1
     dev = indptr.device
     labels = torch.empty(n, dtype=torch.int32, device=dev)
@@ -215,9 +215,9 @@ def cluster_pmk(indptr, indices, data, k, t, seed, kmeans_iters=30, vec_dtype="f
 
 
 def cluster_eigs(indptr, indices, data, k, m, cycles, steps, seed, kmeans_iters=30, vec_dtype="f32"):
-    """Eigenvector baseline (m <= 8 leading eigenvectors by subspace
-    iteration): (labels int32 [n], embedding FP32 n x m, eigenvalue
-    estimates FP64 [m])."""
+    """Eigenvector baseline (m <= 8 leading eigenvectors by orthogonal
+    iteration, cycles * steps steps): (labels int32 [n], embedding FP32
+    n x m, eigenvalue estimates FP64 [m])."""
     n = indptr.numel() - 1
     dev = indptr.device
     labels = torch.empty(n, dtype=torch.int32, device=dev)
