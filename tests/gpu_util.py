@@ -37,6 +37,41 @@ def col_rel_err(got, want):
     return float(np.max(num / np.where(den > 0, den, 1.0)))
 
 
+def elem_rel_err(got, want, floor):
+    """Element-wise error: max over elements of
+    |got - want| / (|want| + floor * rms(want's column)), and the (row,
+    column) where it is largest.  The column-norm error of col_rel_err can
+    hide a few wrong rows of a large block; this bound cannot."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    if want.ndim == 1:
+        got, want = got[:, None], want[:, None]
+    rms = np.sqrt(np.mean(want * want, axis=0))
+    den = np.abs(want) + floor * np.where(rms > 0, rms, 1.0)[None, :]
+    r = np.abs(got - want) / den
+    i, j = np.unravel_index(int(np.argmax(r)), r.shape)
+    return float(r[i, j]), (int(i), int(j))
+
+
+# Element-wise bounds by storage precision, (floor, bound): an entry may be
+# off by bound * (|want| + floor * rms of its column), i.e. by `bound`
+# relative where it is large and by bound * floor * rms where it is near 0
+# (rounding of the block leaves an absolute error of the order of the
+# column's scale there).  Measured worst cases over the parity tests: FP64
+# 2e-11, FP32 1.5e-4, BF16 about 0.03 of the rms near 0.
+ELEM = {"f64": (1e-6, 1e-9), "f32": (1e-3, 1e-3), "bf16": (0.5, 0.05)}
+
+
+def check_elems(got, want, dtype, what=""):
+    """Asserts the element-wise bound of ELEM[dtype] and prints the worst
+    entry."""
+    floor, bound = ELEM[dtype]
+    err, (i, j) = elem_rel_err(got, want, floor)
+    say(f"  {what} element-wise err {err:.2e} at row {i} col {j} (bound {bound:.0e})")
+    assert err <= bound, (err, i, j)
+    return err
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()

@@ -5,7 +5,7 @@ import torch
 
 import synth
 from oracle import fsc_oracle as o
-from tests.gpu_util import col_rel_err, host_weights, say, to_device
+from tests.gpu_util import check_elems, col_rel_err, host_weights, say, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -67,6 +67,8 @@ def test_batched_matches_single_graph_path(gpu_lib, slab_kb):
         say(f"  graph {gi}: n={g.n} k={k} l={l} t={t} err vs single {err_single:.1e} vs oracle {err_oracle:.1e} ARI {a:.4f}")
         assert err_oracle <= 1e-5
         assert err_single <= 1e-5
+        check_elems(E, want, "f32", "vs oracle")
+        check_elems(E, Es, "f32", "vs single")
         assert a >= 0.99
         assert L.min() >= 0 and L.max() < k
         if slab_kb == 16 and g.n * (4 if l <= 4 else 8) * 4 > 16 * 1024:

@@ -18,7 +18,7 @@ import torch
 
 import synth
 from oracle import fsc_oracle as o
-from tests.gpu_util import col_rel_err, say
+from tests.gpu_util import ELEM, check_elems, col_rel_err, elem_rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +37,7 @@ def test_knn70k_bf16_matches_oracle(gpu_lib):
     err_w = col_rel_err(E, o.embed(n, ip_h, ix_h, w.double().cpu().numpy(), 4, 40, seed=0))
     say("  bf16 rel err vs oracle on bf16 weights", err, "vs fp32 weights", err_w)
     assert err <= 2e-2
+    check_elems(E, want, "bf16", "70k kNN")
     labels = gpu_lib.cluster(ip, ix, d, 10, 4, 40, 0, kmeans_iters=30, vec_dtype="bf16")
     deg = o.degrees(n, ip_h, ix_h, w_h)
     lab_o, _ = o.kmeans(want, 10, 30, 0, eligible=deg > 0)
@@ -56,14 +57,20 @@ def test_batched512_matches_plain_path(gpu_lib):
     ls = [p["l"] for p in params]
     ts = [p["t"] for p in params]
     say(f"batched: {len(graphs)} graphs, sum nnz {sum(g[1].numel() for g in graphs)}")
-    labels, off = gpu_lib.cluster_batched(graphs, ks, ls, ts, 0, kmeans_iters=30)
-    worst = 1.0
+    labels, emb, off, eoff = gpu_lib.cluster_batched(graphs, ks, ls, ts, 0, kmeans_iters=30, return_embedding=True)
+    worst, worst_e = 1.0, (0.0, -1, None)
     for i, g in enumerate(graphs):
-        plain = gpu_lib.cluster(*g, ks[i], ls[i], ts[i], i, kmeans_iters=30)
+        plain, Ep = gpu_lib.cluster(*g, ks[i], ls[i], ts[i], i, kmeans_iters=30, return_embedding=True)
         a = float(gpu_lib.ari(labels[off[i]:off[i + 1]], plain, ks[i], ks[i]))
         worst = min(worst, a)
-    say("  min ARI vs plain path", worst)
+        E = emb[eoff[i]:eoff[i + 1]].reshape(Ep.shape).cpu().numpy()
+        e, where = elem_rel_err(E, Ep.cpu().numpy(), ELEM["f32"][0])
+        assert col_rel_err(E, Ep.cpu().numpy()) <= 1e-5, i
+        if e > worst_e[0]:
+            worst_e = (e, i, where)
+    say("  min ARI vs plain path", worst, "worst element-wise err (err, graph, (row, col))", worst_e)
     assert worst >= 0.99
+    assert worst_e[0] <= ELEM["f32"][1]
     # the two smallest graphs against the oracle directly
     for i in sorted(range(len(params)), key=lambda j: params[j]["n"])[:2]:
         ip, ix, d = graphs[i]

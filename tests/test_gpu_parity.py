@@ -12,7 +12,7 @@ import torch
 
 import synth
 from oracle import fsc_oracle as o
-from tests.gpu_util import col_rel_err, host_weights, say, to_device
+from tests.gpu_util import check_elems, col_rel_err, host_weights, say, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +49,7 @@ def test_small_sbm_fp64(gpu_lib):
     err = col_rel_err(E, want)
     say("fp64 rel err", err)
     assert err <= TOL["f64"]
+    check_elems(E, want, "f64")
 
 
 @pytest.mark.parametrize("l", [1, 2, 3, 4, 6, 8])
@@ -65,6 +66,7 @@ def test_ragged_weighted_graph(gpu_lib, l, vec):
         err = col_rel_err(E, want)
         say("  tile", tile, "rel err", err)
         assert err <= TOL[vec]
+        check_elems(E, want, vec)
         assert np.all(E[-13:] == 0)
 
 
@@ -77,6 +79,7 @@ def test_bf16_storage_on_knn_graph(gpu_lib):
     err = col_rel_err(E, want)
     say("bf16 rel err", err)
     assert err <= TOL["bf16"]
+    check_elems(E, want, "bf16")
     # f32 vectors with bf16 weights
     E32 = gpu_lib.embed(ip, ix, d, 4, 40, seed=2, vec_dtype="f32").cpu().numpy()
     assert col_rel_err(E32, want) <= TOL["f32"]

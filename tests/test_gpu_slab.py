@@ -17,7 +17,7 @@ import torch
 
 import synth
 from oracle import fsc_oracle as o
-from tests.gpu_util import col_rel_err, host_weights, say, to_device
+from tests.gpu_util import check_elems, col_rel_err, host_weights, say, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -61,6 +61,7 @@ def test_slab_matches_oracle_and_tiles(gpu_lib, slab, l, vec, wt, mode):
     err, err_plain = col_rel_err(E, want), col_rel_err(plain, want)
     say("  rel err slab", err, "tiles", err_plain)
     assert err <= TOL[vec]
+    check_elems(E, want, vec)
     assert np.all(E[-17:] == 0)
     if vec == "f32":
         assert col_rel_err(E, plain) <= 1e-5
@@ -163,6 +164,7 @@ def test_full_size_sbm_matches_oracle(gpu_lib):
     err = col_rel_err(E, want)
     say("  rel err", err)
     assert err <= TOL["f32"]
+    check_elems(E, want, "f32", "1M SBM")
     lab = gpu_lib.cluster(ip, ix, data, 10, 4, 30, 0, kmeans_iters=30)
     d = o.degrees(g.n, g.indptr, g.indices, None)
     lab_o, _ = o.kmeans(want, 10, 30, 0, eligible=d > 0)
