@@ -38,6 +38,7 @@
 #ifndef FSC_H
 #define FSC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -161,6 +162,20 @@ int fsc_embed(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t t, uint64_t
 int fsc_cluster(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t,
                 uint64_t seed, const fsc_opts* opts, int32_t* labels, void* emb,
                 float* centres, void* stream);
+
+/* fsc_cluster without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as fsc_cluster, but
+ * its workspace is a fixed device array of FSC_NOALLOC_MAX_BYTES that the
+ * library holds on every GPU it runs on until the process ends (its address
+ * is resolved when a context is created on that device).  A graph whose
+ * workspace exceeds that size returns FSC_E_NOMEM with the sizes in
+ * fsc_last_error().  Every call on one GPU shares that GPU's array and leaves
+ * the last call's contents there: calls that overlap on one GPU (other
+ * streams, other contexts, other threads) race.  Event timing is off in it. */
+#define FSC_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int fsc_cluster_noalloc(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t, uint64_t seed,
+                        const fsc_opts* opts, int32_t* labels, void* emb, float* centres, void* stream);
 
 /* k-means (Sec. 2.2) alone on n points of dimension l (1 <= l <= 8) stored as
  * n x l values of `dtype` (FSC_F32 or FSC_F64; computed in FP32): k-means++

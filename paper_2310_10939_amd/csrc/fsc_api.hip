@@ -294,6 +294,9 @@ int fsc_create(int device, fsc_context** out) {
     delete ctx;
     return rc;
   }
+  // the no-allocation entry point's scratch address on this device; a
+  // failure here is reported by that entry point, which tries again
+  if (noalloc_setup(device) != FSC_OK) g_last_error.clear();
   *out = ctx;
   return FSC_OK;
 }
@@ -348,6 +351,22 @@ int fsc_cluster(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_
   const fsc_opts o = opts ? *opts : default_opts();
   if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
   return cluster_run(&ctx->c, g, k, l, t, seed, o, labels, emb, centres, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int fsc_cluster_noalloc(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t, uint64_t seed,
+                        const fsc_opts* opts, int32_t* labels, void* emb, float* centres, void* stream) {
+  if (!ctx) return fail(FSC_E_ARG, "context is NULL");
+  if (!labels) return fail(FSC_E_ARG, "labels is NULL");
+  int rc;
+  if ((rc = check_csr(g))) return rc;
+  if (k < 1 || k > 64 || k > g->n) return fail(FSC_E_ARG, "k must be in [1, min(n, 64)]");
+  if (l < 1 || l > 8) return fail(FSC_E_ARG, "l must be in [1, 8]");
+  if (t < 0) return fail(FSC_E_ARG, "t must be >= 0");
+  const fsc_opts o = opts ? *opts : default_opts();
+  if (o.vec_dtype < FSC_F64 || o.vec_dtype > FSC_BF16) return fail(FSC_E_ARG, "bad vec_dtype");
+  if (o.tile_nnz < 0 || (o.tile_nnz > 0 && o.tile_nnz < 64)) return fail(FSC_E_ARG, "tile_nnz must be 0 or >= 64");
+  if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
+  return cluster_noalloc_run(&ctx->c, g, k, l, t, seed, o, labels, emb, centres, static_cast<hipStream_t>(stream));
 }
 
 int fsc_cluster_pmk(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t t, uint64_t seed, const fsc_opts* opts,

@@ -284,6 +284,10 @@ int points_from_user(Context* ctx, const void* pts, int dtype, int64_t n, int l,
 // allocates only when the arena is too small.
 size_t cluster_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, const fsc_opts& o);
 // With ws, the run uses that workspace instead of the context arena.
+// The no-allocation entry point's scratch (fsc_noalloc.hip).
+int noalloc_setup(int device);
+int cluster_noalloc_run(Context* ctx, const fsc_csr* g, int k, int l, int t, uint64_t seed, const fsc_opts& o,
+                        int32_t* labels, void* emb, float* centres, hipStream_t s);
 int cluster_run(Context* c, const fsc_csr* g, int k, int l, int t, uint64_t seed, const fsc_opts& o,
                 int32_t* labels, void* emb, float* centres, hipStream_t s, const Arena* ws);
 

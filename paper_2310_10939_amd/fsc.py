@@ -72,6 +72,7 @@ _lib.fsc_knn.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]
 _lib.fsc_cluster_eigs.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp,
                                   _vp, _vp]
 _lib.fsc_knn_graph.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp]
+_lib.fsc_cluster_noalloc.argtypes = _lib.fsc_cluster.argtypes
 _lib.fsc_cluster_pmk.argtypes = [_vp, ctypes.POINTER(Csr), _i32, _i32, _u64, ctypes.POINTER(Opts), _vp, _vp, _vp, _vp]
 _lib.fsc_tuning_set.argtypes = [_vp, ctypes.POINTER(Tuning)]
 _lib.fsc_timing_enable.argtypes = [_vp, ctypes.c_int]
@@ -82,7 +83,7 @@ _lib.fsc_version.restype = ctypes.c_int
 EXPORTS = ("fsc_create", "fsc_destroy", "fsc_embed", "fsc_cluster", "fsc_kmeans", "fsc_ari", "fsc_nmi",
            "fsc_cluster_batched", "fsc_autotune", "fsc_mlp_param_count", "fsc_filter_stats",
            "fsc_mlp_forward", "fsc_mlp_loss_grad", "fsc_mlp_adam", "fsc_mlp_train", "fsc_filter_embed",
-           "fsc_cluster_filtered", "fsc_cluster_pmk", "fsc_cluster_eigs", "fsc_knn", "fsc_knn_graph",
+           "fsc_cluster_filtered", "fsc_cluster_noalloc", "fsc_cluster_pmk", "fsc_cluster_eigs", "fsc_knn", "fsc_knn_graph",
            "fsc_tuning_set", "fsc_timing_enable", "fsc_timing_read", "fsc_last_error", "fsc_version")
 
 
@@ -177,6 +178,25 @@ def embed(indptr, indices, data, l, t, seed, vec_dtype="f32", x0=None, traces=Fa
 def cluster(indptr, indices, data, k, l, t, seed, kmeans_iters=30, vec_dtype="f32", x0=None, return_embedding=False,
             return_centres=False, validate=False, renorm=False, traces=False, tile_nnz=0, out=None):
     """FastSpectralCluster: labels (int32 [n]) of the k-way partition."""
+    return _cluster(_lib.fsc_cluster, indptr, indices, data, k, l, t, seed, kmeans_iters, vec_dtype, x0,
+                    return_embedding, return_centres, validate, renorm, traces, tile_nnz, out)
+
+
+def cluster_noalloc(indptr, indices, data, k, l, t, seed, kmeans_iters=30, vec_dtype="f32", x0=None,
+                    return_embedding=False, return_centres=False, validate=False, renorm=False, traces=False,
+                    tile_nnz=0, out=None):
+    """cluster() through fsc_cluster_noalloc: the library allocates no device
+    memory (its workspace is a fixed scratch array of NOALLOC_MAX_BYTES per
+    GPU); the outputs are allocated here unless `out` is given."""
+    return _cluster(_lib.fsc_cluster_noalloc, indptr, indices, data, k, l, t, seed, kmeans_iters, vec_dtype, x0,
+                    return_embedding, return_centres, validate, renorm, traces, tile_nnz, out)
+
+
+NOALLOC_MAX_BYTES = 64 << 20
+
+
+def _cluster(fn, indptr, indices, data, k, l, t, seed, kmeans_iters, vec_dtype, x0, return_embedding,
+             return_centres, validate, renorm, traces, tile_nnz, out):
     n = indptr.numel() - 1
     dev = indptr.device
     vd = _NAMES[vec_dtype]
@@ -187,8 +207,8 @@ def cluster(indptr, indices, data, k, l, t, seed, kmeans_iters=30, vec_dtype="f3
     ray = torch.empty((max(t, 1), l), dtype=torch.float64, device=dev) if traces else None
     g = _csr(indptr, indices, data)
     o = _opts(vec_dtype, kmeans_iters, validate, renorm, x0, sq, ray, tile_nnz)
-    _check(_lib.fsc_cluster(context(dev.index), ctypes.byref(g), k, l, t, seed, ctypes.byref(o), _ptr(labels),
-                            _ptr(emb), _ptr(cen), _stream()))
+    _check(fn(context(dev.index), ctypes.byref(g), k, l, t, seed, ctypes.byref(o), _ptr(labels), _ptr(emb), _ptr(cen),
+              _stream()))
     res = [labels]
     if return_embedding:
         res.append(emb)
