@@ -50,7 +50,8 @@ typedef enum {
   FSC_OK = 0,
   FSC_E_ARG = -1,          /* bad argument: null pointer, size out of range, bad dtype */
   FSC_E_GRAPH = -2,        /* validation found a self-loop, a negative/NaN weight,
-                              an index out of range or a bad row pointer */
+                              an index out of range, a bad row pointer or (level
+                              2) an asymmetric adjacency */
   FSC_E_HIP = -3,          /* a HIP runtime call or kernel launch failed */
   FSC_E_NOMEM = -4,        /* device workspace allocation failed */
   FSC_E_UNSUPPORTED = -5   /* combination of dtypes or sizes not built */
@@ -91,8 +92,13 @@ typedef struct {
   /* Lloyd steps after k-means++ seeding (fsc_cluster); 0 means 30. */
   int32_t kmeans_iters;
   /* 0: no checks.  1: check row_ptr, column range, self-loops and weights on
-   * the device; this synchronises the stream once and returns FSC_E_GRAPH on
-   * failure. */
+   * the device; this synchronises the stream and returns FSC_E_GRAPH on
+   * failure.  2: also check that A is symmetric (Sec. 2: G is undirected):
+   * A(r, c) == A(c, r) for every stored entry, duplicate entries of one
+   * position adding up (FP64, in ascending order of weight), an absent
+   * mirror counting as 0; the entries are radix-sorted on the device in
+   * workspace of about 32 bytes per nonzero (needs nnz < 2^31, else
+   * FSC_E_UNSUPPORTED).  Other values: FSC_E_ARG. */
   int32_t validate;
   /* Non-zero: after every step rescale each column of the iterate to unit
    * D-norm (y-space), keeping the FP64 product of the scales, and undo the
@@ -113,6 +119,11 @@ typedef struct {
    * capturing them into a hipGraph (which is replayed while the batch stays
    * the same). */
   int32_t no_graph;
+  /* fsc_embed only: non-zero writes Y = D^{1/2} Z_t, the PowerMethod
+   * iterates of Algorithm 1 (Algorithm 2's Y), instead of the embedding
+   * D^{-1/2} Y; an isolated vertex's row is 2^-t times its row of X0 (its row
+   * of M is e_v / 2). */
+  int32_t return_y;
 } fsc_opts;
 
 typedef struct fsc_context fsc_context;

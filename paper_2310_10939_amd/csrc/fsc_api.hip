@@ -109,7 +109,9 @@ static int prepare_embed(Context* ctx, const fsc_csr* g, int l, int t, uint64_t 
   io->x0 = o.x0;
   io->sqnorm_trace = o.sqnorm_trace;
   io->rayleigh_trace = o.rayleigh_trace;
-  const size_t bytes = embed_workspace_bytes(ctx, g, l, o.vec_dtype, o.tile_nnz) + extra;
+  if (o.validate < 0 || o.validate > 2) return fail(FSC_E_ARG, "validate must be 0, 1 or 2");
+  const size_t bytes = std::max(embed_workspace_bytes(ctx, g, l, o.vec_dtype, o.tile_nnz) + extra,
+                                o.validate >= 2 ? symmetry_workspace_bytes(g) : size_t(0));
   if (given) {
     if (given->size < bytes) return fail(FSC_E_NOMEM, "given workspace too small");
     *arena = *given;
@@ -172,7 +174,8 @@ size_t cluster_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, cons
   const int LH = padded_width(l);
   const bool direct = o.vec_dtype == FSC_F32 && LH == KD;
   const size_t extra = kmeans_workspace_bytes(g->n, KD) + (direct ? 0 : align_up(g->n * KD * 4)) + 1024;
-  return embed_workspace_bytes(ctx, g, l, o.vec_dtype, o.tile_nnz) + extra;
+  return std::max(embed_workspace_bytes(ctx, g, l, o.vec_dtype, o.tile_nnz) + extra,
+                  o.validate >= 2 ? symmetry_workspace_bytes(g) : size_t(0));
 }
 
 int cluster_run(Context* c, const fsc_csr* g, int k, int l, int t, uint64_t seed, const fsc_opts& o,
@@ -198,7 +201,7 @@ int cluster_run(Context* c, const fsc_csr* g, int k, int l, int t, uint64_t seed
   km.centres_out = centres;
   float* pts = direct ? nullptr : arena.take<float>(g->n * KD);
   if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
-  if (o.validate && (rc = validate_csr(c, g, s))) return rc;
+  if (o.validate && (rc = validate_csr(c, g, o.validate, arena, s))) return rc;
   if ((rc = embed_run(c, &io, s))) return rc;
   if (emb && (rc = embed_unpad(c, &io, emb, s))) return rc;
   if (direct) {
@@ -250,7 +253,7 @@ static int ortho_cluster_run(Context* c, const fsc_csr* g, int k, int m, int t, 
   io.ortho = &oa;
   if ((rc = kmeans_bind_workspace(&arena, &km))) return rc;
   if (arena.used > arena.size) return fail(FSC_E_NOMEM, "orthogonal iteration workspace too small");
-  if (o.validate && (rc = validate_csr(c, g, s))) return rc;
+  if (o.validate && (rc = validate_csr(c, g, o.validate, arena, s))) return rc;
   if ((rc = embed_run(c, &io, s))) return rc;
   if ((rc = embed_to_points(c, &io, pts, s))) return rc;
   if (emb && (rc = points_cols_run(pts, g->n, KD, m, emb, s))) return rc;
@@ -336,9 +339,9 @@ int fsc_embed(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t t, uint64_t
   EmbedIO io;
   Arena arena;
   if ((rc = prepare_embed(&ctx->c, g, l, t, seed, o, 0, &io, &arena))) return rc;
-  if (o.validate && (rc = validate_csr(&ctx->c, g, s))) return rc;
+  if (o.validate && (rc = validate_csr(&ctx->c, g, o.validate, arena, s))) return rc;
   if ((rc = embed_run(&ctx->c, &io, s))) return rc;
-  return embed_unpad(&ctx->c, &io, emb, s);
+  return o.return_y ? embed_y(&ctx->c, &io, emb, s) : embed_unpad(&ctx->c, &io, emb, s);
 }
 
 int fsc_cluster(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t l, int32_t t, uint64_t seed,

@@ -116,6 +116,16 @@ __global__ void fill_i32(int32_t* p, int64_t count, int32_t v) {
 // ---------------------------------------------------------------------------
 // Start block: Z0 = D^{-1/2} X0, X0 Gaussian (Algorithm 2) or given.
 // ---------------------------------------------------------------------------
+// Entry (i, q) of X0: the caller's, or Philox4x32-10 with counter
+// (i, 0, q, 0) and Box-Muller on its two 53-bit uniforms.
+__device__ __forceinline__ double start_value(int32_t i, int q, int32_t l, uint32_t k0, uint32_t k1,
+                                              const double* __restrict__ x0) {
+  if (x0) return x0[(int64_t)i * l + q];
+  const u32x4 r = philox4x32_10(u32x4{(uint32_t)i, 0u, (uint32_t)q, 0u}, k0, k1);
+  const double u1 = uniform53(r.x, r.y), u2 = uniform53(r.z, r.w);
+  return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
 template <typename S, int LH>
 __global__ __launch_bounds__(kBlock) void start_block(int32_t n, int32_t l, uint32_t k0, uint32_t k1,
                                                       const double* __restrict__ x0,
@@ -132,16 +142,7 @@ __global__ __launch_bounds__(kBlock) void start_block(int32_t n, int32_t l, uint
     A row[LH];
 #pragma unroll
     for (int q = 0; q < LH; ++q) {
-      double x = 0.0;
-      if (q < l) {
-        if (x0) {
-          x = x0[(int64_t)i * l + q];
-        } else {
-          const u32x4 r = philox4x32_10(u32x4{(uint32_t)i, 0u, (uint32_t)q, 0u}, k0, k1);
-          const double u1 = uniform53(r.x, r.y), u2 = uniform53(r.z, r.w);
-          x = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
-        }
-      }
+      const double x = q < l ? start_value(i, q, l, k0, k1, x0) : 0.0;
       row[q] = elem<S>::to_acc(elem<S>::from_acc(static_cast<A>(s * x)));
       st[q] += d * (double)row[q] * (double)row[q];
     }
@@ -153,6 +154,28 @@ __global__ __launch_bounds__(kBlock) void start_block(int32_t n, int32_t l, uint
 // ---------------------------------------------------------------------------
 // Output conversions
 // ---------------------------------------------------------------------------
+// Y = D^{1/2} Z_t, the PowerMethod iterates themselves (n x l, unpadded):
+// sqrt(d_v) z_v where d_v > 0; an isolated vertex's row of M is e_v / 2, so
+// its row of Y is 2^-t times its row of X0.
+template <typename S, int LH>
+__global__ void rows_to_y(const S* __restrict__ z, const double* __restrict__ deg, int32_t n, int32_t l, int32_t t,
+                          uint32_t k0, uint32_t k1, const double* __restrict__ x0, S* __restrict__ out) {
+  using A = typename elem<S>::acc;
+  const int64_t total = (int64_t)n * l;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = (int32_t)(i / l);
+    const int q = (int)(i - (int64_t)r * l);
+    const double d = deg[r];
+    double y;
+    if (d > 0.0) {
+      y = sqrt(d) * (double)elem<S>::to_acc(z[(int64_t)r * LH + q]);
+    } else {
+      y = ldexp(start_value(r, q, l, k0, k1, x0), -t);
+    }
+    out[i] = elem<S>::from_acc(static_cast<A>(y));
+  }
+}
+
 template <typename S, int LH>
 __global__ void unpad_rows(const S* __restrict__ z, int32_t n, int32_t l, S* __restrict__ out) {
   const int64_t total = (int64_t)n * l;
@@ -539,6 +562,33 @@ static int unpad_typed(const EmbedIO* io, void* out, hipStream_t s) {
   return check_hip(hipGetLastError(), "unpad_rows launch");
 }
 
+template <typename S>
+static int y_typed(const EmbedIO* io, void* out, hipStream_t s) {
+  const int32_t n = (int32_t)io->g->n;
+  const int64_t total = (int64_t)n * io->l;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  const S* z = reinterpret_cast<const S*>(io->zt);
+  S* o = reinterpret_cast<S*>(out);
+  const uint32_t k0 = (uint32_t)(io->seed & 0xffffffffu), k1 = (uint32_t)(io->seed >> 32);
+  switch (io->LH) {
+    case 1: hipLaunchKernelGGL((rows_to_y<S, 1>), dim3(blocks), dim3(256), 0, s, z, io->deg, n, io->l, io->t, k0, k1, io->x0, o); break;
+    case 2: hipLaunchKernelGGL((rows_to_y<S, 2>), dim3(blocks), dim3(256), 0, s, z, io->deg, n, io->l, io->t, k0, k1, io->x0, o); break;
+    case 4: hipLaunchKernelGGL((rows_to_y<S, 4>), dim3(blocks), dim3(256), 0, s, z, io->deg, n, io->l, io->t, k0, k1, io->x0, o); break;
+    case 8: hipLaunchKernelGGL((rows_to_y<S, 8>), dim3(blocks), dim3(256), 0, s, z, io->deg, n, io->l, io->t, k0, k1, io->x0, o); break;
+  }
+  return check_hip(hipGetLastError(), "rows_to_y launch");
+}
+
+int embed_y(Context*, const EmbedIO* io, void* out, hipStream_t s) {
+  if (io->g->n == 0) return FSC_OK;
+  switch (io->vec_dtype) {
+    case FSC_F64: return y_typed<double>(io, out, s);
+    case FSC_F32: return y_typed<float>(io, out, s);
+    case FSC_BF16: return y_typed<bf16_t>(io, out, s);
+  }
+  return fail(FSC_E_ARG, "bad vec_dtype");
+}
+
 int embed_unpad(Context*, const EmbedIO* io, void* out, hipStream_t s) {
   if (io->g->n == 0) return FSC_OK;
   switch (io->vec_dtype) {
@@ -574,7 +624,7 @@ int embed_to_points(Context*, const EmbedIO* io, float* pts, hipStream_t s) {
   return fail(FSC_E_ARG, "bad vec_dtype");
 }
 
-int validate_csr(Context* ctx, const fsc_csr* g, hipStream_t s) {
+int validate_csr(Context* ctx, const fsc_csr* g, int level, const Arena& scratch, hipStream_t s) {
   int rc;
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, ctx->error_flag, (int64_t)4, 0);
   const int32_t n = (int32_t)g->n;
@@ -602,6 +652,7 @@ int validate_csr(Context* ctx, const fsc_csr* g, hipStream_t s) {
   if (f[1]) return fail(FSC_E_GRAPH, "column index out of range");
   if (f[2]) return fail(FSC_E_GRAPH, "graph has a self-loop");
   if (f[3]) return fail(FSC_E_GRAPH, "weight is negative, NaN or infinite");
+  if (level >= 2) return validate_symmetry(ctx, g, scratch, s);
   return FSC_OK;
 }
 

@@ -213,9 +213,15 @@ int embed_run(Context* ctx, EmbedIO* io, hipStream_t s);
 int embed_unpad(Context* ctx, const EmbedIO* io, void* out, hipStream_t s);
 // Writes Z_t as FP32 n x KD k-means points (KD = kmeans_width(l)).
 int embed_to_points(Context* ctx, const EmbedIO* io, float* pts, hipStream_t s);
+// Writes Y = D^{1/2} Z_t (the PowerMethod iterates, n x l, vec dtype).
+int embed_y(Context* ctx, const EmbedIO* io, void* out, hipStream_t s);
 // Device-side validation of a CSR; synchronises `s`.  Returns FSC_OK or
-// FSC_E_GRAPH.
-int validate_csr(Context* ctx, const fsc_csr* g, hipStream_t s);
+// FSC_E_GRAPH.  Level 2 also checks symmetry (fsc_validate.hip) in
+// `scratch`, which must hold symmetry_workspace_bytes(g) and must not hold
+// live data (validation runs before the call's other kernels).
+int validate_csr(Context* ctx, const fsc_csr* g, int level, const Arena& scratch, hipStream_t s);
+size_t symmetry_workspace_bytes(const fsc_csr* g);
+int validate_symmetry(Context* ctx, const fsc_csr* g, Arena scratch, hipStream_t s);
 
 // ---- column-slab plan (fsc_slab.hip) ----
 // Slab shape for an n-row block of LH columns: true (and the slab width S,

@@ -35,7 +35,7 @@ class Opts(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("renorm", ctypes.c_int32),
                 ("x0", ctypes.c_void_p), ("sqnorm_trace", ctypes.c_void_p),
                 ("rayleigh_trace", ctypes.c_void_p), ("tile_nnz", ctypes.c_int32),
-                ("no_graph", ctypes.c_int32)]
+                ("no_graph", ctypes.c_int32), ("return_y", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -146,7 +146,7 @@ def _opts(vec_dtype="f32", kmeans_iters=0, validate=False, renorm=False, x0=None
     o = Opts()
     o.vec_dtype = _NAMES[vec_dtype] if isinstance(vec_dtype, str) else int(vec_dtype)
     o.kmeans_iters = int(kmeans_iters)
-    o.validate = int(bool(validate))
+    o.validate = int(validate)   # False/True -> 0/1; 2 adds the symmetry check
     o.renorm = int(bool(renorm))
     o.x0 = x0.data_ptr() if x0 is not None else None
     o.sqnorm_trace = sqnorm.data_ptr() if sqnorm is not None else None
@@ -156,11 +156,13 @@ def _opts(vec_dtype="f32", kmeans_iters=0, validate=False, renorm=False, x0=None
 
 
 def embed(indptr, indices, data, l, t, seed, vec_dtype="f32", x0=None, traces=False, renorm=False,
-          validate=False, tile_nnz=0):
-    """D^{-1/2} Y for l Gaussian start vectors and t PowerMethod steps.
+          validate=False, tile_nnz=0, return_y=False):
+    """D^{-1/2} Y for l Gaussian start vectors and t PowerMethod steps
+    (return_y=True: Y itself).
 
     Returns the n x l embedding (dtype per vec_dtype) and, with traces=True,
-    also the FP64 (t+1) x l squared norms and t x l Rayleigh quotients."""
+    also the FP64 (t+1) x l squared norms and t x l Rayleigh quotients.
+    validate: 0/False none, 1/True the cheap checks, 2 also symmetry."""
     n = indptr.numel() - 1
     dev = indptr.device
     vd = _NAMES[vec_dtype]
@@ -171,6 +173,7 @@ def embed(indptr, indices, data, l, t, seed, vec_dtype="f32", x0=None, traces=Fa
     ray = torch.empty((max(t, 0), l), dtype=torch.float64, device=dev) if traces else None
     g = _csr(indptr, indices, data)
     o = _opts(vec_dtype, 0, validate, renorm, x0, sq, ray if (ray is not None and t > 0) else None, tile_nnz)
+    o.return_y = int(bool(return_y))
     _check(_lib.fsc_embed(context(dev.index), ctypes.byref(g), l, t, seed, ctypes.byref(o), _ptr(out), _stream()))
     return (out, sq, ray) if traces else out
 

@@ -51,9 +51,26 @@ def test_binding_covers_the_exports_and_needs_no_gpu_to_load():
     assert seen == [b""]
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the binding's ctypes mirrors
+    equals what a C compiler makes of include/fsc.h."""
     from paper_2310_10939_amd import fsc
-    # int64 n, nnz, 3 pointers, int32 dtype (+pad) ; opts: 4 int32, 3 pointers, int32 (+pad)
-    assert ctypes.sizeof(fsc.Csr) == 8 * 5 + 8
-    assert ctypes.sizeof(fsc.Opts) == 4 * 4 + 8 * 3 + 8
-    assert ctypes.sizeof(fsc.Tuning) == 6 * 4
+    structs = {"fsc_csr": fsc.Csr, "fsc_opts": fsc.Opts, "fsc_tuning": fsc.Tuning}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fsc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)

@@ -74,3 +74,27 @@ def test_trial_report_summary_is_mean_and_population_std():
     res = {"workload": "w", "methods": {"fsc": {"ari": [1.0, 0.5], "nmi": [0.9, 0.7], "ms": [2.0, 4.0]}}}
     row = summary(res).splitlines()[-1]
     assert row == "| w | fsc | 0.7500 ± 0.2500 | 0.8000 ± 0.1000 | 3.00 ± 1.00 |"
+
+
+def test_pattern_only_bytes_drop_the_weights():
+    n, nnz = 1_000_000, 39_988_154
+    assert bench.spmm_bytes(n, nnz, 4, "f32", "f32") - bench.pattern_bytes(n, nnz, 4, "f32") == nnz * 4
+
+
+def test_oracle_report_on_the_oracle_itself():
+    """oracle_report's comparison: the oracle's own embedding and labels give
+    error 0 and ARI 1; a planted error in one entry shows in the element-wise
+    figure and the per-column one; times and thread counts are reported."""
+    import numpy as np
+    import synth
+    from oracle import fsc_oracle as o
+    g = synth.sbm(300, 3, 0.3, 0.01, seed=1)
+    lab, _, E = o.fast_spectral_cluster(g.n, g.indptr, g.indices, None, 3, 2, 10, 4, 10)
+    base, par = bench.oracle_report(g, 3, 2, 10, 10, 4, E, lab)
+    assert par["fp64_rel_err"] == 0.0 and par["fp64_elem_err"] == 0.0 and par["ari_vs_oracle"] == 1.0
+    assert base["kind"] == "oracle" and base["cores"] >= 1 and base["nproc"] >= 1
+    assert base["value"] > 0 and base["value_1thread"] > 0
+    E2 = E.copy()
+    E2[17, 1] += 0.01 * np.abs(E[:, 1]).max()
+    _, par2 = bench.oracle_report(g, 3, 2, 10, 10, 4, E2, lab)
+    assert par2["fp64_elem_err"] > 1e-3 and par2["fp64_rel_err"] > 0
