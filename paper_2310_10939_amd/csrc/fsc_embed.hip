@@ -304,12 +304,12 @@ static int launch_tiles(const Op& op, const TileArgs& ta, const StatsArgs& sa, i
 }
 
 // Phase-form kernel shape: nonzeros in flight per row, rows per lane.
-constexpr int kSlabU = 8;
+constexpr int kSlabU = 4;
 constexpr int kSlabJ = 1;
 
-template <class Op>
-static int launch_slab(const Op& op, const TileArgs& ta, const SlabArgs& sb, const StatsArgs& sa, int grid,
-                       int rgrid, hipStream_t s) {
+template <typename CI, class Op>
+static int launch_slab_ci(const Op& op, const TileArgs& ta, const SlabArgs& sb, const StatsArgs& sa, int grid,
+                          int rgrid, hipStream_t s) {
   if (sb.wave) {
     SlabWaveArgs sw;
     sw.nslab = sb.nslab;
@@ -317,14 +317,22 @@ static int launch_slab(const Op& op, const TileArgs& ta, const SlabArgs& sb, con
     sw.gbase = sb.gbase;
     sw.gunit = sb.gunit;
     sw.scol = sb.scol;
-    hipLaunchKernelGGL((slab_wave_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sw, sa);
+    sw.S = sb.S;
+    hipLaunchKernelGGL((slab_wave_kernel<8, CI, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sw, sa);
   } else if (sb.xcd) {
-    hipLaunchKernelGGL((slab_xcd_kernel<8, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb);
+    hipLaunchKernelGGL((slab_xcd_kernel<8, CI, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb);
     hipLaunchKernelGGL((slab_reduce_kernel<Op>), dim3(rgrid), dim3(kBlock), 0, s, op, ta, sb, sa);
   } else {
-    hipLaunchKernelGGL((slab_kernel<kSlabU, kSlabJ, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb, sa);
+    hipLaunchKernelGGL((slab_kernel<kSlabU, kSlabJ, CI, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb, sa);
   }
   return check_hip(hipGetLastError(), "slab_kernel launch");
+}
+
+template <class Op>
+static int launch_slab(const Op& op, const TileArgs& ta, const SlabArgs& sb, const StatsArgs& sa, int grid,
+                       int rgrid, hipStream_t s) {
+  return sb.c16 ? launch_slab_ci<uint16_t>(op, ta, sb, sa, grid, rgrid, s)
+                : launch_slab_ci<int32_t>(op, ta, sb, sa, grid, rgrid, s);
 }
 
 // One step's launch: the column-slab kernel when the plan has slabs.
@@ -495,6 +503,8 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
   sb.tunit = sp.tunit;
   sb.rgrid = persistent_grid(ctx, ((int64_t)n + kBlock - 1) / kBlock, 8);
   sb.scol = sp.scol;
+  sb.c16 = sp.c16;
+  sb.S = sp.S;
   sb.sperm = sp.sperm;
   sb.sbase = sp.sbase;
   sb.smax = sp.smax;

@@ -67,7 +67,7 @@ struct Tune {
   int xcd_order = 1;       // contiguous short-tile range per XCD
   int unroll = 4;          // nonzeros in flight per lane
   int slab_kb = 1024;      // column-slab size (KiB of the start block); <= 0: off
-  int slab_bpc = 6;        // resident blocks per CU of the column-slab kernel (phases)
+  int slab_bpc = 8;        // resident blocks per CU of the column-slab kernel (phases)
   int slab_xcd_bpc = 7;    // the same for the per-XCD form
   int slab_mode = 0;       // 0 automatic, 1 phases, 2 per-XCD slabs, 4 waves
   int slab_wave_bpc = 8;   // resident blocks per CU of the wave form
@@ -98,7 +98,8 @@ struct SlabPlan {
   float* part = nullptr;       // per-XCD form: [n/64][nslab][64][LH] partial sums
   uint8_t* tunit = nullptr;    // [ntiles] 1: every weight of the tile's short rows is 1
   int64_t max_long = 0, max_chunks = 0;
-  int32_t* scol = nullptr;     // [nnz] column indices in slab order
+  void* scol = nullptr;        // [nnz] column indices in slab order (uint16_t slab-local when c16, else int32_t)
+  int c16 = 0;                 // 1: S <= 65536, indices relative to the slab's first column
   void* sval = nullptr;        // [nnz] weights in slab order (null: unit weights)
   uint16_t* sperm = nullptr;   // [n * nslab]
   int32_t* sbase = nullptr;    // [ntiles * nslab][kSlabLong + 1]

@@ -139,11 +139,11 @@ constexpr int kBuild = 1024;  // threads of the build kernel: one per row of a t
 constexpr int kBuildU = 8;    // nonzeros of a row loaded at once
 constexpr int kStageWords = 12288;  // 48 KiB of LDS staging: column indices, then weights when loaded
 
-template <typename W>
+template <typename W, typename CI>
 __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const W* __restrict__ val, int32_t n,
     int32_t rows, int32_t S, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
-    const int32_t* __restrict__ coff, int32_t* __restrict__ scol, W* __restrict__ sval, uint16_t* __restrict__ sperm,
+    const int32_t* __restrict__ coff, CI* __restrict__ scol, W* __restrict__ sval, uint16_t* __restrict__ sperm,
     int32_t* __restrict__ sbase, int32_t* __restrict__ smax, int64_t* __restrict__ sreg,
     LongChunk* __restrict__ chunks, uint8_t* __restrict__ tunit, DegreeOut dout) {
   __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
@@ -305,8 +305,9 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
           if (p < p0 || p >= p1) continue;
           const int kk = cnt[p * R + rl]++;
           const int32_t off = (int32_t)(regL[p] - g0) + baseL[p * (kSlabLong + 1) + kk] + spos[p * R + rl];
-          if (staged) stcol[off] = c[u];
-          else scol[g0 + off] = c[u];
+          const int32_t ci = sizeof(CI) == 2 ? c[u] - p * S : c[u];  // slab-local in 16 bits
+          if (staged) stcol[off] = ci;
+          else scol[g0 + off] = (CI)ci;
           if constexpr (!std::is_void<W>::value) {
             if (copy_w) {
               const W w = val[j0 + u];
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     __syncthreads();
     if (staged) {
       for (int32_t e = threadIdx.x; e < gsz; e += kBuild) {
-        scol[g0 + e] = stcol[e];
+        scol[g0 + e] = (CI)stcol[e];
         if constexpr (!std::is_void<W>::value) {
           if (copy_w) sval[g0 + e] = stval[e];
         }
@@ -361,11 +362,11 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
 // length (a byte); per group: the start of its nonzeros and a unit-weight
 // flag.  The positions within a group come from wave scans, so no sort is
 // needed.
-template <typename W>
+template <typename W, typename CI>
 __global__ __launch_bounds__(kBuild) void slab_wave_build_kernel(
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const W* __restrict__ val, int32_t n,
     int32_t rows, int32_t S, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
-    const int32_t* __restrict__ coff, int32_t* __restrict__ scol, W* __restrict__ sval, uint8_t* __restrict__ wlen,
+    const int32_t* __restrict__ coff, CI* __restrict__ scol, W* __restrict__ sval, uint8_t* __restrict__ wlen,
     int64_t* __restrict__ gbase, uint8_t* __restrict__ gunit, LongChunk* __restrict__ chunks, DegreeOut dout) {
   __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
   __shared__ uint16_t spos[kSlabMax * kSlabRows];  // start of each (row, slab) segment within its group
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(kBuild) void slab_wave_build_kernel(
         const int p = slab_of(c[u], S, last);
         const int kk = cnt[p * R + rl]++;
         const int64_t dst = gb + spos[p * R + rl] + kk;
-        scol[dst] = c[u];
+        scol[dst] = (CI)(sizeof(CI) == 2 ? c[u] - p * S : c[u]);
         if constexpr (!std::is_void<W>::value) {
           const W w = val[j0 + u];
           sval[dst] = w;
@@ -573,7 +574,8 @@ int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
   sp.ntiles = (int32_t)nt;
   sp.max_long = nnz / (kSlabLong + 1) + 1;
   sp.max_chunks = nnz / kSlabChunk + sp.max_long + 1;
-  sp.scol = a->take<int32_t>(nnz);
+  sp.c16 = sp.S <= 65536 ? 1 : 0;
+  sp.scol = sp.c16 ? (void*)a->take<uint16_t>(nnz) : (void*)a->take<int32_t>(nnz);
   sp.sval = g->val ? (void*)a->take<char>(nnz * weight_bytes(g)) : nullptr;
   sp.wave = !sp.xcd && ctx->tune.slab_mode == 4;
   if (sp.wave) {
@@ -603,18 +605,26 @@ int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
   return FSC_OK;
 }
 
+template <typename W, typename CI>
+static void launch_build_ci(const fsc_csr* g, SlabPlan& sp, const DegreeOut& dout, hipStream_t s) {
+  CI* scol = static_cast<CI*>(sp.scol);
+  if (sp.wave) {
+    hipLaunchKernelGGL((slab_wave_build_kernel<W, CI>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr,
+                       g->col_idx, reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab,
+                       sp.toff, sp.loff, sp.coff, scol, reinterpret_cast<W*>(sp.sval), sp.wlen, sp.gbase, sp.gunit,
+                       sp.chunks, dout);
+  } else {
+    hipLaunchKernelGGL((slab_build_kernel<W, CI>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
+                       reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
+                       sp.coff, scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax, sp.sreg,
+                       sp.chunks, sp.tunit, dout);
+  }
+}
+
 template <typename W>
 static void launch_build(const fsc_csr* g, SlabPlan& sp, const DegreeOut& dout, hipStream_t s) {
-  if (sp.wave) {
-    hipLaunchKernelGGL((slab_wave_build_kernel<W>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
-                       reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
-                       sp.coff, sp.scol, reinterpret_cast<W*>(sp.sval), sp.wlen, sp.gbase, sp.gunit, sp.chunks, dout);
-  } else {
-  hipLaunchKernelGGL((slab_build_kernel<W>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
-                     reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
-                     sp.coff, sp.scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax, sp.sreg,
-                     sp.chunks, sp.tunit, dout);
-  }
+  if (sp.c16) launch_build_ci<W, uint16_t>(g, sp, dout, s);
+  else launch_build_ci<W, int32_t>(g, sp, dout, s);
   hipLaunchKernelGGL((slab_long_degree_kernel<W>), dim3(256), dim3(256), 0, s, g->row_ptr,
                      reinterpret_cast<const W*>(g->val), sp.chunks, sp.meta, dout);
 }

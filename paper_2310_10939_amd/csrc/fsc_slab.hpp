@@ -9,6 +9,10 @@
 // in phase p every block gathers only from slab p, so each XCD's L2 holds one
 // slab at a time.
 //
+// Column indices are stored relative to their slab's first column in 16 bits
+// when a slab has at most 65536 columns (half the index stream), else as
+// 32-bit columns.
+//
 // Layout (built once per graph, fsc_slab.hip): the rows are cut into tiles of
 // at most kSlabRows consecutive rows (about one tile per resident block).  In each (tile, phase) the rows' nonzeros in
 // the phase's slab are stored in jagged-diagonal order: rows sorted by their
@@ -31,7 +35,9 @@ struct SlabArgs {
   int32_t rgrid;                      // per-XCD form: grid of slab_reduce_kernel
   void* part;                         // per-XCD form: A[n/64][nslab][64][LH] partial sums
   const uint8_t* tunit;               // [ntiles] 1: the tile's weights are all 1 (skip them)
-  const int32_t* scol;    // column indices in slab order
+  const void* scol;       // column indices in slab order: uint16_t slab-local (c16) or int32_t columns
+  int32_t c16;            // 1: 16-bit indices relative to the slab's first column p * S
+  int32_t S;              // columns per slab
   const uint16_t* sperm;  // tile T, phase p, sorted position i -> local row, at r0*nslab + p*R + i
   const int32_t* sbase;   // [ntiles*nslab][kSlabLong+1]: start of diagonal k within the region
   const int32_t* smax;    // [ntiles*nslab]: longest segment of the (tile, phase)
@@ -54,11 +60,13 @@ __device__ __forceinline__ int32_t diag_start(const int32_t* base, int32_t lane_
 // two rows at once, positions s0 + lane and s0 + kBlock + lane, whose loads
 // are all issued together (rows are sorted by length, so the first is never
 // shorter); each row's sum is built in the same order either way.
-template <int kU, int J, bool UNIT, class Op>
+template <int kU, int J, bool UNIT, typename CI, class Op>
 __device__ __forceinline__ void slab_region_as(const Op& op, const SlabArgs& sb, int32_t T, int p, int32_t r0,
                                                int32_t R, typename Op::A* acc) {
   constexpr int LH = Op::LH;
   using A = typename Op::A;
+  const CI* scol = static_cast<const CI*>(sb.scol);
+  const int32_t cbase = sizeof(CI) == 2 ? p * sb.S : 0;
   const int wave = threadIdx.x / FSC_WAVE, lane = threadIdx.x % FSC_WAVE;
   const int64_t tp = (int64_t)T * sb.nslab + p;
   const int32_t maxlen = sb.smax[tp];
@@ -91,8 +99,8 @@ __device__ __forceinline__ void slab_region_as(const Op& op, const SlabArgs& sb,
           b0 = b1;
         }
       }
-      if constexpr (J == 2) op.template accumulate_at2<kU, UNIT>(sb.scol, reg, off0, off1, a0, a1);
-      else op.template accumulate_at<kU, UNIT>(sb.scol, reg, off0, a0);
+      if constexpr (J == 2) op.template accumulate_at2<kU, UNIT>(scol, reg, off0, off1, cbase, a0, a1);
+      else op.template accumulate_at<kU, UNIT>(scol, reg, off0, cbase, a0);
       // rows are sorted by length: once diagonal k+kU is no longer than s0
       // rows, the whole slice is done
       const int32_t kn = k + kU;
@@ -110,17 +118,17 @@ __device__ __forceinline__ void slab_region_as(const Op& op, const SlabArgs& sb,
 }
 
 // A tile whose weights are all 1 takes the code path without weight loads.
-template <int kU, int J, class Op>
+template <int kU, int J, typename CI, class Op>
 __device__ __forceinline__ void slab_region(const Op& op, const SlabArgs& sb, int32_t T, int p, int32_t r0,
                                             int32_t R, typename Op::A* acc) {
-  if (sb.tunit[T]) slab_region_as<kU, J, true>(op, sb, T, p, r0, R, acc);
-  else slab_region_as<kU, J, false>(op, sb, T, p, r0, R, acc);
+  if (sb.tunit[T]) slab_region_as<kU, J, true, CI>(op, sb, T, p, r0, R, acc);
+  else slab_region_as<kU, J, false, CI>(op, sb, T, p, r0, R, acc);
 }
 
 // Phase form: each block takes whole tiles and walks the slabs in order, so
 // at any time the blocks gather from about one slab.
-template <int kU, int J, class Op>
-__global__ __launch_bounds__(kBlock) void slab_kernel(Op op_in, TileArgs ta, SlabArgs sb, StatsArgs sa) {
+template <int kU, int J, typename CI, class Op>
+__global__ __launch_bounds__(kBlock, 8) void slab_kernel(Op op_in, TileArgs ta, SlabArgs sb, StatsArgs sa) {
   constexpr int LH = Op::LH;
   using A = typename Op::A;
   __shared__ A acc[kSlabRows * LH];
@@ -136,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void slab_kernel(Op op_in, TileArgs ta, Sla
     for (int i = threadIdx.x; i < R * LH; i += kBlock) acc[i] = A(0);
     __syncthreads();
     for (int p = 0; p < sb.nslab; ++p) {
-      slab_region<kU, J>(op, sb, T, p, r0, R, acc);
+      slab_region<kU, J, CI>(op, sb, T, p, r0, R, acc);
       __syncthreads();  // the next phase may give a row to another wave
     }
     // statistics stay out of registers during the phases: each tile's are
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void slab_kernel(Op op_in, TileArgs ta, Sla
 // rows' sums of each slab go to part[slab]; slab_reduce_kernel adds them in
 // slab order and applies the row operator.  Long rows are summed and finished
 // by their chunks here.
-template <int kU, class Op>
+template <int kU, typename CI, class Op>
 __global__ __launch_bounds__(kBlock) void slab_xcd_kernel(Op op_in, TileArgs ta, SlabArgs sb) {
   constexpr int LH = Op::LH;
   using A = typename Op::A;
@@ -193,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void slab_xcd_kernel(Op op_in, TileArgs ta,
       const int32_t R = min(sb.rows, n - r0);
       for (int i = threadIdx.x; i < R * LH; i += kBlock) acc[i] = A(0);
       __syncthreads();
-      slab_region<kU, 1>(op, sb, T, p, r0, R, acc);
+      slab_region<kU, 1, CI>(op, sb, T, p, r0, R, acc);
       __syncthreads();
       // part: groups of 64 rows, each holding its nslab slabs' 64 x LH sums
       // in a row, so every write here and every read of the reduce is
@@ -262,14 +270,16 @@ struct SlabWaveArgs {
   const uint8_t* wlen;    // [nslab][n] segment length of row r in slab p (0 for long rows)
   const int64_t* gbase;   // [ceil(n/64)] start of group g's nonzeros in scol
   const uint8_t* gunit;   // [ceil(n/64)] 1: the group's weights are all 1
-  const int32_t* scol;
+  const void* scol;       // as SlabArgs::scol
+  int32_t S;
 };
 
-template <int kU, bool UNIT, class Op>
+template <int kU, bool UNIT, typename CI, class Op>
 __device__ __forceinline__ void wave_group(const Op& op, const TileArgs& ta, const SlabWaveArgs& sw, int32_t g,
                                            double* st) {
   constexpr int LH = Op::LH;
   using A = typename Op::A;
+  const CI* scol = static_cast<const CI*>(sw.scol);
   const int lane = threadIdx.x % FSC_WAVE;
   const int32_t n = ta.n;
   const int32_t r = g * FSC_WAVE + lane;
@@ -301,7 +311,7 @@ __device__ __forceinline__ void wave_group(const Op& op, const TileArgs& ta, con
       int32_t off[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) off[u] = k + u < len ? start + k + u : -1;
-      op.template accumulate_at<kU, UNIT>(sw.scol, base, off, a);
+      op.template accumulate_at<kU, UNIT>(scol, base, off, sizeof(CI) == 2 ? p * sw.S : 0, a);
     }
 #pragma unroll
     for (int q = 0; q < LH; ++q) acc[q] += a[q];
@@ -314,7 +324,7 @@ __device__ __forceinline__ void wave_group(const Op& op, const TileArgs& ta, con
   }
 }
 
-template <int kU, class Op>
+template <int kU, typename CI, class Op>
 __global__ __launch_bounds__(kBlock) void slab_wave_kernel(Op op_in, TileArgs ta, SlabWaveArgs sw, StatsArgs sa) {
   constexpr int LH = Op::LH;
   constexpr int WPB = kBlock / FSC_WAVE;
@@ -326,8 +336,8 @@ __global__ __launch_bounds__(kBlock) void slab_wave_kernel(Op op_in, TileArgs ta
   const int wave = threadIdx.x / FSC_WAVE;
   const int32_t ng = (ta.n + FSC_WAVE - 1) / FSC_WAVE;
   for (int32_t g = blockIdx.x * WPB + wave; g < ng; g += gridDim.x * WPB) {
-    if (sw.gunit[g]) wave_group<kU, true>(op, ta, sw, g, st);
-    else wave_group<kU, false>(op, ta, sw, g, st);
+    if (sw.gunit[g]) wave_group<kU, true, CI>(op, ta, sw, g, st);
+    else wave_group<kU, false, CI>(op, ta, sw, g, st);
   }
   const int32_t nch = ta.meta[0];
   for (int32_t c = blockIdx.x; c < nch; c += gridDim.x) long_chunk<kU>(op, ta, c);

@@ -158,15 +158,17 @@ struct StepOp {
   }
   // The same over positions reg + off[u] of the slab-ordered copy (off < 0:
   // none); reg is uniform, so the loads take a scalar base and 32-bit offsets.
-  // UNIT: every weight there is 1, so none is loaded.
-  template <int U, bool UNIT>
-  __device__ __forceinline__ void accumulate_at(const int32_t* scol, int64_t reg, const int32_t* off,
+  // The stored index plus cbase is the column (16-bit slab-local indices
+  // with the slab's first column, or 32-bit columns with 0).  UNIT: every
+  // weight there is 1, so none is loaded.
+  template <int U, bool UNIT, typename CI>
+  __device__ __forceinline__ void accumulate_at(const CI* scol, int64_t reg, const int32_t* off, int32_t cbase,
                                                 A* acc) const {
-    const int32_t* cp = scol + reg;
+    const CI* cp = scol + reg;
     int32_t c[U];
     A w[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) c[u] = off[u] >= 0 ? nt_load(cp + off[u]) : -1;
+    for (int u = 0; u < U; ++u) c[u] = off[u] >= 0 ? cbase + (int32_t)nt_load(cp + off[u]) : -1;
     if constexpr (std::is_void<W>::value || UNIT) {
 #pragma unroll
       for (int u = 0; u < U; ++u) w[u] = A(1);
@@ -180,16 +182,16 @@ struct StepOp {
   // Two rows at once (offsets off0 into acc0, off1 into acc1): every index,
   // weight and row load of both is issued before the first use; each row's
   // sum is built in the same order as by accumulate_at.
-  template <int U, bool UNIT>
-  __device__ __forceinline__ void accumulate_at2(const int32_t* scol, int64_t reg, const int32_t* off0,
-                                                 const int32_t* off1, A* acc0, A* acc1) const {
-    const int32_t* cp = scol + reg;
+  template <int U, bool UNIT, typename CI>
+  __device__ __forceinline__ void accumulate_at2(const CI* scol, int64_t reg, const int32_t* off0,
+                                                 const int32_t* off1, int32_t cbase, A* acc0, A* acc1) const {
+    const CI* cp = scol + reg;
     int32_t c[2 * U];
     A w[2 * U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      c[u] = off0[u] >= 0 ? nt_load(cp + off0[u]) : -1;
-      c[U + u] = off1[u] >= 0 ? nt_load(cp + off1[u]) : -1;
+      c[u] = off0[u] >= 0 ? cbase + (int32_t)nt_load(cp + off0[u]) : -1;
+      c[U + u] = off1[u] >= 0 ? cbase + (int32_t)nt_load(cp + off1[u]) : -1;
     }
     if constexpr (std::is_void<W>::value || UNIT) {
 #pragma unroll
