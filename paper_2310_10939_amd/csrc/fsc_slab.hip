@@ -148,10 +148,9 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     LongChunk* __restrict__ chunks, uint8_t* __restrict__ tunit, DegreeOut dout) {
   __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
   __shared__ uint16_t spos[kSlabMax * kSlabRows];  // sorted position of each row per slab
-  __shared__ int32_t wcnt[kBuild / FSC_WAVE * (kSlabLong + 1)];  // per wave and length
-  __shared__ int32_t wmx[kBuild / FSC_WAVE];
-  __shared__ int32_t cntk[kSlabLong];              // rows longer than k
+  __shared__ int32_t hist[kSlabMax * (kSlabLong + 1)];  // per slab: rows of each length, then its cursor
   __shared__ int32_t baseL[kSlabMax * (kSlabLong + 1)];
+  __shared__ int32_t totL[kSlabMax];
   __shared__ int64_t regL[kSlabMax + 1];
   __shared__ int32_t scan32[kBuild / FSC_WAVE];
   using WS = typename std::conditional<std::is_void<W>::value, char, W>::type;
@@ -202,78 +201,135 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     }
   }
   __syncthreads();
-  int64_t region = toff[T];
-  for (int p = 0; p < nslab; ++p) {
-    // Rows by decreasing segment length, in row order within a length (a
-    // stable counting sort): each wave counts its lanes of every length with
-    // ballots, so no two threads update one counter.  The count of rows
-    // longer than k is both the start of length k in the sorted order and
-    // the height of diagonal k.
-    const int len = rl < R ? (int)cnt[p * R + rl] : 0;
+  // Rows by decreasing segment length, in row order within a length (a
+  // stable counting sort), one wave per slab: wave p counts its slab's rows
+  // of every length, turns the counts into the start of each length in the
+  // sorted order (the number of rows longer than L, which is also the height
+  // of diagonal L) and the diagonal starts, and places the rows 64 at a time.
+  // Only the wave touches its slab's arrays, and a wave's LDS accesses take
+  // effect in program order, so no block barrier is needed until all slabs
+  // are done.
+  {
     const int wave = threadIdx.x / FSC_WAVE, lane = threadIdx.x % FSC_WAVE;
-    {
-      int m = len;
+    constexpr int LPL = (kSlabLong + 1 + FSC_WAVE - 1) / FSC_WAVE;  // lengths per lane
+    for (int p = wave; p < nslab; p += kBuild / FSC_WAVE) {
+      int32_t* h = hist + p * (kSlabLong + 1);
+      int32_t* bl = baseL + p * (kSlabLong + 1);
+      const uint16_t* cp = cnt + p * R;
+      for (int L = lane; L <= kSlabLong; L += FSC_WAVE) h[L] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      int mx = 0, sum = 0;
+      for (int r = lane; r < R; r += FSC_WAVE) {
+        const int L = cp[r];
+        atomicAdd(&h[L], 1);
+        mx = max(mx, L);
+        sum += L;
+      }
 #pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o, FSC_WAVE));
-      if (lane == 0) wmx[wave] = m;
-    }
-    __syncthreads();
-    int32_t maxlen = 0;
+      for (int o = 32; o >= 1; o >>= 1) {
+        mx = max(mx, __shfl_xor(mx, o, FSC_WAVE));
+        sum += __shfl_xor(sum, o, FSC_WAVE);
+      }
+      const int32_t maxlen = mx;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      // start[L] = rows longer than L: a suffix sum over the lengths, lane l
+      // holding lengths [l * LPL, (l + 1) * LPL)
+      int32_t hv[LPL], tl = 0;
 #pragma unroll
-    for (int w = 0; w < kBuild / FSC_WAVE; ++w) maxlen = max(maxlen, wmx[w]);
-    int rank = 0;
-    for (int L = 0; L <= maxlen; ++L) {
-      const uint64_t m = __ballot(rl < R && len == L);
-      if (len == L) rank = __popcll(m & (((uint64_t)1 << lane) - 1));
-      if (lane == 0) wcnt[wave * (kSlabLong + 1) + L] = __popcll(m);
-    }
-    __syncthreads();
-    {
-      const int t = threadIdx.x;  // one thread per length, longest first
-      const int L = kSlabLong - t;
-      int32_t tot = 0;
-      if (t <= kSlabLong && L <= maxlen)
-        for (int w = 0; w < kBuild / FSC_WAVE; ++w) tot += wcnt[w * (kSlabLong + 1) + L];
-      int32_t all;
-      const int32_t incl = block_scan_inclusive<kBuild, int32_t>(tot, scan32, &all);
-      if (t <= kSlabLong) {
-        int32_t run = incl - tot;  // rows longer than L
-        if (L < kSlabLong) cntk[L] = run;
-        if (L <= maxlen)
-          for (int w = 0; w < kBuild / FSC_WAVE; ++w) {
-            const int32_t c = wcnt[w * (kSlabLong + 1) + L];
-            wcnt[w * (kSlabLong + 1) + L] = run;  // start of (length L, wave w)
-            run += c;
+      for (int i = 0; i < LPL; ++i) {
+        const int L = lane * LPL + i;
+        hv[i] = L <= kSlabLong ? h[L] : 0;
+        tl += hv[i];
+      }
+      int32_t incl = tl;
+#pragma unroll
+      for (int o = 1; o < FSC_WAVE; o <<= 1) {
+        const int32_t x = __shfl_up(incl, o, FSC_WAVE);
+        if (lane >= o) incl += x;
+      }
+      const int32_t all = __shfl(incl, FSC_WAVE - 1, FSC_WAVE);
+      int32_t after = all - incl;  // rows in the lanes above: longer
+      int32_t start[LPL];
+#pragma unroll
+      for (int i = LPL - 1; i >= 0; --i) {
+        start[i] = after;
+        after += hv[i];
+      }
+      // diagonal starts: bl[0] = 0, bl[k + 1] = sum over k' <= k of the
+      // height of diagonal k' (start[k'] for k' < maxlen, else 0)
+      int32_t dl = 0, dv[LPL];
+#pragma unroll
+      for (int i = 0; i < LPL; ++i) {
+        const int k = lane * LPL + i;
+        dv[i] = k < maxlen ? start[i] : 0;
+        dl += dv[i];
+      }
+      int32_t dincl = dl;
+#pragma unroll
+      for (int o = 1; o < FSC_WAVE; o <<= 1) {
+        const int32_t x = __shfl_up(dincl, o, FSC_WAVE);
+        if (lane >= o) dincl += x;
+      }
+      int32_t run = dincl - dl;
+      const int64_t tp = (int64_t)T * nslab + p;
+      int32_t* gb = sbase + tp * (kSlabLong + 1);
+#pragma unroll
+      for (int i = 0; i < LPL; ++i) {
+        const int k = lane * LPL + i;
+        run += dv[i];
+        if (k < kSlabLong) bl[k + 1] = run;
+        if (k + 1 <= maxlen) gb[k + 1] = run;
+      }
+      if (lane == 0) {
+        bl[0] = 0;
+        gb[0] = 0;
+        smax[tp] = maxlen;
+        totL[p] = sum;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      // the cursor of each length starts at its start
+#pragma unroll
+      for (int i = 0; i < LPL; ++i) {
+        const int L = lane * LPL + i;
+        if (L <= kSlabLong) h[L] = start[i];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      // place rows 64 at a time, ascending: lanes with one length take the
+      // next positions of that length in lane order
+      for (int r0w = 0; r0w < R; r0w += FSC_WAVE) {
+        const int r = r0w + lane;
+        const bool ok = r < R;
+        const int L = ok ? (int)cp[r] : -1;
+        uint64_t pending = __ballot(ok);
+        while (pending) {
+          const int leader = __ffsll((unsigned long long)pending) - 1;
+          const int Lx = __shfl(L, leader, FSC_WAVE);
+          const uint64_t m = __ballot(L == Lx);
+          const int32_t base = h[Lx];
+          if (L == Lx) {
+            const int i = base + __popcll(m & (((uint64_t)1 << lane) - 1));
+            sperm[(int64_t)r0 * nslab + (int64_t)p * R + i] = (uint16_t)r;
+            spos[p * R + r] = (uint16_t)i;
           }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          if (lane == leader) h[Lx] = base + __popcll(m);
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          pending &= ~m;
+        }
       }
     }
-    __syncthreads();
-    if (rl < R) {
-      const int i = wcnt[wave * (kSlabLong + 1) + len] + rank;
-      sperm[(int64_t)r0 * nslab + (int64_t)p * R + i] = (uint16_t)rl;
-      spos[p * R + rl] = (uint16_t)i;
-    }
-    // diagonal starts: exclusive scan of cntk[0..maxlen)
-    const int k = threadIdx.x;
-    const int32_t v = k < maxlen ? cntk[k] : 0;
-    int32_t total;
-    const int32_t incl = block_scan_inclusive<kBuild, int32_t>(v, scan32, &total);
-    int32_t* bl = baseL + p * (kSlabLong + 1);
-    if (k < kSlabLong) bl[k + 1] = incl;
-    const int64_t tp = (int64_t)T * nslab + p;
-    int32_t* gb = sbase + tp * (kSlabLong + 1);
-    if (k + 1 <= maxlen) gb[k + 1] = incl;
-    if (k == 0) {
-      bl[0] = 0;
-      gb[0] = 0;
-      smax[tp] = maxlen;
-      sreg[tp] = region;
-      regL[p] = region;
-    }
-    region += total;
-    __syncthreads();
   }
-  if (threadIdx.x == 0) regL[nslab] = region;  // end of the tile's last region
+  __syncthreads();
+  // regions of the slabs, one after another
+  if (threadIdx.x == 0) {
+    int64_t region = toff[T];
+    for (int p = 0; p < nslab; ++p) {
+      regL[p] = region;
+      sreg[(int64_t)T * nslab + p] = region;
+      region += totL[p];
+    }
+    regL[nslab] = region;  // end of the tile's last region
+  }
   __syncthreads();
   // Scatter the short rows' nonzeros into slab order (CSR order within a
   // row's segment), a group of consecutive slabs at a time: the group's
@@ -282,9 +338,9 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   // directly.  Weights are copied only for a tile that loads them, so a
   // unit-weight tile stages twice the column indices per pass.
   const bool copy_w = !std::is_void<W>::value && !tile_unit;
-  const int32_t cap = copy_w ? (int32_t)(kStageWords * 4 / (4 + sizeof(WS))) : kStageWords;
-  int32_t* stcol = stage;
-  WS* stval = reinterpret_cast<WS*>(stage + cap);
+  const int32_t cap = (int32_t)(kStageWords * 4 / (sizeof(CI) + (copy_w ? sizeof(WS) : 0)));
+  CI* stcol = reinterpret_cast<CI*>(stage);
+  WS* stval = reinterpret_cast<WS*>(stcol + cap);
   for (int p0 = 0; p0 < nslab;) {
     int p1 = p0 + 1;
     while (p1 < nslab && regL[p1 + 1] - regL[p0] <= cap) ++p1;
@@ -305,9 +361,9 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
           if (p < p0 || p >= p1) continue;
           const int kk = cnt[p * R + rl]++;
           const int32_t off = (int32_t)(regL[p] - g0) + baseL[p * (kSlabLong + 1) + kk] + spos[p * R + rl];
-          const int32_t ci = sizeof(CI) == 2 ? c[u] - p * S : c[u];  // slab-local in 16 bits
+          const CI ci = (CI)(sizeof(CI) == 2 ? c[u] - p * S : c[u]);  // slab-local in 16 bits
           if (staged) stcol[off] = ci;
-          else scol[g0 + off] = (CI)ci;
+          else scol[g0 + off] = ci;
           if constexpr (!std::is_void<W>::value) {
             if (copy_w) {
               const W w = val[j0 + u];
@@ -321,7 +377,7 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     __syncthreads();
     if (staged) {
       for (int32_t e = threadIdx.x; e < gsz; e += kBuild) {
-        scol[g0 + e] = (CI)stcol[e];
+        scol[g0 + e] = stcol[e];
         if constexpr (!std::is_void<W>::value) {
           if (copy_w) sval[g0 + e] = stval[e];
         }
