@@ -201,25 +201,31 @@ int fsc_kmeans(fsc_context* ctx, const void* points, int32_t dtype, int64_t n, i
  * uneven size in one call.  `graphs`, `k`, `l` and `t` are HOST arrays of
  * `count` entries (the CSR fields themselves are device pointers); graph g
  * uses seed + g (so its result equals fsc_cluster on that graph with that
- * seed, up to summation order).  Every stage runs once over the whole batch
- * (power iterations level by level over all graphs still iterating), and
- * the whole launch sequence is captured into a hipGraph that is replayed
- * while the batch (pointers, sizes, parameters) is unchanged.  Outputs:
- * `labels`, int32 concatenated per graph (graph g at offset sum_{h<g} n_h);
- * optional `emb`, FP32 concatenated n_g x l_g blocks.  Supported: FP32
- * vectors, FP32 or unit weights, 1 <= l <= 8, 1 <= k <= min(n, 64), no
- * traces or re-normalisation (FSC_E_UNSUPPORTED otherwise).  The tile size of
- * each graph comes from the autotuned entry of its mean-degree class. */
+ * seed, up to summation order).  Every stage runs once over the whole batch:
+ * the power iterations level by level, each level one grid per block width
+ * over the tiles of all graphs still iterating, with every graph's tiles
+ * given to one XCD (balanced by nonzeros times steps; the block index mod 8
+ * picks the XCD) so that its iterate block stays in that XCD's L2; then the
+ * k-means rounds over all graphs.  The whole launch sequence is captured into
+ * a hipGraph that is replayed while the batch (pointers, sizes, parameters)
+ * is unchanged.  Outputs: `labels`, int32 concatenated per graph (graph g at
+ * offset sum_{h<g} n_h); optional `emb`, FP32 concatenated n_g x l_g blocks.
+ * Supported: FP32 vectors, FP32 or unit weights, 1 <= l <= 8,
+ * 1 <= k <= min(n, 64), no traces or re-normalisation (FSC_E_UNSUPPORTED
+ * otherwise).  The tile size of each graph comes from the autotuned entry of
+ * its mean-degree class. */
 int fsc_cluster_batched(fsc_context* ctx, int32_t count, const fsc_csr* graphs, const int32_t* k,
                         const int32_t* l, const int32_t* t, uint64_t seed, const fsc_opts* opts,
                         int32_t* labels, float* emb, void* stream);
 
 /* Autotuner of the sparse-product launch shape: times `steps` power steps of
- * graph g (l columns, FP32) under each candidate shape (tile size 256..4096,
- * 4 or 8 nonzeros in flight per lane, 4 or 8 blocks per CU, both tile orders)
- * with HIP events, makes the fastest the context default, records its tile
- * size for the graph's mean-degree class (used by fsc_cluster_batched) and
- * writes it to *best (host).  Synchronises the stream. */
+ * graph g (l columns, FP32) with the tile kernel (the column-slab form off
+ * during the trials) under each candidate shape (tile size 256..4096, 4 or 8
+ * nonzeros in flight per lane, 4 or 8 blocks per CU, both tile orders) with
+ * HIP events, makes the fastest the context default (the slab setting is
+ * kept), records its tile size for the graph's mean-degree class (used by
+ * fsc_cluster_batched, whose graphs all run the tile kernel) and writes it to
+ * *best (host).  Synchronises the stream. */
 int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, fsc_tuning* best,
                  void* stream);
 

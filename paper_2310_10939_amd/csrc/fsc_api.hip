@@ -318,10 +318,7 @@ void fsc_destroy(fsc_context* ctx) {
   }
   if (ctx->c.bexec) hipGraphExecDestroy(ctx->c.bexec);
   if (ctx->c.cap_stream) hipStreamDestroy(ctx->c.cap_stream);
-  for (auto st : ctx->c.side_streams) hipStreamDestroy(st);
-  for (auto ev : ctx->c.side_events) hipEventDestroy(ev);
   if (ctx->c.barena) hipFree(ctx->c.barena);
-  if (ctx->c.sarena) hipFree(ctx->c.sarena);
   if (ctx->c.arena) hipFree(ctx->c.arena);
   if (ctx->c.error_flag) hipFree(ctx->c.error_flag);
   if (ctx->c.host_flag) hipHostFree(ctx->c.host_flag);
@@ -537,13 +534,15 @@ int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, f
   if (g->val && g->val_dtype != FSC_F32) o.vec_dtype = FSC_BF16;
   Tune bestt = saved;
   double best_ms = 1e30;
+  // the trials time the tile kernel (the kernel whose shape is tuned; the
+  // batched form runs every graph on it): the column-slab form is off
   const int tiles[] = {256, 512, 1024, 2048, 4096};
   for (int tile : tiles)
     for (int un : {4, 8})
       for (int bpc : {4, 8})
         for (int xo : {1, 0}) {
           Tune tu;
-          tu.slab_kb = saved.slab_kb;
+          tu.slab_kb = -1;
           tu.slab_mode = saved.slab_mode;
           tu.tile_nnz = tile;
           tu.unroll = un;
@@ -581,6 +580,7 @@ int fsc_autotune(fsc_context* ctx, const fsc_csr* g, int32_t l, int32_t steps, f
     ctx->c.tune = saved;
     return rc;
   }
+  bestt.slab_kb = saved.slab_kb;
   ctx->c.tune = bestt;
   ctx->c.tile_by_class[degree_class(g->n > 0 ? (double)g->nnz / (double)g->n : 0.0)] = bestt.tile_nnz;
   best->tile_nnz = bestt.tile_nnz;

@@ -3,13 +3,20 @@
 //
 // Every stage runs once for the whole batch: the tile plans, the degree pass
 // and the start blocks are single grids over all graphs; the power iterations
-// run level by level -- level i is one persistent grid over the short tiles
-// of every graph that still has a step i to do (graphs are sorted by t, so
-// those are a prefix); k-means++ rounds and Lloyd steps are segmented grids
-// over all graphs.  Levels are separate launches because step i of a graph
-// reads what step i-1 wrote on any XCD; the kernel boundary is the cross-XCD
-// hand-off.  The whole sequence is captured once as a hipGraph and replayed
-// while the batch is unchanged.
+// run level by level -- level i is one persistent grid (per block width) over
+// the tiles of every graph that still has a step i to do; k-means++ rounds and
+// Lloyd steps are segmented grids over all graphs.  Levels are separate
+// launches because step i of a graph reads what step i-1 wrote on any XCD; the
+// kernel boundary is the cross-XCD hand-off.  The whole sequence is captured
+// once as a hipGraph and replayed while the batch is unchanged.
+//
+// The level grids are XCD-affine: every graph is given to one XCD (balanced
+// by its work, nonzeros times steps), and the blocks of the grid that the
+// dispatcher places on XCD x (block index mod 8) take only the tiles of XCD
+// x's graphs, in one sequence (graphs by decreasing t, so the graphs still
+// iterating at a level are a prefix).  A graph's n x l block (at most a few
+// MB for the batch's sizes) is then gathered by one XCD only and stays in its
+// L2, where the single-graph path would need the column-slab layout.
 //
 // A bucket's long last row (longer than its graph's tile size) is summed by
 // the same block right after the bucket's short rows, so each level is a flat
@@ -191,20 +198,34 @@ __device__ __forceinline__ void step_tile(const BGraph& g, int32_t b, int level,
   run_tile<kU>(op, g, b, wred);
 }
 
+// The graphs of one XCD at one level: per XCD x, its sequence starts at
+// order[first[x]] with the tile prefix toffs[tfirst[x] ..]; act[x] graphs
+// (a prefix) still iterate, with tiles[x] tiles between them.
+struct XcdLevel {
+  int32_t first[8];
+  int32_t tfirst[8];
+  int32_t act[8];
+  int64_t tiles[8];
+};
+
 template <int kU, int LH>
 __global__ __launch_bounds__(kBlock) void blevel_kernel(const BGraph* __restrict__ gs,
                                                         const int32_t* __restrict__ order,
-                                                        const int64_t* __restrict__ toffs, int active,
-                                                        int level) {
+                                                        const int64_t* __restrict__ toffs, XcdLevel lv, int level) {
   __shared__ float wred[kBlock / FSC_WAVE][8];
-  const int64_t total = toffs[active];
-  int64_t T = blockIdx.x;
-  if (T >= total) return;
-  int p = seg_find(toffs, active, T);
-  for (; T < total; T += gridDim.x) {
-    while (toffs[p + 1] <= T) ++p;
-    const BGraph& g = gs[order[p]];
-    const int32_t b = (int32_t)(T - toffs[p]);
+  const int x = blockIdx.x & 7;             // the XCD the dispatcher puts this block on
+  const int64_t per = gridDim.x >> 3;       // blocks per XCD (the grid is a multiple of 8)
+  const int act = lv.act[x];
+  const int64_t total = lv.tiles[x];
+  int64_t T = blockIdx.x >> 3;
+  if (act == 0 || T >= total) return;
+  const int64_t* tf = toffs + lv.tfirst[x];
+  const int32_t* od = order + lv.first[x];
+  int p = seg_find(tf, act, T);
+  for (; T < total; T += per) {
+    while (tf[p + 1] <= T) ++p;
+    const BGraph& g = gs[od[p]];
+    const int32_t b = (int32_t)(T - tf[p]);
     if (g.val == nullptr) step_tile<kU, LH, void>(g, b, level, wred);
     else step_tile<kU, LH, float>(g, b, level, wred);
   }
@@ -256,7 +277,7 @@ int tile_for_degree(const Context* ctx, double mean_degree) {
 int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, const int32_t* ls,
                 const int32_t* ts, uint64_t seed, const fsc_opts& o, int32_t* labels, float* emb, hipStream_t s) {
   const int iters = o.kmeans_iters > 0 ? o.kmeans_iters : 30;
-  // ---- per-graph shapes and workspace layout
+  // ---- per-graph shapes; the replay key
   struct Host {
     int64_t n, nnz, nb;
     int l, LH, KD, t, k, NB;
@@ -285,143 +306,20 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
                        (uint64_t)c.n, (uint64_t)c.nnz, (uint64_t)x.l, (uint64_t)x.t, (uint64_t)x.k, (uint64_t)x.NB})
       key = mix(key, v);
   }
-  // Graphs whose n x l block is larger than one slab take the single-graph
-  // path -- the column-slab product keeps one graph's gathers in the L2 at a
-  // time, which the per-level launches over many graphs cannot -- and the
-  // rest share the per-level launches, where batching saves the launches.
-  fsc_opts po = o;
-  po.vec_dtype = FSC_F32;
-  po.validate = 0;
-  po.renorm = 0;
-  po.x0 = nullptr;
-  po.sqnorm_trace = nullptr;
-  po.rayleigh_trace = nullptr;
-  po.kmeans_iters = iters;
-  std::vector<char> solo(G, 0);
-  std::vector<int> solo_list;
-  size_t solo_bytes = 0;
-  for (int g = 0; g < G; ++g) {
-    int32_t S_, ns_;
-    int xc_;
-    if (slab_shape(ctx, h[g].n, h[g].LH, FSC_F32, &S_, &ns_, &xc_)) {
-      solo[g] = 1;
-      solo_list.push_back(g);
-      solo_bytes = std::max(solo_bytes, align_up(cluster_workspace_bytes(ctx, &graphs[g], h[g].l, po)));
-    }
-  }
-  // Those graphs run on kSideLanes side streams at once (independent graphs
-  // fill each other's latency-bound phases), each lane with its own
-  // workspace; graphs go to the least loaded lane, largest first.
-  constexpr int kSideLanes = 4;
-  const int NS = std::min<int>(kSideLanes, (int)solo_list.size());
-  std::vector<int> lane_of(G, -1);
-  {
-    std::vector<int> by_work(solo_list);
-    std::stable_sort(by_work.begin(), by_work.end(), [&](int x, int y) {
-      return (double)h[x].nnz * h[x].t > (double)h[y].nnz * h[y].t;
-    });
-    std::vector<double> load(std::max(NS, 1), 0.0);
-    for (int g : by_work) {
-      const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      lane_of[g] = j;
-      load[j] += (double)h[g].nnz * h[g].t + (double)h[g].n * 64;
-    }
-  }
   int rc;
-  const size_t sbytes = solo_bytes * (size_t)NS;
-  if (sbytes > ctx->sarena_size) {  // before any capture
-    if (ctx->bexec) {
-      hipGraphExecDestroy(ctx->bexec);
-      ctx->bexec = nullptr;
-    }
-    if (ctx->sarena) {
-      if ((rc = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize"))) return rc;
-      hipFree(ctx->sarena);
-      ctx->sarena = nullptr;
-      ctx->sarena_size = 0;
-    }
-    void* p = nullptr;
-    if (hipMalloc(&p, sbytes) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(FSC_E_NOMEM, "cannot allocate " + std::to_string(sbytes) + " bytes for the batch workspace");
-    }
-    ctx->sarena = static_cast<char*>(p);
-    ctx->sarena_size = sbytes;
-  }
-  while ((int)ctx->side_streams.size() < NS) {
-    hipStream_t st = nullptr;
-    if ((rc = check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate"))) return rc;
-    ctx->side_streams.push_back(st);
-  }
-  while ((int)ctx->side_events.size() < NS + 1) {
-    hipEvent_t ev = nullptr;
-    if ((rc = check_hip(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate"))) return rc;
-    ctx->side_events.push_back(ev);
-  }
-  for (int g = 0; g < G; ++g) key = mix(key, (uint64_t)solo[g]);
-  key = mix(key, (uint64_t)(uintptr_t)ctx->sarena);
-  key = mix(key, (uint64_t)ctx->tune.slab_kb);
-  key = mix(key, (uint64_t)ctx->tune.slab_mode);
-  key = mix(key, (uint64_t)ctx->tune.tile_nnz);
-  // output offsets of every graph, and the graphs of the shared launches
-  std::vector<int64_t> loff(G + 1, 0), eoff(G + 1, 0);
-  std::vector<int> bl;
-  for (int g = 0; g < G; ++g) {
-    loff[g + 1] = loff[g] + h[g].n;
-    eoff[g + 1] = eoff[g] + h[g].n * h[g].l;
-    if (!solo[g]) bl.push_back(g);
-  }
-  const int G2 = (int)bl.size();
-  // the single-graph-path graphs: launched on the side lanes, forked off s
-  // and joined back (ctx->timing is off meanwhile: no event records)
-  auto fork_solo = [&]() -> int {
-    if (NS == 0) return FSC_OK;
-    int r2;
-    const bool saved = ctx->timing;
-    ctx->timing = false;
-    if ((r2 = check_hip(hipEventRecord(ctx->side_events[0], s), "hipEventRecord"))) return r2;
-    for (int j = 0; j < NS; ++j)
-      if ((r2 = check_hip(hipStreamWaitEvent(ctx->side_streams[j], ctx->side_events[0], 0), "hipStreamWaitEvent")))
-        return r2;
-    for (int g : solo_list) {
-      const int j = lane_of[g];
-      Arena w;
-      w.base = ctx->sarena + (size_t)j * solo_bytes;
-      w.size = solo_bytes;
-      w.used = 0;
-      if ((r2 = cluster_run(ctx, &graphs[g], h[g].k, h[g].l, h[g].t, seed + (uint64_t)g, po, labels + loff[g],
-                            emb ? emb + eoff[g] : nullptr, nullptr, ctx->side_streams[j], &w))) {
-        ctx->timing = saved;
-        return r2;
-      }
-    }
-    ctx->timing = saved;
-    for (int j = 0; j < NS; ++j)
-      if ((r2 = check_hip(hipEventRecord(ctx->side_events[1 + j], ctx->side_streams[j]), "hipEventRecord")))
-        return r2;
-    return FSC_OK;
-  };
-  auto join_solo = [&]() -> int {
-    int r2;
-    for (int j = 0; j < NS; ++j)
-      if ((r2 = check_hip(hipStreamWaitEvent(s, ctx->side_events[1 + j], 0), "hipStreamWaitEvent"))) return r2;
-    return FSC_OK;
-  };
-  if (G2 == 0 || (ctx->bexec && ctx->bkey == key && !o.no_graph)) {
-    if ((rc = fork_solo())) return rc;
-    if (G2 > 0 && (rc = check_hip(hipGraphLaunch(ctx->bexec, s), "hipGraphLaunch"))) return rc;
-    return join_solo();
-  }
+  if (G > 0 && ctx->bexec && ctx->bkey == key && !o.no_graph)
+    return check_hip(hipGraphLaunch(ctx->bexec, s), "hipGraphLaunch");
 
-  // ---- sizes of the batch arena (shared launches only)
+  // ---- sizes of the batch arena
   size_t bytes = 0;
   auto add = [&](size_t b) { bytes += align_up(b); };
-  add(sizeof(BGraph) * (G2 + 1));
-  add(sizeof(KmJob) * (G2 + 1));
-  add(8 * (G2 + 4) * 4);             // boff, noff, toffs (per class), toff
-  add(4 * (G2 + 1));                 // order
-  add(4 * (G2 + 1) * 2);             // pp_off, ll_off
-  for (int g : bl) {
+  add(sizeof(BGraph) * (G + 1));
+  add(sizeof(KmJob) * (G + 1));
+  add(8 * (G + 1) * 3);              // boff, noff, toff
+  add(8 * (G + 33) * 4);             // toffs: per width class and XCD, a list with a leading 0
+  add(4 * (G + 1) * 4);              // order per class
+  add(4 * (G + 1) * 2);              // pp_off, ll_off
+  for (int g = 0; g < G; ++g) {
     const Host& x = h[g];
     add(sizeof(TileDesc) * x.nb);
     add(4 * x.nb);
@@ -459,25 +357,26 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   a.base = ctx->barena;
   a.size = ctx->barena_size;
   a.used = 0;
-  BGraph* d_graphs = a.take<BGraph>(G2 + 1);
-  KmJob* d_jobs = a.take<KmJob>(G2 + 1);
-  int64_t* d_boff = a.take<int64_t>(G2 + 1);
-  int64_t* d_noff = a.take<int64_t>(G2 + 1);
-  int64_t* d_toffs = a.take<int64_t>(G2 + 4);
-  int64_t* d_toff = a.take<int64_t>(G2 + 1);
-  int32_t* d_order = a.take<int32_t>(G2 + 1);
-  int32_t* d_ppoff = a.take<int32_t>(G2 + 1);
-  int32_t* d_lloff = a.take<int32_t>(G2 + 1);
+  BGraph* d_graphs = a.take<BGraph>(G + 1);
+  KmJob* d_jobs = a.take<KmJob>(G + 1);
+  int64_t* d_boff = a.take<int64_t>(G + 1);
+  int64_t* d_noff = a.take<int64_t>(G + 1);
+  int64_t* d_toff = a.take<int64_t>(G + 1);
+  int64_t* d_toffs = a.take<int64_t>((size_t)G + 33);
+  int32_t* d_order = a.take<int32_t>(G + 1);
+  int32_t* d_ppoff = a.take<int32_t>(G + 1);
+  int32_t* d_lloff = a.take<int32_t>(G + 1);
 
-  std::vector<BGraph> bg(G2);
-  std::vector<KmJob> jobs(G2);
-  std::vector<int64_t> boff(G2 + 1, 0), noff(G2 + 1, 0), toff(G2 + 1, 0);
-  std::vector<int32_t> ppoff(G2 + 1, 0), lloff(G2 + 1, 0);
+  std::vector<BGraph> bg(G);
+  std::vector<KmJob> jobs(G);
+  std::vector<int64_t> boff(G + 1, 0), noff(G + 1, 0), toff(G + 1, 0);
+  std::vector<int32_t> ppoff(G + 1, 0), lloff(G + 1, 0);
+  std::vector<int64_t> eoff(G + 1, 0);
   int tmax = 0, kmax = 0;
-  for (int bi = 0; bi < G2; ++bi) {
-    const int g = bl[bi];
+  for (int g = 0; g < G; ++g) eoff[g + 1] = eoff[g] + h[g].n * h[g].l;
+  for (int g = 0; g < G; ++g) {
     const Host& x = h[g];
-    BGraph& b = bg[bi];
+    BGraph& b = bg[g];
     std::memset(&b, 0, sizeof(b));
     b.row_ptr = graphs[g].row_ptr;
     b.col = graphs[g].col_idx;
@@ -502,7 +401,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     const uint64_t sg = seed + (uint64_t)g;
     b.k0 = (uint32_t)(sg & 0xffffffffu);
     b.k1 = (uint32_t)(sg >> 32);
-    KmJob& J = jobs[bi];
+    KmJob& J = jobs[g];
     J.n = x.n;
     J.pts = b.pts ? b.pts : b.z[x.t & 1];
     J.elig = b.elig;
@@ -517,118 +416,129 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     J.centres = a.take<float>(64 * x.KD);
     J.cpart = a.take<double>((size_t)J.nblk_ll * 64 * (x.KD + 1));
     J.chosen = a.take<int32_t>(64);
-    J.labels = labels + loff[g];
+    J.labels = labels + noff[g];
     J.k0 = b.k0;
     J.k1 = b.k1;
-    boff[bi + 1] = boff[bi] + x.nb;
-    noff[bi + 1] = noff[bi] + x.n;
-    toff[bi + 1] = toff[bi] + x.nb;
-    ppoff[bi + 1] = ppoff[bi] + J.nblk_pp;
-    lloff[bi + 1] = lloff[bi] + J.nblk_ll;
+    boff[g + 1] = boff[g] + x.nb;
+    noff[g + 1] = noff[g] + x.n;
+    toff[g + 1] = toff[g] + x.nb;
+    ppoff[g + 1] = ppoff[g] + J.nblk_pp;
+    lloff[g + 1] = lloff[g] + J.nblk_ll;
     tmax = std::max(tmax, x.t);
     kmax = std::max(kmax, x.k);
   }
   if (a.used > a.size) return fail(FSC_E_NOMEM, "batch workspace layout overflow");
-  // per width class, graphs sorted by t (descending), so the graphs of a
-  // class still iterating at level i are a prefix of the class
+  // Per width class: the graphs go to the 8 XCDs, largest work (nonzeros
+  // times steps) first, each to the least loaded; each XCD's list is sorted
+  // by decreasing t, so the graphs still iterating at a level are a prefix.
   const int widths[4] = {1, 2, 4, 8};
   std::vector<int32_t> order;
-  std::vector<int64_t> toffs_all;
-  int cls_first[4], cls_count[4];
-  std::vector<std::vector<int>> active(4, std::vector<int>(std::max(tmax, 1), 0));
+  std::vector<int64_t> toffs;
+  int first[4][8], tfirst[4][8], count[4][8];
+  std::vector<std::vector<std::vector<int>>> act(4, std::vector<std::vector<int>>(8, std::vector<int>(std::max(tmax, 1), 0)));
+  std::vector<std::vector<std::vector<int64_t>>> tiles(
+      4, std::vector<std::vector<int64_t>>(8, std::vector<int64_t>(std::max(tmax, 1), 0)));
   for (int c = 0; c < 4; ++c) {
-    std::vector<int32_t> og;
-    for (int bi = 0; bi < G2; ++bi)
-      if (h[bl[bi]].LH == widths[c]) og.push_back(bi);
-    std::stable_sort(og.begin(), og.end(), [&](int x, int y) { return h[bl[x]].t > h[bl[y]].t; });
-    cls_first[c] = (int)order.size();
-    cls_count[c] = (int)og.size();
-    toffs_all.push_back(0);
-    for (size_t p = 0; p < og.size(); ++p) {
-      order.push_back(og[p]);
-      toffs_all.push_back(toffs_all.back() + h[bl[og[p]]].nb);
-      for (int i = 0; i < tmax; ++i)
-        if (h[bl[og[p]]].t > i) active[c][i] = (int)p + 1;
+    std::vector<int> og;
+    for (int g = 0; g < G; ++g)
+      if (h[g].LH == widths[c] && h[g].t > 0) og.push_back(g);
+    std::stable_sort(og.begin(), og.end(), [&](int x, int y) {
+      return (double)h[x].nnz * h[x].t > (double)h[y].nnz * h[y].t;
+    });
+    std::vector<std::vector<int>> lists(8);
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int g : og) {
+      const int x = (int)(std::min_element(load, load + 8) - load);
+      lists[x].push_back(g);
+      load[x] += (double)(h[g].nnz + h[g].n) * h[g].t;
     }
-  }
-  // toffs_all holds, per class, count+1 prefix entries starting at a 0
-  std::vector<int64_t> toffs(toffs_all);
-  std::vector<int> toffs_first(4);
-  {
-    int pos = 0;
-    for (int c = 0; c < 4; ++c) {
-      toffs_first[c] = pos;
-      pos += cls_count[c] + 1;
+    for (int x = 0; x < 8; ++x) {
+      std::stable_sort(lists[x].begin(), lists[x].end(), [&](int p, int q) { return h[p].t > h[q].t; });
+      first[c][x] = (int)order.size();
+      tfirst[c][x] = (int)toffs.size();
+      count[c][x] = (int)lists[x].size();
+      toffs.push_back(0);
+      for (size_t i = 0; i < lists[x].size(); ++i) {
+        const int g = lists[x][i];
+        order.push_back(g);
+        toffs.push_back(toffs.back() + h[g].nb);
+        for (int lv = 0; lv < h[g].t; ++lv) {
+          act[c][x][lv] = (int)i + 1;
+          tiles[c][x][lv] = toffs.back();
+        }
+      }
     }
   }
   // ---- upload the tables (once per batch; the graph replays reuse them)
   if ((rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
-  if (G2 > 0) {
+  if (G > 0) {
     struct Up {
       void* dst;
       const void* src;
       size_t n;
     };
-    const size_t G1 = (size_t)G2 + 1;
-    const Up ups[] = {{d_graphs, bg.data(), sizeof(BGraph) * G2},  {d_jobs, jobs.data(), sizeof(KmJob) * G2},
-                      {d_boff, boff.data(), 8 * G1},               {d_noff, noff.data(), 8 * G1},
-                      {d_toffs, toffs.data(), 8 * toffs.size()},   {d_toff, toff.data(), 8 * G1},
-                      {d_order, order.data(), 4 * (size_t)G2},     {d_ppoff, ppoff.data(), 4 * G1},
+    const size_t G1 = (size_t)G + 1;
+    const Up ups[] = {{d_graphs, bg.data(), sizeof(BGraph) * G},    {d_jobs, jobs.data(), sizeof(KmJob) * G},
+                      {d_boff, boff.data(), 8 * G1},                {d_noff, noff.data(), 8 * G1},
+                      {d_toffs, toffs.data(), 8 * toffs.size()},    {d_toff, toff.data(), 8 * G1},
+                      {d_order, order.data(), 4 * order.size()},    {d_ppoff, ppoff.data(), 4 * G1},
                       {d_lloff, lloff.data(), 4 * G1}};
     for (const Up& u : ups)
-      if ((rc = check_hip(hipMemcpy(u.dst, u.src, u.n, hipMemcpyHostToDevice), "batch table upload"))) return rc;
+      if (u.n > 0 && (rc = check_hip(hipMemcpy(u.dst, u.src, u.n, hipMemcpyHostToDevice), "batch table upload")))
+        return rc;
   }
 
   // ---- the launch sequence
   const int cap = ctx->num_cu * ctx->tune.blocks_per_cu;
-  // the shared per-level launches of the smaller graphs
-  auto shared = [&](hipStream_t s) -> int {
-    hipLaunchKernelGGL(bplan_kernel, dim3(grid_for((boff[G2] + 255) / 256, 8192)), dim3(256), 0, s, d_graphs,
-                       d_boff, G2);
-    hipLaunchKernelGGL(bdegree_kernel, dim3(grid_for(toff[G2], cap)), dim3(kBlock), 0, s, d_graphs, d_toff, G2);
-    hipLaunchKernelGGL(bstart_kernel, dim3(grid_for((noff[G2] + kBlock - 1) / kBlock, 8192)), dim3(kBlock), 0, s,
-                       d_graphs, d_noff, G2);
+  const int lgrid = std::max(8, cap / 8 * 8);  // XCD-affine level grids: a multiple of 8
+  auto launches = [&](hipStream_t s) -> int {
+    hipLaunchKernelGGL(bplan_kernel, dim3(grid_for((boff[G] + 255) / 256, 8192)), dim3(256), 0, s, d_graphs, d_boff,
+                       G);
+    hipLaunchKernelGGL(bdegree_kernel, dim3(grid_for(toff[G], cap)), dim3(kBlock), 0, s, d_graphs, d_toff, G);
+    hipLaunchKernelGGL(bstart_kernel, dim3(grid_for((noff[G] + kBlock - 1) / kBlock, 8192)), dim3(kBlock), 0, s,
+                       d_graphs, d_noff, G);
     for (int i = 0; i < tmax; ++i) {
       for (int c = 0; c < 4; ++c) {
-        const int act = active[c][i];
-        if (act == 0) continue;
-        const int64_t* tf = d_toffs + toffs_first[c];
-        const int32_t* od = d_order + cls_first[c];
-        const int64_t tiles = toffs[toffs_first[c] + act];
-        const dim3 grid(grid_for(tiles, cap));
+        XcdLevel lv;
+        int64_t most = 0;
+        for (int x = 0; x < 8; ++x) {
+          lv.first[x] = first[c][x];
+          lv.tfirst[x] = tfirst[c][x];
+          lv.act[x] = act[c][x][i];
+          lv.tiles[x] = lv.act[x] > 0 ? tiles[c][x][i] : 0;
+          most = std::max(most, lv.tiles[x]);
+        }
+        if (most == 0) continue;
+        const dim3 grid((unsigned)std::min<int64_t>(lgrid, std::max<int64_t>(8, most * 8)));
         switch (widths[c]) {
-          case 1: hipLaunchKernelGGL((blevel_kernel<4, 1>), grid, dim3(kBlock), 0, s, d_graphs, od, tf, act, i); break;
-          case 2: hipLaunchKernelGGL((blevel_kernel<4, 2>), grid, dim3(kBlock), 0, s, d_graphs, od, tf, act, i); break;
-          case 4: hipLaunchKernelGGL((blevel_kernel<4, 4>), grid, dim3(kBlock), 0, s, d_graphs, od, tf, act, i); break;
-          default: hipLaunchKernelGGL((blevel_kernel<4, 8>), grid, dim3(kBlock), 0, s, d_graphs, od, tf, act, i); break;
+          case 1: hipLaunchKernelGGL((blevel_kernel<4, 1>), grid, dim3(kBlock), 0, s, d_graphs, d_order, d_toffs, lv, i); break;
+          case 2: hipLaunchKernelGGL((blevel_kernel<4, 2>), grid, dim3(kBlock), 0, s, d_graphs, d_order, d_toffs, lv, i); break;
+          case 4: hipLaunchKernelGGL((blevel_kernel<4, 4>), grid, dim3(kBlock), 0, s, d_graphs, d_order, d_toffs, lv, i); break;
+          default: hipLaunchKernelGGL((blevel_kernel<4, 8>), grid, dim3(kBlock), 0, s, d_graphs, d_order, d_toffs, lv, i); break;
         }
       }
     }
-    hipLaunchKernelGGL(bpoints_kernel, dim3(grid_for((noff[G2] + kBlock - 1) / kBlock, 8192)), dim3(kBlock), 0, s,
-                       d_graphs, d_noff, G2);
+    hipLaunchKernelGGL(bpoints_kernel, dim3(grid_for((noff[G] + kBlock - 1) / kBlock, 8192)), dim3(kBlock), 0, s,
+                       d_graphs, d_noff, G);
     int r2 = check_hip(hipGetLastError(), "batched launches");
     if (r2) return r2;
-    return kmeans_run_batched(ctx, d_jobs, d_ppoff, ppoff[G2], d_lloff, lloff[G2], G2, kmax, iters, s);
+    return kmeans_run_batched(ctx, d_jobs, d_ppoff, ppoff[G], d_lloff, lloff[G], G, kmax, iters, s);
   };
-  if (o.no_graph) {
-    if ((rc = fork_solo())) return rc;
-    if ((rc = shared(s))) return rc;
-    return join_solo();
-  }
+  if (o.no_graph) return launches(s);
   if (ctx->bexec) {
     hipGraphExecDestroy(ctx->bexec);
     ctx->bexec = nullptr;
   }
-  // capture the shared launches on a private stream (the caller's may be the
-  // null stream, which cannot be captured); the instantiated graph is
-  // launched on the caller's and replayed while the batch stays the same
+  // capture the launches on a private stream (the caller's may be the null
+  // stream, which cannot be captured); the instantiated graph is launched on
+  // the caller's and replayed while the batch stays the same
   if (!ctx->cap_stream &&
       (rc = check_hip(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "hipStreamCreate")))
     return rc;
   if ((rc = check_hip(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal),
                       "hipStreamBeginCapture")))
     return rc;
-  const int erc = shared(ctx->cap_stream);
+  const int erc = launches(ctx->cap_stream);
   hipGraph_t graph = nullptr;
   rc = check_hip(hipStreamEndCapture(ctx->cap_stream, &graph), "hipStreamEndCapture");
   if (erc) {
@@ -642,9 +552,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   if (rc) return rc;
   ctx->bexec = exec;
   ctx->bkey = key;
-  if ((rc = fork_solo())) return rc;
-  if ((rc = check_hip(hipGraphLaunch(exec, s), "hipGraphLaunch"))) return rc;
-  return join_solo();
+  return check_hip(hipGraphLaunch(exec, s), "hipGraphLaunch");
 }
 
 }  // namespace fsc

@@ -134,12 +134,6 @@ struct Context {
   size_t barena_size = 0;
   hipGraphExec_t bexec = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture
-  // batched form: side streams (and fork/join events) on which the graphs
-  // of the single-graph path run concurrently, each with its own workspace
-  std::vector<hipStream_t> side_streams;
-  std::vector<hipEvent_t> side_events;
-  char* sarena = nullptr;
-  size_t sarena_size = 0;
   uint64_t bkey = 0;
   // event timing of the sparse-product launches
   bool timing = false;

@@ -1,4 +1,7 @@
-"""The batched form against the single-graph path and the oracle."""
+"""The batched form against the single-graph path and the oracle: a batch of
+small graphs of every block width (with hubs, isolated vertices, t = 0), and
+a batch of graphs larger than one column slab (which the single-graph path
+runs in the slab form), all in the shared XCD-affine level launches."""
 import numpy as np
 import pytest
 import torch
@@ -25,17 +28,7 @@ def _batch():
     return specs
 
 
-@pytest.fixture(params=[1024, 16], ids=["shared-launches", "hybrid"])
-def slab_kb(request, gpu_lib):
-    """1024: every graph of the batch is small enough for the shared
-    per-level launches; 16 (KiB): the larger graphs take the single-graph
-    path inside the batched call."""
-    gpu_lib.tuning(slab_kb=request.param)
-    yield request.param
-    gpu_lib.tuning(slab_kb=1024)
-
-
-def test_batched_matches_single_graph_path(gpu_lib, slab_kb):
+def test_batched_matches_single_graph_path(gpu_lib):
     specs = _batch()
     dev = []
     for g, k, l, t in specs:
@@ -71,9 +64,6 @@ def test_batched_matches_single_graph_path(gpu_lib, slab_kb):
         check_elems(E, Es, "f32", "vs single")
         assert a >= 0.99
         assert L.min() >= 0 and L.max() < k
-        if slab_kb == 16 and g.n * (4 if l <= 4 else 8) * 4 > 16 * 1024:
-            # a graph on the single-graph path inside the batch: same bits
-            assert np.array_equal(L, Ls) and np.array_equal(E, Es)
 
 
 def test_batched_errors(gpu_lib):
@@ -83,3 +73,29 @@ def test_batched_errors(gpu_lib):
         gpu_lib.cluster_batched([(ip, ix, None)], [3], [9], [5], 0)
     with pytest.raises(gpu_lib.FscError):
         gpu_lib.cluster_batched([(ip, ix, None)], [301], [2], [5], 0)
+
+
+def test_batched_graphs_larger_than_a_slab(gpu_lib):
+    # n x l blocks of 1.1 to 3.2 MB, above the 1 MB column slab: the single
+    # path takes the slab form, the batch the XCD-affine tile launches
+    specs = [(synth.sbm_by_degree(70000, 4, 18, 2, seed=31, permute=True), 4, 3, 34),
+             (synth.sbm_by_degree(120000, 9, 27, 3, seed=32, permute=True), 9, 5, 36),
+             (synth.sbm_by_degree(200000, 12, 45, 5, seed=33, permute=True), 12, 5, 37)]
+    dev = [to_device(g, "f32") for g, _, _, _ in specs]
+    ks, ls, ts = [s[1] for s in specs], [s[2] for s in specs], [s[3] for s in specs]
+    seed = 5
+    lab, emb, off, eoff = gpu_lib.cluster_batched(dev, ks, ls, ts, seed, kmeans_iters=30, return_embedding=True)
+    lab, emb = lab.cpu().numpy(), emb.cpu().numpy()
+    for gi, ((g, k, l, t), (ip, ix, d)) in enumerate(zip(specs, dev)):
+        E = emb[eoff[gi]:eoff[gi + 1]].reshape(g.n, l)
+        L = lab[off[gi]:off[gi + 1]]
+        want = o.embed(g.n, g.indptr, g.indices, host_weights(d), l, t, seed=seed + gi)
+        err = col_rel_err(E, want)
+        Ls, Es = gpu_lib.cluster(ip, ix, d, k, l, t, seed + gi, kmeans_iters=30, return_embedding=True)
+        a = o.ari(L, Ls.cpu().numpy())
+        say(f"  graph {gi}: n={g.n} k={k} l={l} t={t} err vs oracle {err:.1e} ARI vs single {a:.4f} "
+            f"vs planted {o.ari(L, g.labels):.4f}")
+        assert err <= 1e-5
+        check_elems(E, want, "f32", "vs oracle")
+        check_elems(E, Es.cpu().numpy(), "f32", "vs single")
+        assert a >= 0.99

@@ -6,9 +6,13 @@ times (default tuning).
   t = 40.  The whole embedding against the FP64 oracle run on the same
   BF16-rounded weights (2e-2 relative per column), and the labels against
   the oracle's k-means (ARI >= 0.99).
-* Batched form: the 512-graph batch, every graph's labels against the plain
-  single-graph path (itself checked against the oracle elsewhere), ARI >=
-  0.99, and the first graphs against the oracle directly.
+* Batched form: the 512-graph batch, every graph's embedding against the
+  plain single-graph path (itself checked against the oracle elsewhere) to
+  1e-5 per column and element-wise, its labels against the single-graph
+  k-means on the same embedding (same labels), against the plain path's
+  labels (ARI >= 0.99 on all but 2% of the graphs: the k-means++ draws are
+  discontinuous in the points), and the two smallest graphs against the
+  oracle directly.
 
 (The 1M-vertex SBM is in test_gpu_slab.py.)
 """
@@ -58,18 +62,33 @@ def test_batched512_matches_plain_path(gpu_lib):
     ts = [p["t"] for p in params]
     say(f"batched: {len(graphs)} graphs, sum nnz {sum(g[1].numel() for g in graphs)}")
     labels, emb, off, eoff = gpu_lib.cluster_batched(graphs, ks, ls, ts, 0, kmeans_iters=30, return_embedding=True)
-    worst, worst_e = 1.0, (0.0, -1, None)
+    worst_e, aris, same = (0.0, -1, None), [], 0
     for i, g in enumerate(graphs):
         plain, Ep = gpu_lib.cluster(*g, ks[i], ls[i], ts[i], i, kmeans_iters=30, return_embedding=True)
-        a = float(gpu_lib.ari(labels[off[i]:off[i + 1]], plain, ks[i], ks[i]))
-        worst = min(worst, a)
-        E = emb[eoff[i]:eoff[i + 1]].reshape(Ep.shape).cpu().numpy()
+        Lb = labels[off[i]:off[i + 1]]
+        aris.append(float(gpu_lib.ari(Lb, plain, ks[i], ks[i])))
+        Eb = emb[eoff[i]:eoff[i + 1]].reshape(Ep.shape)
+        E = Eb.cpu().numpy()
         e, where = elem_rel_err(E, Ep.cpu().numpy(), ELEM["f32"][0])
         assert col_rel_err(E, Ep.cpu().numpy()) <= 1e-5, i
         if e > worst_e[0]:
             worst_e = (e, i, where)
-    say("  min ARI vs plain path", worst, "worst element-wise err (err, graph, (row, col))", worst_e)
-    assert worst >= 0.99
+        # the batched k-means against the single-graph k-means on the same
+        # points (the batched embedding), same seed: the same labels
+        elig = (g[0][1:] > g[0][:-1]).to(torch.uint8).contiguous()
+        Lk, _ = gpu_lib.kmeans(Eb.contiguous(), ks[i], 30, i, eligible=elig)
+        same += int(torch.equal(Lk, Lb))
+        assert float(gpu_lib.ari(Lk, Lb, ks[i], ks[i])) >= 0.999, i
+    aris = np.array(aris)
+    low = np.flatnonzero(aris < 0.99)
+    say("  ARI vs plain path: min", aris.min(), "median", np.median(aris), "graphs below 0.99", low.tolist(),
+        "worst element-wise err (err, graph, (row, col))", worst_e, "labels equal to fsc_kmeans on the batched "
+        "embedding", same, "of", len(graphs))
+    # k-means++ draws its centres from a cumulative sum of squared distances,
+    # so rounding-level differences between the two embeddings can move a
+    # draw to another point; Lloyd then ends elsewhere on a few weakly
+    # separated graphs.  The embeddings themselves agree to 1e-5 above.
+    assert len(low) <= len(graphs) // 50 and aris.min() >= 0.9
     assert worst_e[0] <= ELEM["f32"][1]
     # the two smallest graphs against the oracle directly
     for i in sorted(range(len(params)), key=lambda j: params[j]["n"])[:2]:
