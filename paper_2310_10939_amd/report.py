@@ -18,7 +18,7 @@ Methods:
   logk-eigs  the same with l = ceil(log2 k) eigenvectors ("log(k) Eigenvectors")
   learned    the learned polynomial filter with the shipped parameters and the
              plain method as its fallback (SBM workloads only: the filter was
-             trained on SBM graphs)
+             trained on SBM graphs); the row names how many trials fell back
 
 Usage: python -m paper_2310_10939_amd.report --workload sbm1m --trials 10
        [--json out.json]
@@ -81,7 +81,13 @@ def run(name, trials, methods=None):
     if WORKLOADS[name][0] == "sbm":
         from paper_2310_10939_amd.train_filter import PARAMS_FILE
         params = torch.from_numpy(np.load(PARAMS_FILE)).to(dev)
-        runs["learned"] = lambda s: fsc.cluster_filtered(ip, ix, w, k, l, s, params=params, fallback_t=t)[0]
+        fallbacks = []
+
+        def learned(s):
+            lab, _, used = fsc.cluster_filtered(ip, ix, w, k, l, s, params=params, fallback_t=t)
+            fallbacks.append(bool(used))
+            return lab
+        runs["learned"] = learned
     rows = {}
     for m, fn in runs.items():
         if methods and m not in methods:
@@ -100,6 +106,8 @@ def run(name, trials, methods=None):
             ari.append(float(fsc.ari(lab, truth, k, k)))
             nmi.append(float(fsc.nmi(lab, truth, k, k)))
         rows[m] = {"ari": ari, "nmi": nmi, "ms": ms}
+        if m == "learned":
+            rows[m]["fallbacks"] = int(sum(fallbacks[-trials:]))
     return {"workload": name, "n": int(ip.numel() - 1), "nnz": int(ix.numel()), "k": k, "l": l, "t": t,
             "trials": trials, "methods": rows}
 
@@ -112,7 +120,8 @@ def summary(res):
     lines = ["| workload | method | ARI | NMI | time (ms) |", "|---|---|---|---|---|"]
     for m, r in res["methods"].items():
         (am, asd), (nm, nsd), (tm, tsd) = ms(r["ari"]), ms(r["nmi"]), ms(r["ms"])
-        lines.append(f"| {res['workload']} | {m} | {am:.4f} ± {asd:.4f} | {nm:.4f} ± {nsd:.4f} | "
+        name = m if "fallbacks" not in r else f"{m} (fell back {r['fallbacks']} of {len(r['ari'])})"
+        lines.append(f"| {res['workload']} | {name} | {am:.4f} ± {asd:.4f} | {nm:.4f} ± {nsd:.4f} | "
                      f"{tm:.2f} ± {tsd:.2f} |")
     return "\n".join(lines)
 

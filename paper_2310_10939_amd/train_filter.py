@@ -1,8 +1,9 @@
 """Trains the MLP of the learned polynomial-filter form on the GPU.
 
 Training data: degree-corrected SBM graphs (n uniform in [1e5, 2e6], k in
-[2, 50], power-law degree propensities with exponent 2.5 and mean degree 20,
-fp32 unit weights), generated on the device.  For each graph the library's
+[2, 50], mean degree log-uniform in [8, 64], power-law degree propensities
+with exponent uniform in [2.2, 8], in-cluster fraction in [0.85, 0.95], unit
+weights), generated on the device.  For each graph the library's
 kernels run the plain method (t = ceil(3 ln n) PowerMethod steps,
 l = ceil(log2 k) + 1, k-means) for its labels, then the Chebyshev basis, the
 within-cluster and total scatter matrices of the filtered embedding under
@@ -10,8 +11,10 @@ those labels, and the features (fsc_filter_stats); only these statistics are
 kept.  The MLP is then trained by full-batch Adam on the normalised k-means
 cost with the library's forward/backward/Adam kernels (fsc_mlp_train).
 Held-out graphs measure the gain: ARI of the learned filter against the plain
-method, next to the fixed filter gamma^8 (8 plain steps, the same budget of
-sparse products) and the per-graph optimum of the loss, and wall times.
+method and the planted clusters, next to the same head with no network (the
+fixed interval the training starts from), the fixed filter gamma^8 (8 plain
+steps, the same budget of sparse products) and the per-graph optimum of the
+loss, and wall times.
 
 Usage: python -m paper_2310_10939_amd.train_filter --graphs 2000 --heldout 100
        --out <params.npy> --report <report.json>
@@ -59,6 +62,15 @@ def init_params(seed):
     return np.concatenate(parts).astype(np.float32)
 
 
+def fixed_head_params(seed=0):
+    """Parameters whose output layer ignores the features: every graph gets
+    the filter of [INIT_A, INIT_B] (the head with no network)."""
+    p = init_params(seed)
+    w_out = LAYERS[-1][0] * LAYERS[-1][1]
+    p[-(w_out + LAYERS[-1][1]):-LAYERS[-1][1]] = 0.0
+    return p
+
+
 def load_params(path=PARAMS_FILE, device="cuda"):
     import torch
     p = np.load(path, allow_pickle=False).astype(np.float32)
@@ -73,7 +85,7 @@ def collect(specs, device, log=print):
     F, W, T = [], [], []
     t0 = time.perf_counter()
     for i, s in enumerate(specs):
-        ip, ix, _ = synth.dcsbm_device(s["n"], s["k"], 20.0, s["seed"], device=device)
+        ip, ix, _ = synth.learned_graph(s, device=device)
         f, w, tt, _ = fsc.filter_stats(ip, ix, None, s["k"], s["l"], s["t"], s["seed"])
         F.append(f)
         W.append(w)
@@ -121,15 +133,16 @@ def heldout_loss(p, F, W, T):
 
 def evaluate(p, specs, device, stats=None, log=print):
     """ARI against the plain method (and the planted clusters) of the learned
-    filter, of the fixed gamma^8 filter and of the per-graph optimum of the
-    loss, with wall times."""
+    filter, of the same head with no network, of the fixed gamma^8 filter
+    and of the per-graph optimum of the loss, with wall times."""
     import torch
     import synth
     from . import fsc
     g8 = torch.tensor(GAMMA8, dtype=torch.float32, device=device)
+    ph = torch.from_numpy(fixed_head_params()).to(device)
     rows = []
     for i, s in enumerate(specs):
-        ip, ix, lab = synth.dcsbm_device(s["n"], s["k"], 20.0, s["seed"], device=device)
+        ip, ix, lab = synth.learned_graph(s, device=device)
         k, l, t, seed = s["k"], s["l"], s["t"], s["seed"]
         fsc.cluster(ip, ix, None, k, l, t, seed)   # warm the workspace
         torch.cuda.synchronize()
@@ -137,6 +150,11 @@ def evaluate(p, specs, device, stats=None, log=print):
         plain = fsc.cluster(ip, ix, None, k, l, t, seed)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        # the plain method with another seed: how far two runs of it agree
+        reseeded = fsc.cluster(ip, ix, None, k, l, t, seed + 7919)
+        fsc.cluster_filtered(ip, ix, None, k, l, seed, params=p)   # warm the filter's workspace
+        torch.cuda.synchronize()
+        t1f = time.perf_counter()
         learned, coef, used, diag = fsc.cluster_filtered(ip, ix, None, k, l, seed, params=p, diagnostics=True)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -146,6 +164,7 @@ def evaluate(p, specs, device, stats=None, log=print):
         guarded, _, used_g = fsc.cluster_filtered(ip, ix, None, k, l, seed, params=p, fallback_t=t)
         torch.cuda.synchronize()
         t4 = time.perf_counter()
+        head, _, used_h, diagh = fsc.cluster_filtered(ip, ix, None, k, l, seed, params=ph, diagnostics=True)
         # normalised k-means cost of the plain embedding, for calibration
         _, E, Cn = fsc.cluster(ip, ix, None, k, l, t, seed, return_embedding=True, return_centres=True)
         Eh = E.double().cpu().numpy()
@@ -164,18 +183,25 @@ def evaluate(p, specs, device, stats=None, log=print):
             full = np.concatenate([[1.0 - c_l.sum()], c_l])
             extra = dict(loss_optimum=loss_opt, loss_learned=float(full @ Wi @ full / (full @ Ti @ full)),
                          ari_opt_vs_plain=float(fsc.ari(best, plain, k, k)))
-        rows.append(dict(n=s["n"], k=k, l=l, t=t, **extra,
+        if stats is not None:
+            ch = fsc.cluster_filtered(ip, ix, None, k, l, seed, params=ph)[1].double().cpu().numpy()
+            full = np.concatenate([[1.0 - ch.sum()], ch])
+            extra["loss_head"] = float(full @ Wi @ full / (full @ Ti @ full))
+        rows.append(dict(n=s["n"], k=k, l=l, t=t, deg=s["deg"], alpha=s["alpha"], in_frac=s["in_frac"], **extra,
                          ari_learned_vs_plain=float(fsc.ari(learned, plain, k, k)),
                          ari_fixed8_vs_plain=float(fsc.ari(fixed, plain, k, k)),
                          ari_plain_vs_planted=float(fsc.ari(plain, lab, k, k)),
+                         ari_plain_reseeded_vs_plain=float(fsc.ari(reseeded, plain, k, k)),
                          ari_learned_vs_planted=float(fsc.ari(learned, lab, k, k)),
                          ari_fixed8_vs_planted=float(fsc.ari(fixed, lab, k, k)),
                          ari_guarded_vs_plain=float(fsc.ari(guarded, plain, k, k)),
                          ari_guarded_vs_planted=float(fsc.ari(guarded, lab, k, k)),
-                         fallback=used, ms_plain=(t1 - t0) * 1e3, ms_learned=(t2 - t1) * 1e3,
+                         ari_head_vs_plain=float(fsc.ari(head, plain, k, k)),
+                         ari_head_vs_planted=float(fsc.ari(head, lab, k, k)),
+                         fallback=used, fallback_head=used_h, ms_plain=(t1 - t0) * 1e3, ms_learned=(t2 - t1f) * 1e3,
                          ms_fixed8=(t3 - t2) * 1e3, ms_guarded=(t4 - t3) * 1e3,
                          rho_learned=float(dg[0]), rho_8=float(dg[1]), cost_learned=float(dg[2]),
-                         cost_fixed8=float(d8[2]), cost_plain=cost_plain))
+                         cost_fixed8=float(d8[2]), cost_head=float(diagh.cpu().numpy()[2]), cost_plain=cost_plain))
         if (i + 1) % 10 == 0 or i + 1 == len(specs):
             log(f"eval {i + 1}/{len(specs)}")
     return rows
@@ -185,6 +211,7 @@ def summarize(rows):
     keys = [k for k in rows[0] if k.split("_")[0] in ("ari", "ms", "loss", "rho", "cost")]
     out = {k: float(np.mean([r[k] for r in rows])) for k in keys}
     out["fallback_rate"] = float(np.mean([r["fallback"] for r in rows]))
+    out["fallback_rate_head"] = float(np.mean([r["fallback_head"] for r in rows]))
     out["graphs"] = len(rows)
     return out
 
@@ -215,6 +242,7 @@ def main(argv=None):
         p = load_params(args.out, dev)
         rows = evaluate(p, test_specs, dev, stats_t, log)
         report = {"heldout_graphs": args.heldout, "heldout_loss": heldout_loss(p, *stats_t),
+                  "heldout_loss_fixed_head": heldout_loss(torch.from_numpy(fixed_head_params()).to(dev), *stats_t),
                   "summary": summarize(rows), "rows": rows}
         if args.report:
             with open(args.report, "w") as fh:
@@ -237,6 +265,7 @@ def main(argv=None):
               "heldout_loss": heldout_loss(p, *stats_t),
               "heldout_loss_identity_init": heldout_loss(torch.from_numpy(init_params(args.seed)).to(dev),
                                                          *stats_t),
+              "heldout_loss_fixed_head": heldout_loss(torch.from_numpy(fixed_head_params()).to(dev), *stats_t),
               "summary": summarize(rows), "rows": rows}
     if args.report:
         with open(args.report, "w") as fh:

@@ -400,13 +400,24 @@ def dcsbm_device(n, k, mean_deg, seed, alpha=2.5, in_frac=0.9, device="cuda"):
 
 def learned_params(count, seed0):
     """Per-graph parameters of the learned-form workload: n uniform in
-    [100000, 2000000], k uniform in [2, 50], mean degree 20, l = ceil(log2 k)
-    + 1, t = ceil(3 ln n), graph seed seed0 + index."""
+    [100000, 2000000], k uniform in [2, 50], mean degree log-uniform in
+    [8, 64], degree-propensity exponent alpha uniform in [2.2, 8] (heavy-tailed
+    to nearly uniform degrees), in-cluster fraction uniform in [0.85, 0.95],
+    l = ceil(log2 k) + 1, t = ceil(3 ln n), graph seed seed0 + index."""
     rng = np.random.default_rng(seed0)
     out = []
     for i in range(count):
         n = int(rng.integers(100_000, 2_000_001))
         k = int(rng.integers(2, 51))
+        deg = float(np.exp(rng.uniform(np.log(8.0), np.log(64.0))))
+        alpha = float(rng.uniform(2.2, 8.0))
+        in_frac = float(rng.uniform(0.85, 0.95))
         out.append(dict(n=n, k=k, l=int(np.ceil(np.log2(k))) + 1, t=int(np.ceil(3.0 * np.log(n))),
-                        seed=seed0 + i))
+                        deg=deg, alpha=alpha, in_frac=in_frac, seed=seed0 + i))
     return out
+
+
+def learned_graph(spec, device="cuda"):
+    """The DC-SBM of one learned-form spec: (indptr, indices, labels)."""
+    return dcsbm_device(spec["n"], spec["k"], spec["deg"], spec["seed"], alpha=spec["alpha"],
+                        in_frac=spec["in_frac"], device=device)
