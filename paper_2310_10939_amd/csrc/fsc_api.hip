@@ -393,9 +393,8 @@ int fsc_knn(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int32_t kn
   int rc;
   if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
   Arena arena;
-  if ((rc = reserve_arena(&ctx->c, align_up((size_t)n * 4) + 256, &arena))) return rc;
-  float* norms = arena.take<float>((size_t)n);
-  return knn_run(X, n, dim, knn, norms, nbr, dist, s);
+  if ((rc = reserve_arena(&ctx->c, knn_workspace_bytes(n, ctx->c.num_cu), &arena))) return rc;
+  return knn_run(&arena, X, n, dim, knn, ctx->c.num_cu, nbr, dist, s);
 }
 
 int fsc_knn_graph(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int32_t knn, int64_t* indptr,
@@ -411,8 +410,8 @@ int fsc_knn_graph(fsc_context* ctx, const float* X, int64_t n, int32_t dim, int3
   int rc;
   if ((rc = check_hip(hipSetDevice(ctx->c.device), "hipSetDevice"))) return rc;
   Arena arena;
-  if ((rc = reserve_arena(&ctx->c, knn_graph_workspace_bytes(n, knn), &arena))) return rc;
-  return knn_graph_run(&arena, X, n, dim, knn, indptr, indices, weights, s);
+  if ((rc = reserve_arena(&ctx->c, knn_graph_workspace_bytes(n, knn, ctx->c.num_cu), &arena))) return rc;
+  return knn_graph_run(&arena, X, n, dim, knn, ctx->c.num_cu, indptr, indices, weights, s);
 }
 
 int fsc_cluster_eigs(fsc_context* ctx, const fsc_csr* g, int32_t k, int32_t m, int32_t cycles, int32_t steps,

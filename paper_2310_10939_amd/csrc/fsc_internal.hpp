@@ -331,9 +331,11 @@ int ortho_run(const EmbedIO* io, void* z, bool last, hipStream_t s);
 int points_cols_run(const float* pts, int64_t n, int KD, int k, float* out, hipStream_t s);
 
 // ---- k-nearest neighbours (fsc_knn.hip) ----
-int knn_run(const float* X, int64_t n, int dim, int knn, float* norms, int32_t* nbr, float* dist, hipStream_t s);
-size_t knn_graph_workspace_bytes(int64_t n, int knn);
-int knn_graph_run(Arena* a, const float* X, int64_t n, int dim, int knn, int64_t* indptr, int32_t* indices,
+size_t knn_workspace_bytes(int64_t n, int num_cu);
+int knn_run(Arena* a, const float* X, int64_t n, int dim, int knn, int num_cu, int32_t* nbr, float* dist,
+            hipStream_t s);
+size_t knn_graph_workspace_bytes(int64_t n, int knn, int num_cu);
+int knn_graph_run(Arena* a, const float* X, int64_t n, int dim, int knn, int num_cu, int64_t* indptr, int32_t* indices,
                   float* weights, hipStream_t s);
 
 // ---- ARI and NMI (fsc_ari.hip) ----

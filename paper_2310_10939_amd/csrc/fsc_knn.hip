@@ -19,6 +19,9 @@ typedef float knn_f4 __attribute__((ext_vector_type(4)));
 constexpr int kKnnQ = 32;         // queries per block
 constexpr int kKnnList = 16;      // entries of each partial list
 constexpr int kKnnPerPart = 8;    // candidates of a tile per partial list
+constexpr int kKnnNW = 4;         // waves per block
+constexpr int kKnnC = 16 * kKnnNW;  // candidates per tile
+constexpr int kKnnMaxSplit = 16;  // candidate ranges per query group
 
 // |x_v|^2 in FP64, one wave per row, rounded to FP32.
 __global__ __launch_bounds__(256) void knn_norms_kernel(const float* __restrict__ X, int64_t n, int dim,
@@ -35,41 +38,81 @@ __global__ __launch_bounds__(256) void knn_norms_kernel(const float* __restrict_
   }
 }
 
-// Block b takes queries 32b .. 32b + 31, held in LDS for the whole run.
-// Candidates stream through LDS in chunks of C = 16 NW rows x 64 dimensions
-// (NW waves per block), loaded once per block with coalesced 16-byte loads
-// (the next chunk's loads are in flight while the current one is used).
-// Wave w computes the dot products of queries 16 (w & 1) + 0..15 with
-// candidates 32 (w >> 1) + 0..31 of each tile of C: lane (col, kk) supplies
-// dimensions k + 4 kk + s (s = 0..3) of query col and of candidate col, and
-// receives the products of queries 4 kk + r with candidate col.  The tile's
-// products go through LDS to the selection: thread t keeps the 16 nearest of
-// the candidates 8 (t % P) + 0..7 of every tile for query t / P (P = 2 NW
-// partial lists per query), sorted by (distance, index).  At the end the P
-// lists of a query are merged.  MAXD bounds the dimension the query buffer
-// holds: 8 waves with MAXD = 800 and 4 waves with MAXD = 1024 both fit LDS.
-template <int NW, int MAXD>
+// (distance, index) order: ties go to the lower index.
+__device__ __forceinline__ bool knn_less(float d1, int i1, float d2, int i2) {
+  return d1 < d2 || (d1 == d2 && i1 < i2);
+}
+
+// Lanes l and l ^ s hold sorted lists (d, i) of kKnnList entries; both end
+// with the kKnnList smallest entries of the two lists, sorted.  The
+// element-wise minimum of one list and the other reversed is a bitonic
+// sequence holding those entries; a bitonic merge sorts it.
+__device__ __forceinline__ void knn_merge_xor(float (&d)[kKnnList], int (&ix)[kKnnList], int s) {
+  float od[kKnnList];
+  int oi[kKnnList];
+#pragma unroll
+  for (int j = 0; j < kKnnList; ++j) {
+    od[j] = __shfl_xor(d[j], s, FSC_WAVE);
+    oi[j] = __shfl_xor(ix[j], s, FSC_WAVE);
+  }
+#pragma unroll
+  for (int j = 0; j < kKnnList; ++j) {
+    const float e = od[kKnnList - 1 - j];
+    const int ei = oi[kKnnList - 1 - j];
+    if (knn_less(e, ei, d[j], ix[j])) {
+      d[j] = e;
+      ix[j] = ei;
+    }
+  }
+#pragma unroll
+  for (int h = kKnnList / 2; h >= 1; h >>= 1)
+#pragma unroll
+    for (int j = 0; j < kKnnList; ++j)
+      if ((j & h) == 0 && knn_less(d[j + h], ix[j + h], d[j], ix[j])) {
+        const float td = d[j];
+        d[j] = d[j + h];
+        d[j + h] = td;
+        const int ti = ix[j];
+        ix[j] = ix[j + h];
+        ix[j + h] = ti;
+      }
+}
+
+// Block (b, s) takes queries 32b .. 32b + 31 and streams the candidates of
+// range s (one of S contiguous ranges of tiles) past them, so that the grid
+// has several blocks per resident slot and no long tail.  Both operands go through LDS in chunks of 64 dimensions: the 32
+// queries' chunk and a tile of C = 16 NW candidates' chunk, loaded with
+// coalesced 16-byte loads (the next chunk's loads are in flight while the
+// current one is used).  Nothing stays resident, so a block needs 26 KB of
+// LDS (NW = 4) and four blocks share a CU.  Wave w computes the dot products
+// of queries 16 (w & 1) + 0..15 with candidates 32 (w >> 1) + 0..31 of the
+// tile: lane (col, kk) supplies dimensions k + 4 kk + s (s = 0..3) of query
+// col and of candidate col, and receives the products of queries 4 kk + r
+// with candidate col.  When a tile's last chunk is done its products go
+// through LDS (over the candidate buffer) to the selection: thread t keeps
+// the 16 nearest of the candidates 8 (t % P) + 0..7 of every tile for query
+// t / P (P = 2 NW partial lists per query, held by P neighbouring lanes),
+// sorted by (distance, index).  At the end the P lanes of a query merge
+// their lists pairwise (log2 P exchange rounds) and write the range's 16
+// nearest to pd/pi[s][query][16] (sorted; missing entries are (inf, INT_MAX)).
+template <int NW>
 __global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ X, const float* __restrict__ nrm,
-                                                      int n, int dim, int knn, int32_t* __restrict__ nbr,
-                                                      float* __restrict__ dist) {
+                                                      int n, int dim, float* __restrict__ pd,
+                                                      int32_t* __restrict__ pi) {
   constexpr int NT = 64 * NW;          // threads
   constexpr int C = 16 * NW;           // candidates per tile
-  constexpr int LDC = 64 + 4;          // padded row of the candidate chunk
+  constexpr int LDC = 64 + 4;          // padded row of a chunk
   constexpr int P = NT / kKnnQ;        // partial lists per query
+  constexpr int QP = kKnnQ * 16 / NT;  // 16-byte pieces of the query chunk per thread
   static_assert(C == P * kKnnPerPart, "each tile candidate belongs to one list");
-  static_assert(C * 16 == 4 * NT, "four 16-byte pieces per thread per chunk");
-  static_assert(kKnnQ * P * kKnnList * 2 <= kKnnQ * (MAXD + 4), "the merge fits the query buffer");
-  __shared__ __align__(16) float qs[kKnnQ * (MAXD + 4)];
+  static_assert(C * 16 == 4 * NT, "four 16-byte candidate pieces per thread per chunk");
+  static_assert(QP >= 1 && QP * NT == kKnnQ * 16, "whole query pieces per thread");
+  static_assert(kKnnQ * (C + 1) <= C * LDC, "the tile's products fit the candidate buffer");
+  static_assert(P <= FSC_WAVE && (FSC_WAVE % P) == 0, "a query's lists lie in one wave");
+  __shared__ __align__(16) float qs[kKnnQ * LDC];
   __shared__ __align__(16) float cs[C * LDC];
-  __shared__ float dt[kKnnQ][C + 1];
-  const int dim16 = (dim + 15) & ~15;
-  const int ldq = dim16 + 4;
+  float(*dt)[C + 1] = reinterpret_cast<float(*)[C + 1]>(cs);  // products of a finished tile
   const int q0 = blockIdx.x * kKnnQ;
-  for (int i = threadIdx.x; i < kKnnQ * dim16; i += NT) {
-    const int r = i / dim16, c = i - r * dim16;
-    qs[r * ldq + c] = (q0 + r < n && c < dim) ? X[(int64_t)(q0 + r) * dim + c] : 0.f;
-  }
-
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kk = lane >> 4;
   const int qw = (wave & 1) * 16;
@@ -84,16 +127,19 @@ __global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ 
     bd[j] = __builtin_inff();
     bi[j] = INT_MAX;
   }
-  const float* qrow = qs + (qw + col) * ldq + 4 * kk;
+  const float* qrow = qs + (qw + col) * LDC + 4 * kk;
   const float* crow0 = cs + (cw + col) * LDC + 4 * kk;
   const float* crow1 = crow0 + 16 * LDC;
   const knn_f4 zero = {0.f, 0.f, 0.f, 0.f};
 
   // chunk ci covers candidates C (ci / nkc) + 0..C-1, dimensions 64 (ci % nkc) + 0..63;
-  // thread t loads 16-byte pieces t + NT i (i = 0..3): row piece / 16, dims 4 (piece % 16)
+  // thread t loads candidate pieces t + NT i (i = 0..3) and query pieces
+  // t + NT i (i < QP): row piece / 16, dims 4 (piece % 16)
   const int nkc = (dim + 63) / 64;
-  const int64_t total = (int64_t)((n + C - 1) / C) * nkc;
-  knn_f4 pre[4];
+  const int64_t tiles = (n + C - 1) / C;
+  const int64_t S = gridDim.y, sp = blockIdx.y;
+  const int64_t ci_begin = (sp * tiles / S) * nkc, ci_end = ((sp + 1) * tiles / S) * nkc;
+  knn_f4 pre[4], qpre[QP];
   auto load = [&](int64_t ci) {
     const int c0 = (int)(ci / nkc) * C, kc = (int)(ci % nkc) * 64;
 #pragma unroll
@@ -105,19 +151,32 @@ __global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ 
       const knn_f4 v = *reinterpret_cast<const knn_f4*>(X + (int64_t)(ok ? r : 0) * dim + (ok ? d : 0));
       pre[i] = ok ? v : zero;
     }
+#pragma unroll
+    for (int i = 0; i < QP; ++i) {
+      const int piece = threadIdx.x + NT * i;
+      const int r = q0 + (piece >> 4), d = kc + 4 * (piece & 15);
+      const bool ok = r < n && d < dim;
+      const knn_f4 v = *reinterpret_cast<const knn_f4*>(X + (int64_t)(ok ? r : 0) * dim + (ok ? d : 0));
+      qpre[i] = ok ? v : zero;
+    }
   };
-  load(0);
+  if (ci_begin < ci_end) load(ci_begin);
   knn_f4 acc0 = zero, acc1 = zero;
-  for (int64_t ci = 0; ci < total; ++ci) {
+  for (int64_t ci = ci_begin; ci < ci_end; ++ci) {
     const int c0 = (int)(ci / nkc) * C, kc = (int)(ci % nkc) * 64;
-    __syncthreads();  // every wave is done with the previous chunk (and the query staging)
+    __syncthreads();  // every wave is done with the previous chunk, or with the products
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int piece = threadIdx.x + NT * i;
       *reinterpret_cast<knn_f4*>(cs + (piece >> 4) * LDC + 4 * (piece & 15)) = pre[i];
     }
+#pragma unroll
+    for (int i = 0; i < QP; ++i) {
+      const int piece = threadIdx.x + NT * i;
+      *reinterpret_cast<knn_f4*>(qs + (piece >> 4) * LDC + 4 * (piece & 15)) = qpre[i];
+    }
     __syncthreads();
-    if (ci + 1 < total) load(ci + 1);
+    if (ci + 1 < ci_end) load(ci + 1);
     if (kc == 0) {
       acc0 = zero;
       acc1 = zero;
@@ -125,7 +184,7 @@ __global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ 
 #pragma unroll
     for (int k = 0; k < 64; k += 16) {
       if (kc + k < dim) {
-        const knn_f4 a = *reinterpret_cast<const knn_f4*>(qrow + kc + k);
+        const knn_f4 a = *reinterpret_cast<const knn_f4*>(qrow + k);
         const knn_f4 b0 = *reinterpret_cast<const knn_f4*>(crow0 + k);
         const knn_f4 b1 = *reinterpret_cast<const knn_f4*>(crow1 + k);
 #pragma unroll
@@ -136,6 +195,7 @@ __global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ 
       }
     }
     if (kc + 64 < dim) continue;  // more dimensions of this tile to come
+    __syncthreads();  // the candidate buffer is read by every wave before it takes the products
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       dt[qw + 4 * kk + r][cw + col] = acc0[r];
@@ -166,51 +226,75 @@ __global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ 
       }
     }
   }
-  __syncthreads();
-
-  // merge: the query buffer is free now
-  float* ld = qs;                                                 // [32][P][16] distances
-  int* li = reinterpret_cast<int*>(qs + kKnnQ * P * kKnnList);     // and indices
+  // the P lanes of a query merge their lists
 #pragma unroll
-  for (int j = 0; j < kKnnList; ++j) {
-    ld[(tq * P + te) * kKnnList + j] = bd[j];
-    li[(tq * P + te) * kKnnList + j] = bi[j];
-  }
-  __syncthreads();
-  if (threadIdx.x < kKnnQ && q0 + (int)threadIdx.x < n) {
-    const int q = threadIdx.x;
-    int head[P];
-    for (int e = 0; e < P; ++e) head[e] = 0;
-    for (int o = 0; o < knn; ++o) {
-      int be = -1;
-      float bdv = __builtin_inff();
-      int biv = INT_MAX;
-      for (int e = 0; e < P; ++e) {
-        if (head[e] >= kKnnList) continue;
-        const float d = ld[(q * P + e) * kKnnList + head[e]];
-        const int i = li[(q * P + e) * kKnnList + head[e]];
-        if (be < 0 || d < bdv || (d == bdv && i < biv)) {
-          be = e;
-          bdv = d;
-          biv = i;
-        }
-      }
-      if (be < 0) break;  // cannot happen: P * 16 entries cover knn <= 16
-      head[be] += 1;
-      nbr[(int64_t)(q0 + q) * knn + o] = biv;
-      dist[(int64_t)(q0 + q) * knn + o] = bdv;
+  for (int sft = 1; sft < P; sft <<= 1) knn_merge_xor(bd, bi, sft);
+  if (te == 0 && gq < n) {
+    const int64_t base = (sp * n + gq) * kKnnList;
+#pragma unroll
+    for (int o = 0; o < kKnnList; ++o) {
+      pd[base + o] = bd[o];
+      pi[base + o] = bi[o];
     }
   }
 }
 
-int knn_run(const float* X, int64_t n, int dim, int knn, float* norms, int32_t* nbr, float* dist, hipStream_t s) {
+// The knn nearest of each query from the S sorted range lists.
+__global__ __launch_bounds__(256) void knn_merge_kernel(const float* __restrict__ pd, const int32_t* __restrict__ pi,
+                                                        int64_t n, int S, int knn, int32_t* __restrict__ nbr,
+                                                        float* __restrict__ dist) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+    int head[kKnnMaxSplit];
+    for (int s = 0; s < S; ++s) head[s] = 0;
+    for (int o = 0; o < knn; ++o) {
+      int be = 0;
+      float bdv = __builtin_inff();
+      int biv = INT_MAX;
+      for (int s = 0; s < S; ++s) {
+        if (head[s] >= kKnnList) continue;
+        const int64_t e = ((int64_t)s * n + q) * kKnnList + head[s];
+        if (knn_less(pd[e], pi[e], bdv, biv)) {
+          be = s;
+          bdv = pd[e];
+          biv = pi[e];
+        }
+      }
+      head[be] += 1;
+      nbr[q * knn + o] = biv;
+      dist[q * knn + o] = bdv;
+    }
+  }
+}
+
+// Candidate ranges per query group: about 8 blocks per resident slot (four
+// per CU), at most one range per tile and kKnnMaxSplit in all.
+static int knn_splits(int64_t n, int num_cu) {
+  const int64_t groups = (n + kKnnQ - 1) / kKnnQ;
+  const int64_t tiles = (n + kKnnC - 1) / kKnnC;
+  const int64_t slots = (int64_t)std::max(num_cu, 1) * 4;
+  int64_t S = (8 * slots + groups - 1) / groups;
+  S = std::min<int64_t>(S, std::min<int64_t>(tiles, kKnnMaxSplit));
+  return (int)std::max<int64_t>(1, S);
+}
+
+size_t knn_workspace_bytes(int64_t n, int num_cu) {
+  const int64_t S = knn_splits(n, num_cu);
+  return align_up((size_t)n * 4) + 2 * align_up((size_t)(S * n * kKnnList) * 4) + 1024;
+}
+
+int knn_run(Arena* a, const float* X, int64_t n, int dim, int knn, int num_cu, int32_t* nbr, float* dist,
+            hipStream_t s) {
+  const int S = knn_splits(n, num_cu);
+  float* norms = a->take<float>((size_t)n);
+  float* pd = a->take<float>((size_t)(S * n * kKnnList));
+  int32_t* pi = a->take<int32_t>((size_t)(S * n * kKnnList));
+  if (a->used > a->size) return fail(FSC_E_NOMEM, "knn workspace too small");
   const int nb = (int)std::min<int64_t>((n + 3) / 4, 8192);
   hipLaunchKernelGGL(knn_norms_kernel, dim3(nb), dim3(256), 0, s, X, n, dim, norms);
-  const int grid = (int)((n + kKnnQ - 1) / kKnnQ);
-  if (dim <= 800)
-    hipLaunchKernelGGL((knn_kernel<8, 800>), dim3(grid), dim3(512), 0, s, X, norms, (int)n, dim, knn, nbr, dist);
-  else
-    hipLaunchKernelGGL((knn_kernel<4, 1024>), dim3(grid), dim3(256), 0, s, X, norms, (int)n, dim, knn, nbr, dist);
+  const int groups = (int)((n + kKnnQ - 1) / kKnnQ);
+  hipLaunchKernelGGL((knn_kernel<kKnnNW>), dim3(groups, S), dim3(64 * kKnnNW), 0, s, X, norms, (int)n, dim, pd, pi);
+  const int mb = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(knn_merge_kernel, dim3(mb), dim3(256), 0, s, pd, pi, n, S, knn, nbr, dist);
   return check_hip(hipGetLastError(), "knn launch");
 }
 
@@ -308,19 +392,18 @@ static size_t kg_temp_bytes(int64_t n, int knn) {
   return std::max(t1, std::max(t2, t3));
 }
 
-size_t knn_graph_workspace_bytes(int64_t n, int knn) {
+size_t knn_graph_workspace_bytes(int64_t n, int knn, int num_cu) {
   const int64_t E = n * knn, M = 2 * E;
-  return align_up((size_t)n * 4) +                                    // norms
+  return knn_workspace_bytes(n, num_cu) +                             // the search
          align_up((size_t)E * 4) * 3 +                                // nbr, dist, sorted distances
          align_up((size_t)E * 8) * 2 + align_up((size_t)E * 4) * 2 +  // pair keys and edge ids, sorted
          align_up((size_t)M * 8) * 2 + align_up((size_t)M * 4) * 2 +  // CSR keys and weights, sorted
          align_up(64 * 4) + align_up(kg_temp_bytes(n, knn)) + 4096;
 }
 
-int knn_graph_run(Arena* a, const float* X, int64_t n, int dim, int knn, int64_t* indptr, int32_t* indices,
-                  float* weights, hipStream_t s) {
+int knn_graph_run(Arena* a, const float* X, int64_t n, int dim, int knn, int num_cu, int64_t* indptr,
+                  int32_t* indices, float* weights, hipStream_t s) {
   const int64_t E = n * knn, M = 2 * E;
-  float* norms = a->take<float>((size_t)n);
   int32_t* nbr = a->take<int32_t>((size_t)E);
   float* dist = a->take<float>((size_t)E);
   float* dsort = a->take<float>((size_t)E);
@@ -337,7 +420,7 @@ int knn_graph_run(Arena* a, const float* X, int64_t n, int dim, int knn, int64_t
   void* temp = a->take<char>(temp_bytes);
   if (a->used > a->size) return fail(FSC_E_NOMEM, "knn graph workspace too small");
   int rc;
-  if ((rc = knn_run(X, n, dim, knn, norms, nbr, dist, s))) return rc;
+  if ((rc = knn_run(a, X, n, dim, knn, num_cu, nbr, dist, s))) return rc;
   const int blocks = (int)std::min<int64_t>((M + 255) / 256, 8192);
   const unsigned long long nn = (unsigned long long)n * (unsigned long long)n;
   if ((rc = check_hip(hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, dist, dsort, (int)E, 0, 32, s),

@@ -55,8 +55,10 @@ def make(name, dev):
     import synth
     kind, n, k, din, dout, t, permute = WORKLOADS[name]
     if kind == "knn":
-        ip, ix, w, lab = synth.knn_mixture_device(n // k, k, 784, seed=0, device=dev)
-        return ip, ix, w.float().contiguous(), torch.from_numpy(lab.astype(np.int32)).to(dev), k, t
+        from paper_2310_10939_amd import fsc
+        X, lab = synth.gaussian_mixture(n // k, k, 784, seed=0)
+        ip, ix, w = fsc.knn_graph(torch.from_numpy(X).to(dev), 10)
+        return ip, ix, w.contiguous(), torch.from_numpy(lab.astype(np.int32)).to(dev), k, t
     g = synth.sbm_by_degree(n, k, din, dout, seed=0, permute=permute)
     ip = torch.from_numpy(g.indptr).to(dev)
     ix = torch.from_numpy(g.indices).to(dev)

@@ -421,3 +421,27 @@ def learned_graph(spec, device="cuda"):
     """The DC-SBM of one learned-form spec: (indptr, indices, labels)."""
     return dcsbm_device(spec["n"], spec["k"], spec["deg"], spec["seed"], alpha=spec["alpha"],
                         in_frac=spec["in_frac"], device=device)
+
+
+def graph_agreement(a, b):
+    """How two device CSR graphs (indptr, indices, weights) of the same n
+    agree: the fraction of each one's entries the other holds, and the
+    largest relative weight difference over the shared entries."""
+    import torch
+    out = []
+    keys = []
+    for ip, ix, _ in (a, b):
+        n = ip.numel() - 1
+        rows = torch.repeat_interleave(torch.arange(n, device=ip.device), ip[1:] - ip[:-1])
+        keys.append(rows * n + ix.long())
+    ka, kb = keys
+    wa, wb = a[2].double(), b[2].double()
+    oa, ob = torch.argsort(ka), torch.argsort(kb)
+    ka, kb, wa, wb = ka[oa], kb[ob], wa[oa], wb[ob]
+    pos = torch.searchsorted(kb, ka).clamp(max=kb.numel() - 1)
+    hit = kb[pos] == ka
+    common = int(hit.sum())
+    rel = ((wa[hit] - wb[pos[hit]]).abs() / wb[pos[hit]].abs().clamp_min(1e-300)).max() if common else torch.zeros(())
+    return {"entries": [int(ka.numel()), int(kb.numel())], "common": common,
+            "common_frac": [common / max(1, ka.numel()), common / max(1, kb.numel())],
+            "weight_max_rel_diff": float(rel)}

@@ -2,10 +2,12 @@
 times (default tuning).
 
 * Precision form on the k-NN graph: 70,000 points of 10 Gaussians in 784
-  dimensions, symmetrised 10-NN graph, BF16 weights and vectors, l = 4,
-  t = 40.  The whole embedding against the FP64 oracle run on the same
-  BF16-rounded weights (2e-2 relative per column), and the labels against
-  the oracle's k-means (ARI >= 0.99).
+  dimensions, the library's symmetrised 10-NN graph (fsc_knn_graph), BF16
+  weights and vectors, l = 4, t = 40.  The graph against the same definition
+  computed with torch ops (all but 0.01% of the entries shared, weights to
+  1e-5), the whole embedding against the FP64 oracle run on that graph with
+  BF16-rounded weights (2e-2 relative per column, element-wise bound), and
+  the labels against the oracle's k-means (ARI >= 0.99).
 * Batched form: the 512-graph batch, every graph's embedding against the
   plain single-graph path (itself checked against the oracle elsewhere) to
   1e-5 per column and element-wise, its labels against the single-graph
@@ -28,17 +30,24 @@ pytestmark = pytest.mark.gpu
 
 
 def test_knn70k_bf16_matches_oracle(gpu_lib):
-    ip, ix, w, lab = synth.knn_mixture_device(7000, 10, 784, seed=0)
-    d = w.to(torch.bfloat16)
+    X_h, lab = synth.gaussian_mixture(7000, 10, 784, seed=0)
+    X = torch.from_numpy(X_h).cuda()
+    ip, ix, w = gpu_lib.knn_graph(X, 10)          # the graph the library builds and clusters
     n = ip.numel() - 1
-    say(f"kNN graph n={n} nnz={ix.numel()}")
-    ip_h, ix_h = ip.cpu().numpy(), ix.cpu().numpy()
-    w_h = d.double().cpu().numpy()
+    # the oracle's input: the same graph definition computed with torch ops
+    # on the same points (the oracle's own brute force takes hours at 70,000)
+    rip, rix, rw, _ = synth.knn_mixture_device(7000, 10, 784, seed=0)
+    agree = synth.graph_agreement((ip, ix, w), (rip, rix, rw))
+    say(f"kNN graph n={n} nnz={ix.numel()} vs torch-built {rix.numel()}: {agree}")
+    assert min(agree["common_frac"]) >= 0.9999 and agree["weight_max_rel_diff"] <= 1e-5
+    d = w.to(torch.bfloat16)
+    ip_h, ix_h = rip.cpu().numpy(), rix.cpu().numpy()
+    w_h = rw.to(torch.bfloat16).double().cpu().numpy()
     E = gpu_lib.embed(ip, ix, d, 4, 40, seed=0, vec_dtype="bf16").float().cpu().numpy()
     want = o.embed(n, ip_h, ix_h, w_h, 4, 40, seed=0)
     err = col_rel_err(E, want)
-    # the same with the FP64 weights the generator drew, for the record
-    err_w = col_rel_err(E, o.embed(n, ip_h, ix_h, w.double().cpu().numpy(), 4, 40, seed=0))
+    # the same with the FP32 weights, for the record
+    err_w = col_rel_err(E, o.embed(n, ip_h, ix_h, rw.double().cpu().numpy(), 4, 40, seed=0))
     say("  bf16 rel err vs oracle on bf16 weights", err, "vs fp32 weights", err_w)
     assert err <= 2e-2
     check_elems(E, want, "bf16", "70k kNN")
