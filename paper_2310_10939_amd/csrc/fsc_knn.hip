@@ -16,11 +16,11 @@ namespace fsc {
 
 typedef float knn_f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kKnnQ = 32;         // queries per block
-constexpr int kKnnList = 16;      // entries of each partial list
-constexpr int kKnnPerPart = 8;    // candidates of a tile per partial list
 constexpr int kKnnNW = 4;         // waves per block
-constexpr int kKnnC = 16 * kKnnNW;  // candidates per tile
+constexpr int kKnnQ = 16 * kKnnNW;  // queries per block
+constexpr int kKnnC = 64;         // candidates per tile
+constexpr int kKnnList = 16;      // entries of each partial list
+constexpr int kKnnPerPart = 16;   // candidates of a tile per partial list
 constexpr int kKnnMaxSplit = 16;  // candidate ranges per query group
 
 // |x_v|^2 in FP64, one wave per row, rounded to FP32.
@@ -78,35 +78,36 @@ __device__ __forceinline__ void knn_merge_xor(float (&d)[kKnnList], int (&ix)[kK
       }
 }
 
-// Block (b, s) takes queries 32b .. 32b + 31 and streams the candidates of
+// Block (b, s) takes queries 64b .. 64b + 63 and streams the candidates of
 // range s (one of S contiguous ranges of tiles) past them, so that the grid
-// has several blocks per resident slot and no long tail.  Both operands go through LDS in chunks of 64 dimensions: the 32
-// queries' chunk and a tile of C = 16 NW candidates' chunk, loaded with
-// coalesced 16-byte loads (the next chunk's loads are in flight while the
-// current one is used).  Nothing stays resident, so a block needs 26 KB of
-// LDS (NW = 4) and four blocks share a CU.  Wave w computes the dot products
-// of queries 16 (w & 1) + 0..15 with candidates 32 (w >> 1) + 0..31 of the
-// tile: lane (col, kk) supplies dimensions k + 4 kk + s (s = 0..3) of query
-// col and of candidate col, and receives the products of queries 4 kk + r
-// with candidate col.  When a tile's last chunk is done its products go
-// through LDS (over the candidate buffer) to the selection: thread t keeps
-// the 16 nearest of the candidates 8 (t % P) + 0..7 of every tile for query
-// t / P (P = 2 NW partial lists per query, held by P neighbouring lanes),
-// sorted by (distance, index).  At the end the P lanes of a query merge
-// their lists pairwise (log2 P exchange rounds) and write the range's 16
-// nearest to pd/pi[s][query][16] (sorted; missing entries are (inf, INT_MAX)).
-template <int NW>
-__global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ X, const float* __restrict__ nrm,
-                                                      int n, int dim, float* __restrict__ pd,
-                                                      int32_t* __restrict__ pi) {
-  constexpr int NT = 64 * NW;          // threads
-  constexpr int C = 16 * NW;           // candidates per tile
+// has several blocks per resident slot and no long tail.  Both operands go
+// through LDS in chunks of 64 dimensions: the 64 queries' chunk and a tile of
+// C = 64 candidates' chunk, loaded with coalesced 16-byte loads (the next
+// chunk's loads are in flight while the current one is used).  Nothing stays
+// resident, so a block needs 35 KB of LDS and four blocks share a CU.  Wave w
+// computes the dot products of queries 16 w + 0..15 with all C candidates of
+// the tile (four 16 x 16 accumulators): lane (col, kk) supplies dimensions
+// k + 4 kk + s (s = 0..3) of query col and of candidate col of each group,
+// and receives the products of queries 4 kk + r with candidate col.  When a
+// tile's last chunk is done its products go through LDS (over the candidate
+// buffer) to the selection: thread t keeps the 16 nearest of the candidates
+// 16 (t % P) + 0..15 of every tile for query t / P (P = 4 partial lists per
+// query, held by neighbouring lanes), sorted by (distance, index).  At the
+// end the P lanes of a query merge their lists pairwise (two exchange
+// rounds) and write the range's 16 nearest to pd/pi[s][query][16] (sorted;
+// missing entries are (inf, INT_MAX)).
+__global__ __launch_bounds__(64 * kKnnNW, 4) void knn_kernel(const float* __restrict__ X, const float* __restrict__ nrm,
+                                                          int n, int dim, float* __restrict__ pd,
+                                                          int32_t* __restrict__ pi) {
+  constexpr int NT = 64 * kKnnNW;      // threads
+  constexpr int C = kKnnC;             // candidates per tile
   constexpr int LDC = 64 + 4;          // padded row of a chunk
   constexpr int P = NT / kKnnQ;        // partial lists per query
-  constexpr int QP = kKnnQ * 16 / NT;  // 16-byte pieces of the query chunk per thread
+  constexpr int CP = C * 16 / NT;      // 16-byte pieces of the candidate chunk per thread
+  constexpr int QP = kKnnQ * 16 / NT;  // and of the query chunk
+  static_assert(kKnnQ == 16 * kKnnNW && C == 64, "a wave takes 16 queries and the whole tile");
   static_assert(C == P * kKnnPerPart, "each tile candidate belongs to one list");
-  static_assert(C * 16 == 4 * NT, "four 16-byte candidate pieces per thread per chunk");
-  static_assert(QP >= 1 && QP * NT == kKnnQ * 16, "whole query pieces per thread");
+  static_assert(CP * NT == C * 16 && QP * NT == kKnnQ * 16, "whole pieces per thread");
   static_assert(kKnnQ * (C + 1) <= C * LDC, "the tile's products fit the candidate buffer");
   static_assert(P <= FSC_WAVE && (FSC_WAVE % P) == 0, "a query's lists lie in one wave");
   __shared__ __align__(16) float qs[kKnnQ * LDC];
@@ -115,8 +116,7 @@ __global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ 
   const int q0 = blockIdx.x * kKnnQ;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kk = lane >> 4;
-  const int qw = (wave & 1) * 16;
-  const int cw = (wave >> 1) * 32;
+  const int qw = wave * 16;
   const int tq = threadIdx.x / P, te = threadIdx.x % P;
   const int gq = q0 + tq;
   const float qn = gq < n ? nrm[gq] : 0.f;
@@ -128,22 +128,21 @@ __global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ 
     bi[j] = INT_MAX;
   }
   const float* qrow = qs + (qw + col) * LDC + 4 * kk;
-  const float* crow0 = cs + (cw + col) * LDC + 4 * kk;
-  const float* crow1 = crow0 + 16 * LDC;
+  const float* crow = cs + col * LDC + 4 * kk;   // candidate group g at crow + 16 g LDC
   const knn_f4 zero = {0.f, 0.f, 0.f, 0.f};
 
   // chunk ci covers candidates C (ci / nkc) + 0..C-1, dimensions 64 (ci % nkc) + 0..63;
-  // thread t loads candidate pieces t + NT i (i = 0..3) and query pieces
+  // thread t loads candidate pieces t + NT i (i < CP) and query pieces
   // t + NT i (i < QP): row piece / 16, dims 4 (piece % 16)
   const int nkc = (dim + 63) / 64;
   const int64_t tiles = (n + C - 1) / C;
   const int64_t S = gridDim.y, sp = blockIdx.y;
   const int64_t ci_begin = (sp * tiles / S) * nkc, ci_end = ((sp + 1) * tiles / S) * nkc;
-  knn_f4 pre[4], qpre[QP];
+  knn_f4 pre[CP], qpre[QP];
   auto load = [&](int64_t ci) {
     const int c0 = (int)(ci / nkc) * C, kc = (int)(ci % nkc) * 64;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < CP; ++i) {
       const int piece = threadIdx.x + NT * i;
       const int r = c0 + (piece >> 4), d = kc + 4 * (piece & 15);
       const bool ok = r < n && d < dim;
@@ -161,12 +160,14 @@ __global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ 
     }
   };
   if (ci_begin < ci_end) load(ci_begin);
-  knn_f4 acc0 = zero, acc1 = zero;
+  knn_f4 acc[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) acc[g] = zero;
   for (int64_t ci = ci_begin; ci < ci_end; ++ci) {
     const int c0 = (int)(ci / nkc) * C, kc = (int)(ci % nkc) * 64;
     __syncthreads();  // every wave is done with the previous chunk, or with the products
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < CP; ++i) {
       const int piece = threadIdx.x + NT * i;
       *reinterpret_cast<knn_f4*>(cs + (piece >> 4) * LDC + 4 * (piece & 15)) = pre[i];
     }
@@ -178,31 +179,30 @@ __global__ __launch_bounds__(64 * NW) void knn_kernel(const float* __restrict__ 
     __syncthreads();
     if (ci + 1 < ci_end) load(ci + 1);
     if (kc == 0) {
-      acc0 = zero;
-      acc1 = zero;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) acc[g] = zero;
     }
 #pragma unroll
     for (int k = 0; k < 64; k += 16) {
       if (kc + k < dim) {
         const knn_f4 a = *reinterpret_cast<const knn_f4*>(qrow + k);
-        const knn_f4 b0 = *reinterpret_cast<const knn_f4*>(crow0 + k);
-        const knn_f4 b1 = *reinterpret_cast<const knn_f4*>(crow1 + k);
+        knn_f4 b[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b0[s], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b1[s], acc1, 0, 0, 0);
-        }
+        for (int g = 0; g < 4; ++g) b[g] = *reinterpret_cast<const knn_f4*>(crow + 16 * g * LDC + k);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int g = 0; g < 4; ++g) acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s4], b[g][s4], acc[g], 0, 0, 0);
       }
     }
     if (kc + 64 < dim) continue;  // more dimensions of this tile to come
     __syncthreads();  // the candidate buffer is read by every wave before it takes the products
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      dt[qw + 4 * kk + r][cw + col] = acc0[r];
-      dt[qw + 4 * kk + r][cw + 16 + col] = acc1[r];
-    }
-    __syncthreads();
+    for (int g = 0; g < 4; ++g)
 #pragma unroll
+      for (int r = 0; r < 4; ++r) dt[qw + 4 * kk + r][16 * g + col] = acc[g][r];
+    __syncthreads();
+#pragma unroll 4
     for (int j = 0; j < kKnnPerPart; ++j) {
       const int cl = te * kKnnPerPart + j;
       const int c = c0 + cl;
@@ -292,7 +292,7 @@ int knn_run(Arena* a, const float* X, int64_t n, int dim, int knn, int num_cu, i
   const int nb = (int)std::min<int64_t>((n + 3) / 4, 8192);
   hipLaunchKernelGGL(knn_norms_kernel, dim3(nb), dim3(256), 0, s, X, n, dim, norms);
   const int groups = (int)((n + kKnnQ - 1) / kKnnQ);
-  hipLaunchKernelGGL((knn_kernel<kKnnNW>), dim3(groups, S), dim3(64 * kKnnNW), 0, s, X, norms, (int)n, dim, pd, pi);
+  hipLaunchKernelGGL(knn_kernel, dim3(groups, S), dim3(64 * kKnnNW), 0, s, X, norms, (int)n, dim, pd, pi);
   const int mb = (int)std::min<int64_t>((n + 255) / 256, 8192);
   hipLaunchKernelGGL(knn_merge_kernel, dim3(mb), dim3(256), 0, s, pd, pi, n, S, knn, nbr, dist);
   return check_hip(hipGetLastError(), "knn launch");
