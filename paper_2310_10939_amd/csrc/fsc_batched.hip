@@ -328,10 +328,10 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     if (x.LH != x.KD) add(4 * x.n * x.KD);
     int pp, ll, tpw;
     kmeans_shape(x.n, ctx->num_cu, &pp, &ll, &tpw);
-    // d2, bsum, cand, cand_row, centres, cpart, chosen: 7 takes, each padded
-    // to 256 bytes
+    // d2, bsum, cand, cand_row, centres, cpart, chosen, conv: 8 takes, each
+    // padded to 256 bytes
     add(4 * x.n + 8 * 6 * pp + 4 * 6 * x.KD + 4 * 6 + 4 * 64 * x.KD + 8 * (size_t)ll * 64 * (x.KD + 1) + 4 * 64 +
-        8 * 256);
+        4 * 4 + 9 * 256);
   }
   bytes += 64 * 1024;
   if (bytes > ctx->barena_size) {
@@ -416,6 +416,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     J.centres = a.take<float>(64 * x.KD);
     J.cpart = a.take<double>((size_t)J.nblk_ll * 64 * (x.KD + 1));
     J.chosen = a.take<int32_t>(64);
+    J.conv = a.take<int32_t>(4);
     J.labels = labels + noff[g];
     J.k0 = b.k0;
     J.k1 = b.k1;

@@ -246,6 +246,7 @@ struct KmeansIO {
   float* centres;          // 64 x KD (padded)
   double* cpart;           // blocks x 64 x (KD+1)
   int32_t* chosen;         // 64
+  int32_t* conv;           // 4: labels changed by the current Lloyd step; 1 once a step changed none
   int nblk_pp, nblk_ll;
 };
 // One k-means problem as the kernels see it.
@@ -265,6 +266,7 @@ struct KmJob {
   double* cpart;
   uint32_t k0, k1;         // Philox key (seed)
   int nblk_pp, nblk_ll, tpw;
+  int32_t* conv;           // Lloyd convergence state (KmeansIO::conv)
 };
 void kmeans_shape(int64_t n, int num_cu, int* nblk_pp, int* nblk_ll, int* tpw);
 int kpp_trials(int k);

@@ -28,6 +28,13 @@
 // summed in FP64 in wave order, and the per-block sums are combined in a fixed
 // order by a one-block kernel per job after the step, so results are
 // deterministic.
+//
+// Convergence: every step after the first counts the points whose label it
+// changes.  A step that changes none leaves the centres where they were (the
+// same labels give the same sums in the same order), so every later step
+// would repeat it exactly; its centre update then marks the job converged and
+// the remaining steps' launches return at once.  The result is bit for bit
+// that of running all the steps.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
 
@@ -45,6 +52,12 @@ constexpr int kMaxK = 64;
 constexpr int kMaxTrials = 6;  // 2 + floor(ln 64)
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, FSC_WAVE);
+  return v;
+}
 
 // Shared state of a block, declared once per kernel (the segmented kernels
 // instantiate several block bodies, which must not each own LDS).
@@ -356,7 +369,7 @@ __device__ __forceinline__ void argmin_xor(float& d, int& j, int mask) {
 }
 
 template <int KD, int KT, bool UPDATE>
-__device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh) {
+__device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh, bool count) {
   auto& wsum = sh.wsum;
   auto& lab_s = sh.lab;
   const int64_t n = J.n;
@@ -399,6 +412,7 @@ __device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh) {
   floatx4 uacc[KT];
 #pragma unroll
   for (int jt = 0; jt < KT; ++jt) uacc[jt] = floatx4{0.f, 0.f, 0.f, 0.f};
+  int changed = 0;  // labels this lane changed (counted steps only)
 
   const int tpw = J.tpw;
   const int64_t tile0 = ((int64_t)blk * kLW + wave) * tpw;  // this wave's first tile
@@ -458,7 +472,10 @@ __device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh) {
       argmin_xor(bd, bj, 32);
       if (kk == 0) {
         const int64_t row = row0 + col;
-        if (row < n) J.labels[row] = bj;
+        if (row < n) {
+          if (UPDATE && count) changed += J.labels[row] != bj ? 1 : 0;
+          J.labels[row] = bj;
+        }
         if constexpr (UPDATE) lab_s[wave][col] = bj;
       }
       if constexpr (UPDATE) {
@@ -493,6 +510,10 @@ __device__ void lloyd_block(const KmJob& J, int blk, LloydShared& sh) {
     }
   }
 
+  if (UPDATE && count) {
+    changed = wave_sum_i32(changed);
+    if (lane == 0 && changed > 0) atomicAdd(J.conv, changed);
+  }
   if constexpr (UPDATE) {
     // uacc[jt][r] = sum over this wave's rows for centre jt*16 + 4*kk + r, dim col
     if (col <= KD) {
@@ -584,16 +605,39 @@ __global__ __launch_bounds__(kKB) void kpp_select_kernel(KmJob J, int r) {
   kpp_select_block(J, r, sh);
 }
 
+// Step `it` of Lloyd (the final assignment when !UPDATE); a converged job
+// returns at once.
 template <int KD, int KT, bool UPDATE>
-__global__ __launch_bounds__(kLB) void lloyd_kernel(KmJob J) {
+__global__ __launch_bounds__(kLB) void lloyd_kernel(KmJob J, int it) {
   __shared__ LloydShared sh;
-  lloyd_block<KD, KT, UPDATE>(J, blockIdx.x, sh);
+  if (UPDATE && J.conv[1]) return;
+  lloyd_block<KD, KT, UPDATE>(J, blockIdx.x, sh, it > 0);
 }
 
-__global__ __launch_bounds__(kLB) void lloyd_finish_kernel(KmJob J) {
+// The centre update of step `it`, then the convergence state: a counted step
+// that changed no label marks the job converged; the count restarts at 0.
+__device__ void lloyd_finish_step(const KmJob& J, int it, double* tot, double* part) {
+  if (J.conv[1]) return;
+  lloyd_finish(J, tot, part);
+  if (threadIdx.x == 0) {
+    if (it > 0 && J.conv[0] == 0) J.conv[1] = 1;
+    J.conv[0] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kLB) void lloyd_finish_kernel(KmJob J, int it) {
   __shared__ double tot[kMaxK * 9];
   __shared__ double part[kLB];
-  lloyd_finish(J, tot, part);
+  lloyd_finish_step(J, it, tot, part);
+}
+
+// Clears the convergence state of every job before the Lloyd steps.
+__global__ void kmeans_conv_reset(const KmJob* __restrict__ jobs, int njobs) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < njobs) {
+    jobs[g].conv[0] = 0;
+    jobs[g].conv[1] = 0;
+  }
 }
 
 __device__ __forceinline__ int find_job(const int32_t* off, int njobs, int b) {
@@ -647,28 +691,30 @@ __global__ __launch_bounds__(kKB) void kpp_pick_kernel_seg(const KmJob* __restri
 
 template <bool UPDATE>
 __global__ __launch_bounds__(kLB) void lloyd_kernel_seg(const KmJob* __restrict__ jobs,
-                                                        const int32_t* __restrict__ off, int njobs) {
+                                                        const int32_t* __restrict__ off, int njobs, int it) {
   __shared__ LloydShared sh;
   const int g = find_job(off, njobs, blockIdx.x);
   const KmJob J = jobs[g];
+  if (UPDATE && J.conv[1]) return;
   const int b = blockIdx.x - off[g];
   const int KT = (J.k + 15) / 16;
+  const bool count = it > 0;
   if (J.KD == 4) {
-    if (KT == 1) lloyd_block<4, 1, UPDATE>(J, b, sh);
-    else if (KT == 2) lloyd_block<4, 2, UPDATE>(J, b, sh);
-    else lloyd_block<4, 4, UPDATE>(J, b, sh);
+    if (KT == 1) lloyd_block<4, 1, UPDATE>(J, b, sh, count);
+    else if (KT == 2) lloyd_block<4, 2, UPDATE>(J, b, sh, count);
+    else lloyd_block<4, 4, UPDATE>(J, b, sh, count);
   } else {
-    if (KT == 1) lloyd_block<8, 1, UPDATE>(J, b, sh);
-    else if (KT == 2) lloyd_block<8, 2, UPDATE>(J, b, sh);
-    else lloyd_block<8, 4, UPDATE>(J, b, sh);
+    if (KT == 1) lloyd_block<8, 1, UPDATE>(J, b, sh, count);
+    else if (KT == 2) lloyd_block<8, 2, UPDATE>(J, b, sh, count);
+    else lloyd_block<8, 4, UPDATE>(J, b, sh, count);
   }
 }
 
 // One block per job.
-__global__ __launch_bounds__(kLB) void lloyd_finish_kernel_seg(const KmJob* __restrict__ jobs) {
+__global__ __launch_bounds__(kLB) void lloyd_finish_kernel_seg(const KmJob* __restrict__ jobs, int it) {
   __shared__ double tot[kMaxK * 9];
   __shared__ double part[kLB];
-  lloyd_finish(jobs[blockIdx.x], tot, part);
+  lloyd_finish_step(jobs[blockIdx.x], it, tot, part);
 }
 
 // Normalised k-means cost of the final assignment over the eligible rows:
@@ -766,6 +812,7 @@ size_t kmeans_workspace_bytes(int64_t n, int KD) {
   b += align_up(kMaxK * KD * 4);                          // centres
   b += align_up((size_t)nblk_ll * kMaxK * (KD + 1) * 8);  // cpart
   b += align_up(kMaxK * 4);                               // chosen
+  b += align_up(4 * 4);                                   // conv
   return b + 8 * 256;
 }
 
@@ -779,6 +826,7 @@ int kmeans_bind_workspace(Arena* a, KmeansIO* io) {
   io->centres = a->take<float>(kMaxK * io->KD);
   io->cpart = a->take<double>((size_t)((n + 15) / 16 / kLW + 1) * kMaxK * (io->KD + 1));
   io->chosen = a->take<int32_t>(kMaxK);
+  io->conv = a->take<int32_t>(4);
   if (a->used > a->size) return fail(FSC_E_NOMEM, "workspace arena too small");
   return FSC_OK;
 }
@@ -801,17 +849,20 @@ KmJob make_job(Context* ctx, const KmeansIO* io) {
   J.cpart = io->cpart;
   J.k0 = (uint32_t)(io->seed & 0xffffffffu);
   J.k1 = (uint32_t)(io->seed >> 32);
+  J.conv = io->conv;
   kmeans_shape(io->n, ctx->num_cu, &J.nblk_pp, &J.nblk_ll, &J.tpw);
   return J;
 }
 
 template <int KD, int KT>
 static int lloyd_all(const KmJob& J, int iters, hipStream_t s) {
+  int rc;
+  if ((rc = fill_zero_i32(J.conv, 4, s))) return rc;
   for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL((lloyd_kernel<KD, KT, true>), dim3(J.nblk_ll), dim3(kLB), 0, s, J);
-    hipLaunchKernelGGL(lloyd_finish_kernel, dim3(1), dim3(kLB), 0, s, J);
+    hipLaunchKernelGGL((lloyd_kernel<KD, KT, true>), dim3(J.nblk_ll), dim3(kLB), 0, s, J, it);
+    hipLaunchKernelGGL(lloyd_finish_kernel, dim3(1), dim3(kLB), 0, s, J, it);
   }
-  hipLaunchKernelGGL((lloyd_kernel<KD, KT, false>), dim3(J.nblk_ll), dim3(kLB), 0, s, J);
+  hipLaunchKernelGGL((lloyd_kernel<KD, KT, false>), dim3(J.nblk_ll), dim3(kLB), 0, s, J, iters);
   return check_hip(hipGetLastError(), "lloyd_kernel launch");
 }
 
@@ -860,11 +911,12 @@ int kmeans_run_batched(Context* ctx, const KmJob* jobs_dev, const int32_t* pp_of
       hipLaunchKernelGGL(kpp_select_kernel_seg, dim3(njobs), dim3(kKB), 0, s, jobs_dev, r);
     }
   }
+  hipLaunchKernelGGL(kmeans_conv_reset, dim3((njobs + 255) / 256), dim3(256), 0, s, jobs_dev, njobs);
   for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL(lloyd_kernel_seg<true>, dim3(ll_total), dim3(kLB), 0, s, jobs_dev, ll_off_dev, njobs);
-    hipLaunchKernelGGL(lloyd_finish_kernel_seg, dim3(njobs), dim3(kLB), 0, s, jobs_dev);
+    hipLaunchKernelGGL(lloyd_kernel_seg<true>, dim3(ll_total), dim3(kLB), 0, s, jobs_dev, ll_off_dev, njobs, it);
+    hipLaunchKernelGGL(lloyd_finish_kernel_seg, dim3(njobs), dim3(kLB), 0, s, jobs_dev, it);
   }
-  hipLaunchKernelGGL(lloyd_kernel_seg<false>, dim3(ll_total), dim3(kLB), 0, s, jobs_dev, ll_off_dev, njobs);
+  hipLaunchKernelGGL(lloyd_kernel_seg<false>, dim3(ll_total), dim3(kLB), 0, s, jobs_dev, ll_off_dev, njobs, iters);
   return check_hip(hipGetLastError(), "batched k-means launch");
 }
 

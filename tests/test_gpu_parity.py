@@ -185,6 +185,29 @@ def test_kmeanspp_with_fewer_distinct_points_than_k(gpu_lib):
     assert _valid_assignment(X.astype(np.float64), lab, C.cpu().numpy().astype(np.float64), 1e-6)
 
 
+def test_lloyd_stops_at_its_fixed_point(gpu_lib):
+    """Overlapping clusters take several Lloyd steps to settle.  The results
+    for 0, 1, 2, ... steps change until a step changes no label, and from
+    then on every step count gives the same labels and centres bit for bit
+    (the library skips the steps after such a step, which would repeat it)."""
+    X, _ = synth.gaussian_mixture(2000, 12, 6, seed=5, mean_scale=2.0)
+    Xt = torch.from_numpy(X.astype(np.float32)).cuda()
+    runs = []
+    for it in range(0, 41):
+        lab, C = gpu_lib.kmeans(Xt, 12, it, seed=4)
+        runs.append((lab.cpu().numpy(), C.cpu().numpy()))
+    same = [np.array_equal(runs[i][0], runs[i - 1][0]) and np.array_equal(runs[i][1], runs[i - 1][1])
+            for i in range(1, len(runs))]
+    first = next((i + 1 for i, v in enumerate(same) if v), None)
+    say(f"lloyd settles after {first} steps")
+    assert first is not None and first >= 3
+    for it in list(range(first, len(runs))) + [200]:
+        lab, C = runs[it] if it < len(runs) else (x.cpu().numpy() for x in gpu_lib.kmeans(Xt, 12, it, seed=4))
+        assert np.array_equal(lab, runs[first][0]) and np.array_equal(C, runs[first][1]), it
+    lab_o, _ = o.kmeans(X.astype(np.float64), 12, first, seed=4)
+    assert o.ari(runs[first][0], lab_o) >= 0.99
+
+
 def test_kmeans_eligibility_and_fp64_points(gpu_lib):
     X, _ = synth.gaussian_mixture(300, 4, 3, seed=1, mean_scale=5.0)
     X = X.astype(np.float64)
