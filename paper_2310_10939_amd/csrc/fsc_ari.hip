@@ -1,7 +1,8 @@
 // Accuracy scores of Sec. 4.2: the adjusted Rand index (Hubert and Arabie)
 // and normalised mutual information.  The contingency table is built with
 // integer atomics (exact, so the result does not depend on the order of the
-// updates); each score is then formed in FP64 by one block.  C(x, 2) of
+// updates), counted per block in LDS when it is small; each score is then
+// formed in FP64 by one block.  C(x, 2) of
 // integer counts below 2^26 is exact in FP64.
 #include "fsc_device.hpp"
 #include "fsc_internal.hpp"
@@ -20,6 +21,29 @@ __global__ void ari_count(const int32_t* __restrict__ a, const int32_t* __restri
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int x = a[i], y = b[i];
     if (x >= 0 && x < ka && y >= 0 && y < kb) atomicAdd(&table[(int64_t)x * kb + y], 1ull);
+  }
+}
+
+// The same with the table first counted in LDS by each block (tables of at
+// most kAriLdsCells cells): one global atomic per nonzero cell per block
+// instead of one per pair.
+constexpr int kAriLdsCells = 8192;
+
+__global__ __launch_bounds__(256) void ari_count_lds(const int32_t* __restrict__ a, const int32_t* __restrict__ b,
+                                                     int64_t n, int ka, int kb,
+                                                     unsigned long long* __restrict__ table) {
+  __shared__ uint32_t t[kAriLdsCells];
+  const int cells = ka * kb;
+  for (int c = threadIdx.x; c < cells; c += 256) t[c] = 0u;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int x = a[i], y = b[i];
+    if (x >= 0 && x < ka && y >= 0 && y < kb) atomicAdd(&t[x * kb + y], 1u);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < cells; c += 256) {
+    const uint32_t v = t[c];
+    if (v) atomicAdd(&table[c], (unsigned long long)v);
   }
 }
 
@@ -104,7 +128,10 @@ static void contingency(const int32_t* a, const int32_t* b, int64_t n, int ka, i
                         hipStream_t s) {
   const int64_t cells = (int64_t)ka * kb;
   hipLaunchKernelGGL(ari_zero, dim3((int)std::min<int64_t>((cells + 255) / 256, 4096)), dim3(256), 0, s, table, cells);
-  if (n > 0)
+  if (n > 0 && cells <= kAriLdsCells)
+    hipLaunchKernelGGL(ari_count_lds, dim3((int)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s, a, b, n,
+                       ka, kb, table);
+  else if (n > 0)
     hipLaunchKernelGGL(ari_count, dim3((int)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s, a, b, n, ka,
                        kb, table);
 }

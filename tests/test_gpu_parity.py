@@ -225,6 +225,13 @@ def test_ari_kernel(gpu_lib):
         b = np.where(rng.random(n) < 0.6, a, rng.integers(0, 9, n)).astype(np.int32)
         got = float(gpu_lib.ari(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), 6, 9))
         assert abs(got - o.ari(a, b)) < 1e-12
+    # tables counted in LDS per block (up to 8192 cells) and in global memory
+    # (larger); agreeing labelings put most pairs in a few cells
+    for n, ka, kb in [(1_000_000, 10, 10), (50_000, 64, 64), (20_000, 100, 100), (30_000, 8192, 2)]:
+        a = rng.integers(0, ka, n).astype(np.int32)
+        b = np.where(rng.random(n) < 0.97, a % kb, rng.integers(0, kb, n)).astype(np.int32)
+        got = float(gpu_lib.ari(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), ka, kb))
+        assert abs(got - o.ari(a, b)) < 1e-12, (n, ka, kb)
 
 
 def test_nmi_kernel(gpu_lib):
