@@ -135,6 +135,59 @@ __global__ __launch_bounds__(1024) void slab_scan_kernel(const int64_t* __restri
   }
 }
 
+// Four consecutive column indices / weights starting at j0 (j0 a multiple of
+// 4): one 16-byte (weights: 16- or 8-byte) load when `vec` says the arrays
+// are 16-byte aligned and the quad lies inside them, else element by element
+// inside [a, b) (0 elsewhere).
+__device__ __forceinline__ void quad_cols(const int32_t* col, int64_t j0, int64_t a, int64_t b, bool vec,
+                                          int32_t (&c)[4]) {
+  if (vec) {
+    const int4 v = *reinterpret_cast<const int4*>(col + j0);
+    c[0] = v.x;
+    c[1] = v.y;
+    c[2] = v.z;
+    c[3] = v.w;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = j0 + u >= a && j0 + u < b ? col[j0 + u] : 0;
+  }
+}
+template <typename W> struct quad_w;
+template <> struct quad_w<void> {
+  __device__ static void get(const void*, int64_t, int64_t, int64_t, bool, float (&w)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = 1.0f;
+  }
+};
+template <> struct quad_w<float> {
+  __device__ static void get(const float* v, int64_t j0, int64_t a, int64_t b, bool vec, float (&w)[4]) {
+    if (vec) {
+      const float4 x = *reinterpret_cast<const float4*>(v + j0);
+      w[0] = x.x;
+      w[1] = x.y;
+      w[2] = x.z;
+      w[3] = x.w;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w[u] = j0 + u >= a && j0 + u < b ? v[j0 + u] : 0.f;
+    }
+  }
+};
+template <> struct quad_w<bf16_t> {
+  __device__ static void get(const bf16_t* v, int64_t j0, int64_t a, int64_t b, bool vec, float (&w)[4]) {
+    if (vec) {
+      const uint2 x = *reinterpret_cast<const uint2*>(v + j0);
+      w[0] = bf16_to_f32((uint16_t)(x.x & 0xffffu));
+      w[1] = bf16_to_f32((uint16_t)(x.x >> 16));
+      w[2] = bf16_to_f32((uint16_t)(x.y & 0xffffu));
+      w[3] = bf16_to_f32((uint16_t)(x.y >> 16));
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w[u] = j0 + u >= a && j0 + u < b ? bf16_to_f32(v[j0 + u].bits) : 0.f;
+    }
+  }
+};
+
 constexpr int kBuild = 1024;  // threads of the build kernel: one per row of a tile
 constexpr int kBuildU = 8;    // nonzeros of a row loaded at once
 constexpr int kStageWords = 12288;  // 48 KiB of LDS staging: column indices, then weights when loaded
@@ -145,7 +198,7 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     int32_t rows, int32_t S, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
     const int32_t* __restrict__ coff, CI* __restrict__ scol, W* __restrict__ sval, uint16_t* __restrict__ sperm,
     int32_t* __restrict__ sbase, int32_t* __restrict__ smax, int64_t* __restrict__ sreg,
-    LongChunk* __restrict__ chunks, uint8_t* __restrict__ tunit, DegreeOut dout) {
+    LongChunk* __restrict__ chunks, uint8_t* __restrict__ tunit, DegreeOut dout, int64_t nnz, int aligned) {
   __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
   __shared__ uint16_t spos[kSlabMax * kSlabRows];  // sorted position of each row per slab
   __shared__ int32_t hist[kSlabMax * (kSlabLong + 1)];  // per slab: rows of each length, then its cursor
@@ -172,23 +225,24 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   // segment length of every short row in every slab, and whether every
   // weight of the tile's short rows is exactly 1
   // (and the row's degree: its weights are read here anyway)
+  // the row's nonzeros by aligned quads (one 16-byte load per quad where the
+  // arrays allow it), in CSR order
   int unit = 1;
   if (shortrow) {
     double dsum = 0.0;
-    for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
-      int32_t c[kBuildU];
+    for (int64_t j0 = a & ~(int64_t)3; j0 < b; j0 += 4) {
+      const bool vec = aligned && j0 + 4 <= nnz;
+      int32_t c[4];
+      float w[4];
+      quad_cols(col, j0, a, b, vec, c);
+      quad_w<W>::get(val, j0, a, b, vec, w);
 #pragma unroll
-      for (int u = 0; u < kBuildU; ++u) c[u] = j0 + u < b ? col[j0 + u] : 0;
-#pragma unroll
-      for (int u = 0; u < kBuildU; ++u) {
-        if (j0 + u >= b) continue;
-        const float w = weight<W, float>::get(val, j0 + u);
-        if (w != 1.0f) unit = 0;
-        dsum += (double)w;
+      for (int u = 0; u < 4; ++u) {
+        if (j0 + u < a || j0 + u >= b) continue;
+        if (w[u] != 1.0f) unit = 0;
+        dsum += (double)w[u];
+        cnt[slab_of(c[u], S, last) * R + rl] += 1;
       }
-#pragma unroll
-      for (int u = 0; u < kBuildU; ++u)
-        if (j0 + u < b) cnt[slab_of(c[u], S, last) * R + rl] += 1;
     }
     write_degree(dout, r0 + rl, dsum);
   }
@@ -350,13 +404,13 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
     for (int i = p0 * R + threadIdx.x; i < p1 * R; i += kBuild) cnt[i] = 0;
     __syncthreads();
     if (shortrow) {
-      for (int64_t j0 = a; j0 < b; j0 += kBuildU) {
-        int32_t c[kBuildU];
+      for (int64_t j0 = a & ~(int64_t)3; j0 < b; j0 += 4) {
+        const bool vec = aligned && j0 + 4 <= nnz;
+        int32_t c[4];
+        quad_cols(col, j0, a, b, vec, c);
 #pragma unroll
-        for (int u = 0; u < kBuildU; ++u) c[u] = j0 + u < b ? col[j0 + u] : 0;
-#pragma unroll
-        for (int u = 0; u < kBuildU; ++u) {
-          if (j0 + u >= b) continue;
+        for (int u = 0; u < 4; ++u) {
+          if (j0 + u < a || j0 + u >= b) continue;
           const int p = slab_of(c[u], S, last);
           if (p < p0 || p >= p1) continue;
           const int kk = cnt[p * R + rl]++;
@@ -670,10 +724,14 @@ static void launch_build_ci(const fsc_csr* g, SlabPlan& sp, const DegreeOut& dou
                        sp.toff, sp.loff, sp.coff, scol, reinterpret_cast<W*>(sp.sval), sp.wlen, sp.gbase, sp.gunit,
                        sp.chunks, dout);
   } else {
+    // quads of indices and weights load as one access when both arrays are
+    // 16-byte aligned
+    const int aligned = reinterpret_cast<uintptr_t>(g->col_idx) % 16 == 0 &&
+                        reinterpret_cast<uintptr_t>(g->val) % 16 == 0;
     hipLaunchKernelGGL((slab_build_kernel<W, CI>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
                        reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
                        sp.coff, scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax, sp.sreg,
-                       sp.chunks, sp.tunit, dout);
+                       sp.chunks, sp.tunit, dout, (int64_t)g->nnz, aligned);
   }
 }
 
