@@ -199,3 +199,59 @@ def test_return_y_with_a_given_start_block(gpu_lib):
     Y = gpu_lib.embed(ip, ix, d, 4, 5, seed=0, vec_dtype="f64", x0=xt, return_y=True).cpu().numpy()
     want = o.power_method(o.signless_laplacian(g.n, g.indptr, g.indices, g.data), x0, 5)
     assert col_rel_err(Y, want) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Degenerate graphs of Sec. 2's setting, through the C ABI against the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [300, 100_000])
+def test_graph_without_edges(gpu_lib, n):
+    """No edges: every vertex isolated (d = 0), so every embedding row is 0
+    and no row takes part in the k-means fit; the seeding falls back to the
+    smallest unchosen rows, every centre is 0 and every label is 0 (the
+    lowest centre on a tie), as in the oracle.  100,000 vertices take the
+    column-slab form with nothing in it."""
+    ip = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    ix = torch.zeros(0, dtype=torch.int32, device="cuda")
+    E = gpu_lib.embed(ip, ix, None, 3, 5, seed=1).cpu().numpy()
+    assert E.shape == (n, 3) and not E.any()
+    lab, E2 = gpu_lib.cluster(ip, ix, None, 4, 3, 5, 1, kmeans_iters=10, return_embedding=True)
+    lab_o, _, E_o = o.fast_spectral_cluster(n, np.zeros(n + 1, dtype=np.int64), np.zeros(0, dtype=np.int64), None,
+                                            4, 3, 5, 1, 10)
+    assert not E_o.any() and not E2.cpu().numpy().any()
+    assert np.array_equal(lab.cpu().numpy(), np.asarray(lab_o, dtype=np.int32))
+    assert not lab.cpu().numpy().any()
+
+
+def test_single_vertex(gpu_lib):
+    ip = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ix = torch.zeros(0, dtype=torch.int32, device="cuda")
+    lab, E = gpu_lib.cluster(ip, ix, None, 1, 1, 3, 0, kmeans_iters=5, return_embedding=True)
+    assert lab.cpu().numpy().tolist() == [0] and E.cpu().numpy().tolist() == [[0.0]]
+
+
+@pytest.mark.parametrize("vec", ["f64", "f32"])
+def test_one_edge(gpu_lib, vec):
+    """Two vertices joined by one edge: M = [[1/2, 1/2], [1/2, 1/2]] projects
+    onto the constant vector after one step, so both embedding rows are
+    equal; k = 2 then puts both vertices in cluster 0 (the second centre is
+    the first's copy and ties go to the lower index), as in the oracle."""
+    indptr = np.array([0, 1, 2], dtype=np.int64)
+    indices = np.array([1, 0], dtype=np.int64)
+    ip, ix, _ = _dev(indptr, indices, None, "f64")
+    E = gpu_lib.embed(ip, ix, None, 2, 3, seed=5, vec_dtype=vec).double().cpu().numpy()
+    want = o.embed(2, indptr, indices, None, 2, 3, seed=5)
+    assert col_rel_err(E, want) <= (1e-12 if vec == "f64" else 1e-6)
+    assert np.allclose(E[0], E[1], rtol=1e-6, atol=0)
+    lab = gpu_lib.cluster(ip, ix, None, 2, 2, 3, 5, kmeans_iters=5, vec_dtype=vec).cpu().numpy()
+    lab_o, _, _ = o.fast_spectral_cluster(2, indptr, indices, None, 2, 2, 3, 5, 5)
+    assert np.array_equal(lab, np.asarray(lab_o, dtype=np.int32))
+
+
+def test_t0_cluster_is_kmeans_of_the_start_block(gpu_lib):
+    """t = 0: no power step; the labels are k-means of D^{-1/2} X0."""
+    g = synth.random_weighted(2000, 8000, seed=8, isolated=3)
+    ip, ix, d = _dev(g.indptr, g.indices, g.data, "f64")
+    lab = gpu_lib.cluster(ip, ix, d, 4, 3, 0, 2, kmeans_iters=15, vec_dtype="f64").cpu().numpy()
+    lab_o, _, _ = o.fast_spectral_cluster(g.n, g.indptr, g.indices, g.data, 4, 3, 0, 2, 15)
+    assert o.ari(lab, lab_o) >= 0.99
