@@ -68,64 +68,92 @@ __global__ __launch_bounds__(kOrthoBlock) void ortho_gram_kernel(const S* __rest
   }
 }
 
-// One block: sums the partials in block order (deterministic), then one lane
-// diagonalises the leading k x k block of G and writes W = V diag(1/sigma)
-// (LH x LH, row a = input column, zero outside k x k, columns in descending
-// order of sigma) and, when sigma_out is given, the k singular values.
+// One block: sums the partials (each entry over the blocks in a fixed
+// order), then wave 0 diagonalises the leading k x k block of G, lane
+// a * LH + b holding G[a][b] and V[a][b], and lane 0 writes
+// W = V diag(1/sigma) (LH x LH, row a = input column, zero outside k x k,
+// columns in descending order of sigma) and, when sigma_out is given, the k
+// singular values.
+constexpr int kOrthoFinish = 256;
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int LH>
-__global__ __launch_bounds__(64) void ortho_finish_kernel(const double* __restrict__ partials, int grid, int k,
-                                                          double* __restrict__ W, double* __restrict__ sigma_out) {
+__global__ __launch_bounds__(kOrthoFinish) void ortho_finish_kernel(const double* __restrict__ partials, int grid,
+                                                                    int k, double* __restrict__ W,
+                                                                    double* __restrict__ sigma_out) {
   constexpr int NT = LH * (LH + 1) / 2;
+  static_assert(LH * LH <= FSC_WAVE, "one lane per element of G");
+  __shared__ double red[kOrthoFinish / FSC_WAVE];
   __shared__ double gs[NT];
-  __shared__ double G[LH][LH];
-  __shared__ double V[LH][LH];
-  if (threadIdx.x < NT) {
-    double s = 0.0;
-    for (int b = 0; b < grid; ++b) s += partials[(int64_t)b * NT + threadIdx.x];
-    gs[threadIdx.x] = s;
+  __shared__ double G[LH * LH];
+  __shared__ double V[LH * LH];
+  double acc[NT];
+#pragma unroll
+  for (int e = 0; e < NT; ++e) acc[e] = 0.0;
+  for (int b = threadIdx.x; b < grid; b += kOrthoFinish)
+#pragma unroll
+    for (int e = 0; e < NT; ++e) acc[e] += partials[(int64_t)b * NT + e];
+#pragma unroll
+  for (int e = 0; e < NT; ++e) {
+    const double t = block_sum<kOrthoFinish>(acc[e], red);
+    if (threadIdx.x == 0) gs[e] = t;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int a = 0, i = 0; a < LH; ++a)
-    for (int b = a; b < LH; ++b, ++i) G[a][b] = G[b][a] = gs[i];
-  for (int a = 0; a < LH; ++a)
-    for (int b = 0; b < LH; ++b) V[a][b] = a == b ? 1.0 : 0.0;
+  if (threadIdx.x >= FSC_WAVE) return;
+  const int lane = threadIdx.x;
+  const bool own = lane < LH * LH;
+  const int r = lane / LH, c = lane % LH;
+  if (own) {
+    const int lo = min(r, c), hi = max(r, c);
+    G[lane] = gs[lo * LH - lo * (lo - 1) / 2 + (hi - lo)];
+    V[lane] = r == c ? 1.0 : 0.0;
+  }
+  wave_sync_lds();
   // cyclic Jacobi (Golub and Van Loan, the symmetric Schur rotation); a
   // block orthonormalised one step earlier gives a nearly diagonal G after
   // the first few steps, which takes one or two sweeps
+  const bool inner = own && r < k && c < k;
   for (int sweep = 0; sweep < 64; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int p = 0; p < k; ++p)
-      for (int q = 0; q < k; ++q) {
-        const double x = G[p][q] * G[p][q];
-        tot += x;
-        if (p != q) off += x;
-      }
+    const double x = inner ? G[lane] * G[lane] : 0.0;
+    const double tot = wave_sum(x), off = wave_sum(r != c ? x : 0.0);
     if (off <= 1e-30 * tot) break;
     for (int p = 0; p < k - 1; ++p)
       for (int q = p + 1; q < k; ++q) {
-        const double apq = G[p][q];
+        const double apq = G[p * LH + q];
         if (apq == 0.0) continue;
-        const double tau = (G[q][q] - G[p][p]) / (2.0 * apq);
+        const double tau = (G[q * LH + q] - G[p * LH + p]) / (2.0 * apq);
         const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(tau * tau + 1.0));
-        const double c = 1.0 / sqrt(tt * tt + 1.0), s = tt * c;
-        for (int r = 0; r < k; ++r) {
-          const double gp = G[r][p], gq = G[r][q];
-          G[r][p] = c * gp - s * gq;
-          G[r][q] = s * gp + c * gq;
+        const double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
+        // columns p and q of G, then rows p and q, then columns p and q of V
+        double up = 0.0, uq = 0.0;
+        if (own) {
+          up = G[r * LH + p];
+          uq = G[r * LH + q];
         }
-        for (int r = 0; r < k; ++r) {
-          const double gp = G[p][r], gq = G[q][r];
-          G[p][r] = c * gp - s * gq;
-          G[q][r] = s * gp + c * gq;
+        wave_sync_lds();
+        if (own && r < k && (c == p || c == q)) G[lane] = c == p ? cs * up - sn * uq : sn * up + cs * uq;
+        wave_sync_lds();
+        if (own) {
+          up = G[p * LH + c];
+          uq = G[q * LH + c];
         }
-        for (int r = 0; r < k; ++r) {
-          const double vp = V[r][p], vq = V[r][q];
-          V[r][p] = c * vp - s * vq;
-          V[r][q] = s * vp + c * vq;
+        wave_sync_lds();
+        if (own && c < k && (r == p || r == q)) G[lane] = r == p ? cs * up - sn * uq : sn * up + cs * uq;
+        if (own) {
+          up = V[r * LH + p];
+          uq = V[r * LH + q];
         }
+        wave_sync_lds();
+        if (own && r < k && (c == p || c == q)) V[lane] = c == p ? cs * up - sn * uq : sn * up + cs * uq;
+        wave_sync_lds();
       }
   }
+  if (lane != 0) return;
   // descending order of eigenvalue, ties to the lower index
   int order[LH];
   bool used[LH];
@@ -134,20 +162,20 @@ __global__ __launch_bounds__(64) void ortho_finish_kernel(const double* __restri
   for (int j = 0; j < k; ++j) {
     int best = -1;
     for (int i = 0; i < k; ++i)
-      if (!used[i] && (best < 0 || G[i][i] > G[best][best])) best = i;
+      if (!used[i] && (best < 0 || G[i * LH + i] > G[best * LH + best])) best = i;
     used[best] = true;
     order[j] = best;
-    if (j == 0) lmax = fmax(G[best][best], 0.0);
+    if (j == 0) lmax = fmax(G[best * LH + best], 0.0);
   }
   for (int a = 0; a < LH; ++a)
     for (int j = 0; j < LH; ++j) W[a * LH + j] = 0.0;
   for (int j = 0; j < k; ++j) {
     const int src = order[j];
-    const double lam = fmax(G[src][src], 0.0);
+    const double lam = fmax(G[src * LH + src], 0.0);
     const double sv = sqrt(lam);
     if (sigma_out) sigma_out[j] = sv;
     if (!(lmax > 0.0 && lam > 1e-12 * lmax)) continue;  // sigma <= 1e-6 sigma_max: 0
-    for (int a = 0; a < k; ++a) W[a * LH + j] = V[a][src] / sv;
+    for (int a = 0; a < k; ++a) W[a * LH + j] = V[a * LH + src] / sv;
   }
 }
 
@@ -285,7 +313,7 @@ static int ortho_typed(const EmbedIO* io, void* zv, bool last, hipStream_t s) {
   const int agrid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kOrthoBlock - 1) / kOrthoBlock, 8192));
   hipLaunchKernelGGL((ortho_gram_kernel<S, LH>), dim3(oa->grid), dim3(kOrthoBlock), 0, s, z, io->deg, n,
                      oa->partials);
-  hipLaunchKernelGGL(ortho_finish_kernel<LH>, dim3(1), dim3(64), 0, s, oa->partials, oa->grid, oa->k, oa->W,
+  hipLaunchKernelGGL(ortho_finish_kernel<LH>, dim3(1), dim3(kOrthoFinish), 0, s, oa->partials, oa->grid, oa->k, oa->W,
                      last ? oa->sigma_out : nullptr);
   hipLaunchKernelGGL((ortho_apply_kernel<S, LH>), dim3(agrid), dim3(kOrthoBlock), 0, s, z, n, oa->W);
   if (last) {
