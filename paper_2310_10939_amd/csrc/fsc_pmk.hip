@@ -268,18 +268,27 @@ __global__ __launch_bounds__(kOrthoBlock) void ortho_sign_partial_kernel(const S
 }
 
 // One block: W = diag(sign_j), sign_j = -1 when the entry at column j's
-// largest-magnitude row is negative.
+// largest-magnitude row is negative.  Column j's block maxima are merged by
+// the kOrthoFinish / LH threads of its group (merging is order-free: the
+// larger magnitude, then the lower row), then across the group.
 template <typename S, int LH>
-__global__ __launch_bounds__(64) void ortho_sign_finish_kernel(const S* __restrict__ z,
-                                                               const double* __restrict__ pmax,
-                                                               const int64_t* __restrict__ prow, int grid,
-                                                               double* __restrict__ W) {
+__global__ __launch_bounds__(kOrthoFinish) void ortho_sign_finish_kernel(const S* __restrict__ z,
+                                                                         const double* __restrict__ pmax,
+                                                                         const int64_t* __restrict__ prow, int grid,
+                                                                         double* __restrict__ W) {
   using A = typename elem<S>::acc;
-  if (threadIdx.x >= LH) return;
-  const int j = threadIdx.x;
+  constexpr int PER = kOrthoFinish / LH;  // threads per column
+  __shared__ double sm[kOrthoFinish];
+  __shared__ int64_t sr[kOrthoFinish];
+  const int j = threadIdx.x / PER, i = threadIdx.x % PER;
   double bm = -1.0;
   int64_t br = -1;
-  for (int b = 0; b < grid; ++b) absmax_merge(bm, br, pmax[(int64_t)b * LH + j], prow[(int64_t)b * LH + j]);
+  for (int b = i; b < grid; b += PER) absmax_merge(bm, br, pmax[(int64_t)b * LH + j], prow[(int64_t)b * LH + j]);
+  sm[threadIdx.x] = bm;
+  sr[threadIdx.x] = br;
+  __syncthreads();
+  if (i != 0) return;
+  for (int t = 1; t < PER; ++t) absmax_merge(bm, br, sm[threadIdx.x + t], sr[threadIdx.x + t]);
   double sg = 1.0;
   if (br >= 0) {
     A p[LH];
@@ -319,7 +328,7 @@ static int ortho_typed(const EmbedIO* io, void* zv, bool last, hipStream_t s) {
   if (last) {
     hipLaunchKernelGGL((ortho_sign_partial_kernel<S, LH>), dim3(oa->grid), dim3(kOrthoBlock), 0, s, z, io->deg, n,
                        oa->pmax, oa->prow);
-    hipLaunchKernelGGL((ortho_sign_finish_kernel<S, LH>), dim3(1), dim3(64), 0, s, z, oa->pmax, oa->prow, oa->grid,
+    hipLaunchKernelGGL((ortho_sign_finish_kernel<S, LH>), dim3(1), dim3(kOrthoFinish), 0, s, z, oa->pmax, oa->prow, oa->grid,
                        oa->W);
     hipLaunchKernelGGL((ortho_apply_kernel<S, LH>), dim3(agrid), dim3(kOrthoBlock), 0, s, z, n, oa->W);
   }
