@@ -133,26 +133,31 @@ __device__ __forceinline__ void run_tile(const Op& op, const BGraph& g, int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Degree pass over all graphs' tiles
+// Degree pass over all graphs' rows: one thread per row sums its weights in
+// CSR order in FP64 (a unit-weight graph counts its entries), and writes d,
+// 1/(2d), d^{-1/2} and the k-means eligibility d > 0.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void bdegree_kernel(const BGraph* __restrict__ gs,
-                                                         const int64_t* __restrict__ toff, int ng) {
-  __shared__ double wred[kBlock / FSC_WAVE][8];
-  const int64_t total = toff[ng];
-  int64_t T = blockIdx.x;
-  if (T >= total) return;
-  int p = seg_find(toff, ng, T);
-  for (; T < total; T += gridDim.x) {
-    while (toff[p + 1] <= T) ++p;
+                                                         const int64_t* __restrict__ noff, int ng) {
+  const int64_t total = noff[ng];
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= total) return;
+  int p = seg_find(noff, ng, i);
+  for (; i < total; i += (int64_t)gridDim.x * kBlock) {
+    while (noff[p + 1] <= i) ++p;
     const BGraph& g = gs[p];
-    const int32_t b = (int32_t)(T - toff[p]);
-    if (g.val) {
-      DegreeOp<float, float> op{g.val, g.deg, g.hinv, g.isq, g.elig};
-      run_tile<8>(op, g, b, wred);
+    const int32_t r = (int32_t)(i - noff[p]);
+    const int64_t a = g.row_ptr[r], e = g.row_ptr[r + 1];
+    double d = 0.0;
+    if (g.val == nullptr) {
+      d = (double)(e - a);
     } else {
-      DegreeOp<void, float> op{nullptr, g.deg, g.hinv, g.isq, g.elig};
-      run_tile<8>(op, g, b, wred);
+      for (int64_t j = a; j < e; ++j) d += (double)g.val[j];
     }
+    g.deg[r] = d;
+    g.hinv[r] = d > 0.0 ? (float)(0.5 / d) : 0.f;
+    g.isq[r] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    g.elig[r] = d > 0.0 ? 1 : 0;
   }
 }
 
@@ -315,7 +320,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   auto add = [&](size_t b) { bytes += align_up(b); };
   add(sizeof(BGraph) * (G + 1));
   add(sizeof(KmJob) * (G + 1));
-  add(8 * (G + 1) * 3);              // boff, noff, toff
+  add(8 * (G + 1) * 2);              // boff, noff
   add(8 * (G + 33) * 4);             // toffs: per width class and XCD, a list with a leading 0
   add(4 * (G + 1) * 4);              // order per class
   add(4 * (G + 1) * 2);              // pp_off, ll_off
@@ -361,7 +366,6 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   KmJob* d_jobs = a.take<KmJob>(G + 1);
   int64_t* d_boff = a.take<int64_t>(G + 1);
   int64_t* d_noff = a.take<int64_t>(G + 1);
-  int64_t* d_toff = a.take<int64_t>(G + 1);
   int64_t* d_toffs = a.take<int64_t>((size_t)G + 33);
   int32_t* d_order = a.take<int32_t>(G + 1);
   int32_t* d_ppoff = a.take<int32_t>(G + 1);
@@ -369,7 +373,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
 
   std::vector<BGraph> bg(G);
   std::vector<KmJob> jobs(G);
-  std::vector<int64_t> boff(G + 1, 0), noff(G + 1, 0), toff(G + 1, 0);
+  std::vector<int64_t> boff(G + 1, 0), noff(G + 1, 0);
   std::vector<int32_t> ppoff(G + 1, 0), lloff(G + 1, 0);
   std::vector<int64_t> eoff(G + 1, 0);
   int tmax = 0, kmax = 0;
@@ -422,7 +426,6 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     J.k1 = b.k1;
     boff[g + 1] = boff[g] + x.nb;
     noff[g + 1] = noff[g] + x.n;
-    toff[g + 1] = toff[g] + x.nb;
     ppoff[g + 1] = ppoff[g] + J.nblk_pp;
     lloff[g + 1] = lloff[g] + J.nblk_ll;
     tmax = std::max(tmax, x.t);
@@ -481,7 +484,7 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
     const size_t G1 = (size_t)G + 1;
     const Up ups[] = {{d_graphs, bg.data(), sizeof(BGraph) * G},    {d_jobs, jobs.data(), sizeof(KmJob) * G},
                       {d_boff, boff.data(), 8 * G1},                {d_noff, noff.data(), 8 * G1},
-                      {d_toffs, toffs.data(), 8 * toffs.size()},    {d_toff, toff.data(), 8 * G1},
+                      {d_toffs, toffs.data(), 8 * toffs.size()},
                       {d_order, order.data(), 4 * order.size()},    {d_ppoff, ppoff.data(), 4 * G1},
                       {d_lloff, lloff.data(), 4 * G1}};
     for (const Up& u : ups)
@@ -495,7 +498,8 @@ int batched_run(Context* ctx, int G, const fsc_csr* graphs, const int32_t* ks, c
   auto launches = [&](hipStream_t s) -> int {
     hipLaunchKernelGGL(bplan_kernel, dim3(grid_for((boff[G] + 255) / 256, 8192)), dim3(256), 0, s, d_graphs, d_boff,
                        G);
-    hipLaunchKernelGGL(bdegree_kernel, dim3(grid_for(toff[G], cap)), dim3(kBlock), 0, s, d_graphs, d_toff, G);
+    hipLaunchKernelGGL(bdegree_kernel, dim3(grid_for((noff[G] + kBlock - 1) / kBlock, 8192)), dim3(kBlock), 0, s,
+                       d_graphs, d_noff, G);
     hipLaunchKernelGGL(bstart_kernel, dim3(grid_for((noff[G] + kBlock - 1) / kBlock, 8192)), dim3(kBlock), 0, s,
                        d_graphs, d_noff, G);
     for (int i = 0; i < tmax; ++i) {
