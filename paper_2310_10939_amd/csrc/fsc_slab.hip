@@ -6,9 +6,8 @@
 //   slab_scan_kernel   exclusive scans of those over the tiles;
 //   slab_build_kernel  per tile: segment lengths per (row, slab), rows sorted
 //                      by length per slab (counting sort in LDS), diagonal
-//                      starts, the scatter of the nonzeros into slab order
-//                      (assembled in LDS, written out coalesced), and the
-//                      long-row chunks.
+//                      starts, the scatter of the nonzeros into slab order,
+//                      and the long-row chunks.
 // The wave form replaces the last kernel by slab_wave_build_kernel (no sort:
 // each 64-row group's nonzeros slab by slab, row by row).
 // The layout is a function of the CSR alone: rows are sorted stably, and a
@@ -190,65 +189,72 @@ template <> struct quad_w<bf16_t> {
 
 constexpr int kBuild = 1024;  // threads of the build kernel: one per row of a tile
 constexpr int kBuildU = 8;    // nonzeros of a row loaded at once
-constexpr int kStageWords = 12288;  // 48 KiB of LDS staging: column indices, then weights when loaded
+constexpr int kBuildQ = 4;    // quads of a row whose loads are issued together
 
-template <typename W, typename CI>
-__global__ __launch_bounds__(kBuild) void slab_build_kernel(
+// NT threads, one per row of a tile of at most NT rows.  Tiles of 512 rows
+// take NT = 512, whose 66 KB of LDS let two blocks share a CU.
+template <typename W, typename CI, int NT>
+__global__ __launch_bounds__(NT) void slab_build_kernel(
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const W* __restrict__ val, int32_t n,
     int32_t rows, int32_t S, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
     const int32_t* __restrict__ coff, CI* __restrict__ scol, W* __restrict__ sval, uint16_t* __restrict__ sperm,
     int32_t* __restrict__ sbase, int32_t* __restrict__ smax, int64_t* __restrict__ sreg,
     LongChunk* __restrict__ chunks, uint8_t* __restrict__ tunit, DegreeOut dout, int64_t nnz, int aligned) {
-  __shared__ uint16_t cnt[kSlabMax * kSlabRows];   // segment length, later the scatter cursor
-  __shared__ uint16_t spos[kSlabMax * kSlabRows];  // sorted position of each row per slab
-  __shared__ int32_t hist[kSlabMax * (kSlabLong + 1)];  // per slab: rows of each length, then its cursor
+  __shared__ uint16_t cnt[kSlabMax * NT];   // segment length, later the scatter cursor
+  __shared__ uint16_t spos[kSlabMax * NT];  // sorted position of each row per slab
+  __shared__ uint16_t hist[NT / FSC_WAVE * (kSlabLong + 1)];  // per wave: rows of each length, then its cursor
   __shared__ int32_t baseL[kSlabMax * (kSlabLong + 1)];
   __shared__ int32_t totL[kSlabMax];
   __shared__ int64_t regL[kSlabMax + 1];
-  __shared__ int32_t scan32[kBuild / FSC_WAVE];
-  using WS = typename std::conditional<std::is_void<W>::value, char, W>::type;
-  __shared__ int32_t stage[kStageWords];           // staging of a group of regions
+  __shared__ int32_t scan32[NT / FSC_WAVE];
   __shared__ int tile_unit;
   const int32_t T = blockIdx.x;
   const int32_t r0 = T * rows;
   const int32_t R = min(rows, n - r0);
   const int last = nslab - 1;
-  const int rl = threadIdx.x;  // this thread's row (rows <= kSlabRows == kBuild)
+  const int rl = threadIdx.x;  // this thread's row (rows <= NT)
   int64_t a = 0, b = 0;
   if (rl < R) {
     a = row_ptr[r0 + rl];
     b = row_ptr[r0 + rl + 1];
   }
   const bool shortrow = rl < R && b - a <= kSlabLong;
-  for (int i = threadIdx.x; i < nslab * R; i += kBuild) cnt[i] = 0;
+  for (int i = threadIdx.x; i < nslab * R; i += NT) cnt[i] = 0;
   __syncthreads();
-  // segment length of every short row in every slab, and whether every
-  // weight of the tile's short rows is exactly 1
-  // (and the row's degree: its weights are read here anyway)
-  // the row's nonzeros by aligned quads (one 16-byte load per quad where the
-  // arrays allow it), in CSR order
+  // A short row's nonzeros in CSR order, kBuildQ aligned quads at a time
+  // (one 16-byte load per quad where the arrays allow it): its segment
+  // length in every slab, its degree (its weights are read here anyway), and
+  // whether every weight of the tile's short rows is exactly 1.
   int unit = 1;
   if (shortrow) {
     double dsum = 0.0;
-    for (int64_t j0 = a & ~(int64_t)3; j0 < b; j0 += 4) {
-      const bool vec = aligned && j0 + 4 <= nnz;
-      int32_t c[4];
-      float w[4];
-      quad_cols(col, j0, a, b, vec, c);
-      quad_w<W>::get(val, j0, a, b, vec, w);
+    for (int64_t g0 = a & ~(int64_t)3; g0 < b; g0 += 4 * kBuildQ) {
+      int32_t c[kBuildQ][4];
+      float w[kBuildQ][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (j0 + u < a || j0 + u >= b) continue;
-        if (w[u] != 1.0f) unit = 0;
-        dsum += (double)w[u];
-        cnt[slab_of(c[u], S, last) * R + rl] += 1;
+      for (int q = 0; q < kBuildQ; ++q) {
+        const int64_t j0 = g0 + 4 * q;
+        const bool vec = aligned && j0 + 4 <= nnz;
+        quad_cols(col, j0, a, b, vec, c[q]);
+        quad_w<W>::get(val, j0, a, b, vec, w[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < kBuildQ; ++q) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t j = g0 + 4 * q + u;
+          if (j < a || j >= b) continue;
+          if (w[q][u] != 1.0f) unit = 0;
+          dsum += (double)w[q][u];
+          cnt[slab_of(c[q][u], S, last) * R + rl] += 1;
+        }
       }
     }
     write_degree(dout, r0 + rl, dsum);
   }
   {
     int32_t nonunit;
-    block_scan_inclusive<kBuild, int32_t>(unit ? 0 : 1, scan32, &nonunit);
+    block_scan_inclusive<NT, int32_t>(unit ? 0 : 1, scan32, &nonunit);
     if (threadIdx.x == 0) {
       tile_unit = nonunit == 0;
       tunit[T] = nonunit == 0 ? 1 : 0;  // such a tile skips the weight stream, so its weights are not copied
@@ -256,26 +262,29 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   }
   __syncthreads();
   // Rows by decreasing segment length, in row order within a length (a
-  // stable counting sort), one wave per slab: wave p counts its slab's rows
-  // of every length, turns the counts into the start of each length in the
-  // sorted order (the number of rows longer than L, which is also the height
-  // of diagonal L) and the diagonal starts, and places the rows 64 at a time.
-  // Only the wave touches its slab's arrays, and a wave's LDS accesses take
-  // effect in program order, so no block barrier is needed until all slabs
-  // are done.
+  // stable counting sort), one wave per slab: the wave counts its slab's
+  // rows of every length, turns the counts into the start of each length in
+  // the sorted order (the number of rows longer than L, which is also the
+  // height of diagonal L) and the diagonal starts, and places the rows 64 at
+  // a time.  In a group of 64 rows, the lanes that share a lane's length
+  // come from one ballot per bit of the lengths (a lane keeps the lanes that
+  // agree with it on every bit); the first lane of each length then speaks
+  // for them all, so neither the count nor the placement loops over the
+  // lengths or needs an atomic.  Only the wave touches its slab's arrays and
+  // its own histogram, and a wave's LDS accesses take effect in program
+  // order, so no block barrier is needed until all slabs are done.
   {
     const int wave = threadIdx.x / FSC_WAVE, lane = threadIdx.x % FSC_WAVE;
     constexpr int LPL = (kSlabLong + 1 + FSC_WAVE - 1) / FSC_WAVE;  // lengths per lane
-    for (int p = wave; p < nslab; p += kBuild / FSC_WAVE) {
-      int32_t* h = hist + p * (kSlabLong + 1);
+    const uint64_t lower = ((uint64_t)1 << lane) - 1;
+    uint16_t* h = hist + wave * (kSlabLong + 1);
+    for (int p = wave; p < nslab; p += NT / FSC_WAVE) {
       int32_t* bl = baseL + p * (kSlabLong + 1);
       const uint16_t* cp = cnt + p * R;
       for (int L = lane; L <= kSlabLong; L += FSC_WAVE) h[L] = 0;
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       int mx = 0, sum = 0;
       for (int r = lane; r < R; r += FSC_WAVE) {
         const int L = cp[r];
-        atomicAdd(&h[L], 1);
         mx = max(mx, L);
         sum += L;
       }
@@ -285,7 +294,26 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
         sum += __shfl_xor(sum, o, FSC_WAVE);
       }
       const int32_t maxlen = mx;
+      int nbits = 0;
+      while ((1 << nbits) <= maxlen) ++nbits;
+      auto same_length = [nbits](int L, bool ok) {
+        uint64_t m = __ballot(ok);
+        for (int bit = 0; bit < nbits; ++bit) {
+          const bool set = (L >> bit) & 1;
+          const uint64_t on = __ballot(set);
+          m &= set ? on : ~on;
+        }
+        return m;
+      };
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      for (int r0w = 0; r0w < R; r0w += FSC_WAVE) {
+        const int r = r0w + lane;
+        const bool ok = r < R;
+        const int L = ok ? (int)cp[r] : 0;
+        const uint64_t m = same_length(L, ok);
+        if (ok && (m & lower) == 0) h[L] = (uint16_t)(h[L] + __popcll(m));
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
       // start[L] = rows longer than L: a suffix sum over the lengths, lane l
       // holding lengths [l * LPL, (l + 1) * LPL)
       int32_t hv[LPL], tl = 0;
@@ -345,31 +373,26 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
 #pragma unroll
       for (int i = 0; i < LPL; ++i) {
         const int L = lane * LPL + i;
-        if (L <= kSlabLong) h[L] = start[i];
+        if (L <= kSlabLong) h[L] = (uint16_t)start[i];
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       // place rows 64 at a time, ascending: lanes with one length take the
-      // next positions of that length in lane order
+      // next positions of that length in lane order, and the first of them
+      // advances that length's cursor
       for (int r0w = 0; r0w < R; r0w += FSC_WAVE) {
         const int r = r0w + lane;
         const bool ok = r < R;
-        const int L = ok ? (int)cp[r] : -1;
-        uint64_t pending = __ballot(ok);
-        while (pending) {
-          const int leader = __ffsll((unsigned long long)pending) - 1;
-          const int Lx = __shfl(L, leader, FSC_WAVE);
-          const uint64_t m = __ballot(L == Lx);
-          const int32_t base = h[Lx];
-          if (L == Lx) {
-            const int i = base + __popcll(m & (((uint64_t)1 << lane) - 1));
-            sperm[(int64_t)r0 * nslab + (int64_t)p * R + i] = (uint16_t)r;
-            spos[p * R + r] = (uint16_t)i;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          if (lane == leader) h[Lx] = base + __popcll(m);
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          pending &= ~m;
+        const int L = ok ? (int)cp[r] : 0;
+        const uint64_t m = same_length(L, ok);
+        const int32_t base = ok ? h[L] : 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (ok) {
+          const int i = base + __popcll(m & lower);
+          sperm[(int64_t)r0 * nslab + (int64_t)p * R + i] = (uint16_t)r;
+          spos[p * R + r] = (uint16_t)i;
+          if ((m & lower) == 0) h[L] = (uint16_t)(base + __popcll(m));
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
     }
   }
@@ -386,67 +409,42 @@ __global__ __launch_bounds__(kBuild) void slab_build_kernel(
   }
   __syncthreads();
   // Scatter the short rows' nonzeros into slab order (CSR order within a
-  // row's segment), a group of consecutive slabs at a time: the group's
-  // regions are contiguous, so they are assembled in LDS and written out in
-  // one coalesced pass.  A region too large for the buffer is written
-  // directly.  Weights are copied only for a tile that loads them, so a
-  // unit-weight tile stages twice the column indices per pass.
+  // row's segment), each straight to its place: a tile's regions span a few
+  // tens of KB, so the partial lines meet in L2 before they go to memory.
+  // Weights are copied only for a tile that loads them.
   const bool copy_w = !std::is_void<W>::value && !tile_unit;
-  const int32_t cap = (int32_t)(kStageWords * 4 / (sizeof(CI) + (copy_w ? sizeof(WS) : 0)));
-  CI* stcol = reinterpret_cast<CI*>(stage);
-  WS* stval = reinterpret_cast<WS*>(stcol + cap);
-  for (int p0 = 0; p0 < nslab;) {
-    int p1 = p0 + 1;
-    while (p1 < nslab && regL[p1 + 1] - regL[p0] <= cap) ++p1;
-    const int64_t g0 = regL[p0];
-    const int32_t gsz = (int32_t)(regL[p1] - g0);
-    const bool staged = gsz <= cap;
-    for (int i = p0 * R + threadIdx.x; i < p1 * R; i += kBuild) cnt[i] = 0;
-    __syncthreads();
-    if (shortrow) {
-      for (int64_t j0 = a & ~(int64_t)3; j0 < b; j0 += 4) {
-        const bool vec = aligned && j0 + 4 <= nnz;
-        int32_t c[4];
-        quad_cols(col, j0, a, b, vec, c);
+  for (int i = threadIdx.x; i < nslab * R; i += NT) cnt[i] = 0;
+  __syncthreads();
+  if (shortrow) {
+    for (int64_t q0 = a & ~(int64_t)3; q0 < b; q0 += 4 * kBuildQ) {
+      int32_t cq[kBuildQ][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (j0 + u < a || j0 + u >= b) continue;
-          const int p = slab_of(c[u], S, last);
-          if (p < p0 || p >= p1) continue;
-          const int kk = cnt[p * R + rl]++;
-          const int32_t off = (int32_t)(regL[p] - g0) + baseL[p * (kSlabLong + 1) + kk] + spos[p * R + rl];
-          const CI ci = (CI)(sizeof(CI) == 2 ? c[u] - p * S : c[u]);  // slab-local in 16 bits
-          if (staged) stcol[off] = ci;
-          else scol[g0 + off] = ci;
-          if constexpr (!std::is_void<W>::value) {
-            if (copy_w) {
-              const W w = val[j0 + u];
-              if (staged) stval[off] = w;
-              else sval[g0 + off] = w;
-            }
-          }
-        }
+      for (int q = 0; q < kBuildQ; ++q) {
+        const int64_t j0 = q0 + 4 * q;
+        quad_cols(col, j0, a, b, aligned && j0 + 4 <= nnz, cq[q]);
       }
-    }
-    __syncthreads();
-    if (staged) {
-      for (int32_t e = threadIdx.x; e < gsz; e += kBuild) {
-        scol[g0 + e] = stcol[e];
+#pragma unroll
+      for (int e = 0; e < 4 * kBuildQ; ++e) {
+        const int64_t j = q0 + e;
+        if (j < a || j >= b) continue;
+        const int32_t c = cq[e / 4][e % 4];
+        const int p = slab_of(c, S, last);
+        const int kk = cnt[p * R + rl]++;
+        const int64_t off = regL[p] + baseL[p * (kSlabLong + 1) + kk] + spos[p * R + rl];
+        scol[off] = (CI)(sizeof(CI) == 2 ? c - p * S : c);  // slab-local in 16 bits
         if constexpr (!std::is_void<W>::value) {
-          if (copy_w) sval[g0 + e] = stval[e];
+          if (copy_w) sval[off] = val[j];
         }
       }
     }
-    __syncthreads();
-    p0 = p1;
   }
   // long rows: chunks of kSlabChunk nonzeros of the original CSR
   {
     const int32_t isl = rl < R && !shortrow ? 1 : 0;
     const int32_t nc = isl ? (int32_t)((b - a + kSlabChunk - 1) / kSlabChunk) : 0;
     int32_t tl, tc;
-    const int32_t il = block_scan_inclusive<kBuild, int32_t>(isl, scan32, &tl);
-    const int32_t ic = block_scan_inclusive<kBuild, int32_t>(nc, scan32, &tc);
+    const int32_t il = block_scan_inclusive<NT, int32_t>(isl, scan32, &tl);
+    const int32_t ic = block_scan_inclusive<NT, int32_t>(nc, scan32, &tc);
     if (isl) {
       const int32_t lid = loff[T] + il - 1;
       const int32_t first = coff[T] + ic - nc;
@@ -728,10 +726,16 @@ static void launch_build_ci(const fsc_csr* g, SlabPlan& sp, const DegreeOut& dou
     // 16-byte aligned
     const int aligned = reinterpret_cast<uintptr_t>(g->col_idx) % 16 == 0 &&
                         reinterpret_cast<uintptr_t>(g->val) % 16 == 0;
-    hipLaunchKernelGGL((slab_build_kernel<W, CI>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr, g->col_idx,
-                       reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff, sp.loff,
-                       sp.coff, scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax, sp.sreg,
-                       sp.chunks, sp.tunit, dout, (int64_t)g->nnz, aligned);
+    if (sp.rows <= 512)
+      hipLaunchKernelGGL((slab_build_kernel<W, CI, 512>), dim3(sp.ntiles), dim3(512), 0, s, g->row_ptr, g->col_idx,
+                         reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff,
+                         sp.loff, sp.coff, scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax,
+                         sp.sreg, sp.chunks, sp.tunit, dout, (int64_t)g->nnz, aligned);
+    else
+      hipLaunchKernelGGL((slab_build_kernel<W, CI, kBuild>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr,
+                         g->col_idx, reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab,
+                         sp.toff, sp.loff, sp.coff, scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase,
+                         sp.smax, sp.sreg, sp.chunks, sp.tunit, dout, (int64_t)g->nnz, aligned);
   }
 }
 
