@@ -220,6 +220,30 @@ __device__ __forceinline__ double block_sum(double v, double* lds /* BLOCK/64 */
   return s;
 }
 
+// N sums across a block at once: wave sums of each, then one exchange of the
+// wave totals through LDS (one barrier for all N instead of N block_sums).
+// The results are valid in every thread; fixed order, so deterministic.
+template <int BLOCK, int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], double* lds /* N * BLOCK/64 */) {
+  constexpr int W = BLOCK / FSC_WAVE;
+  const int w = threadIdx.x / FSC_WAVE;
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = wave_sum(v[q]);
+  __syncthreads();
+  if ((threadIdx.x & (FSC_WAVE - 1)) == 0)
+#pragma unroll
+    for (int q = 0; q < N; ++q) lds[q * W + w] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) s += lds[q * W + i];
+    v[q] = s;
+  }
+  __syncthreads();
+}
+
 // Inclusive scan across a block of BLOCK threads (wave shuffles, then the
 // wave totals through LDS); fixed order, so deterministic.  Also returns the
 // block total in *total.  `lds` holds BLOCK/64 + 1 values.

@@ -396,7 +396,7 @@ static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta, const SlabAr
     if (stats) {
       // the partials come from the per-XCD form's reduce kernel, else from the step kernel
       const bool reduce = sb && sb->xcd && !std::is_same<A, double>::value;
-      hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kBlock), 0, s, sa, reduce ? sb->rgrid : io->grid);
+      hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kFinish), 0, s, sa, reduce ? sb->rgrid : io->grid);
       if ((rc = check_hip(hipGetLastError(), "stats_finish launch"))) return rc;
     }
     if (io->ortho && (rc = ortho_run(io, zout, step == io->t, s))) return rc;
@@ -477,7 +477,7 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
                        reinterpret_cast<S*>(io->z[0]), sa, stats ? 1 : 0);
     if ((rc = check_hip(hipGetLastError(), "start_block launch"))) return rc;
     if (stats) {
-      hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kBlock), 0, s, sa, grid);
+      hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kFinish), 0, s, sa, grid);
       if ((rc = check_hip(hipGetLastError(), "stats_finish launch"))) return rc;
     }
     if (io->ortho && (rc = ortho_run(io, io->z[0], io->t == 0, s))) return rc;

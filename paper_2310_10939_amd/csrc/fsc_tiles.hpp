@@ -320,25 +320,26 @@ struct StatsArgs {
   int acc_is_double;
 };
 
+constexpr int kFinish = 256;  // threads of the statistics finish
+
 template <int LH>
 __device__ void stats_finish(const StatsArgs& sa, int grid) {
-  __shared__ double red[kBlock / FSC_WAVE];
+  __shared__ double red[2 * LH * (kFinish / FSC_WAVE)];
   __shared__ double tot[2 * LH];
   const int32_t nlong = sa.step > 0 ? sa.meta[1] : 0;
   double v[2 * LH];
 #pragma unroll
   for (int q = 0; q < 2 * LH; ++q) v[q] = 0.0;
-  for (int32_t g = threadIdx.x; g < grid; g += kBlock)
+  for (int32_t g = threadIdx.x; g < grid; g += kFinish)
 #pragma unroll
     for (int q = 0; q < 2 * LH; ++q) v[q] += sa.partials[(int64_t)g * 2 * LH + q];
-  for (int32_t g = threadIdx.x; g < nlong; g += kBlock)
+  for (int32_t g = threadIdx.x; g < nlong; g += kFinish)
 #pragma unroll
     for (int q = 0; q < 2 * LH; ++q) v[q] += sa.lnorm[(int64_t)g * 2 * LH + q];
+  block_sum_n<kFinish, 2 * LH>(v, red);
+  if (threadIdx.x == 0)
 #pragma unroll
-  for (int q = 0; q < 2 * LH; ++q) {
-    const double s = block_sum<kBlock>(v[q], red);
-    if (threadIdx.x == 0) tot[q] = s;
-  }
+    for (int q = 0; q < 2 * LH; ++q) tot[q] = v[q];
   __syncthreads();
   if (threadIdx.x < LH) {
     const int q = threadIdx.x;
@@ -386,7 +387,7 @@ __device__ __forceinline__ void stats_epilogue(const StatsArgs& sa, const double
 // One block: the statistics of a step from the `grid` partials of the kernel
 // that wrote them (in a fixed order, so deterministic).
 template <int LH>
-__global__ __launch_bounds__(kBlock) void stats_finish_kernel(StatsArgs sa, int grid) {
+__global__ __launch_bounds__(kFinish) void stats_finish_kernel(StatsArgs sa, int grid) {
   stats_finish<LH>(sa, grid);
 }
 
