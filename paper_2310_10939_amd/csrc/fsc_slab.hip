@@ -26,7 +26,8 @@ static_assert(kSlabRows == 1024, "one build thread per row of a tile");
 
 // Slab of column c: slabs are S consecutive columns.
 __device__ __forceinline__ int slab_of(int32_t c, int32_t S, int last) {
-  const int p = c < 0 ? 0 : c / S;
+  // S is a power of two in the phase and wave forms: a shift, not a division
+  const int p = c < 0 ? 0 : ((S & (S - 1)) == 0 ? c >> (__ffs(S) - 1) : c / S);
   return p > last ? last : p;
 }
 
@@ -190,20 +191,77 @@ template <> struct quad_w<bf16_t> {
 constexpr int kBuild = 1024;  // threads of the build kernel: one per row of a tile
 constexpr int kBuildU = 8;    // nonzeros of a row loaded at once
 constexpr int kBuildQ = 4;    // quads of a row whose loads are issued together
+constexpr int kGroupQ = 8;    // group form: rounds of 8 nonzeros per row whose loads are issued together
 
-// NT threads, one per row of a tile of at most NT rows.  Tiles of 512 rows
-// take NT = 512, whose 66 KB of LDS let two blocks share a CU.
-template <typename W, typename CI, int NT>
+// Weight j as a float (1 without weights).
+template <typename W> __device__ __forceinline__ float weight_at(const W* v, int64_t j);
+template <> __device__ __forceinline__ float weight_at<void>(const void*, int64_t) { return 1.0f; }
+template <> __device__ __forceinline__ float weight_at<float>(const float* v, int64_t j) { return v[j]; }
+template <> __device__ __forceinline__ float weight_at<bf16_t>(const bf16_t* v, int64_t j) {
+  return bf16_to_f32(v[j].bits);
+}
+
+// The group form's view of a row: eight lanes of a wave take one row, lane g
+// the nonzeros g, g + 8, ... of it, so that each round of a group reads 8
+// consecutive entries.  In a round, the lanes that hold nonzeros of one slab
+// come from one ballot per bit of the slab index, restricted to the group;
+// their rank among those lanes is their order in CSR order.
+struct GroupRow {
+  int64_t a;  // first nonzero
+  int len;    // nonzeros (0 for a long row or a row past the tile)
+  bool shortrow;
+  int mlen;   // the longest of the wave's 8 rows of this round
+};
+
+// Row i * 8 + lane / 8 of the wave's 64, whose bounds [a, b) are held by the
+// lane of that index (the lanes' own rows).
+__device__ __forceinline__ GroupRow group_row(int64_t a, int64_t b, int i, int32_t rg, int32_t R) {
+  const int src = i * 8 + (threadIdx.x % FSC_WAVE) / 8;
+  GroupRow gr;
+  gr.a = __shfl(a, src, FSC_WAVE);
+  const int64_t e = __shfl(b, src, FSC_WAVE);
+  gr.shortrow = rg < R && e - gr.a <= kSlabLong;
+  gr.len = gr.shortrow ? (int)(e - gr.a) : 0;
+  int m = gr.len;
+#pragma unroll
+  for (int o = 8; o < FSC_WAVE; o <<= 1) m = max(m, __shfl_xor(m, o, FSC_WAVE));
+  gr.mlen = m;
+  return gr;
+}
+
+// Lanes of this lane's group whose nonzero (ok) lies in the same slab p.
+__device__ __forceinline__ uint64_t group_match(bool ok, int p, int sbits, uint64_t gmask) {
+  uint64_t m = __ballot(ok) & gmask;
+  for (int bit = 0; bit < sbits; ++bit) {
+    const bool set = (p >> bit) & 1;
+    const uint64_t on = __ballot(set);
+    m &= set ? on : ~on;
+  }
+  return m;
+}
+
+// NT threads; tiles of at most NT rows.  Row form (GROUP false): one thread
+// per row.  Group form (GROUP true, NT = 512): eight lanes per row, so that
+// the reads of the indices and weights are coalesced; the layout is the
+// same.  With NT = 512 the block's 53 KB of LDS let three blocks share a CU.
+template <typename W, typename CI, int NT, bool GROUP>
 __global__ __launch_bounds__(NT) void slab_build_kernel(
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const W* __restrict__ val, int32_t n,
     int32_t rows, int32_t S, int32_t nslab, const int64_t* __restrict__ toff, const int32_t* __restrict__ loff,
     const int32_t* __restrict__ coff, CI* __restrict__ scol, W* __restrict__ sval, uint16_t* __restrict__ sperm,
     int32_t* __restrict__ sbase, int32_t* __restrict__ smax, int64_t* __restrict__ sreg,
     LongChunk* __restrict__ chunks, uint8_t* __restrict__ tunit, DegreeOut dout, int64_t nnz, int aligned) {
-  __shared__ uint16_t cnt[kSlabMax * NT];   // segment length, later the scatter cursor
-  __shared__ uint16_t spos[kSlabMax * NT];  // sorted position of each row per slab
-  __shared__ uint16_t hist[NT / FSC_WAVE * (kSlabLong + 1)];  // per wave: rows of each length, then its cursor
-  __shared__ int32_t baseL[kSlabMax * (kSlabLong + 1)];
+  // Per-slab arrays in LDS have strides of 2 more than their length, so that
+  // one row's (or one length's) entries of different slabs fall in different
+  // banks.
+  constexpr int RS = NT + 2;
+  constexpr int LS = kSlabLong + 2;
+  __shared__ uint16_t cnt[kSlabMax * RS];   // segment length, later the scatter cursor
+  __shared__ uint16_t spos[kSlabMax * RS];  // sorted position of each row per slab
+  // per wave: rows of each length, then its cursor (aligned: the group form
+  // passes floats through it first)
+  __shared__ __align__(16) uint16_t hist[NT / FSC_WAVE * (kSlabLong + 1)];
+  __shared__ int32_t baseL[kSlabMax * LS];
   __shared__ int32_t totL[kSlabMax];
   __shared__ int64_t regL[kSlabMax + 1];
   __shared__ int32_t scan32[NT / FSC_WAVE];
@@ -219,14 +277,75 @@ __global__ __launch_bounds__(NT) void slab_build_kernel(
     b = row_ptr[r0 + rl + 1];
   }
   const bool shortrow = rl < R && b - a <= kSlabLong;
-  for (int i = threadIdx.x; i < nslab * R; i += NT) cnt[i] = 0;
+  for (int i = threadIdx.x; i < nslab * RS; i += NT) cnt[i] = 0;
   __syncthreads();
   // A short row's nonzeros in CSR order, kBuildQ aligned quads at a time
   // (one 16-byte load per quad where the arrays allow it): its segment
   // length in every slab, its degree (its weights are read here anyway), and
   // whether every weight of the tile's short rows is exactly 1.
   int unit = 1;
-  if (shortrow) {
+  const int wave = threadIdx.x / FSC_WAVE, lane = threadIdx.x % FSC_WAVE;
+  const int g = lane & 7;
+  const uint64_t gmask = (uint64_t)0xff << (lane & ~7);
+  const uint64_t lower = ((uint64_t)1 << lane) - 1;
+  int sbits = 0;
+  while ((1 << sbits) <= last) ++sbits;
+  if constexpr (GROUP) {
+    // group form: while every weight of a row so far is exactly 1 its degree
+    // is their count (the same bits as adding them one by one); from its
+    // first other weight on, the group's first lane adds the round's weights
+    // in CSR order, passed through LDS (the histograms' space, free until
+    // the sort)
+    float* wb = reinterpret_cast<float*>(hist) + wave * FSC_WAVE;
+    for (int i = 0; i < FSC_WAVE / 8; ++i) {
+      const int32_t rg = wave * FSC_WAVE + i * 8 + lane / 8;
+      const GroupRow gr = group_row(a, b, i, rg, R);
+      double dsum = 0.0;
+      bool exact = true;  // every weight of the row so far is 1: dsum counts them
+      for (int u0 = 0; u0 < gr.mlen; u0 += 8 * kGroupQ) {
+        int32_t c[kGroupQ];
+        float w[kGroupQ];
+#pragma unroll
+        for (int q = 0; q < kGroupQ; ++q) {
+          const int e = u0 + 8 * q + g;
+          c[q] = e < gr.len ? col[gr.a + e] : 0;
+          w[q] = e < gr.len ? weight_at<W>(val, gr.a + e) : 1.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < kGroupQ; ++q) {
+          const int e = u0 + 8 * q + g;
+          const bool ok = e < gr.len;
+          const int p = slab_of(c[q], S, last);
+          const uint64_t m = group_match(ok, p, sbits, gmask);
+          const bool other = ok && w[q] != 1.0f;
+          if (ok) {
+            if (other) unit = 0;
+            if ((m & lower) == 0) cnt[p * RS + rg] = (uint16_t)(cnt[p * RS + rg] + __popcll(m));
+          }
+          if constexpr (!std::is_void<W>::value) {
+            const int k1 = gr.len - (u0 + 8 * q);  // the row's nonzeros in this round (if below 8)
+            exact = exact && (__ballot(other) & gmask) == 0;
+            if (exact) {
+              if (g == 0 && k1 > 0) dsum += (double)min(k1, 8);
+            } else {
+              wb[lane] = w[q];
+              __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+              if (g == 0) {
+                const float4 x0 = *reinterpret_cast<const float4*>(wb + lane);
+                const float4 x1 = *reinterpret_cast<const float4*>(wb + lane + 4);
+                const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                  if (k < k1) dsum += (double)x[k];
+              }
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
+      }
+      if (g == 0 && gr.shortrow) write_degree(dout, r0 + rg, std::is_void<W>::value ? (double)gr.len : dsum);
+    }
+  } else if (shortrow) {
     double dsum = 0.0;
     for (int64_t g0 = a & ~(int64_t)3; g0 < b; g0 += 4 * kBuildQ) {
       int32_t c[kBuildQ][4];
@@ -246,7 +365,7 @@ __global__ __launch_bounds__(NT) void slab_build_kernel(
           if (j < a || j >= b) continue;
           if (w[q][u] != 1.0f) unit = 0;
           dsum += (double)w[q][u];
-          cnt[slab_of(c[q][u], S, last) * R + rl] += 1;
+          cnt[slab_of(c[q][u], S, last) * RS + rl] += 1;
         }
       }
     }
@@ -274,13 +393,11 @@ __global__ __launch_bounds__(NT) void slab_build_kernel(
   // its own histogram, and a wave's LDS accesses take effect in program
   // order, so no block barrier is needed until all slabs are done.
   {
-    const int wave = threadIdx.x / FSC_WAVE, lane = threadIdx.x % FSC_WAVE;
     constexpr int LPL = (kSlabLong + 1 + FSC_WAVE - 1) / FSC_WAVE;  // lengths per lane
-    const uint64_t lower = ((uint64_t)1 << lane) - 1;
     uint16_t* h = hist + wave * (kSlabLong + 1);
     for (int p = wave; p < nslab; p += NT / FSC_WAVE) {
-      int32_t* bl = baseL + p * (kSlabLong + 1);
-      const uint16_t* cp = cnt + p * R;
+      int32_t* bl = baseL + p * LS;
+      const uint16_t* cp = cnt + p * RS;
       for (int L = lane; L <= kSlabLong; L += FSC_WAVE) h[L] = 0;
       int mx = 0, sum = 0;
       for (int r = lane; r < R; r += FSC_WAVE) {
@@ -389,7 +506,7 @@ __global__ __launch_bounds__(NT) void slab_build_kernel(
         if (ok) {
           const int i = base + __popcll(m & lower);
           sperm[(int64_t)r0 * nslab + (int64_t)p * R + i] = (uint16_t)r;
-          spos[p * R + r] = (uint16_t)i;
+          spos[p * RS + r] = (uint16_t)i;
           if ((m & lower) == 0) h[L] = (uint16_t)(base + __popcll(m));
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -413,9 +530,46 @@ __global__ __launch_bounds__(NT) void slab_build_kernel(
   // tens of KB, so the partial lines meet in L2 before they go to memory.
   // Weights are copied only for a tile that loads them.
   const bool copy_w = !std::is_void<W>::value && !tile_unit;
-  for (int i = threadIdx.x; i < nslab * R; i += NT) cnt[i] = 0;
+  for (int i = threadIdx.x; i < nslab * RS; i += NT) cnt[i] = 0;
   __syncthreads();
-  if (shortrow) {
+  if constexpr (GROUP) {
+    using WS = typename std::conditional<std::is_void<W>::value, char, W>::type;
+    for (int i = 0; i < FSC_WAVE / 8; ++i) {
+      const int32_t rg = wave * FSC_WAVE + i * 8 + lane / 8;
+      const GroupRow gr = group_row(a, b, i, rg, R);
+      for (int u0 = 0; u0 < gr.mlen; u0 += 8 * kGroupQ) {
+        int32_t c[kGroupQ];
+        WS wv[kGroupQ];
+#pragma unroll
+        for (int q = 0; q < kGroupQ; ++q) {
+          const int e = u0 + 8 * q + g;
+          c[q] = e < gr.len ? col[gr.a + e] : 0;
+          if constexpr (!std::is_void<W>::value) {
+            if (copy_w && e < gr.len) wv[q] = val[gr.a + e];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kGroupQ; ++q) {
+          const int e = u0 + 8 * q + g;
+          const bool ok = e < gr.len;
+          const int p = slab_of(c[q], S, last);
+          const uint64_t m = group_match(ok, p, sbits, gmask);
+          const int base = ok ? (int)cnt[p * RS + rg] : 0;
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          if (ok) {
+            const int kk = base + __popcll(m & lower);
+            const int64_t off = regL[p] + baseL[p * LS + kk] + spos[p * RS + rg];
+            scol[off] = (CI)(sizeof(CI) == 2 ? c[q] - p * S : c[q]);  // slab-local in 16 bits
+            if constexpr (!std::is_void<W>::value) {
+              if (copy_w) sval[off] = wv[q];
+            }
+            if ((m & lower) == 0) cnt[p * RS + rg] = (uint16_t)(base + __popcll(m));
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
+      }
+    }
+  } else if (shortrow) {
     for (int64_t q0 = a & ~(int64_t)3; q0 < b; q0 += 4 * kBuildQ) {
       int32_t cq[kBuildQ][4];
 #pragma unroll
@@ -429,8 +583,8 @@ __global__ __launch_bounds__(NT) void slab_build_kernel(
         if (j < a || j >= b) continue;
         const int32_t c = cq[e / 4][e % 4];
         const int p = slab_of(c, S, last);
-        const int kk = cnt[p * R + rl]++;
-        const int64_t off = regL[p] + baseL[p * (kSlabLong + 1) + kk] + spos[p * R + rl];
+        const int kk = cnt[p * RS + rl]++;
+        const int64_t off = regL[p] + baseL[p * LS + kk] + spos[p * RS + rl];
         scol[off] = (CI)(sizeof(CI) == 2 ? c - p * S : c);  // slab-local in 16 bits
         if constexpr (!std::is_void<W>::value) {
           if (copy_w) sval[off] = val[j];
@@ -727,12 +881,12 @@ static void launch_build_ci(const fsc_csr* g, SlabPlan& sp, const DegreeOut& dou
     const int aligned = reinterpret_cast<uintptr_t>(g->col_idx) % 16 == 0 &&
                         reinterpret_cast<uintptr_t>(g->val) % 16 == 0;
     if (sp.rows <= 512)
-      hipLaunchKernelGGL((slab_build_kernel<W, CI, 512>), dim3(sp.ntiles), dim3(512), 0, s, g->row_ptr, g->col_idx,
+      hipLaunchKernelGGL((slab_build_kernel<W, CI, 512, true>), dim3(sp.ntiles), dim3(512), 0, s, g->row_ptr, g->col_idx,
                          reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab, sp.toff,
                          sp.loff, sp.coff, scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase, sp.smax,
                          sp.sreg, sp.chunks, sp.tunit, dout, (int64_t)g->nnz, aligned);
     else
-      hipLaunchKernelGGL((slab_build_kernel<W, CI, kBuild>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr,
+      hipLaunchKernelGGL((slab_build_kernel<W, CI, kBuild, false>), dim3(sp.ntiles), dim3(kBuild), 0, s, g->row_ptr,
                          g->col_idx, reinterpret_cast<const W*>(g->val), (int32_t)g->n, sp.rows, sp.S, sp.nslab,
                          sp.toff, sp.loff, sp.coff, scol, reinterpret_cast<W*>(sp.sval), sp.sperm, sp.sbase,
                          sp.smax, sp.sreg, sp.chunks, sp.tunit, dout, (int64_t)g->nnz, aligned);
