@@ -150,6 +150,34 @@ def test_wave_form_equals_phase_form(gpu_lib, slab, kb, l, wt):
     assert torch.allclose(raa, rab, rtol=1e-10, atol=1e-12)
 
 
+@pytest.mark.parametrize("kb", [4, 64])
+def test_group_build_degrees_in_csr_order(gpu_lib, slab, kb):
+    """The phase form's layout builder reads each row with eight lanes and
+    counts the ones while every weight of a row so far is exactly 1, then
+    sums the remaining weights in CSR order.  Rows here switch between the
+    two at various positions, with weights whose FP64 sum depends on the
+    order (1e8 and 1e-8 among ones); the wave form, whose builder sums each
+    row in one thread, must give the same bits."""
+    g = synth.random_weighted(9000, 60000, seed=61, hubs=4, hub_degree=1500, isolated=9)
+    w = np.ones(g.nnz, dtype=np.float32)
+    j = np.arange(g.nnz)
+    w[j % 13 == 11] = 1e8
+    w[j % 29 == 17] = 1e-8
+    w[j % 31 == 0] = 0.1
+    ip, ix, _ = to_device(g, "none")
+    d = torch.from_numpy(w).cuda()
+    slab(kb, 1)
+    a, sqa, _ = gpu_lib.embed(ip, ix, d, 4, 9, seed=5, traces=True)
+    slab(kb, 4)
+    b, sqb, _ = gpu_lib.embed(ip, ix, d, 4, 9, seed=5, traces=True)
+    say(f"group-form degrees kb={kb}")
+    assert torch.equal(a, b)
+    assert torch.allclose(sqa, sqb, rtol=1e-10, atol=0)
+    E = a.cpu().numpy()
+    want = o.embed(g.n, g.indptr, g.indices, w.astype(np.float64), 4, 9, seed=5)
+    assert col_rel_err(E, want) <= TOL["f32"]
+
+
 def test_full_size_sbm_matches_oracle(gpu_lib):
     """The 1M-vertex SBM (k = 10, in-degree 36, out-degree 4, fp32 unit
     weights, l = 4, t = 30, 30 Lloyd steps) in the benchmark's launch
