@@ -249,7 +249,7 @@ size_t embed_workspace_bytes(const Context* ctx, const fsc_csr* g, int l, int ve
   size_t b = 0;
   b += align_up(n * 8) * 2 + align_up(n * ae) + align_up(n);        // deg, isq, hinv, elig
   b += 2 * align_up(n * LH * se);                                   // z ping-pong
-  b += align_up((size_t)kMaxGrid * 2 * LH * 8);                     // partials
+  b += align_up((size_t)2 * kMaxGrid * 2 * LH * 8);                 // partials (two steps')
   b += align_up((5 * LH + 8) * 8);                                  // state
   b += align_up(nb * 2 * LH * 8);                                   // lnorm
   b += align_up((2 * nb + 1) * std::max<size_t>(LH * ae, 8));       // lpart (FP64 for degrees)
@@ -276,7 +276,7 @@ int embed_bind_workspace(Context* ctx, Arena* a, EmbedIO* io) {
   io->elig = a->take<uint8_t>(n);
   io->z[0] = a->take<char>(n * LH * se);
   io->z[1] = a->take<char>(n * LH * se);
-  io->partials = a->take<double>((size_t)kMaxGrid * 2 * LH);
+  io->partials = a->take<double>((size_t)2 * kMaxGrid * 2 * LH);
   io->state = a->take<double>(5 * LH + 8);
   io->lnorm = a->take<double>(nb * 2 * LH);
   io->lpart = a->take<char>((2 * nb + 1) * std::max<size_t>(LH * ae, 8));
@@ -309,7 +309,7 @@ constexpr int kSlabJ = 1;
 
 template <typename CI, class Op>
 static int launch_slab_ci(const Op& op, const TileArgs& ta, const SlabArgs& sb, const StatsArgs& sa, int grid,
-                          int rgrid, hipStream_t s) {
+                          int rgrid, const PendingFinish& pf, hipStream_t s) {
   if (sb.wave) {
     SlabWaveArgs sw;
     sw.nslab = sb.nslab;
@@ -323,24 +323,25 @@ static int launch_slab_ci(const Op& op, const TileArgs& ta, const SlabArgs& sb, 
     hipLaunchKernelGGL((slab_xcd_kernel<8, CI, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb);
     hipLaunchKernelGGL((slab_reduce_kernel<Op>), dim3(rgrid), dim3(kBlock), 0, s, op, ta, sb, sa);
   } else {
-    hipLaunchKernelGGL((slab_kernel<kSlabU, kSlabJ, CI, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb, sa);
+    hipLaunchKernelGGL((slab_kernel<kSlabU, kSlabJ, CI, Op>), dim3(grid), dim3(kBlock), 0, s, op, ta, sb, sa, pf);
   }
   return check_hip(hipGetLastError(), "slab_kernel launch");
 }
 
 template <class Op>
 static int launch_slab(const Op& op, const TileArgs& ta, const SlabArgs& sb, const StatsArgs& sa, int grid,
-                       int rgrid, hipStream_t s) {
-  return sb.c16 ? launch_slab_ci<uint16_t>(op, ta, sb, sa, grid, rgrid, s)
-                : launch_slab_ci<int32_t>(op, ta, sb, sa, grid, rgrid, s);
+                       int rgrid, const PendingFinish& pf, hipStream_t s) {
+  return sb.c16 ? launch_slab_ci<uint16_t>(op, ta, sb, sa, grid, rgrid, pf, s)
+                : launch_slab_ci<int32_t>(op, ta, sb, sa, grid, rgrid, pf, s);
 }
 
-// One step's launch: the column-slab kernel when the plan has slabs.
+// One step's launch: the column-slab kernel when the plan has slabs (only
+// its phase form takes a pending finish).
 template <class Op>
 static int launch_step(const Op& op, const TileArgs& ta, const SlabArgs* sb, const StatsArgs& sa, int grid,
-                       int unroll, hipStream_t s) {
+                       int unroll, const PendingFinish& pf, hipStream_t s) {
   if constexpr (!std::is_same<typename Op::A, double>::value) {
-    if (sb) return launch_slab(op, ta, *sb, sa, grid, sb->rgrid, s);
+    if (sb) return launch_slab(op, ta, *sb, sa, grid, sb->rgrid, pf, s);
   }
   return launch_tiles(op, ta, sa, grid, unroll, s);
 }
@@ -356,19 +357,42 @@ static int persistent_grid(const Context* ctx, int64_t tiles, int blocks_per_cu)
   return (int)g;
 }
 
+// Whether a step's statistics are finished inside the next step kernel: the
+// phase form of the column-slab kernel, with the statistics on and no scale
+// to apply (without re-normalisation every scale is 1, so the next step does
+// not wait for them).  The partials (and the long rows' statistics) then
+// alternate between two buffers by step parity, so that a step writes its
+// own while the previous step's are being finished.
+static bool fold_finish(const EmbedIO* io, bool stats) {
+  return stats && !io->renorm && !io->ortho && io->slab.enabled && !io->slab.wave && !io->slab.xcd &&
+         io->vec_dtype != FSC_F64;
+}
+
 template <typename S, typename W, int LH>
-static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta, const SlabArgs* sb_in, StatsArgs sa,
-                     hipStream_t s, bool stats) {
+static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta_in, const SlabArgs* sb_in, StatsArgs sa,
+                     hipStream_t s, bool stats, PendingFinish pending) {
   const SlabArgs* sb = sb_in;
   using A = typename elem<S>::acc;
   const fsc_csr* g = io->g;
   const W* sval = reinterpret_cast<const W*>(io->slab.sval);
   const A* scale = reinterpret_cast<const A*>(io->state + 3 * LH);
+  const bool fold = sb && fold_finish(io, stats);
+  TileArgs ta = ta_in;
+  int rc;
   for (int step = 1; step <= io->t; ++step) {
     const S* zin = reinterpret_cast<const S*>(io->z[(step - 1) & 1]);
     S* zout = reinterpret_cast<S*>(io->z[step & 1]);
     sa.step = step;
-    int rc;
+    int grid = io->grid;
+    PendingFinish pf;
+    pf.grid = 0;
+    if (fold) {
+      sa.partials = io->partials + (size_t)(step & 1) * kMaxGrid * 2 * LH;
+      ta.lnorm = io->slab.lnorm + (size_t)(step & 1) * io->slab.max_long * 2 * LH;
+      sa.lnorm = ta.lnorm;
+      if (grid <= sb->ntiles) ++grid;  // a block for the finish
+      pf = pending;
+    }
     auto* ev = timing_start(ctx, s);
     if (stats) {
       StepOp<S, W, LH, true> op;
@@ -378,8 +402,8 @@ static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta, const SlabAr
       op.zout = zout;
       op.hinv = reinterpret_cast<const A*>(io->hinv);
       op.deg = io->deg;
-      op.scale = scale;
-      rc = launch_step(op, ta, sb, sa, io->grid, ctx->tune.unroll, s);
+      op.scale = fold ? nullptr : scale;  // folded: every scale is 1
+      rc = launch_step(op, ta, sb, sa, grid, ctx->tune.unroll, pf, s);
     } else {
       StepOp<S, W, LH, false> op;
       op.val = reinterpret_cast<const W*>(g->val);
@@ -389,17 +413,24 @@ static int run_steps(Context* ctx, EmbedIO* io, const TileArgs& ta, const SlabAr
       op.hinv = reinterpret_cast<const A*>(io->hinv);
       op.deg = io->deg;
       op.scale = nullptr;
-      rc = launch_step(op, ta, sb, sa, io->grid, ctx->tune.unroll, s);
+      rc = launch_step(op, ta, sb, sa, grid, ctx->tune.unroll, pf, s);
     }
     timing_stop(ev, s);
     if (rc) return rc;
-    if (stats) {
+    if (fold) {
+      pending.sa = sa;
+      pending.grid = grid;
+    } else if (stats) {
       // the partials come from the per-XCD form's reduce kernel, else from the step kernel
       const bool reduce = sb && sb->xcd && !std::is_same<A, double>::value;
       hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kFinish), 0, s, sa, reduce ? sb->rgrid : io->grid);
       if ((rc = check_hip(hipGetLastError(), "stats_finish launch"))) return rc;
     }
     if (io->ortho && (rc = ortho_run(io, zout, step == io->t, s))) return rc;
+  }
+  if (pending.grid > 0) {  // the last step's statistics (or the start block's when t = 0)
+    hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kFinish), 0, s, pending.sa, pending.grid);
+    if ((rc = check_hip(hipGetLastError(), "stats_finish launch"))) return rc;
   }
   io->zt = io->z[io->t & 1];
   return FSC_OK;
@@ -469,6 +500,8 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
     if ((rc = launch_tiles(op, ta, sa, io->grid, 8, s))) return rc;
   }
   // start block (and the statistics of X0)
+  PendingFinish pending;
+  pending.grid = 0;
   {
     const uint64_t seed = io->seed;
     const int grid = persistent_grid(ctx, ((int64_t)n + 255) / 256, 8);
@@ -476,13 +509,16 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
                        (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), io->x0, io->isq, io->deg,
                        reinterpret_cast<S*>(io->z[0]), sa, stats ? 1 : 0);
     if ((rc = check_hip(hipGetLastError(), "start_block launch"))) return rc;
-    if (stats) {
+    if (slab_steps && fold_finish(io, stats)) {
+      pending.sa = sa;  // finished inside the first step kernel
+      pending.grid = grid;
+    } else if (stats) {
       hipLaunchKernelGGL((stats_finish_kernel<LH>), dim3(1), dim3(kFinish), 0, s, sa, grid);
       if ((rc = check_hip(hipGetLastError(), "stats_finish launch"))) return rc;
     }
     if (io->ortho && (rc = ortho_run(io, io->z[0], io->t == 0, s))) return rc;
   }
-  if (!slab_steps) return run_steps<S, W, LH>(ctx, io, ta, nullptr, sa, s, stats);
+  if (!slab_steps) return run_steps<S, W, LH>(ctx, io, ta, nullptr, sa, s, stats, pending);
   const SlabPlan& sp = io->slab;
   TileArgs ts = ta;
   ts.nb = 0;
@@ -516,7 +552,7 @@ static int run_embed_typed(Context* ctx, EmbedIO* io, hipStream_t s) {
   io->grid = sp.wave  ? persistent_grid(ctx, ((int64_t)n + 4 * FSC_WAVE - 1) / (4 * FSC_WAVE), ctx->tune.slab_wave_bpc)
              : sp.xcd ? persistent_grid(ctx, (int64_t)sp.ntiles * sp.nslab, ctx->tune.slab_xcd_bpc)
                       : persistent_grid(ctx, sp.ntiles, ctx->tune.slab_bpc);
-  return run_steps<S, W, LH>(ctx, io, ts, &sb, ss, s, stats);
+  return run_steps<S, W, LH>(ctx, io, ts, &sb, ss, s, stats, pending);
 }
 
 template <typename S, typename W>

@@ -817,7 +817,7 @@ size_t slab_workspace_bytes(const Context* ctx, const fsc_csr* g, int LH, int ve
   }
   b += align_up(nt * 8) + align_up((nt + 1) * 8) + 4 * align_up((nt + 1) * 4);
   b += align_up(mc * sizeof(LongChunk)) + align_up(16);
-  b += align_up(ml * 2 * LH * 8) + align_up(mc * LH * 4) + align_up(ml * 4);
+  b += align_up(2 * ml * 2 * LH * 8) + align_up(mc * LH * 4) + align_up(ml * 4);  // lnorm: two steps'
   if (xcd) b += align_up((size_t)nslab * ((n + 63) / 64 * 64) * LH * 4);  // partial sums (float)
   b += align_up(nt);                                     // unit-weight flags
   b += 24 * 256;  // alignment slack
@@ -858,7 +858,7 @@ int slab_bind(Context* ctx, Arena* a, EmbedIO* io) {
   sp.coff = a->take<int32_t>(nt + 1);
   sp.chunks = a->take<LongChunk>(sp.max_chunks);
   sp.meta = a->take<int32_t>(4);
-  sp.lnorm = a->take<double>(sp.max_long * 2 * io->LH);
+  sp.lnorm = a->take<double>(2 * sp.max_long * 2 * io->LH);  // two steps' (the finish may lag a step)
   sp.lpart = a->take<float>(sp.max_chunks * io->LH);
   sp.lcount = a->take<int32_t>(sp.max_long);
   sp.tunit = a->take<uint8_t>(nt);

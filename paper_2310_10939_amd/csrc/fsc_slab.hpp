@@ -128,7 +128,8 @@ __device__ __forceinline__ void slab_region(const Op& op, const SlabArgs& sb, in
 // Phase form: each block takes whole tiles and walks the slabs in order, so
 // at any time the blocks gather from about one slab.
 template <int kU, int J, typename CI, class Op>
-__global__ __launch_bounds__(kBlock, 8) void slab_kernel(Op op_in, TileArgs ta, SlabArgs sb, StatsArgs sa) {
+__global__ __launch_bounds__(kBlock, 8) void slab_kernel(Op op_in, TileArgs ta, SlabArgs sb, StatsArgs sa,
+                                                      PendingFinish pf) {
   constexpr int LH = Op::LH;
   using A = typename Op::A;
   __shared__ A acc[kSlabRows * LH];
@@ -136,6 +137,11 @@ __global__ __launch_bounds__(kBlock, 8) void slab_kernel(Op op_in, TileArgs ta, 
   __shared__ double blk[2 * LH];  // this block's statistics so far (thread 0 adds)
   Op op = op_in;
   op.init();
+  // the previous step's statistics, finished by the last block (the host
+  // adds a block to the grid when every block has a tile)
+  if constexpr (Op::STATS) {
+    if (pf.grid > 0 && blockIdx.x == gridDim.x - 1) stats_finish_lean<LH>(pf.sa, pf.grid);
+  }
   if (threadIdx.x < 2 * LH) blk[threadIdx.x] = 0.0;
   const int32_t n = ta.n;
   for (int32_t T = blockIdx.x; T < sb.ntiles; T += gridDim.x) {

@@ -322,6 +322,11 @@ struct StatsArgs {
 
 constexpr int kFinish = 256;  // threads of the statistics finish
 
+// The column statistics of a step from their block sums tot[0..2LH): the
+// squared norms, the Rayleigh quotients of the previous step, the scales.
+template <int LH>
+__device__ void stats_apply(const StatsArgs& sa, const double* tot);
+
 template <int LH>
 __device__ void stats_finish(const StatsArgs& sa, int grid) {
   __shared__ double red[2 * LH * (kFinish / FSC_WAVE)];
@@ -341,6 +346,40 @@ __device__ void stats_finish(const StatsArgs& sa, int grid) {
 #pragma unroll
     for (int q = 0; q < 2 * LH; ++q) tot[q] = v[q];
   __syncthreads();
+  stats_apply<LH>(sa, tot);
+}
+
+// The same finish by one block of a later kernel (a block that has no other
+// work there): one sum at a time, so that it adds few registers to that
+// kernel.  Each sum is formed as above (per thread in the same order, then
+// the wave sums, then the wave totals in order), so the bits are the same.
+template <int LH>
+__device__ void stats_finish_lean(const StatsArgs& sa, int grid) {
+  static_assert(kFinish == kBlock, "the finishing block has the finish's width");
+  __shared__ double red[kBlock / FSC_WAVE];
+  __shared__ double tot[2 * LH];
+  const int32_t nlong = sa.step > 0 ? sa.meta[1] : 0;
+#pragma unroll 1
+  for (int q = 0; q < 2 * LH; ++q) {
+    double v = 0.0;
+    for (int32_t g = threadIdx.x; g < grid; g += kBlock) v += sa.partials[(int64_t)g * 2 * LH + q];
+    for (int32_t g = threadIdx.x; g < nlong; g += kBlock) v += sa.lnorm[(int64_t)g * 2 * LH + q];
+    const double t = block_sum<kBlock>(v, red);
+    if (threadIdx.x == 0) tot[q] = t;
+  }
+  __syncthreads();
+  stats_apply<LH>(sa, tot);
+}
+
+// A step's statistics left to be finished inside the next step kernel
+// (grid = 0: none): its partials come from `grid` blocks.
+struct PendingFinish {
+  StatsArgs sa;
+  int grid;
+};
+
+template <int LH>
+__device__ void stats_apply(const StatsArgs& sa, const double* tot) {
   if (threadIdx.x < LH) {
     const int q = threadIdx.x;
     double* prev_sq = sa.state;
@@ -370,9 +409,10 @@ __device__ void stats_finish(const StatsArgs& sa, int grid) {
 }
 
 // Writes this block's partial statistics.  They are finished by
-// stats_finish_kernel, launched after the kernel on the same stream: a
-// last-block finish inside the kernel would need a device-scope release by
-// every block, which writes back its XCD's L2 and cost 15% of a power step.
+// stats_finish_kernel, launched after the kernel on the same stream, or by a
+// block of the next step kernel (PendingFinish): a last-block finish inside
+// the same kernel would need a device-scope release by every block, which
+// writes back its XCD's L2 and cost 15% of a power step.
 // Called by every thread of every block.
 template <int LH>
 __device__ __forceinline__ void stats_epilogue(const StatsArgs& sa, const double* st) {
